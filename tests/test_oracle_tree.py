@@ -1,0 +1,308 @@
+"""Pins of the oracle's reference tree, groups and interaction lists (no GPU).
+
+Section 2.2 steps 2 and 5 (local tree, Barnes' interaction-list walk), Section 3.1.2 (N_leaf
+stopping rule, N_crit grouping), Section 2.2 step 3 (opening criterion and cutoff both
+measured from the surface of the receiving region).  The method is an approximation, so the
+pins are: hand-computed keys, structural invariants, a brute-force frontier built from all
+nodes without recursion, geometric checks of every pruned and accepted node against the
+particles themselves, exact coverage of every particle within r_cut, and the theta -> 0
+limit equal to the exact direct sum.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import boxgen
+
+
+def decode(code: int):
+    """Node code (1 << 3l) | prefix -> (level, ix, iy, iz)."""
+    lev = (int(code).bit_length() - 1) // 3
+    pre = int(code) ^ (1 << (3 * lev))
+    ix = iy = iz = 0
+    for b in range(lev):
+        d = (pre >> (3 * (lev - 1 - b))) & 7
+        ix = 2 * ix + ((d >> 2) & 1)
+        iy = 2 * iy + ((d >> 1) & 1)
+        iz = 2 * iz + (d & 1)
+    return lev, ix, iy, iz
+
+
+def test_keys_hand_computed(orc):
+    # x is the most significant bit of each triplet, then y, then z.
+    assert orc.key(0.5, 0.0, 0.0) == 1 << 62
+    assert orc.key(0.0, 0.5, 0.0) == 1 << 61
+    assert orc.key(0.0, 0.0, 0.5) == 1 << 60
+    assert orc.key(0.0, 0.0, 0.0) == 0
+    top = 1.0 - 2.0 ** -21
+    assert orc.key(top, top, top) == (1 << 63) - 1
+    # the lowest triplet: one cell of 2^-21 along each axis
+    assert orc.key(2.0 ** -21, 0.0, 0.0) == 4
+    assert orc.key(0.0, 2.0 ** -21, 2.0 ** -21) == 3
+    # the quantisation clamps at 2^21 - 1 (x just below L rounds to the top cell)
+    assert orc.key(np.nextafter(1.0, 0.0), 0.0, 0.0) == orc.key(top, 0.0, 0.0)
+    # another box size: key depends on x / L only
+    assert orc.key(1.5, 0.75, 0.0, 3.0) == orc.key(0.5, 0.25, 0.0, 1.0)
+
+
+def test_keys_decode_to_cells(orc):
+    x, y, z, _ = boxgen.uniform_box(200, 3)
+    for i in range(200):
+        k = orc.key(x[i], y[i], z[i])
+        lev, ix, iy, iz = decode((1 << 63) | k)
+        assert lev == 21
+        assert (ix, iy, iz) == tuple(int(math.floor(p * 2 ** 21)) for p in (x[i], y[i], z[i]))
+
+
+def _tree(orc, n, seed, theta=0.5, n_leaf=4, n_crit=24, r_cut=0.2, eps=0.003, kind="nfw"):
+    if kind == "nfw":
+        x, y, z, m = boxgen.nfw_box(n, max(1, n // 100), seed)
+    else:
+        x, y, z, m = boxgen.uniform_box(n, seed)
+    T = orc.Tree(x, y, z, m, 1.0, r_cut, eps, theta, n_leaf, n_crit)
+    return T, (x, y, z, m)
+
+
+def test_sort_is_stable_key_sort(orc):
+    # coarse positions force many equal keys; ties must keep input order
+    rng = boxgen.SplitMix64(9)
+    n = 3000
+    x = np.floor(rng.uniform(n) * 4) / 4
+    y = np.floor(rng.uniform(n) * 4) / 4
+    z = np.floor(rng.uniform(n) * 4) / 4
+    T = orc.Tree(x, y, z, np.full(n, 1.0 / n), 1.0, 0.2, 0.01, 0.5, 10, 64)
+    k, idx = T.sorted()
+    keys = np.array([orc.key(a, b, c) for a, b, c in zip(x, y, z)], dtype=np.uint64)
+    ref = np.argsort(keys, kind="stable")
+    np.testing.assert_array_equal(idx, ref)
+    np.testing.assert_array_equal(k, keys[ref])
+
+
+@pytest.mark.parametrize("seed,n_leaf", [(1, 2), (2, 4), (3, 10)])
+def test_tree_invariants(orc, seed, n_leaf):
+    T, (x, y, z, m) = _tree(orc, 1500, seed, n_leaf=n_leaf)
+    k, idx = T.sorted()
+    nd = T.nodes()
+    n_nodes = nd["code"].size
+    leaf_cover = np.zeros(T.n, dtype=np.int64)
+    for u in range(n_nodes):
+        lev, ix, iy, iz = decode(nd["code"][u])
+        f, c = int(nd["first"][u]), int(nd["count"][u])
+        assert c >= 1
+        # every particle of the node shares its key prefix, and the neighbours outside do not
+        pre = int(nd["code"][u]) ^ (1 << (3 * lev))
+        sh = 3 * (21 - lev)
+        assert all((int(kk) >> sh) == pre for kk in k[f:f + c])
+        if f > 0:
+            assert (int(k[f - 1]) >> sh) != pre
+        if f + c < T.n:
+            assert (int(k[f + c]) >> sh) != pre
+        # mass is the sum of the particle masses; com lies inside the cube
+        msum = float(np.sum(m[idx[f:f + c]]))
+        assert nd["mass"][u] == pytest.approx(msum, rel=1e-13)
+        l = 2.0 ** -lev
+        lo = np.array([ix, iy, iz]) * l
+        assert np.all(nd["com"][u] >= lo - 1e-15) and np.all(nd["com"][u] <= lo + l + 1e-15)
+        # subdivision rule: leaf iff count < n_leaf or level 21
+        is_leaf = nd["nchild"][u] == 0
+        assert is_leaf == (c < n_leaf or lev == 21)
+        if is_leaf:
+            leaf_cover[f:f + c] += 1
+    assert np.all(leaf_cover == 1)  # leaves partition the particles
+    # children: codes at level+1 whose parent code is u, counts summing to the parent
+    codes = {int(c): u for u, c in enumerate(nd["code"])}
+    for u in range(n_nodes):
+        if nd["nchild"][u] == 0:
+            continue
+        kids = [codes[(int(nd["code"][u]) << 3) | o] for o in range(8)
+                if ((int(nd["code"][u]) << 3) | o) in codes]
+        assert len(kids) == nd["nchild"][u]
+        assert sum(int(nd["count"][v]) for v in kids) == nd["count"][u]
+
+
+def test_groups_rule(orc):
+    n_crit = 24
+    T, (x, y, z, m) = _tree(orc, 3000, 4, n_crit=n_crit)
+    nd = T.nodes()
+    codes = {int(c): u for u, c in enumerate(nd["code"])}
+    G = T.groups()
+    cover = np.zeros(T.n, dtype=np.int64)
+    k, idx = T.sorted()
+    pos = np.stack([x, y, z], axis=1)[idx]
+    for g in range(G["code"].size):
+        u = codes[int(G["code"][g])]
+        f, c = int(G["first"][g]), int(G["count"][g])
+        assert c == nd["count"][u] and f == nd["first"][u]
+        assert c <= n_crit or nd["nchild"][u] == 0
+        if nd["code"][u] != 1:
+            parent = codes[int(nd["code"][u]) >> 3]
+            assert nd["count"][parent] > n_crit
+        cover[f:f + c] += 1
+        np.testing.assert_array_equal(G["lo"][g], pos[f:f + c].min(axis=0))
+        np.testing.assert_array_equal(G["hi"][g], pos[f:f + c].max(axis=0))
+        lev, ix, iy, iz = decode(G["code"][g])
+        np.testing.assert_array_equal(G["xg"][g], (np.array([ix, iy, iz]) + 0.5) * 2.0 ** -lev)
+    assert np.all(cover == 1)
+    assert np.all(np.diff(G["first"]) > 0)  # key order
+
+
+def _min_image(d):
+    return d - np.floor(d + 0.5)
+
+
+def _frontier_check(orc, T, pos_in, m_in, theta, r_cut):
+    """Rebuild each group's list from all nodes without recursion and check every entry
+    geometrically against the particles."""
+    k, idx = T.sorted()
+    pos = pos_in[idx]
+    nd = T.nodes()
+    G = T.groups()
+    off, isc, val = T.lists()
+    n_nodes = nd["code"].size
+    lev = np.array([decode(c)[0] for c in nd["code"]])
+    cube = np.array([decode(c)[1:] for c in nd["code"]], dtype=np.float64)
+    side = 2.0 ** -lev
+    centre = (cube + 0.5) * side[:, None]
+    codes = {int(c): u for u, c in enumerate(nd["code"])}
+    ancestors = []
+    for u in range(n_nodes):
+        a, c = [], int(nd["code"][u])
+        while c != 1:
+            c >>= 3
+            a.append(codes[c])
+        ancestors.append(a)
+    th2, rc2 = theta * theta, r_cut * r_cut
+    total_inter = 0
+    for g in range(G["code"].size):
+        lo, hi = G["lo"][g], G["hi"][g]
+        cg, hg = (lo + hi) * 0.5, (hi - lo) * 0.5
+        gap = np.maximum(0.0, np.abs(_min_image(centre - cg)) - (side[:, None] * 0.5 + hg))
+        Gs = (gap * gap).sum(axis=1)
+        P = Gs >= rc2
+        dc = np.maximum(0.0, np.abs(_min_image(nd["com"] - cg)) - hg)
+        A = (side * side < th2 * (dc * dc).sum(axis=1)) & (Gs > 0.0) & ~P
+        opened = ~A & ~P
+        live = np.array([all(opened[a] for a in ancestors[u]) for u in range(n_nodes)])
+        exp_cells = {int(nd["code"][u]) for u in np.nonzero(live & A)[0]}
+        exp_parts = set()
+        for u in np.nonzero(live & opened & (nd["nchild"] == 0))[0]:
+            exp_parts.update(int(i) for i in idx[nd["first"][u]:nd["first"][u] + nd["count"][u]])
+        s, e = off[g], off[g + 1]
+        got_cells = [int(v) for v, c in zip(val[s:e], isc[s:e]) if c]
+        got_parts = [int(v) for v, c in zip(val[s:e], isc[s:e]) if not c]
+        assert len(set(got_cells)) == len(got_cells) and set(got_cells) == exp_cells
+        assert len(set(got_parts)) == len(got_parts) and set(got_parts) == exp_parts
+        total_inter += int(G["count"][g]) * (e - s)
+        # geometry against the particles themselves
+        gpos = pos[G["first"][g]:G["first"][g] + G["count"][g]]
+        covered = np.zeros(T.n, dtype=np.int64)  # in sorted order
+        for u in np.nonzero(live & A)[0]:
+            f, c = int(nd["first"][u]), int(nd["count"][u])
+            covered[f:f + c] += 1
+            # accepted: side/theta < distance from com to the nearest group particle
+            dmin = np.sqrt((_min_image(gpos - nd["com"][u]) ** 2).sum(axis=1)).min()
+            assert side[u] < theta * dmin
+        for u in np.nonzero(live & P)[0]:
+            f, c = int(nd["first"][u]), int(nd["count"][u])
+            # pruned: every particle of the node is at least r_cut from every group particle
+            d = _min_image(pos[f:f + c][:, None, :] - gpos[None, :, :])
+            assert np.sqrt((d * d).sum(axis=2)).min() >= r_cut
+        inv = np.empty(T.n, dtype=np.int64)
+        inv[idx] = np.arange(T.n)
+        covered[inv[np.array(sorted(exp_parts), dtype=np.int64)]] += 1
+        # every particle within r_cut of the group is covered exactly once, none twice
+        d = _min_image(pos[:, None, :] - gpos[None, :, :])
+        near = np.sqrt((d * d).sum(axis=2)).min(axis=1) < r_cut
+        assert np.all(covered[near] == 1)
+        assert np.all(covered <= 1)
+        # mass partition: list mass + pruned frontier mass = total mass
+        mlist = sum(nd["mass"][codes[c]] for c in got_cells) + m_in[got_parts].sum()
+        mpruned = nd["mass"][live & P].sum()
+        assert mlist + mpruned == pytest.approx(m_in.sum(), rel=1e-12)
+    assert total_inter == T.interactions()
+
+
+@pytest.mark.parametrize("theta", [0.0, 0.3, 0.5, 0.8, 1.0])
+def test_lists_equal_brute_force_frontier(orc, theta):
+    n, r_cut = 400, 0.2
+    T, (x, y, z, m) = _tree(orc, n, 5, theta=theta, n_leaf=3, n_crit=20, r_cut=r_cut)
+    _frontier_check(orc, T, np.stack([x, y, z], axis=1), m, theta, r_cut)
+
+
+def test_lists_uniform_box(orc):
+    T, (x, y, z, m) = _tree(orc, 512, 6, theta=0.6, n_leaf=4, n_crit=16, r_cut=0.3,
+                            kind="uniform")
+    _frontier_check(orc, T, np.stack([x, y, z], axis=1), m, 0.6, 0.3)
+
+
+@pytest.mark.parametrize("kind,seed", [("uniform", 7), ("nfw", 8)])
+def test_theta_zero_is_direct_sum(orc, kind, seed):
+    n, r_cut, eps = 6000, 0.1, 0.002
+    T, (x, y, z, m) = _tree(orc, n, seed, theta=0.0, n_leaf=10, n_crit=64, r_cut=r_cut,
+                            eps=eps, kind=kind)
+    a = np.stack(T.force())
+    b = np.stack(orc.direct_cells(x, y, z, m, 1.0, r_cut, eps))
+    # condition-aware: compare against the scale of the largest accelerations
+    assert np.max(np.abs(a - b)) <= 1e-13 * np.max(np.linalg.norm(b, axis=0))
+    off, isc, val = T.lists()
+    assert not isc.any()
+
+
+def test_small_theta_without_cells_is_direct_sum(orc):
+    """theta <= l_min/(r_cut + sqrt(3) l_min) can never accept a node, so the list force is
+    the direct sum."""
+    n, r_cut, eps = 3000, 0.1, 0.002
+    x, y, z, m = boxgen.uniform_box(n, 9)
+    T0 = orc.Tree(x, y, z, m, 1.0, r_cut, eps, 0.0, 10, 64)
+    lev = max(decode(c)[0] for c in T0.nodes()["code"])
+    lmin = 2.0 ** -lev
+    theta = lmin / (r_cut + math.sqrt(3.0) * lmin)
+    T = orc.Tree(x, y, z, m, 1.0, r_cut, eps, theta, 10, 64)
+    off, isc, val = T.lists()
+    assert not isc.any()
+    a = np.stack(T.force())
+    b = np.stack(orc.direct_brute(x, y, z, m, 1.0, r_cut, eps))
+    assert np.max(np.abs(a - b)) <= 1e-13 * np.max(np.linalg.norm(b, axis=0))
+
+
+def test_theta_error_trend(orc):
+    """Sanity (no absolute pin exists): the tree error against the direct sum shrinks with
+    theta roughly like theta^2 (Section 3.1.2), and the interaction count grows as theta
+    falls (Section 3.2, N_int ~ theta^-2 at small theta)."""
+    n, r_cut, eps = 20000, 0.06, 0.001
+    x, y, z, m = boxgen.nfw_box(n, 30, 12)
+    b = np.stack(orc.direct_cells(x, y, z, m, 1.0, r_cut, eps))
+    nb = np.linalg.norm(b, axis=0)
+    errs, ints = {}, {}
+    for th in (0.25, 0.5, 1.0):
+        T = orc.Tree(x, y, z, m, 1.0, r_cut, eps, th, 10, 64)
+        a = np.stack(T.force())
+        errs[th] = np.sqrt(np.mean(np.linalg.norm(a - b, axis=0) ** 2)) / np.sqrt(np.mean(nb ** 2))
+        ints[th] = T.interactions()
+    assert errs[0.25] < errs[0.5] < errs[1.0]
+    assert 1.5 < errs[0.5] / errs[0.25] < 16.0
+    assert ints[0.25] > ints[0.5] > ints[1.0]
+
+
+def test_lists_never_accept_a_node_holding_the_group(orc):
+    """For theta > 1/sqrt(3) a node that contains the group can have its centre of mass far
+    enough from the group's bbox to pass l < theta d; it must still be opened (the group's
+    own particles cannot be replaced by a monopole that includes them).  Crafted box: a
+    3-particle clump at the corner of the level-1 octant [0, 0.5)^3 whose mass sits in a
+    100-particle clump at the opposite corner."""
+    rng = boxgen.SplitMix64(21)
+    small = 0.01 + 0.002 * rng.uniform(9).reshape(3, 3)
+    big = 0.45 + 0.03 * rng.uniform(300).reshape(100, 3)
+    far = 0.55 + 0.4 * rng.uniform(600).reshape(200, 3)
+    pos = np.concatenate([small, big, far])
+    m = np.full(pos.shape[0], 1.0 / pos.shape[0])
+    for theta in (0.7, 1.0):
+        T = orc.Tree(pos[:, 0], pos[:, 1], pos[:, 2], m, 1.0, 0.5, 0.001, theta, 2, 4)
+        _frontier_check(orc, T, pos, m, theta, 0.5)
+        # the octant [0, 0.5)^3 (code 0b1000) never appears as a cell entry of the small group
+        G = T.groups()
+        off, isc, val = T.lists()
+        g0 = int(np.argmin(G["first"]))
+        s, e = off[g0], off[g0 + 1]
+        assert 8 not in [int(v) for v, c in zip(val[s:e], isc[s:e]) if c]
