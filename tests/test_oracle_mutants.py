@@ -1,0 +1,79 @@
+"""The oracle's pins must catch plausible mistakes in it.
+
+Each case plants one mistake in a copy of the oracle source (a dropped term, a wrong sign,
+index, rule or constant), builds it with gcc on the CPU, and runs the pin that should catch
+it against the broken build; that pin must fail.  The exact boundary convention of the
+minimum image (v >= L/2 versus v > L/2) is not listed: it is unobservable (the absolute
+value used by the walk is the same, and the pair force is zero at r = L/2 >= r_cut).
+"""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "treepm_oracle.c")
+
+PAIR = "tests/test_oracle_pair.py"
+TREE = "tests/test_oracle_tree.py"
+
+MUTANTS = [
+    ("g1_coefficient", "48.0 * R7 - 21.0 * R8) / 140.0", "48.0 * R7 - 20.0 * R8) / 140.0",
+     PAIR + "::test_g_is_s2_cloud_complement"),
+    ("g2_coefficient", "- 840.0 * R4", "- 841.0 * R4", PAIR + "::test_g_branch2_factored"),
+    ("g_branch_point", "if (R < 1.0)\n", "if (R <= 0.9)\n", PAIR + "::test_g_is_s2_cloud_complement"),
+    ("wrap_dropped", "if (v < -h) return v + L;", "if (v < -h) return v;",
+     PAIR + "::test_two_body_across_boundary"),
+    ("softening_dropped", "double s2 = r2 + eps2;", "double s2 = r2;",
+     PAIR + "::test_two_body_across_boundary"),
+    ("force_sign", "acc[0] += f * d[0];", "acc[0] -= f * d[0];",
+     PAIR + "::test_two_body_across_boundary"),
+    ("eta_is_rcut", "double eta = 0.5 * r_cut, eps2 = eps * eps;\n#ifdef _OPENMP\n    if (nthreads > 0) omp_set_num_threads(nthreads);\n#pragma omp parallel for schedule(dynamic, 64)\n#endif\n    for (int64_t i = 0; i < n; ++i) {\n        double acc[3] = {0.0, 0.0, 0.0};\n        for (int64_t j = 0; j < n; ++j) {",
+     "double eta = r_cut, eps2 = eps * eps;\n#ifdef _OPENMP\n    if (nthreads > 0) omp_set_num_threads(nthreads);\n#pragma omp parallel for schedule(dynamic, 64)\n#endif\n    for (int64_t i = 0; i < n; ++i) {\n        double acc[3] = {0.0, 0.0, 0.0};\n        for (int64_t j = 0; j < n; ++j) {",
+     PAIR + "::test_zero_at_and_beyond_cutoff"),
+    ("key_axis_order", "k |= ((q[0] >> b) & 1u) << (3 * b + 2);", "k |= ((q[0] >> b) & 1u) << (3 * b);",
+     TREE + "::test_keys_hand_computed"),
+    ("sort_unstable", "return (p->idx < q->idx) ? -1 : (p->idx > q->idx) ? 1 : 0;",
+     "return (p->idx < q->idx) ? 1 : (p->idx > q->idx) ? -1 : 0;",
+     TREE + "::test_sort_is_stable_key_sort"),
+    ("leaf_rule", "if (nd.count < t->n_leaf || nd.level >= ORC_MAXLEVEL)",
+     "if (nd.count <= t->n_leaf || nd.level >= ORC_MAXLEVEL)", TREE + "::test_tree_invariants"),
+    ("com_not_divided", "nd->com[a] = S[a] / M;", "nd->com[a] = S[a];",
+     TREE + "::test_tree_invariants"),
+    ("group_rule", "if (nd->nchild == 0 || nd->count <= t->n_crit) return push_group(t, u);",
+     "if (nd->nchild == 0 || nd->count < t->n_crit) return push_group(t, u);",
+     TREE + "::test_groups_rule"),
+    ("group_centre", "g->xg[a] = ((double)ic[a] + 0.5) * l;", "g->xg[a] = ((double)ic[a]) * l;",
+     TREE + "::test_groups_rule"),
+    ("bbox_half_size", "g->hg[a] = (hi[a] - lo[a]) * 0.5;", "g->hg[a] = (hi[a] - lo[a]) * 0.4;",
+     TREE + "::test_lists_equal_brute_force_frontier"),
+    ("prune_uses_full_side", "- (half + g->hg[a]);", "- (l + g->hg[a]);",
+     TREE + "::test_lists_equal_brute_force_frontier"),
+    ("accept_not_squared", "if (l * l < th2 * D && G > 0.0)", "if (l < th2 * D && G > 0.0)",
+     TREE + "::test_lists_equal_brute_force_frontier"),
+    ("accept_guard_dropped", "if (l * l < th2 * D && G > 0.0)", "if (l * l < th2 * D)",
+     TREE + "::test_lists_never_accept_a_node_holding_the_group"),
+    ("accept_on_tie", "if (l * l < th2 * D && G > 0.0)", "if (l * l <= th2 * D && G > 0.0)",
+     TREE + "::test_opening_tie_opens_the_node"),
+    ("leaf_particles_skipped", "for (int64_t k = nd->first; k < nd->first + nd->count; ++k)\n            if (elist_push(out, k, 0)) return -1;",
+     "for (int64_t k = nd->first + 1; k < nd->first + nd->count; ++k)\n            if (elist_push(out, k, 0)) return -1;",
+     TREE + "::test_theta_zero_is_direct_sum"),
+]
+
+
+@pytest.mark.parametrize("name,old,new,pin", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_pin_catches_planted_mistake(tmp_path, name, old, new, pin):
+    src = open(SRC).read()
+    assert src.count(old) >= 1, f"mutation site for {name} not found"
+    mutated = src.replace(old, new, 1)
+    c = tmp_path / f"{name}.c"
+    so = tmp_path / f"{name}.so"
+    c.write_text(mutated)
+    subprocess.run(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-fopenmp",
+                    "-ffp-contract=off", str(c), "-o", str(so), "-lm"], check=True)
+    env = dict(os.environ, TREEPM_ORACLE_LIB=str(so))
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        os.path.join(ROOT, pin)], cwd=ROOT, env=env, capture_output=True,
+                       text=True, timeout=600)
+    assert r.returncode == 1, f"{name} survived {pin}:\n{r.stdout[-2000:]}"

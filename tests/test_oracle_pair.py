@@ -108,7 +108,7 @@ def _s2_pair_mass_within(r, a=1.0):
     return tot
 
 
-@pytest.mark.parametrize("R", [0.25, 0.6, 1.0, 1.35, 1.8, 2.0])
+@pytest.mark.parametrize("R", [0.25, 0.6, 0.95, 1.0, 1.35, 1.8, 2.0])
 def test_g_is_s2_cloud_complement(orc, R):
     """g_P3M is the Hockney-Eastwood S2 split: 1 - g(r/eta) is the fraction of the force of
     two S2 clouds of radius eta that has not been cut, i.e. the mass of their

@@ -306,3 +306,23 @@ def test_lists_never_accept_a_node_holding_the_group(orc):
         g0 = int(np.argmin(G["first"]))
         s, e = off[g0], off[g0 + 1]
         assert 8 not in [int(v) for v, c in zip(val[s:e], isc[s:e]) if c]
+
+
+def test_opening_tie_opens_the_node(orc):
+    """l = theta d exactly (dyadic positions, exact FP64) must open the node: the test is the
+    strict l^2 < theta^2 d^2.  Group A = cube [0, 1/4)^3; node B = [1/4, 3/8) x [0, 1/8)^2
+    holds two particles with centre of mass exactly 1/4 (= l / theta for l = 1/8,
+    theta = 1/2) from A's bbox, so B itself is opened and its two children (side 1/16)
+    are accepted instead."""
+    pos = np.array([[0.03125, 0.03125, 0.03125], [0.0625, 0.0625, 0.0625],
+                    [0.28125, 0.046875, 0.046875], [0.34375, 0.046875, 0.046875]])
+    m = np.full(4, 0.25)
+    T = orc.Tree(pos[:, 0], pos[:, 1], pos[:, 2], m, 1.0, 0.5, 0.001, 0.5, 2, 2)
+    _frontier_check(orc, T, pos, m, 0.5, 0.5)
+    G = T.groups()
+    off, isc, val = T.lists()
+    gA = int(np.argmin(G["first"]))
+    cells = sorted(int(v) for v, c in zip(val[off[gA]:off[gA + 1]], isc[off[gA]:off[gA + 1]]) if c)
+    # level-4 codes (marker 1 << 12) under B = level-3 code 0b1_000_100_000
+    b3 = (1 << 9) | (0b000 << 6) | (0b100 << 3) | 0b000
+    assert cells == sorted([(b3 << 3) | 0b000, (b3 << 3) | 0b100])
