@@ -1,0 +1,167 @@
+/*
+ * treepm.h -- C ABI of the MI355X short-range TreePM tree force.
+ *
+ * The library computes the particle-particle (short-range) part of the TreePM force of
+ * Ishiyama, Fukushige & Makino, "GreeM: Massively Parallel TreePM Code for Large
+ * Cosmological N-body Simulations" (PASJ 2009, arXiv:0910.0121), for one periodic box held
+ * on one GPU:
+ *
+ *   a_i = sum over the interaction list of i's group of
+ *         m_j d g_P3M(|d|/eta) / (|d|^2 + eps^2)^(3/2),   d = x_j - x_i (nearest image),
+ *
+ * with the cutoff function g_P3M of eq. (2), 2 eta = r_cut (Section 2.1, eq. 1; Section 2.2
+ * step 1 sets r_cut = 3 / N_PM), Plummer softening eps (Section 2.4), and the lists built by
+ * Barnes' group walk over a Morton-key octree (Section 2.2 steps 2 and 5; Section 3.1.2 for
+ * N_leaf and N_crit).  Sources are particles or tree nodes (mass and centre of mass).
+ * Accelerations point toward the sources; G = 1.
+ *
+ * Conventions for every call:
+ *  - Return value: TREEPM_OK (0), TREEPM_PENDING (1, ensemble poll only) or a negative
+ *    TREEPM_ERR_* code.  No C++ exception or abort crosses this interface.  The text of the
+ *    last error of a context is returned by treepm_last_error().
+ *  - Memory kinds: TREEPM_HOST buffers are ordinary host memory; TREEPM_DEVICE buffers are
+ *    device pointers on the context's GPU.  All buffers are owned by the caller.  Inputs are
+ *    copied or read by the library before the call's work completes on the stream.
+ *  - Streams: hip_stream is a hipStream_t (NULL = the default stream).  Calls on one context
+ *    are stream-ordered and must be made from one thread at a time.  Calls that return
+ *    results to host memory synchronise the stream before returning.
+ *  - Handles are owned by the library until the matching *_destroy call.
+ */
+#ifndef TREEPM_H
+#define TREEPM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    TREEPM_OK = 0,
+    TREEPM_PENDING = 1,
+    TREEPM_ERR_ARG = -1,        /* invalid parameter or argument                          */
+    TREEPM_ERR_RANGE = -2,      /* a position outside [0, L): the caller must wrap          */
+    TREEPM_ERR_OOM = -3,        /* device memory (or the ensemble's HBM budget) exhausted   */
+    TREEPM_ERR_DEVICE = -4,     /* a HIP runtime error                                      */
+    TREEPM_ERR_STATE = -5,      /* call out of order (walk before build, force before walk) */
+    TREEPM_ERR_QUEUE_FULL = -6, /* ensemble request queue full                              */
+    TREEPM_ERR_OVERFLOW = -7    /* an internal capacity was exceeded (see last_error)       */
+};
+
+enum { TREEPM_FP32 = 0, TREEPM_FP64 = 1 };   /* pair-kernel / output precision */
+enum { TREEPM_HOST = 0, TREEPM_DEVICE = 1 }; /* memory kind of caller buffers  */
+
+/* Parameters of one box (Section 2.2 step 1; Section 2.4; Section 3.1.2).
+ *   L        periodic box side, > 0 (the paper normalises it to 1).
+ *   mesh     PM mesh spacing L / N_PM, > 0.
+ *   r_cut    cutoff radius, 0 < r_cut <= L/2, and r_cut = 3 mesh to relative 1e-12
+ *            (2 eta = r_cut = 3 / N_PM).
+ *   eps      Plummer softening, >= 0; the FP32 kernel requires eps > 0.
+ *   theta    opening angle, 0 <= theta <= 1.  A node of side l is used as one source when
+ *            l < theta d, d = distance from its centre of mass to the group's bounding box
+ *            (minimum image), and its cube does not touch that box.
+ *   n_leaf   a node is subdivided iff it holds >= n_leaf particles (and level < 21); >= 2.
+ *   n_crit   groups are the maximal nodes holding <= n_crit particles (or leaves); >= 1;
+ *            0 selects the library default (128).
+ *   precision TREEPM_FP32: pair force in FP32 on positions relative to the group's cube
+ *            centre with compensated accumulation (Section 3.1.1); TREEPM_FP64: plain FP64.
+ *            The tree, moments and every walk decision are FP64 in both cases. */
+typedef struct {
+    double L;
+    double mesh;
+    double r_cut;
+    double eps;
+    double theta;
+    int32_t n_leaf;
+    int32_t n_crit;
+    int32_t precision;
+} treepm_params;
+
+typedef struct treepm_ctx treepm_ctx; /* one resident box on one GPU */
+typedef struct treepm_ens treepm_ens; /* ensemble server            */
+
+/* Counts and timings of the last build/walk/force of a context. */
+typedef struct {
+    int64_t n;              /* particles                                                  */
+    int64_t n_nodes;        /* tree nodes                                                 */
+    int64_t n_groups;       /* groups (one interaction list each)                         */
+    int64_t n_cell_entries; /* list entries that are tree nodes                           */
+    int64_t n_part_entries; /* list entries that are particles                            */
+    int64_t interactions;   /* sum over groups of (group size x list length)              */
+    int32_t max_level;      /* deepest tree level                                         */
+    int32_t max_group;      /* largest group                                              */
+    double t_ms[4];         /* device time of build, walk, force, and their sum (ms);
+                               0 unless timing is enabled with treepm_set_timing          */
+} treepm_stats;
+
+/* Create a context for one box on HIP device `device`.  Validates *params (ERR_ARG).  The
+ * context allocates device memory lazily and keeps it for later calls. */
+int treepm_create(const treepm_params *params, int device, treepm_ctx **out);
+
+/* Release every resource of the context.  NULL is accepted. */
+int treepm_destroy(treepm_ctx *ctx);
+
+/* Replace the parameters of an existing context (same validation as create).  The next
+ * call must be treepm_build. */
+int treepm_set_params(treepm_ctx *ctx, const treepm_params *params);
+
+/* Record per-phase device times into treepm_stats.t_ms (adds event records to the stream). */
+int treepm_set_timing(treepm_ctx *ctx, int enable);
+
+/* Build the tree of n particles (Section 2.2 step 2): validate, compute 63-bit Morton keys,
+ * stable radix sort, gather positions and masses into key order, build the octree with the
+ * N_leaf rule, FP64 node masses and centres of mass, and the N_crit groups.
+ * x, y, z, m: n doubles each, of kind mem_kind.  Requires 0 <= x < L on each axis
+ * (ERR_RANGE otherwise), finite values and m > 0 (ERR_ARG).  A failed build leaves the
+ * context empty. */
+int treepm_build(treepm_ctx *ctx, int64_t n, const double *x, const double *y, const double *z,
+                 const double *m, int mem_kind, void *hip_stream);
+
+/* Barnes' group walk (Section 2.2 step 5): one interaction list per group.  Requires a
+ * build (ERR_STATE).  Fills *stats if non-NULL. */
+int treepm_walk(treepm_ctx *ctx, void *hip_stream, treepm_stats *stats);
+
+/* Short-range force on every particle from its group's list (eq. 1, 2), written in the
+ * caller's original particle order.  ax, ay, az: n values each of type out_prec
+ * (TREEPM_FP32 = float, TREEPM_FP64 = double) and kind mem_kind.  Requires a walk
+ * (ERR_STATE). */
+int treepm_force_short(treepm_ctx *ctx, void *ax, void *ay, void *az, int out_prec,
+                       int mem_kind, void *hip_stream);
+
+/* Counts (and timings) of the last calls.  Synchronises the context's last stream. */
+int treepm_get_stats(treepm_ctx *ctx, treepm_stats *stats);
+
+/* ------------------------------------------------------------ exports (host buffers) */
+
+/* Sorted Morton keys and, for each sorted particle, its input index (n each). */
+int treepm_export_sorted(treepm_ctx *ctx, uint64_t *keys, int64_t *idx);
+
+/* Tree nodes (cap >= n_nodes): code = (1 << 3 level) | key prefix, first and count in key
+ * order, number of children, FP64 mass and centre of mass (com: 3 doubles per node). */
+int treepm_export_nodes(treepm_ctx *ctx, int64_t cap, uint64_t *code, int64_t *first,
+                        int64_t *count, int32_t *nchild, double *mass, double *com);
+
+/* Groups in key order (cap >= n_groups): node code, first, count, bounding box lo/hi and
+ * cube centre x_g (3 doubles each per group). */
+int treepm_export_groups(treepm_ctx *ctx, int64_t cap, uint64_t *code, int64_t *first,
+                         int64_t *count, double *lo, double *hi, double *xg);
+
+/* Interaction lists in canonical form: offsets[n_groups + 1] (groups in key order); for each
+ * entry is_cell (1 = tree node, 0 = particle) and value = node code or the particle's input
+ * index.  Entries of one group are in the library's traversal order.  entry_cap must be >=
+ * the number of entries (ERR_ARG otherwise). */
+int treepm_export_lists(treepm_ctx *ctx, int64_t group_cap, int64_t entry_cap, int64_t *offsets,
+                        uint8_t *is_cell, uint64_t *value);
+
+/* Text of the last error on this context ("" if none).  Valid until the next call. */
+const char *treepm_last_error(const treepm_ctx *ctx);
+
+/* Library version string. */
+const char *treepm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TREEPM_H */

@@ -49,6 +49,8 @@ def lib():
         L.orc_tree_walk.argtypes = [_p]
         L.orc_tree_force.restype = C.c_int
         L.orc_tree_force.argtypes = [_p, _p, _p, _p, C.c_int]
+        L.orc_tree_force_mag.restype = C.c_int
+        L.orc_tree_force_mag.argtypes = [_p, _p, _p, C.c_int]
         L.orc_tree_walk_force_sample.restype = _i64
         L.orc_tree_walk_force_sample.argtypes = [_p, _i64, _i64, _p, _p, _p, C.c_int, _p]
         for name in ("orc_tree_n_nodes", "orc_tree_n_groups", "orc_tree_n_entries",
@@ -193,6 +195,21 @@ class Tree:
         if lib().orc_tree_force(self.h, _ptr(ax), _ptr(ay), _ptr(az), nthreads) != 0:
             raise RuntimeError("oracle list force failed")
         return ax, ay, az
+
+    def force_mag(self, nthreads=0):
+        """Per particle: sum over its list of |pair force|, and of the same magnitudes
+        without the cutoff factor g -- the scales of rounding error in the list force."""
+        mag = np.zeros(self.n)
+        newt = np.zeros(self.n)
+        if lib().orc_tree_force_mag(self.h, _ptr(mag), _ptr(newt), nthreads) != 0:
+            raise RuntimeError("oracle list force magnitude failed")
+        return mag, newt
+
+    def error_scale(self, nthreads=0):
+        """sum_j |f_ij| + sum_j m_j r/(r^2+eps^2)^1.5 per particle: the FP64 comparison scale
+        (the oracle's expanded eq. (2) rounds to a few 1e-14 of the uncut magnitude)."""
+        mag, newt = self.force_mag(nthreads)
+        return mag + newt
 
     def walk_force_sample(self, stride, offset=0, nthreads=0):
         """Walk + list force for groups offset, offset+stride, ...; returns

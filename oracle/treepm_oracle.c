@@ -90,6 +90,22 @@ static void pair_acc(const double d[3], double m, double eta, double eps2, doubl
     acc[2] += f * d[2];
 }
 
+/* |pair force| of the same pair, and the same magnitude without the cutoff factor g, for
+ * condition-aware tolerances: adds into *mag and *newt.  The expanded polynomial of eq. (2)
+ * sums terms up to ~300 in size near R = 2, so its rounding error is a few 1e-14 of the
+ * uncut magnitude, not of |f|. */
+static void pair_mag(const double d[3], double m, double eta, double eps2, double *mag,
+                     double *newt)
+{
+    double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+    if (r2 == 0.0) return;
+    double r = sqrt(r2);
+    double s2 = r2 + eps2;
+    double nm = m * r / (s2 * sqrt(s2));
+    *mag += orc_g_p3m(r / eta) * nm;
+    *newt += nm;
+}
+
 /* Public single-pair evaluation (tests): acceleration at (xi) from (xj, m) in box L. */
 void orc_pair(const double xi[3], const double xj[3], double m, double L, double r_cut,
               double eps, double out[3])
@@ -586,6 +602,36 @@ static int64_t group_force(const otree *t, int64_t gi, const int64_t *ent, const
         az[i] = acc[2];
     }
     return ne;
+}
+
+/* Sum over each particle's list of the pair-force magnitudes, sum_j |f_ij|, and of the same
+ * magnitudes without g (input order): the scales of rounding error in the list force, for
+ * condition-aware comparisons. */
+int orc_tree_force_mag(otree *t, double *mag, double *newt, int nthreads)
+{
+    if (!t) return -1;
+    if (orc_tree_walk(t) < 0) return -1;
+    double eta = 0.5 * t->r_cut, eps2 = t->eps * t->eps;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+    for (int64_t gi = 0; gi < t->n_groups; ++gi) {
+        const ogroup *g = &t->groups[gi];
+        for (int64_t k = g->first; k < g->first + g->count; ++k) {
+            double s = 0.0, sn = 0.0;
+            for (int64_t q = t->list_off[gi]; q < t->list_off[gi + 1]; ++q) {
+                double p[3], mj;
+                entry_source(t, t->list[q], t->list_is_cell[q], p, &mj);
+                double d[3] = {wrap(p[0] - t->px[k], t->L), wrap(p[1] - t->py[k], t->L),
+                               wrap(p[2] - t->pz[k], t->L)};
+                pair_mag(d, mj, eta, eps2, &s, &sn);
+            }
+            mag[t->idx[k]] = s;
+            newt[t->idx[k]] = sn;
+        }
+    }
+    return 0;
 }
 
 /* List force for every particle (output in input order), from the lists of orc_tree_walk.

@@ -1,0 +1,240 @@
+"""ctypes declarations of include/treepm.h and the argument marshalling for each call."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libtreepm.so")
+
+TREEPM_OK, TREEPM_PENDING = 0, 1
+TREEPM_FP32, TREEPM_FP64 = 0, 1
+TREEPM_HOST, TREEPM_DEVICE = 0, 1
+
+ERROR_NAMES = {
+    -1: "TREEPM_ERR_ARG", -2: "TREEPM_ERR_RANGE", -3: "TREEPM_ERR_OOM",
+    -4: "TREEPM_ERR_DEVICE", -5: "TREEPM_ERR_STATE", -6: "TREEPM_ERR_QUEUE_FULL",
+    -7: "TREEPM_ERR_OVERFLOW",
+}
+
+
+class TreePMError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERROR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class treepm_params(C.Structure):
+    _fields_ = [("L", C.c_double), ("mesh", C.c_double), ("r_cut", C.c_double),
+                ("eps", C.c_double), ("theta", C.c_double), ("n_leaf", C.c_int32),
+                ("n_crit", C.c_int32), ("precision", C.c_int32)]
+
+
+class treepm_stats(C.Structure):
+    _fields_ = [("n", C.c_int64), ("n_nodes", C.c_int64), ("n_groups", C.c_int64),
+                ("n_cell_entries", C.c_int64), ("n_part_entries", C.c_int64),
+                ("interactions", C.c_int64), ("max_level", C.c_int32),
+                ("max_group", C.c_int32), ("t_ms", C.c_double * 4)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "t_ms"}
+        d["t_ms"] = list(self.t_ms)
+        return d
+
+
+_lib = None
+_p = C.c_void_p
+_i = C.c_int
+_i64 = C.c_int64
+
+_SIGS = {
+    "treepm_version": (C.c_char_p, []),
+    "treepm_create": (_i, [C.POINTER(treepm_params), _i, C.POINTER(_p)]),
+    "treepm_destroy": (_i, [_p]),
+    "treepm_set_params": (_i, [_p, C.POINTER(treepm_params)]),
+    "treepm_set_timing": (_i, [_p, _i]),
+    "treepm_build": (_i, [_p, _i64, _p, _p, _p, _p, _i, _p]),
+    "treepm_walk": (_i, [_p, _p, C.POINTER(treepm_stats)]),
+    "treepm_force_short": (_i, [_p, _p, _p, _p, _i, _i, _p]),
+    "treepm_get_stats": (_i, [_p, C.POINTER(treepm_stats)]),
+    "treepm_export_sorted": (_i, [_p, _p, _p]),
+    "treepm_export_nodes": (_i, [_p, _i64, _p, _p, _p, _p, _p, _p]),
+    "treepm_export_groups": (_i, [_p, _i64, _p, _p, _p, _p, _p, _p]),
+    "treepm_export_lists": (_i, [_p, _i64, _i64, _p, _p, _p]),
+    "treepm_last_error": (C.c_char_p, [_p]),
+}
+
+
+def lib():
+    """Load libtreepm.so (built by paper_0910_0121_amd/build.py); raises if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is not built; run `python -m paper_0910_0121_amd.build` "
+                "(the tree force has no non-HIP implementation)")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def treepm_version() -> str:
+    return lib().treepm_version().decode()
+
+
+def treepm_last_error(ctx) -> str:
+    return lib().treepm_last_error(ctx).decode()
+
+
+def _check(rc: int, ctx=None):
+    if rc < 0:
+        msg = treepm_last_error(ctx) if ctx else ""
+        raise TreePMError(rc, msg)
+    return rc
+
+
+def make_params(L=1.0, mesh=None, r_cut=None, eps=0.0, theta=0.5, n_leaf=10, n_crit=0,
+                precision=TREEPM_FP32) -> treepm_params:
+    if mesh is None and r_cut is None:
+        raise ValueError("give mesh or r_cut")
+    if mesh is None:
+        mesh = r_cut / 3.0
+    if r_cut is None:
+        r_cut = 3.0 * mesh
+    return treepm_params(L, mesh, r_cut, eps, theta, n_leaf, n_crit, precision)
+
+
+# ----------------------------------------------------------------------------- buffers
+
+def _is_torch(a):
+    return type(a).__module__.startswith("torch")
+
+
+def _buf(a, dtype_name):
+    """(pointer, mem_kind, keepalive) for a torch tensor or numpy array."""
+    if _is_torch(a):
+        if not a.is_contiguous():
+            raise ValueError("buffers must be contiguous")
+        if str(a.dtype) != "torch." + dtype_name:
+            raise TypeError(f"expected torch.{dtype_name}, got {a.dtype}")
+        kind = TREEPM_DEVICE if a.is_cuda else TREEPM_HOST
+        return a.data_ptr(), kind, a
+    arr = np.asarray(a)
+    if arr.dtype != np.dtype(dtype_name) or not arr.flags.c_contiguous:
+        raise TypeError(f"expected a contiguous numpy {dtype_name} array")
+    return arr.ctypes.data, TREEPM_HOST, arr
+
+
+def _stream(stream, kind):
+    if stream is not None:
+        return stream if isinstance(stream, int) else stream.cuda_stream
+    if kind == TREEPM_DEVICE:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return 0
+
+
+# ----------------------------------------------------------------------------- entry points
+
+def treepm_create(params: treepm_params, device: int = 0):
+    h = C.c_void_p()
+    _check(lib().treepm_create(C.byref(params), device, C.byref(h)))
+    return h.value
+
+
+def treepm_destroy(ctx) -> None:
+    _check(lib().treepm_destroy(ctx))
+
+
+def treepm_set_params(ctx, params: treepm_params) -> None:
+    _check(lib().treepm_set_params(ctx, C.byref(params)), ctx)
+
+
+def treepm_set_timing(ctx, enable: bool) -> None:
+    _check(lib().treepm_set_timing(ctx, int(bool(enable))), ctx)
+
+
+def treepm_build(ctx, x, y, z, m, stream=None) -> None:
+    bufs = [_buf(a, "float64") for a in (x, y, z, m)]
+    kinds = {b[1] for b in bufs}
+    if len(kinds) != 1:
+        raise ValueError("x, y, z, m must all be host or all be device buffers")
+    kind = kinds.pop()
+    n = len(bufs[0][2])
+    _check(lib().treepm_build(ctx, n, bufs[0][0], bufs[1][0], bufs[2][0], bufs[3][0], kind,
+                              _stream(stream, kind)), ctx)
+
+
+def treepm_walk(ctx, stream=None) -> treepm_stats:
+    st = treepm_stats()
+    _check(lib().treepm_walk(ctx, _stream(stream, TREEPM_DEVICE), C.byref(st)), ctx)
+    return st
+
+
+def treepm_force_short(ctx, ax, ay, az, stream=None) -> None:
+    dt = "float64" if (str(getattr(ax, "dtype", "")) in ("torch.float64", "float64")) else "float32"
+    bufs = [_buf(a, dt) for a in (ax, ay, az)]
+    kinds = {b[1] for b in bufs}
+    if len(kinds) != 1:
+        raise ValueError("ax, ay, az must all be host or all be device buffers")
+    kind = kinds.pop()
+    prec = TREEPM_FP64 if dt == "float64" else TREEPM_FP32
+    _check(lib().treepm_force_short(ctx, bufs[0][0], bufs[1][0], bufs[2][0], prec, kind,
+                                    _stream(stream, kind)), ctx)
+
+
+def treepm_get_stats(ctx) -> treepm_stats:
+    st = treepm_stats()
+    _check(lib().treepm_get_stats(ctx, C.byref(st)), ctx)
+    return st
+
+
+def treepm_export_sorted(ctx):
+    n = treepm_get_stats(ctx).n
+    keys = np.zeros(n, dtype=np.uint64)
+    idx = np.zeros(n, dtype=np.int64)
+    _check(lib().treepm_export_sorted(ctx, keys.ctypes.data, idx.ctypes.data), ctx)
+    return keys, idx
+
+
+def treepm_export_nodes(ctx):
+    nn = treepm_get_stats(ctx).n_nodes
+    code = np.zeros(nn, dtype=np.uint64)
+    first = np.zeros(nn, dtype=np.int64)
+    count = np.zeros(nn, dtype=np.int64)
+    nchild = np.zeros(nn, dtype=np.int32)
+    mass = np.zeros(nn)
+    com = np.zeros((nn, 3))
+    _check(lib().treepm_export_nodes(ctx, nn, code.ctypes.data, first.ctypes.data,
+                                     count.ctypes.data, nchild.ctypes.data, mass.ctypes.data,
+                                     com.ctypes.data), ctx)
+    return dict(code=code, first=first, count=count, nchild=nchild, mass=mass, com=com)
+
+
+def treepm_export_groups(ctx):
+    ng = treepm_get_stats(ctx).n_groups
+    code = np.zeros(ng, dtype=np.uint64)
+    first = np.zeros(ng, dtype=np.int64)
+    count = np.zeros(ng, dtype=np.int64)
+    lo, hi, xg = (np.zeros((ng, 3)) for _ in range(3))
+    _check(lib().treepm_export_groups(ctx, ng, code.ctypes.data, first.ctypes.data,
+                                      count.ctypes.data, lo.ctypes.data, hi.ctypes.data,
+                                      xg.ctypes.data), ctx)
+    return dict(code=code, first=first, count=count, lo=lo, hi=hi, xg=xg)
+
+
+def treepm_export_lists(ctx):
+    st = treepm_get_stats(ctx)
+    ne = st.n_cell_entries + st.n_part_entries
+    off = np.zeros(st.n_groups + 1, dtype=np.int64)
+    isc = np.zeros(max(ne, 1), dtype=np.uint8)
+    val = np.zeros(max(ne, 1), dtype=np.uint64)
+    _check(lib().treepm_export_lists(ctx, st.n_groups + 1, max(ne, 1), off.ctypes.data,
+                                     isc.ctypes.data, val.ctypes.data), ctx)
+    return off, isc[:ne], val[:ne]

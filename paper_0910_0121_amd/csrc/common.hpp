@@ -1,0 +1,116 @@
+// Internal declarations shared by the library's translation units (host launchers and the
+// small device helpers they need).  Nothing here is part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace tpm {
+
+constexpr int kMaxLevel = 21;             // 21 bits per axis, 63-bit keys
+constexpr uint32_t kCellTag = 0x80000000u; // list entry: node index | tag, else sorted index
+constexpr int kSortBits = 8;               // radix digit width
+constexpr int kSortBins = 1 << kSortBits;
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 16;
+constexpr int kSortTile = kSortThreads * kSortItems;
+
+// Flags raised by the validation/key kernel.
+constexpr unsigned kFlagNonFinite = 1u; // non-finite position or mass, or mass <= 0
+constexpr unsigned kFlagRange = 2u;     // position outside [0, L)
+
+// Device arrays of one tree (structure of arrays).  Nodes are stored level by level; the
+// children of a node are contiguous and in octant order.
+struct NodeArrays {
+    uint64_t *code;        // (1 << 3 level) | key prefix
+    uint32_t *first;       // first particle (key order)
+    uint32_t *count;       // particles
+    uint32_t *child_first; // index of the first child
+    uint32_t *parent;      // index of the parent (root: itself)
+    uint8_t *nchild;       // 0 for a leaf
+    uint8_t *level;
+    double *mass;          // FP64 moments
+    double *comx, *comy, *comz;
+    double *cnx, *cny, *cnz; // cube centres ((i + 1/2) * L / 2^level)
+};
+
+struct GroupArrays {
+    uint32_t *node, *first, *count;
+    double *cgx, *cgy, *cgz;  // bbox centre (lo + hi) / 2
+    double *hgx, *hgy, *hgz;  // bbox half size (hi - lo) / 2
+    double *xgx, *xgy, *xgz;  // cube centre of the group node (FP32 origin)
+    double *lox, *loy, *loz, *hix, *hiy, *hiz;
+};
+
+// ------------------------------------------------------------------ launchers (k_scan.hip)
+// Exclusive prefix sum in place over n values; the total is written to *total (device).
+// tmp must hold scan_tmp_elems(n) values of the same type.
+size_t scan_tmp_elems(size_t n);
+void fill_u32(uint32_t *p, size_t n, uint32_t v, hipStream_t s);
+void fill_u64(uint64_t *p, size_t n, uint64_t v, hipStream_t s);
+void scan_u32(uint32_t *data, size_t n, uint32_t *total, uint32_t *tmp, hipStream_t s);
+void scan_u64(uint64_t *data, size_t n, uint64_t *total, uint64_t *tmp, hipStream_t s);
+
+// ------------------------------------------------------------------ launchers (k_build.hip)
+void launch_keys(int64_t n, const double *x, const double *y, const double *z, const double *m,
+                 double L, uint64_t *key, uint32_t *idx, unsigned *flags, hipStream_t s);
+// Stable LSD radix sort of (key, idx) by key; results end in key/idx.  hist holds
+// sort_hist_elems(n) values.
+size_t sort_hist_elems(int64_t n);
+void radix_sort(int64_t n, uint64_t *key, uint32_t *idx, uint64_t *key_alt, uint32_t *idx_alt,
+                uint32_t *hist, uint32_t *scan_tmp, hipStream_t s);
+void launch_permute(int64_t n, const uint32_t *idx, const double *x, const double *y,
+                    const double *z, const double *m, double *px, double *py, double *pz,
+                    double *pm, hipStream_t s);
+void launch_root(NodeArrays nd, uint32_t n, double L, hipStream_t s);
+// Level step: nodes [lo, hi) of level `level`; writes nchild and per-node child counts into
+// cnt (hi - lo values) for the scan.
+void launch_split(NodeArrays nd, const uint64_t *key, uint32_t lo, uint32_t hi, int level,
+                  int n_leaf, uint32_t *cnt, hipStream_t s);
+// Emit children of nodes [lo, hi) at base + exclusive prefix in cnt.
+void launch_emit(NodeArrays nd, const uint64_t *key, uint32_t lo, uint32_t hi, int level,
+                 uint32_t base, const uint32_t *cnt, double L, hipStream_t s);
+void launch_moments(NodeArrays nd, const double *px, const double *py, const double *pz,
+                    const double *pm, uint32_t lo, uint32_t hi, hipStream_t s);
+// com = S / M for every node, after all levels' moments.
+void launch_com_divide(NodeArrays nd, uint32_t n_nodes, hipStream_t s);
+// Groups: mark in gstart[first] (n values, zeroed here) every maximal node with
+// count <= n_crit or no children; then compact in key order.
+void launch_group_mark(NodeArrays nd, uint32_t n_nodes, int n_crit, uint32_t *gstart,
+                       uint32_t *gflag, int64_t n, hipStream_t s);
+void launch_group_compact(const uint32_t *gstart, const uint32_t *gpos, int64_t n,
+                          uint32_t *gnode, hipStream_t s);
+// Also lowers *min_level to the shallowest group level and raises *max_count to the
+// largest group.
+void launch_group_bbox(NodeArrays nd, GroupArrays gr, uint32_t n_groups, const double *px,
+                       const double *py, const double *pz, unsigned *min_level,
+                       unsigned *max_count, hipStream_t s);
+
+// ------------------------------------------------------------------ launchers (k_walk.hip)
+struct WalkParams {
+    double L, rc2, th2;
+    const double *lside; // device table: L / 2^level, level 0..21
+};
+// Count (emit == 0) or write (emit == 1) the interaction list of every group.
+// The emit pass adds (cell entries, particle entries, interactions) into stats[0..2].
+void launch_walk(NodeArrays nd, GroupArrays gr, uint32_t n_groups, WalkParams wp, int emit,
+                 uint64_t *counts_or_offsets, uint32_t *entries, unsigned *overflow,
+                 unsigned long long *stats, hipStream_t s);
+
+// ------------------------------------------------------------------ launchers (k_force.hip)
+struct ForceParams {
+    double L, eps2, inv_eta, eta;
+};
+void launch_force_f32(NodeArrays nd, GroupArrays gr, uint32_t n_groups, const uint64_t *off,
+                      const uint32_t *entries, const double *px, const double *py,
+                      const double *pz, const double *pm, const uint32_t *pidx,
+                      ForceParams fp, void *ax, void *ay, void *az, int out_prec,
+                      hipStream_t s);
+void launch_force_f64(NodeArrays nd, GroupArrays gr, uint32_t n_groups, const uint64_t *off,
+                      const uint32_t *entries, const double *px, const double *py,
+                      const double *pz, const double *pm, const uint32_t *pidx,
+                      ForceParams fp, void *ax, void *ay, void *az, int out_prec,
+                      hipStream_t s);
+
+} // namespace tpm

@@ -1,0 +1,489 @@
+// Tree construction kernels (Section 2.2 step 2): input validation and 63-bit Morton keys,
+// stable LSD radix sort of (key, index), gather into key order, the octree built level by
+// level with the N_leaf stopping rule (Section 3.1.2), FP64 node masses and centres of mass,
+// and the N_crit groups of Barnes' interaction-list method.
+//
+// Every floating-point operation here is FP64 and this file is compiled without FMA
+// contraction: keys, node moments, group boxes and cube centres must equal, bit for bit,
+// what a plain IEEE evaluation of the same expressions gives, so that the walk takes exactly
+// the decisions the definition takes.
+#include "common.hpp"
+
+namespace tpm {
+namespace {
+
+__device__ __forceinline__ uint64_t spread3(uint64_t v)
+{
+    v &= 0x1fffffull;
+    v = (v | v << 32) & 0x1f00000000ffffull;
+    v = (v | v << 16) & 0x1f0000ff0000ffull;
+    v = (v | v << 8) & 0x100f00f00f00f00full;
+    v = (v | v << 4) & 0x10c30c30c30c30c3ull;
+    v = (v | v << 2) & 0x1249249249249249ull;
+    return v;
+}
+
+__device__ __forceinline__ uint32_t compact3(uint64_t v)
+{
+    v &= 0x1249249249249249ull;
+    v = (v ^ (v >> 2)) & 0x10c30c30c30c30c3ull;
+    v = (v ^ (v >> 4)) & 0x100f00f00f00f00full;
+    v = (v ^ (v >> 8)) & 0x1f0000ff0000ffull;
+    v = (v ^ (v >> 16)) & 0x1f00000000ffffull;
+    v = (v ^ (v >> 32)) & 0x1fffffull;
+    return (uint32_t)v;
+}
+
+// q = min(2^21 - 1, floor(p * 2^21 / L)), clamped at 0 for safety (validated separately).
+__device__ __forceinline__ uint64_t quantise(double p, double scale)
+{
+    double f = floor(p * scale);
+    if (!(f > 0.0)) return 0;
+    if (f >= 2097151.0) return 2097151ull;
+    return (uint64_t)f;
+}
+
+__global__ __launch_bounds__(256) void k_keys(int64_t n, const double *__restrict__ x,
+                                              const double *__restrict__ y,
+                                              const double *__restrict__ z,
+                                              const double *__restrict__ m, double L,
+                                              double scale, uint64_t *__restrict__ key,
+                                              uint32_t *__restrict__ idx, unsigned *flags)
+{
+    unsigned f = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        double p0 = x[i], p1 = y[i], p2 = z[i], mi = m[i];
+        if (!isfinite(p0) || !isfinite(p1) || !isfinite(p2) || !isfinite(mi) || !(mi > 0.0))
+            f |= kFlagNonFinite;
+        else if (!(p0 >= 0.0 && p0 < L && p1 >= 0.0 && p1 < L && p2 >= 0.0 && p2 < L))
+            f |= kFlagRange;
+        uint64_t k = (spread3(quantise(p0, scale)) << 2) | (spread3(quantise(p1, scale)) << 1) |
+                     spread3(quantise(p2, scale));
+        key[i] = k;
+        idx[i] = (uint32_t)i;
+    }
+    if (f) atomicOr(flags, f);
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_hist(const uint64_t *__restrict__ key,
+                                                       int64_t n, int shift,
+                                                       uint32_t *__restrict__ hist,
+                                                       uint32_t nblocks)
+{
+    __shared__ uint32_t h[kSortBins];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    int64_t base = (int64_t)blockIdx.x * kSortTile;
+    for (int it = 0; it < kSortItems; ++it) {
+        int64_t k = base + (int64_t)it * kSortThreads + threadIdx.x;
+        if (k < n) atomicAdd(&h[(uint32_t)(key[k] >> shift) & (kSortBins - 1)], 1u);
+    }
+    __syncthreads();
+    hist[(size_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+}
+
+// Stable scatter of one tile: element order inside the tile is (iteration, thread), and each
+// element's rank among equal digits follows that order.
+__global__ __launch_bounds__(kSortThreads) void k_scatter(const uint64_t *__restrict__ key,
+                                                          const uint32_t *__restrict__ idx,
+                                                          int64_t n, int shift,
+                                                          const uint32_t *__restrict__ hist,
+                                                          uint32_t nblocks,
+                                                          uint64_t *__restrict__ key_out,
+                                                          uint32_t *__restrict__ idx_out)
+{
+    constexpr int kWaves = kSortThreads / 64;
+    __shared__ uint32_t goff[kSortBins];
+    __shared__ uint32_t wcnt[kWaves][kSortBins];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    goff[tid] = hist[(size_t)tid * nblocks + blockIdx.x];
+#pragma unroll
+    for (int q = 0; q < kWaves; ++q) wcnt[q][tid] = 0;
+    __syncthreads();
+    const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+    int64_t base = (int64_t)blockIdx.x * kSortTile;
+    for (int it = 0; it < kSortItems; ++it) {
+        int64_t k = base + (int64_t)it * kSortThreads + tid;
+        bool valid = k < n;
+        uint64_t kv = valid ? key[k] : 0ull;
+        uint32_t iv = valid ? idx[k] : 0u;
+        uint32_t d = (uint32_t)(kv >> shift) & (kSortBins - 1);
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < kSortBits; ++b) {
+            bool bit = (d >> b) & 1u;
+            uint64_t bb = __ballot(bit);
+            peers &= bit ? bb : ~bb;
+        }
+        uint32_t rank = (uint32_t)__popcll(peers & lt);
+        if (valid && (peers & lt) == 0) wcnt[w][d] = (uint32_t)__popcll(peers);
+        __syncthreads();
+        if (valid) {
+            uint32_t before = 0;
+            for (int q = 0; q < w; ++q) before += wcnt[q][d];
+            uint32_t pos = goff[d] + before + rank;
+            key_out[pos] = kv;
+            idx_out[pos] = iv;
+        }
+        __syncthreads();
+        uint32_t add = 0;
+#pragma unroll
+        for (int q = 0; q < kWaves; ++q) {
+            add += wcnt[q][tid];
+            wcnt[q][tid] = 0;
+        }
+        goff[tid] += add;
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(256) void k_permute(int64_t n, const uint32_t *__restrict__ idx,
+                                                 const double *__restrict__ x,
+                                                 const double *__restrict__ y,
+                                                 const double *__restrict__ z,
+                                                 const double *__restrict__ m,
+                                                 double *__restrict__ px, double *__restrict__ py,
+                                                 double *__restrict__ pz,
+                                                 double *__restrict__ pm)
+{
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t i = idx[k];
+        px[k] = x[i];
+        py[k] = y[i];
+        pz[k] = z[i];
+        pm[k] = m[i];
+    }
+}
+
+// Cube centre of a node from its code: ((i + 0.5) * L / 2^level) per axis.
+__device__ __forceinline__ void cube_centre(uint64_t code, int level, double L, double *c)
+{
+    uint64_t pre = code ^ (1ull << (3 * level));
+    double l = ldexp(L, -level);
+    c[0] = ((double)compact3(pre >> 2) + 0.5) * l;
+    c[1] = ((double)compact3(pre >> 1) + 0.5) * l;
+    c[2] = ((double)compact3(pre) + 0.5) * l;
+}
+
+__global__ void k_root(NodeArrays nd, uint32_t n, double L)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        nd.code[0] = 1;
+        nd.first[0] = 0;
+        nd.count[0] = n;
+        nd.parent[0] = 0;
+        nd.level[0] = 0;
+        nd.nchild[0] = 0;
+        nd.child_first[0] = 0;
+        double c[3];
+        cube_centre(1, 0, L, c);
+        nd.cnx[0] = c[0];
+        nd.cny[0] = c[1];
+        nd.cnz[0] = c[2];
+    }
+}
+
+// Boundaries of the 8 octants of a node's key range at the next level: b[o] = first sorted
+// position whose next-level digit is >= o; b[8] = end.
+__device__ __forceinline__ void octant_bounds(const uint64_t *__restrict__ key, uint32_t f,
+                                              uint32_t c, int level, uint32_t *b)
+{
+    int shift = 3 * (kMaxLevel - (level + 1));
+    b[0] = f;
+    b[8] = f + c;
+    for (int o = 1; o < 8; ++o) {
+        uint32_t lo = b[o - 1], hi = f + c;
+        while (lo < hi) {
+            uint32_t mid = lo + ((hi - lo) >> 1);
+            if ((int)((key[mid] >> shift) & 7u) < o)
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        b[o] = lo;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_split(NodeArrays nd, const uint64_t *__restrict__ key,
+                                               uint32_t lo, uint32_t hi, int level, int n_leaf,
+                                               uint32_t *__restrict__ cnt)
+{
+    for (uint32_t u = lo + blockIdx.x * blockDim.x + threadIdx.x; u < hi;
+         u += gridDim.x * blockDim.x) {
+        uint32_t c = nd.count[u];
+        uint32_t nch = 0;
+        if ((int64_t)c >= n_leaf && level < kMaxLevel) {
+            uint32_t b[9];
+            octant_bounds(key, nd.first[u], c, level, b);
+            for (int o = 0; o < 8; ++o) nch += (b[o + 1] > b[o]);
+        }
+        nd.nchild[u] = (uint8_t)nch;
+        cnt[u - lo] = nch;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_emit(NodeArrays nd, const uint64_t *__restrict__ key,
+                                              uint32_t lo, uint32_t hi, int level,
+                                              uint32_t base, const uint32_t *__restrict__ cnt,
+                                              double L)
+{
+    for (uint32_t u = lo + blockIdx.x * blockDim.x + threadIdx.x; u < hi;
+         u += gridDim.x * blockDim.x) {
+        uint32_t nch = nd.nchild[u];
+        if (!nch) {
+            nd.child_first[u] = 0;
+            continue;
+        }
+        uint32_t cf = base + cnt[u - lo];
+        nd.child_first[u] = cf;
+        uint32_t b[9];
+        octant_bounds(key, nd.first[u], nd.count[u], level, b);
+        uint64_t pc = nd.code[u];
+        uint32_t v = cf;
+        for (int o = 0; o < 8; ++o) {
+            if (b[o + 1] <= b[o]) continue;
+            uint64_t code = (pc << 3) | (uint64_t)o;
+            nd.code[v] = code;
+            nd.first[v] = b[o];
+            nd.count[v] = b[o + 1] - b[o];
+            nd.parent[v] = u;
+            nd.level[v] = (uint8_t)(level + 1);
+            nd.nchild[v] = 0;
+            double cc[3];
+            cube_centre(code, level + 1, L, cc);
+            nd.cnx[v] = cc[0];
+            nd.cny[v] = cc[1];
+            nd.cnz[v] = cc[2];
+            ++v;
+        }
+    }
+}
+
+// Mass M and mass-weighted position sum S of the nodes of one level; S is kept in com* until
+// k_com_divide.  Leaf: sum over its particles in key order.  Internal node: sum over its
+// children in octant order.
+__global__ __launch_bounds__(256) void k_moments(NodeArrays nd, const double *__restrict__ px,
+                                                 const double *__restrict__ py,
+                                                 const double *__restrict__ pz,
+                                                 const double *__restrict__ pm, uint32_t lo,
+                                                 uint32_t hi)
+{
+    for (uint32_t u = lo + blockIdx.x * blockDim.x + threadIdx.x; u < hi;
+         u += gridDim.x * blockDim.x) {
+        double M = 0.0, Sx = 0.0, Sy = 0.0, Sz = 0.0;
+        uint32_t nch = nd.nchild[u];
+        if (nch == 0) {
+            uint32_t f = nd.first[u], e = f + nd.count[u];
+            for (uint32_t k = f; k < e; ++k) {
+                double mk = pm[k];
+                M += mk;
+                Sx += mk * px[k];
+                Sy += mk * py[k];
+                Sz += mk * pz[k];
+            }
+        } else {
+            uint32_t cf = nd.child_first[u];
+            for (uint32_t c = cf; c < cf + nch; ++c) {
+                M += nd.mass[c];
+                Sx += nd.comx[c];
+                Sy += nd.comy[c];
+                Sz += nd.comz[c];
+            }
+        }
+        nd.mass[u] = M;
+        nd.comx[u] = Sx;
+        nd.comy[u] = Sy;
+        nd.comz[u] = Sz;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_com_divide(NodeArrays nd, uint32_t n_nodes)
+{
+    for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < n_nodes;
+         u += gridDim.x * blockDim.x) {
+        double M = nd.mass[u];
+        nd.comx[u] = nd.comx[u] / M;
+        nd.comy[u] = nd.comy[u] / M;
+        nd.comz[u] = nd.comz[u] / M;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_group_mark(NodeArrays nd, uint32_t n_nodes, int n_crit,
+                                                    uint32_t *__restrict__ gstart,
+                                                    uint32_t *__restrict__ gflag)
+{
+    for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < n_nodes;
+         u += gridDim.x * blockDim.x) {
+        int64_t c = nd.count[u];
+        bool cand = (c <= n_crit) || nd.nchild[u] == 0;
+        bool top = (u == 0) || ((int64_t)nd.count[nd.parent[u]] > n_crit);
+        if (cand && top) {
+            uint32_t f = nd.first[u];
+            gstart[f] = u + 1;
+            gflag[f] = 1;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_group_compact(const uint32_t *__restrict__ gstart,
+                                                       const uint32_t *__restrict__ gpos,
+                                                       int64_t n, uint32_t *__restrict__ gnode)
+{
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t s = gstart[k];
+        if (s) gnode[gpos[k]] = s - 1;
+    }
+}
+
+// One wave per group: exact min/max of its particle positions.
+__global__ __launch_bounds__(256) void k_group_bbox(NodeArrays nd, GroupArrays gr,
+                                                    uint32_t n_groups,
+                                                    const double *__restrict__ px,
+                                                    const double *__restrict__ py,
+                                                    const double *__restrict__ pz,
+                                                    unsigned *min_level, unsigned *max_count)
+{
+    uint32_t g = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (g >= n_groups) return;
+    uint32_t u = gr.node[g];
+    uint32_t f = nd.first[u], c = nd.count[u];
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (uint32_t k = f + lane; k < f + c; k += 64) {
+        double p[3] = {px[k], py[k], pz[k]};
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = fmin(lo[a], p[a]);
+            hi[a] = fmax(hi[a], p[a]);
+        }
+    }
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = fmin(lo[a], __shfl_xor(lo[a], d, 64));
+            hi[a] = fmax(hi[a], __shfl_xor(hi[a], d, 64));
+        }
+    }
+    if (lane == 0) {
+        atomicMin(min_level, (unsigned)nd.level[u]);
+        atomicMax(max_count, c);
+        gr.first[g] = f;
+        gr.count[g] = c;
+        gr.lox[g] = lo[0]; gr.loy[g] = lo[1]; gr.loz[g] = lo[2];
+        gr.hix[g] = hi[0]; gr.hiy[g] = hi[1]; gr.hiz[g] = hi[2];
+        gr.cgx[g] = (lo[0] + hi[0]) * 0.5;
+        gr.cgy[g] = (lo[1] + hi[1]) * 0.5;
+        gr.cgz[g] = (lo[2] + hi[2]) * 0.5;
+        gr.hgx[g] = (hi[0] - lo[0]) * 0.5;
+        gr.hgy[g] = (hi[1] - lo[1]) * 0.5;
+        gr.hgz[g] = (hi[2] - lo[2]) * 0.5;
+        gr.xgx[g] = nd.cnx[u];
+        gr.xgy[g] = nd.cny[u];
+        gr.xgz[g] = nd.cnz[u];
+    }
+}
+
+inline unsigned grid_for(int64_t n, int threads, int64_t cap = 65536)
+{
+    int64_t b = (n + threads - 1) / threads;
+    if (b < 1) b = 1;
+    if (b > cap) b = cap;
+    return (unsigned)b;
+}
+
+} // namespace
+
+void launch_keys(int64_t n, const double *x, const double *y, const double *z, const double *m,
+                 double L, uint64_t *key, uint32_t *idx, unsigned *flags, hipStream_t s)
+{
+    double scale = 2097152.0 / L;
+    k_keys<<<grid_for(n, 256), 256, 0, s>>>(n, x, y, z, m, L, scale, key, idx, flags);
+}
+
+size_t sort_hist_elems(int64_t n)
+{
+    size_t nb = (size_t)((n + kSortTile - 1) / kSortTile);
+    if (nb < 1) nb = 1;
+    return nb * kSortBins;
+}
+
+void radix_sort(int64_t n, uint64_t *key, uint32_t *idx, uint64_t *key_alt, uint32_t *idx_alt,
+                uint32_t *hist, uint32_t *scan_tmp, hipStream_t s)
+{
+    if (n <= 1) return;
+    uint32_t nb = (uint32_t)((n + kSortTile - 1) / kSortTile);
+    uint64_t *kin = key, *kout = key_alt;
+    uint32_t *iin = idx, *iout = idx_alt;
+    for (int shift = 0; shift < 64; shift += kSortBits) {
+        k_hist<<<nb, kSortThreads, 0, s>>>(kin, n, shift, hist, nb);
+        scan_u32(hist, (size_t)nb * kSortBins, scan_tmp, scan_tmp + 1, s);
+        k_scatter<<<nb, kSortThreads, 0, s>>>(kin, iin, n, shift, hist, nb, kout, iout);
+        uint64_t *tk = kin; kin = kout; kout = tk;
+        uint32_t *ti = iin; iin = iout; iout = ti;
+    }
+    // 64 / kSortBits passes is even: the result is back in key / idx.
+}
+
+void launch_permute(int64_t n, const uint32_t *idx, const double *x, const double *y,
+                    const double *z, const double *m, double *px, double *py, double *pz,
+                    double *pm, hipStream_t s)
+{
+    k_permute<<<grid_for(n, 256), 256, 0, s>>>(n, idx, x, y, z, m, px, py, pz, pm);
+}
+
+void launch_root(NodeArrays nd, uint32_t n, double L, hipStream_t s)
+{
+    k_root<<<1, 64, 0, s>>>(nd, n, L);
+}
+
+void launch_split(NodeArrays nd, const uint64_t *key, uint32_t lo, uint32_t hi, int level,
+                  int n_leaf, uint32_t *cnt, hipStream_t s)
+{
+    k_split<<<grid_for(hi - lo, 256), 256, 0, s>>>(nd, key, lo, hi, level, n_leaf, cnt);
+}
+
+void launch_emit(NodeArrays nd, const uint64_t *key, uint32_t lo, uint32_t hi, int level,
+                 uint32_t base, const uint32_t *cnt, double L, hipStream_t s)
+{
+    k_emit<<<grid_for(hi - lo, 256), 256, 0, s>>>(nd, key, lo, hi, level, base, cnt, L);
+}
+
+void launch_moments(NodeArrays nd, const double *px, const double *py, const double *pz,
+                    const double *pm, uint32_t lo, uint32_t hi, hipStream_t s)
+{
+    k_moments<<<grid_for(hi - lo, 256), 256, 0, s>>>(nd, px, py, pz, pm, lo, hi);
+}
+
+void launch_com_divide(NodeArrays nd, uint32_t n_nodes, hipStream_t s)
+{
+    k_com_divide<<<grid_for(n_nodes, 256), 256, 0, s>>>(nd, n_nodes);
+}
+
+void launch_group_mark(NodeArrays nd, uint32_t n_nodes, int n_crit, uint32_t *gstart,
+                       uint32_t *gflag, int64_t n, hipStream_t s)
+{
+    fill_u32(gstart, (size_t)n, 0u, s);
+    fill_u32(gflag, (size_t)n + 1, 0u, s);
+    k_group_mark<<<grid_for(n_nodes, 256), 256, 0, s>>>(nd, n_nodes, n_crit, gstart, gflag);
+}
+
+void launch_group_compact(const uint32_t *gstart, const uint32_t *gpos, int64_t n,
+                          uint32_t *gnode, hipStream_t s)
+{
+    k_group_compact<<<grid_for(n, 256), 256, 0, s>>>(gstart, gpos, n, gnode);
+}
+
+void launch_group_bbox(NodeArrays nd, GroupArrays gr, uint32_t n_groups, const double *px,
+                       const double *py, const double *pz, unsigned *min_level,
+                       unsigned *max_count, hipStream_t s)
+{
+    if (!n_groups) return;
+    k_group_bbox<<<(n_groups + 3) / 4, 256, 0, s>>>(nd, gr, n_groups, px, py, pz, min_level,
+                                                    max_count);
+}
+
+} // namespace tpm

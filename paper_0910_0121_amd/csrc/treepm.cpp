@@ -1,0 +1,689 @@
+// C ABI of the short-range TreePM tree force: context management, argument checks, device
+// buffers, and the order of the kernels of one build / walk / force evaluation.
+#include "treepm.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+
+#define TREEPM_API extern "C" __attribute__((visibility("default")))
+
+using namespace tpm;
+
+namespace {
+
+struct Buf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    void release()
+    {
+        if (p) hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    template <typename T>
+    T *as() const
+    {
+        return static_cast<T *>(p);
+    }
+};
+
+constexpr int kDefaultNCrit = 128;
+
+} // namespace
+
+struct treepm_ctx {
+    treepm_params prm{};
+    int device = 0;
+    std::string err;
+    int state = 0; // 0 empty, 1 built, 2 walked
+    int64_t n = 0;
+    hipStream_t last = nullptr;
+    bool timing = false;
+    hipEvent_t ev[6] = {};
+    bool ev_valid[3] = {false, false, false};
+    // particles and sort
+    Buf in[4], key, key_alt, idx, idx_alt, pos[4], hist, scan32, flags, levcnt, gstart, gflag;
+    // nodes
+    Buf n_code, n_first, n_count, n_cf, n_parent, n_nch, n_level, n_mass, n_com[3], n_cn[3];
+    size_t node_cap = 0;
+    uint32_t n_nodes = 0;
+    std::vector<uint32_t> lvl;
+    int max_level = 0;
+    // groups
+    Buf g_node, g_first, g_count, g_cg[3], g_hg[3], g_xg[3], g_lo[3], g_hi[3], g_misc;
+    size_t group_cap = 0;
+    uint32_t n_groups = 0;
+    unsigned min_group_level = 0, max_group = 0;
+    // lists
+    Buf off, scan64, entries, lside, wstats, overflow, out[3];
+    uint64_t n_entries = 0;
+    uint64_t st[3] = {0, 0, 0};
+    Buf host_total; // unused placeholder for alignment of future pinned buffers
+};
+
+namespace {
+
+int fail(treepm_ctx *c, int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf;
+    return code;
+}
+
+int hip_fail(treepm_ctx *c, hipError_t e, const char *what)
+{
+    int code = (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) ? TREEPM_ERR_OOM
+                                                                           : TREEPM_ERR_DEVICE;
+    return fail(c, code, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIPCHK(ctx, call)                                                                      \
+    do {                                                                                       \
+        hipError_t e_ = (call);                                                                \
+        if (e_ != hipSuccess) return hip_fail((ctx), e_, #call);                               \
+    } while (0)
+
+hipError_t reserve(Buf &b, size_t bytes)
+{
+    if (bytes <= b.bytes && b.p) return hipSuccess;
+    b.release();
+    size_t want = bytes + bytes / 8 + 256;
+    hipError_t e = hipMalloc(&b.p, want);
+    if (e != hipSuccess) {
+        b.p = nullptr;
+        b.bytes = 0;
+        (void)hipGetLastError();
+        return e;
+    }
+    b.bytes = want;
+    return hipSuccess;
+}
+
+int check_params(treepm_ctx *c, const treepm_params *p)
+{
+    if (!p) return fail(c, TREEPM_ERR_ARG, "params is NULL");
+    if (!std::isfinite(p->L) || !(p->L > 0.0)) return fail(c, TREEPM_ERR_ARG, "L must be > 0");
+    if (!std::isfinite(p->mesh) || !(p->mesh > 0.0))
+        return fail(c, TREEPM_ERR_ARG, "mesh must be > 0");
+    if (!std::isfinite(p->r_cut) || !(p->r_cut > 0.0) || p->r_cut > 0.5 * p->L)
+        return fail(c, TREEPM_ERR_ARG, "r_cut must satisfy 0 < r_cut <= L/2");
+    if (std::fabs(p->r_cut - 3.0 * p->mesh) > 1e-12 * p->r_cut)
+        return fail(c, TREEPM_ERR_ARG, "r_cut must equal 3 * mesh (2 eta = r_cut = 3 / N_PM)");
+    if (!std::isfinite(p->eps) || p->eps < 0.0) return fail(c, TREEPM_ERR_ARG, "eps must be >= 0");
+    if (!std::isfinite(p->theta) || p->theta < 0.0 || p->theta > 1.0)
+        return fail(c, TREEPM_ERR_ARG, "theta must be in [0, 1]");
+    if (p->n_leaf < 2) return fail(c, TREEPM_ERR_ARG, "n_leaf must be >= 2");
+    if (p->n_crit < 0) return fail(c, TREEPM_ERR_ARG, "n_crit must be >= 1 (0 = default)");
+    if (p->precision != TREEPM_FP32 && p->precision != TREEPM_FP64)
+        return fail(c, TREEPM_ERR_ARG, "precision must be TREEPM_FP32 or TREEPM_FP64");
+    if (p->precision == TREEPM_FP32 && !(p->eps > 0.0))
+        return fail(c, TREEPM_ERR_ARG, "the FP32 kernel requires eps > 0");
+    return TREEPM_OK;
+}
+
+NodeArrays nodes_view(treepm_ctx *c)
+{
+    NodeArrays nd;
+    nd.code = c->n_code.as<uint64_t>();
+    nd.first = c->n_first.as<uint32_t>();
+    nd.count = c->n_count.as<uint32_t>();
+    nd.child_first = c->n_cf.as<uint32_t>();
+    nd.parent = c->n_parent.as<uint32_t>();
+    nd.nchild = c->n_nch.as<uint8_t>();
+    nd.level = c->n_level.as<uint8_t>();
+    nd.mass = c->n_mass.as<double>();
+    nd.comx = c->n_com[0].as<double>();
+    nd.comy = c->n_com[1].as<double>();
+    nd.comz = c->n_com[2].as<double>();
+    nd.cnx = c->n_cn[0].as<double>();
+    nd.cny = c->n_cn[1].as<double>();
+    nd.cnz = c->n_cn[2].as<double>();
+    return nd;
+}
+
+GroupArrays groups_view(treepm_ctx *c)
+{
+    GroupArrays g;
+    g.node = c->g_node.as<uint32_t>();
+    g.first = c->g_first.as<uint32_t>();
+    g.count = c->g_count.as<uint32_t>();
+    g.cgx = c->g_cg[0].as<double>(); g.cgy = c->g_cg[1].as<double>(); g.cgz = c->g_cg[2].as<double>();
+    g.hgx = c->g_hg[0].as<double>(); g.hgy = c->g_hg[1].as<double>(); g.hgz = c->g_hg[2].as<double>();
+    g.xgx = c->g_xg[0].as<double>(); g.xgy = c->g_xg[1].as<double>(); g.xgz = c->g_xg[2].as<double>();
+    g.lox = c->g_lo[0].as<double>(); g.loy = c->g_lo[1].as<double>(); g.loz = c->g_lo[2].as<double>();
+    g.hix = c->g_hi[0].as<double>(); g.hiy = c->g_hi[1].as<double>(); g.hiz = c->g_hi[2].as<double>();
+    return g;
+}
+
+// Node arrays with room for `need` nodes; existing contents (n_nodes) are kept.
+int ensure_nodes(treepm_ctx *c, size_t need, hipStream_t s)
+{
+    if (need <= c->node_cap) return TREEPM_OK;
+    size_t cap = std::max(need, c->node_cap * 2);
+    struct F {
+        Buf *b;
+        size_t elem;
+    } fields[] = {{&c->n_code, 8}, {&c->n_first, 4}, {&c->n_count, 4}, {&c->n_cf, 4},
+                  {&c->n_parent, 4}, {&c->n_nch, 1}, {&c->n_level, 1}, {&c->n_mass, 8},
+                  {&c->n_com[0], 8}, {&c->n_com[1], 8}, {&c->n_com[2], 8}, {&c->n_cn[0], 8},
+                  {&c->n_cn[1], 8}, {&c->n_cn[2], 8}};
+    for (auto &f : fields) {
+        Buf nb;
+        hipError_t e = reserve(nb, cap * f.elem);
+        if (e != hipSuccess) return hip_fail(c, e, "node arrays");
+        if (f.b->p && c->n_nodes) {
+            e = hipMemcpyAsync(nb.p, f.b->p, (size_t)c->n_nodes * f.elem,
+                               hipMemcpyDeviceToDevice, s);
+            if (e != hipSuccess) return hip_fail(c, e, "node copy");
+            e = hipStreamSynchronize(s);
+            if (e != hipSuccess) return hip_fail(c, e, "node copy sync");
+        }
+        f.b->release();
+        *f.b = nb;
+    }
+    c->node_cap = cap;
+    return TREEPM_OK;
+}
+
+int ensure_groups(treepm_ctx *c, size_t need)
+{
+    if (need <= c->group_cap && c->g_node.p) return TREEPM_OK;
+    size_t cap = need + need / 8 + 64;
+    Buf *u32s[] = {&c->g_node, &c->g_first, &c->g_count};
+    for (Buf *b : u32s) {
+        hipError_t e = reserve(*b, cap * 4);
+        if (e != hipSuccess) return hip_fail(c, e, "group arrays");
+    }
+    Buf *f64s[] = {&c->g_cg[0], &c->g_cg[1], &c->g_cg[2], &c->g_hg[0], &c->g_hg[1], &c->g_hg[2],
+                   &c->g_xg[0], &c->g_xg[1], &c->g_xg[2], &c->g_lo[0], &c->g_lo[1], &c->g_lo[2],
+                   &c->g_hi[0], &c->g_hi[1], &c->g_hi[2]};
+    for (Buf *b : f64s) {
+        hipError_t e = reserve(*b, cap * 8);
+        if (e != hipSuccess) return hip_fail(c, e, "group arrays");
+    }
+    c->group_cap = cap;
+    return TREEPM_OK;
+}
+
+template <typename T>
+int d2h(treepm_ctx *c, T *dst, const void *src, size_t count, hipStream_t s)
+{
+    if (!count) return TREEPM_OK;
+    HIPCHK(c, hipMemcpyAsync(dst, src, count * sizeof(T), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    return TREEPM_OK;
+}
+
+void record(treepm_ctx *c, int i, hipStream_t s)
+{
+    if (c->timing) hipEventRecord(c->ev[i], s);
+}
+
+int do_build(treepm_ctx *c, int64_t n, const double *x, const double *y, const double *z,
+             const double *m, int mem_kind, hipStream_t s)
+{
+    const treepm_params &P = c->prm;
+    int rc;
+    size_t N = (size_t)n;
+    // particle-sized buffers
+    struct R {
+        Buf *b;
+        size_t bytes;
+    } res[] = {{&c->key, N * 8},         {&c->key_alt, N * 8},   {&c->idx, N * 4},
+               {&c->idx_alt, N * 4},     {&c->pos[0], N * 8},    {&c->pos[1], N * 8},
+               {&c->pos[2], N * 8},      {&c->pos[3], N * 8},    {&c->flags, 64},
+               {&c->levcnt, (N + 1) * 4 + scan_tmp_elems(N + 1) * 4 + 64},
+               {&c->gstart, N * 4},      {&c->gflag, (N + 1) * 4},
+               {&c->hist, sort_hist_elems(n) * 4},
+               {&c->scan32, (scan_tmp_elems(std::max(sort_hist_elems(n), N + 1)) + 64) * 4},
+               {&c->lside, 32 * 8},      {&c->g_misc, 64}};
+    for (auto &r : res) {
+        hipError_t e = reserve(*r.b, std::max<size_t>(r.bytes, 64));
+        if (e != hipSuccess) return hip_fail(c, e, "particle buffers");
+    }
+    const double *src[4] = {x, y, z, m};
+    if (mem_kind == TREEPM_HOST) {
+        for (int a = 0; a < 4; ++a) {
+            hipError_t e = reserve(c->in[a], N * 8);
+            if (e != hipSuccess) return hip_fail(c, e, "input staging");
+            HIPCHK(c, hipMemcpyAsync(c->in[a].p, src[a], N * 8, hipMemcpyHostToDevice, s));
+            src[a] = c->in[a].as<double>();
+        }
+    }
+    unsigned *flags = c->flags.as<unsigned>();
+    fill_u32(flags, 4, 0u, s);
+    launch_keys(n, src[0], src[1], src[2], src[3], P.L, c->key.as<uint64_t>(),
+                c->idx.as<uint32_t>(), flags, s);
+    unsigned hf = 0;
+    if ((rc = d2h(c, &hf, flags, 1, s))) return rc;
+    if (hf & kFlagNonFinite)
+        return fail(c, TREEPM_ERR_ARG, "non-finite position or mass, or a mass <= 0");
+    if (hf & kFlagRange)
+        return fail(c, TREEPM_ERR_RANGE, "a position lies outside [0, L); wrap it first");
+    uint32_t *scan_tmp = c->scan32.as<uint32_t>();
+    radix_sort(n, c->key.as<uint64_t>(), c->idx.as<uint32_t>(), c->key_alt.as<uint64_t>(),
+               c->idx_alt.as<uint32_t>(), c->hist.as<uint32_t>(), scan_tmp, s);
+    launch_permute(n, c->idx.as<uint32_t>(), src[0], src[1], src[2], src[3],
+                   c->pos[0].as<double>(), c->pos[1].as<double>(), c->pos[2].as<double>(),
+                   c->pos[3].as<double>(), s);
+    // octree, level by level
+    c->n_nodes = 0;
+    if ((rc = ensure_nodes(c, std::max<size_t>(1024, N / 2 + 64), s))) return rc;
+    NodeArrays nd = nodes_view(c);
+    launch_root(nd, (uint32_t)n, P.L, s);
+    c->n_nodes = 1;
+    c->lvl.assign({0u, 1u});
+    c->max_level = 0;
+    uint32_t *cnt = c->levcnt.as<uint32_t>();
+    uint32_t *cnt_total = cnt + (N + 1);
+    uint32_t *cnt_tmp = cnt_total + 16;
+    for (int l = 0; l <= kMaxLevel; ++l) {
+        uint32_t lo = c->lvl[l], hi = c->lvl[l + 1];
+        nd = nodes_view(c);
+        launch_split(nd, c->key.as<uint64_t>(), lo, hi, l, P.n_leaf, cnt, s);
+        scan_u32(cnt, hi - lo, cnt_total, cnt_tmp, s);
+        uint32_t add = 0;
+        if ((rc = d2h(c, &add, cnt_total, 1, s))) return rc;
+        c->max_level = l;
+        if (add == 0) break;
+        if ((uint64_t)hi + add > 0x7fffffffull)
+            return fail(c, TREEPM_ERR_OVERFLOW, "more than 2^31 tree nodes");
+        if ((rc = ensure_nodes(c, (size_t)hi + add, s))) return rc;
+        nd = nodes_view(c);
+        launch_emit(nd, c->key.as<uint64_t>(), lo, hi, l, hi, cnt, P.L, s);
+        c->lvl.push_back(hi + add);
+        c->n_nodes = hi + add;
+    }
+    nd = nodes_view(c);
+    const double *px = c->pos[0].as<double>(), *py = c->pos[1].as<double>(),
+                 *pz = c->pos[2].as<double>(), *pm = c->pos[3].as<double>();
+    for (int l = c->max_level; l >= 0; --l)
+        launch_moments(nd, px, py, pz, pm, c->lvl[l], c->lvl[l + 1], s);
+    launch_com_divide(nd, c->n_nodes, s);
+    // groups in key order
+    int n_crit = P.n_crit > 0 ? P.n_crit : kDefaultNCrit;
+    uint32_t *gstart = c->gstart.as<uint32_t>(), *gflag = c->gflag.as<uint32_t>();
+    launch_group_mark(nd, c->n_nodes, n_crit, gstart, gflag, n, s);
+    scan_u32(gflag, N + 1, cnt_total, cnt_tmp, s);
+    uint32_t ng = 0;
+    if ((rc = d2h(c, &ng, cnt_total, 1, s))) return rc;
+    if ((rc = ensure_groups(c, ng))) return rc;
+    GroupArrays gr = groups_view(c);
+    launch_group_compact(gstart, gflag, n, gr.node, s);
+    unsigned *misc = c->g_misc.as<unsigned>();
+    fill_u32(misc, 1, 255u, s);
+    fill_u32(misc + 1, 1, 0u, s);
+    launch_group_bbox(nd, gr, ng, px, py, pz, misc, misc + 1, s);
+    unsigned hm[2] = {0, 0};
+    if ((rc = d2h(c, hm, misc, 2, s))) return rc;
+    c->n_groups = ng;
+    c->min_group_level = hm[0];
+    c->max_group = hm[1];
+    double ls[kMaxLevel + 1];
+    for (int l = 0; l <= kMaxLevel; ++l) ls[l] = std::ldexp(P.L, -l);
+    HIPCHK(c, hipMemcpyAsync(c->lside.p, ls, sizeof ls, hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    return TREEPM_OK;
+}
+
+int do_walk(treepm_ctx *c, hipStream_t s)
+{
+    int rc;
+    uint32_t G = c->n_groups;
+    hipError_t e;
+    if ((e = reserve(c->off, ((size_t)G + 1) * 8)) != hipSuccess) return hip_fail(c, e, "offsets");
+    if ((e = reserve(c->scan64, (scan_tmp_elems((size_t)G + 1) + 64) * 8)) != hipSuccess)
+        return hip_fail(c, e, "scan buffer");
+    if ((e = reserve(c->wstats, 64)) != hipSuccess) return hip_fail(c, e, "stats");
+    if ((e = reserve(c->overflow, 64)) != hipSuccess) return hip_fail(c, e, "flags");
+    uint64_t *off = c->off.as<uint64_t>();
+    uint64_t *tot = c->scan64.as<uint64_t>();
+    unsigned *ovf = c->overflow.as<unsigned>();
+    unsigned long long *ws = c->wstats.as<unsigned long long>();
+    fill_u64(off, (size_t)G + 1, 0ull, s);
+    fill_u32(ovf, 1, 0u, s);
+    fill_u64((uint64_t *)ws, 3, 0ull, s);
+    const treepm_params &P = c->prm;
+    WalkParams wp{P.L, P.r_cut * P.r_cut, P.theta * P.theta, c->lside.as<double>()};
+    NodeArrays nd = nodes_view(c);
+    GroupArrays gr = groups_view(c);
+    launch_walk(nd, gr, G, wp, 0, off, nullptr, ovf, ws, s);
+    scan_u64(off, (size_t)G + 1, tot, tot + 1, s);
+    uint64_t total = 0;
+    if ((rc = d2h(c, &total, tot, 1, s))) return rc;
+    unsigned hov = 0;
+    if ((rc = d2h(c, &hov, ovf, 1, s))) return rc;
+    if (hov) return fail(c, TREEPM_ERR_OVERFLOW, "walk stack overflow");
+    if ((e = reserve(c->entries, std::max<size_t>(total, 1) * 4)) != hipSuccess)
+        return hip_fail(c, e, "interaction lists");
+    launch_walk(nd, gr, G, wp, 1, off, c->entries.as<uint32_t>(), ovf, ws, s);
+    unsigned long long hs[3];
+    if ((rc = d2h(c, hs, ws, 3, s))) return rc;
+    if ((rc = d2h(c, &hov, ovf, 1, s))) return rc;
+    if (hov) return fail(c, TREEPM_ERR_OVERFLOW, "walk stack overflow");
+    c->n_entries = total;
+    for (int i = 0; i < 3; ++i) c->st[i] = hs[i];
+    return TREEPM_OK;
+}
+
+void fill_stats(treepm_ctx *c, treepm_stats *st)
+{
+    memset(st, 0, sizeof *st);
+    st->n = c->n;
+    st->n_nodes = c->n_nodes;
+    st->n_groups = c->n_groups;
+    st->max_level = c->max_level;
+    st->max_group = (int32_t)c->max_group;
+    if (c->state >= 2) {
+        st->n_cell_entries = (int64_t)c->st[0];
+        st->n_part_entries = (int64_t)c->st[1];
+        st->interactions = (int64_t)c->st[2];
+    }
+    if (c->timing) {
+        float t;
+        for (int i = 0; i < 3; ++i) {
+            if (c->ev_valid[i] &&
+                hipEventElapsedTime(&t, c->ev[2 * i], c->ev[2 * i + 1]) == hipSuccess)
+                st->t_ms[i] = t;
+        }
+        st->t_ms[3] = st->t_ms[0] + st->t_ms[1] + st->t_ms[2];
+    }
+}
+
+} // namespace
+
+TREEPM_API const char *treepm_version(void) { return "treepm-mi355x 0.1"; }
+
+TREEPM_API int treepm_create(const treepm_params *params, int device, treepm_ctx **out)
+{
+    if (!out) return TREEPM_ERR_ARG;
+    *out = nullptr;
+    int rc = check_params(nullptr, params);
+    if (rc) return rc;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
+        return TREEPM_ERR_DEVICE;
+    treepm_ctx *c = new (std::nothrow) treepm_ctx();
+    if (!c) return TREEPM_ERR_OOM;
+    c->prm = *params;
+    c->device = device;
+    *out = c;
+    return TREEPM_OK;
+}
+
+TREEPM_API int treepm_destroy(treepm_ctx *c)
+{
+    if (!c) return TREEPM_OK;
+    hipSetDevice(c->device);
+    if (c->last) hipStreamSynchronize(c->last);
+    else hipDeviceSynchronize();
+    Buf *all[] = {&c->in[0], &c->in[1], &c->in[2], &c->in[3], &c->key, &c->key_alt, &c->idx,
+                  &c->idx_alt, &c->pos[0], &c->pos[1], &c->pos[2], &c->pos[3], &c->hist,
+                  &c->scan32, &c->flags, &c->levcnt, &c->gstart, &c->gflag, &c->n_code,
+                  &c->n_first, &c->n_count, &c->n_cf, &c->n_parent, &c->n_nch, &c->n_level,
+                  &c->n_mass, &c->n_com[0], &c->n_com[1], &c->n_com[2], &c->n_cn[0],
+                  &c->n_cn[1], &c->n_cn[2], &c->g_node, &c->g_first, &c->g_count, &c->g_cg[0],
+                  &c->g_cg[1], &c->g_cg[2], &c->g_hg[0], &c->g_hg[1], &c->g_hg[2], &c->g_xg[0],
+                  &c->g_xg[1], &c->g_xg[2], &c->g_lo[0], &c->g_lo[1], &c->g_lo[2], &c->g_hi[0],
+                  &c->g_hi[1], &c->g_hi[2], &c->g_misc, &c->off, &c->scan64, &c->entries,
+                  &c->lside, &c->wstats, &c->overflow, &c->out[0], &c->out[1], &c->out[2]};
+    for (Buf *b : all) b->release();
+    if (c->ev[0])
+        for (hipEvent_t &e : c->ev) hipEventDestroy(e);
+    delete c;
+    return TREEPM_OK;
+}
+
+TREEPM_API int treepm_set_params(treepm_ctx *c, const treepm_params *params)
+{
+    if (!c) return TREEPM_ERR_ARG;
+    int rc = check_params(c, params);
+    if (rc) return rc;
+    c->prm = *params;
+    c->state = 0;
+    return TREEPM_OK;
+}
+
+TREEPM_API int treepm_set_timing(treepm_ctx *c, int enable)
+{
+    if (!c) return TREEPM_ERR_ARG;
+    HIPCHK(c, hipSetDevice(c->device));
+    if (enable && !c->ev[0])
+        for (hipEvent_t &e : c->ev) HIPCHK(c, hipEventCreate(&e));
+    c->timing = enable != 0;
+    for (bool &v : c->ev_valid) v = false;
+    return TREEPM_OK;
+}
+
+TREEPM_API int treepm_build(treepm_ctx *c, int64_t n, const double *x, const double *y,
+                            const double *z, const double *m, int mem_kind, void *hip_stream)
+{
+    if (!c) return TREEPM_ERR_ARG;
+    c->err.clear();
+    c->state = 0;
+    if (n < 1 || n > 0x7fffffffLL) return fail(c, TREEPM_ERR_ARG, "n must be in [1, 2^31)");
+    if (!x || !y || !z || !m) return fail(c, TREEPM_ERR_ARG, "NULL input buffer");
+    if (mem_kind != TREEPM_HOST && mem_kind != TREEPM_DEVICE)
+        return fail(c, TREEPM_ERR_ARG, "mem_kind must be TREEPM_HOST or TREEPM_DEVICE");
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)hip_stream;
+    c->last = s;
+    record(c, 0, s);
+    int rc = do_build(c, n, x, y, z, m, mem_kind, s);
+    if (rc) return rc;
+    record(c, 1, s);
+    c->ev_valid[0] = c->timing;
+    c->ev_valid[1] = c->ev_valid[2] = false;
+    c->n = n;
+    c->state = 1;
+    return TREEPM_OK;
+}
+
+TREEPM_API int treepm_walk(treepm_ctx *c, void *hip_stream, treepm_stats *stats)
+{
+    if (!c) return TREEPM_ERR_ARG;
+    if (c->state < 1) return fail(c, TREEPM_ERR_STATE, "treepm_walk needs a build");
+    c->err.clear();
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)hip_stream;
+    c->last = s;
+    record(c, 2, s);
+    int rc = do_walk(c, s);
+    if (rc) {
+        c->state = 1;
+        return rc;
+    }
+    record(c, 3, s);
+    c->ev_valid[1] = c->timing;
+    c->state = 2;
+    if (stats) fill_stats(c, stats);
+    return TREEPM_OK;
+}
+
+TREEPM_API int treepm_force_short(treepm_ctx *c, void *ax, void *ay, void *az, int out_prec,
+                                  int mem_kind, void *hip_stream)
+{
+    if (!c) return TREEPM_ERR_ARG;
+    if (c->state < 2) return fail(c, TREEPM_ERR_STATE, "treepm_force_short needs a walk");
+    c->err.clear();
+    if (!ax || !ay || !az) return fail(c, TREEPM_ERR_ARG, "NULL output buffer");
+    if (out_prec != TREEPM_FP32 && out_prec != TREEPM_FP64)
+        return fail(c, TREEPM_ERR_ARG, "out_prec must be TREEPM_FP32 or TREEPM_FP64");
+    if (mem_kind != TREEPM_HOST && mem_kind != TREEPM_DEVICE)
+        return fail(c, TREEPM_ERR_ARG, "mem_kind must be TREEPM_HOST or TREEPM_DEVICE");
+    const treepm_params &P = c->prm;
+    if (P.precision == TREEPM_FP32) {
+        // Positions are taken relative to the group's cube centre with one image per list
+        // entry; that image is the nearest one for every particle of the group only if half
+        // the group cube plus r_cut stays within L/2.
+        double half_side = 0.5 * std::ldexp(P.L, -(int)c->min_group_level);
+        if (half_side + P.r_cut > 0.5 * P.L)
+            return fail(c, TREEPM_ERR_ARG,
+                        "FP32 path needs group cube half-side + r_cut <= L/2 (a group at "
+                        "level %u is too large for r_cut); use TREEPM_FP64",
+                        c->min_group_level);
+    }
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)hip_stream;
+    c->last = s;
+    size_t esz = out_prec == TREEPM_FP64 ? 8 : 4;
+    void *dst[3] = {ax, ay, az};
+    if (mem_kind == TREEPM_HOST) {
+        for (int a = 0; a < 3; ++a) {
+            hipError_t e = reserve(c->out[a], (size_t)c->n * esz);
+            if (e != hipSuccess) return hip_fail(c, e, "output staging");
+            dst[a] = c->out[a].p;
+        }
+    }
+    record(c, 4, s);
+    NodeArrays nd = nodes_view(c);
+    GroupArrays gr = groups_view(c);
+    double eta = 0.5 * P.r_cut;
+    ForceParams fp{P.L, P.eps * P.eps, 1.0 / eta, eta};
+    auto fn = P.precision == TREEPM_FP32 ? launch_force_f32 : launch_force_f64;
+    fn(nd, gr, c->n_groups, c->off.as<uint64_t>(), c->entries.as<uint32_t>(),
+       c->pos[0].as<double>(), c->pos[1].as<double>(), c->pos[2].as<double>(),
+       c->pos[3].as<double>(), c->idx.as<uint32_t>(), fp, dst[0], dst[1], dst[2], out_prec, s);
+    HIPCHK(c, hipGetLastError());
+    record(c, 5, s);
+    c->ev_valid[2] = c->timing;
+    if (mem_kind == TREEPM_HOST) {
+        void *hdst[3] = {ax, ay, az};
+        for (int a = 0; a < 3; ++a)
+            HIPCHK(c, hipMemcpyAsync(hdst[a], dst[a], (size_t)c->n * esz, hipMemcpyDeviceToHost,
+                                     s));
+        HIPCHK(c, hipStreamSynchronize(s));
+    }
+    return TREEPM_OK;
+}
+
+TREEPM_API int treepm_get_stats(treepm_ctx *c, treepm_stats *stats)
+{
+    if (!c || !stats) return TREEPM_ERR_ARG;
+    HIPCHK(c, hipSetDevice(c->device));
+    if (c->timing) HIPCHK(c, hipStreamSynchronize(c->last));
+    fill_stats(c, stats);
+    return TREEPM_OK;
+}
+
+TREEPM_API int treepm_export_sorted(treepm_ctx *c, uint64_t *keys, int64_t *idx)
+{
+    if (!c || !keys || !idx) return TREEPM_ERR_ARG;
+    if (c->state < 1) return fail(c, TREEPM_ERR_STATE, "no build");
+    HIPCHK(c, hipSetDevice(c->device));
+    int rc;
+    size_t n = (size_t)c->n;
+    if ((rc = d2h(c, keys, c->key.p, n, c->last))) return rc;
+    std::vector<uint32_t> i32(n);
+    if ((rc = d2h(c, i32.data(), c->idx.p, n, c->last))) return rc;
+    for (size_t k = 0; k < n; ++k) idx[k] = i32[k];
+    return TREEPM_OK;
+}
+
+TREEPM_API int treepm_export_nodes(treepm_ctx *c, int64_t cap, uint64_t *code, int64_t *first,
+                                   int64_t *count, int32_t *nchild, double *mass, double *com)
+{
+    if (!c || !code || !first || !count || !nchild || !mass || !com) return TREEPM_ERR_ARG;
+    if (c->state < 1) return fail(c, TREEPM_ERR_STATE, "no build");
+    if (cap < (int64_t)c->n_nodes) return fail(c, TREEPM_ERR_ARG, "cap < n_nodes");
+    HIPCHK(c, hipSetDevice(c->device));
+    int rc;
+    size_t nn = c->n_nodes;
+    hipStream_t s = c->last;
+    std::vector<uint32_t> u(nn);
+    std::vector<uint8_t> b(nn);
+    std::vector<double> d(nn);
+    if ((rc = d2h(c, code, c->n_code.p, nn, s))) return rc;
+    if ((rc = d2h(c, u.data(), c->n_first.p, nn, s))) return rc;
+    for (size_t k = 0; k < nn; ++k) first[k] = u[k];
+    if ((rc = d2h(c, u.data(), c->n_count.p, nn, s))) return rc;
+    for (size_t k = 0; k < nn; ++k) count[k] = u[k];
+    if ((rc = d2h(c, b.data(), c->n_nch.p, nn, s))) return rc;
+    for (size_t k = 0; k < nn; ++k) nchild[k] = b[k];
+    if ((rc = d2h(c, mass, c->n_mass.p, nn, s))) return rc;
+    for (int a = 0; a < 3; ++a) {
+        if ((rc = d2h(c, d.data(), c->n_com[a].p, nn, s))) return rc;
+        for (size_t k = 0; k < nn; ++k) com[3 * k + a] = d[k];
+    }
+    return TREEPM_OK;
+}
+
+TREEPM_API int treepm_export_groups(treepm_ctx *c, int64_t cap, uint64_t *code, int64_t *first,
+                                    int64_t *count, double *lo, double *hi, double *xg)
+{
+    if (!c || !code || !first || !count || !lo || !hi || !xg) return TREEPM_ERR_ARG;
+    if (c->state < 1) return fail(c, TREEPM_ERR_STATE, "no build");
+    if (cap < (int64_t)c->n_groups) return fail(c, TREEPM_ERR_ARG, "cap < n_groups");
+    HIPCHK(c, hipSetDevice(c->device));
+    int rc;
+    size_t ng = c->n_groups, nn = c->n_nodes;
+    hipStream_t s = c->last;
+    std::vector<uint32_t> u(ng);
+    std::vector<uint64_t> codes(nn);
+    std::vector<double> d(ng);
+    if ((rc = d2h(c, codes.data(), c->n_code.p, nn, s))) return rc;
+    if ((rc = d2h(c, u.data(), c->g_node.p, ng, s))) return rc;
+    for (size_t g = 0; g < ng; ++g) code[g] = codes[u[g]];
+    if ((rc = d2h(c, u.data(), c->g_first.p, ng, s))) return rc;
+    for (size_t g = 0; g < ng; ++g) first[g] = u[g];
+    if ((rc = d2h(c, u.data(), c->g_count.p, ng, s))) return rc;
+    for (size_t g = 0; g < ng; ++g) count[g] = u[g];
+    Buf *srcs[3][3] = {{&c->g_lo[0], &c->g_lo[1], &c->g_lo[2]},
+                       {&c->g_hi[0], &c->g_hi[1], &c->g_hi[2]},
+                       {&c->g_xg[0], &c->g_xg[1], &c->g_xg[2]}};
+    double *dsts[3] = {lo, hi, xg};
+    for (int q = 0; q < 3; ++q)
+        for (int a = 0; a < 3; ++a) {
+            if ((rc = d2h(c, d.data(), srcs[q][a]->p, ng, s))) return rc;
+            for (size_t g = 0; g < ng; ++g) dsts[q][3 * g + a] = d[g];
+        }
+    return TREEPM_OK;
+}
+
+TREEPM_API int treepm_export_lists(treepm_ctx *c, int64_t group_cap, int64_t entry_cap,
+                                   int64_t *offsets, uint8_t *is_cell, uint64_t *value)
+{
+    if (!c || !offsets || !is_cell || !value) return TREEPM_ERR_ARG;
+    if (c->state < 2) return fail(c, TREEPM_ERR_STATE, "no walk");
+    if (group_cap < (int64_t)c->n_groups + 1 || entry_cap < (int64_t)c->n_entries)
+        return fail(c, TREEPM_ERR_ARG, "capacity too small (%lld groups, %llu entries)",
+                    (long long)c->n_groups, (unsigned long long)c->n_entries);
+    HIPCHK(c, hipSetDevice(c->device));
+    int rc;
+    hipStream_t s = c->last;
+    size_t ng = c->n_groups, nn = c->n_nodes, ne = c->n_entries, n = c->n;
+    std::vector<uint64_t> off(ng + 1), codes(nn);
+    std::vector<uint32_t> ent(ne), idx(n);
+    if ((rc = d2h(c, off.data(), c->off.p, ng + 1, s))) return rc;
+    if ((rc = d2h(c, ent.data(), c->entries.p, ne, s))) return rc;
+    if ((rc = d2h(c, codes.data(), c->n_code.p, nn, s))) return rc;
+    if ((rc = d2h(c, idx.data(), c->idx.p, n, s))) return rc;
+    for (size_t g = 0; g <= ng; ++g) offsets[g] = (int64_t)off[g];
+    for (size_t q = 0; q < ne; ++q) {
+        uint32_t e = ent[q];
+        if (e & kCellTag) {
+            is_cell[q] = 1;
+            value[q] = codes[e & ~kCellTag];
+        } else {
+            is_cell[q] = 0;
+            value[q] = idx[e];
+        }
+    }
+    return TREEPM_OK;
+}
+
+TREEPM_API const char *treepm_last_error(const treepm_ctx *c)
+{
+    return c ? c->err.c_str() : "NULL context";
+}

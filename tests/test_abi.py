@@ -1,0 +1,71 @@
+"""The C-ABI library loads and exports every entry point declared in include/treepm.h, and the
+host-side argument checks behave as documented (no GPU needed: no compute call is made)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "treepm.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(treepm_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def native():
+    import paper_0910_0121_amd as t
+    t.lib()
+    return t
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ("treepm_create", "treepm_destroy", "treepm_build", "treepm_walk",
+                 "treepm_force_short", "treepm_export_lists", "treepm_last_error"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol(native):
+    lib = C.CDLL(native._native.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_version(native):
+    assert native.treepm_version().startswith("treepm")
+
+
+@pytest.mark.parametrize("kw", [
+    dict(L=0.0, mesh=0.1),
+    dict(L=1.0, mesh=0.2),                      # r_cut = 0.6 > L/2
+    dict(L=1.0, mesh=0.1, r_cut=0.31),          # r_cut != 3 mesh
+    dict(L=1.0, mesh=0.1, theta=1.5),
+    dict(L=1.0, mesh=0.1, theta=-0.1),
+    dict(L=1.0, mesh=0.1, n_leaf=1),
+    dict(L=1.0, mesh=0.1, eps=-1.0),
+    dict(L=1.0, mesh=0.1, eps=0.0, precision=0),  # FP32 needs eps > 0
+    dict(L=1.0, mesh=0.1, eps=0.01, precision=7),
+    dict(L=float("nan"), mesh=0.1),
+])
+def test_invalid_params_rejected_before_any_device_call(native, kw):
+    base = dict(L=1.0, mesh=0.1, eps=0.01, theta=0.5, n_leaf=10, n_crit=64, precision=0)
+    base.update(kw)
+    r_cut = base.pop("r_cut", 3.0 * base["mesh"])
+    p = native.treepm_params(base["L"], base["mesh"], r_cut, base["eps"], base["theta"],
+                             base["n_leaf"], base["n_crit"], base["precision"])
+    with pytest.raises(native.TreePMError) as e:
+        native.treepm_create(p, 0)
+    assert e.value.code == -1
+
+
+def test_null_handles_are_rejected(native):
+    lib = native.lib()
+    assert lib.treepm_destroy(None) == 0
+    assert lib.treepm_walk(None, None, None) == -1
+    assert lib.treepm_build(None, 1, None, None, None, None, 0, None) == -1
+    assert lib.treepm_last_error(None) == b"NULL context"

@@ -1,0 +1,304 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle on the same seeded
+boxes.
+
+Bars:
+  * keys, sort order, tree nodes, node masses/centres of mass, groups and interaction lists:
+    bit-identical (the walk's FP64 decisions are taken with the same IEEE operations);
+  * FP64 forces: |a_gpu - a_oracle| <= 1e-13 * (sum_j |f_ij| + sum_j N_ij) per particle and
+    component, N_ij = m_j r/(r^2+eps^2)^1.5 the magnitude without the cutoff factor:
+    summation order differs, and the oracle's expanded eq. (2) rounds to a few 1e-14 of the
+    uncut magnitude near R = 2 (its terms reach ~300 there) while the kernel's factored form
+    does not;
+  * FP32 forces: RMS over particles of |a_gpu - a_oracle| / |a_oracle| <= 1e-6 on the same
+    lists, and per particle |da_i| <= 8 u B_i with u = 2^-24 and
+    B_i = sum_j m_j (|x_i - x_g|_inf + |x_j - x_g|_inf + r_ij) / (r_ij^2 + eps^2)^1.5:
+    rounding the group-relative positions to FP32 moves d by at most ~u(|x_i'| + |x_j'|), the
+    pair law's Jacobian is at most 4 m / (r^2 + eps^2)^1.5, and the pair arithmetic adds a
+    few u of |f_ij| <= m r / (r^2 + eps^2)^1.5.  Particles whose exact force is zero must get
+    exactly zero.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import boxgen
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def tp():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_0910_0121_amd as t
+    t.lib()
+    return t
+
+
+class Run:
+    def __init__(self, tp, x, y, z, m, L, r_cut, eps, theta, n_leaf, n_crit, precision,
+                 out64=True, host=False):
+        self.tp = tp
+        p = tp.treepm_params(L, r_cut / 3.0, r_cut, eps, theta, n_leaf, n_crit, precision)
+        self.ctx = tp.treepm_create(p, 0)
+        dev = "cpu" if host else "cuda"
+        xs = [torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in (x, y, z, m)]
+        tp.treepm_build(self.ctx, *xs)
+        self.stats = tp.treepm_walk(self.ctx)
+        dt = torch.float64 if out64 else torch.float32
+        self.a = [torch.zeros(len(x), dtype=dt, device=dev) for _ in range(3)]
+        tp.treepm_force_short(self.ctx, *self.a)
+        torch.cuda.synchronize()
+        self.acc = np.stack([t.cpu().numpy().astype(np.float64) for t in self.a])
+
+    def close(self):
+        if self.ctx:
+            self.tp.treepm_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _box(kind, n, seed):
+    if kind == "uniform":
+        return boxgen.uniform_box(n, seed)
+    return boxgen.nfw_box(n, max(1, n // 400), seed)
+
+
+CASES = [
+    # kind, n, seed, r_cut, theta, n_leaf, n_crit
+    ("uniform", 32768, 1, 3 / 32, 0.5, 10, 64),      # the plain-method box (32^3, mesh 32^3)
+    ("nfw", 40000, 2, 0.06, 0.5, 10, 128),
+    ("nfw", 20011, 3, 0.08, 0.8, 4, 37),             # ragged N, deep chains, odd n_crit
+    ("uniform", 777, 4, 0.25, 0.3, 2, 5),            # tiny, n_leaf 2
+    ("nfw", 30000, 5, 0.05, 1.0, 10, 300),
+]
+
+
+def _ids(c):
+    return f"{c[0]}-n{c[1]}-th{c[4]}-leaf{c[5]}-crit{c[6]}"
+
+
+@pytest.mark.parametrize("case", CASES, ids=[_ids(c) for c in CASES])
+def test_tree_and_lists_bit_identical(tp, orc, case):
+    kind, n, seed, r_cut, theta, n_leaf, n_crit = case
+    _say(f"tree/lists {_ids(case)}")
+    x, y, z, m = _box(kind, n, seed)
+    eps = r_cut / 60
+    run = Run(tp, x, y, z, m, 1.0, r_cut, eps, theta, n_leaf, n_crit, tp.TREEPM_FP64)
+    T = orc.Tree(x, y, z, m, 1.0, r_cut, eps, theta, n_leaf, n_crit)
+    # keys and stable order
+    gk, gi = tp.treepm_export_sorted(run.ctx)
+    ok, oi = T.sorted()
+    np.testing.assert_array_equal(gk, ok)
+    np.testing.assert_array_equal(gi, oi)
+    # nodes: same set of codes, same ranges, bitwise equal moments
+    gn, on = tp.treepm_export_nodes(run.ctx), T.nodes()
+    assert gn["code"].size == on["code"].size
+    go, oo = np.argsort(gn["code"]), np.argsort(on["code"])
+    for k in ("code", "first", "count", "nchild", "mass", "com"):
+        np.testing.assert_array_equal(gn[k][go], on[k][oo], err_msg=k)
+    # groups in key order
+    gg, og = tp.treepm_export_groups(run.ctx), T.groups()
+    for k in ("code", "first", "count", "lo", "hi", "xg"):
+        np.testing.assert_array_equal(gg[k], og[k], err_msg=k)
+    # lists: per group the same multiset of (kind, value)
+    goff, gisc, gval = tp.treepm_export_lists(run.ctx)
+    ooff, oisc, oval = T.lists()
+    np.testing.assert_array_equal(np.diff(goff), np.diff(ooff))
+    for g in range(og["code"].size):
+        a = sorted(zip(gisc[goff[g]:goff[g + 1]].tolist(), gval[goff[g]:goff[g + 1]].tolist()))
+        b = sorted(zip(oisc[ooff[g]:ooff[g + 1]].tolist(), oval[ooff[g]:ooff[g + 1]].tolist()))
+        assert a == b, f"group {g}"
+    assert run.stats.interactions == T.interactions()
+    assert run.stats.n_cell_entries == int(oisc.sum())
+    run.close()
+
+
+@pytest.mark.parametrize("case", CASES, ids=[_ids(c) for c in CASES])
+def test_fp64_force_matches_oracle(tp, orc, case):
+    kind, n, seed, r_cut, theta, n_leaf, n_crit = case
+    _say(f"fp64 force {_ids(case)}")
+    x, y, z, m = _box(kind, n, seed)
+    eps = r_cut / 60
+    run = Run(tp, x, y, z, m, 1.0, r_cut, eps, theta, n_leaf, n_crit, tp.TREEPM_FP64)
+    T = orc.Tree(x, y, z, m, 1.0, r_cut, eps, theta, n_leaf, n_crit)
+    ref = np.stack(T.force())
+    scale = T.error_scale()
+    err = np.abs(run.acc - ref)
+    assert np.all(err <= 1e-13 * scale[None, :] + 1e-300), float(np.max(err / (scale + 1e-300)))
+    run.close()
+
+
+@pytest.mark.parametrize("case", CASES[:3] + CASES[4:], ids=[_ids(c) for c in CASES[:3] + CASES[4:]])
+def test_fp32_force_error_vs_fp64_oracle(tp, orc, case):
+    kind, n, seed, r_cut, theta, n_leaf, n_crit = case
+    _say(f"fp32 force {_ids(case)}")
+    x, y, z, m = _box(kind, n, seed)
+    eps = r_cut / 60
+    run = Run(tp, x, y, z, m, 1.0, r_cut, eps, theta, n_leaf, n_crit, tp.TREEPM_FP32,
+              out64=True)
+    T = orc.Tree(x, y, z, m, 1.0, r_cut, eps, theta, n_leaf, n_crit)
+    ref = np.stack(T.force())
+    B = fp32_error_scale(T, x, y, z, m, eps)
+    d = np.linalg.norm(run.acc - ref, axis=0)
+    nr = np.linalg.norm(ref, axis=0)
+    nz = nr > 0
+    rel = d[nz] / nr[nz]
+    rms = float(np.sqrt(np.mean(rel ** 2)))
+    _say(f"  rms rel {rms:.3e} max rel {rel.max():.3e} p99 {np.quantile(rel, 0.99):.3e} "
+         f"max |da|/(u B) {np.max(d / (2.0 ** -24 * B)):.3f}")
+    assert rms <= 1e-6
+    assert np.all(d[~nz] == 0.0)
+    assert np.all(d <= 8 * 2.0 ** -24 * B)
+    run.close()
+
+
+def fp32_error_scale(T, x, y, z, m, eps):
+    """B_i of the FP32 bound, from the oracle's groups and lists (FP64, numpy)."""
+    k, idx = T.sorted()
+    pos = np.stack([x, y, z], axis=1)[idx]
+    nd = T.nodes()
+    G = T.groups()
+    off, isc, val = T.lists()
+    code_to_node = {int(c): u for u, c in enumerate(nd["code"])}
+    B = np.zeros(len(x))
+    for g in range(G["code"].size):
+        s, e = off[g], off[g + 1]
+        cells = isc[s:e].astype(bool)
+        src = np.empty((e - s, 3))
+        sm = np.empty(e - s)
+        pj = val[s:e][~cells].astype(np.int64)
+        src[~cells] = np.stack([x[pj], y[pj], z[pj]], axis=1)
+        sm[~cells] = m[pj]
+        if cells.any():
+            us = np.array([code_to_node[int(c)] for c in val[s:e][cells]])
+            src[cells] = nd["com"][us]
+            sm[cells] = nd["mass"][us]
+        f0, c = int(G["first"][g]), int(G["count"][g])
+        xi = pos[f0:f0 + c] - G["xg"][g]
+        xj = src - G["xg"][g]
+        xj -= np.floor(xj + 0.5)
+        dd = xj[None, :, :] - xi[:, None, :]
+        r2 = (dd * dd).sum(-1)
+        w = np.abs(xi).max(1)[:, None] + np.abs(xj).max(1)[None, :] + np.sqrt(r2)
+        B[idx[f0:f0 + c]] = (sm[None, :] * w / (r2 + eps * eps) ** 1.5).sum(1)
+    return B
+
+
+def test_theta_zero_equals_direct_sum(tp, orc):
+    _say("theta=0 vs direct sum")
+    x, y, z, m = boxgen.uniform_box(32768, 1)
+    r_cut, eps = 3 / 32, 1 / 640
+    run = Run(tp, x, y, z, m, 1.0, r_cut, eps, 0.0, 10, 64, tp.TREEPM_FP64)
+    ref = np.stack(orc.direct_cells(x, y, z, m, 1.0, r_cut, eps))
+    scale = np.max(np.linalg.norm(ref, axis=0))
+    assert np.max(np.abs(run.acc - ref)) <= 1e-12 * scale
+    run.close()
+
+
+def test_deterministic_repeat(tp):
+    _say("determinism")
+    x, y, z, m = boxgen.nfw_box(50000, 80, 9)
+    outs = []
+    for prec in (tp.TREEPM_FP32, tp.TREEPM_FP64):
+        a = Run(tp, x, y, z, m, 1.0, 0.06, 0.001, 0.5, 10, 96, prec)
+        b = Run(tp, x, y, z, m, 1.0, 0.06, 0.001, 0.5, 10, 96, prec)
+        np.testing.assert_array_equal(a.acc, b.acc)
+        a.close(); b.close()
+
+
+def test_host_buffers_and_fp32_output(tp, orc):
+    _say("host buffers")
+    x, y, z, m = boxgen.uniform_box(5000, 11)
+    a = Run(tp, x, y, z, m, 1.0, 0.15, 0.002, 0.5, 10, 64, tp.TREEPM_FP32, out64=False, host=True)
+    b = Run(tp, x, y, z, m, 1.0, 0.15, 0.002, 0.5, 10, 64, tp.TREEPM_FP32, out64=True)
+    np.testing.assert_array_equal(a.acc, b.acc.astype(np.float32).astype(np.float64))
+    a.close(); b.close()
+
+
+def test_edge_cases(tp, orc):
+    _say("edge cases")
+    # a single particle feels nothing
+    r = Run(tp, np.array([0.3]), np.array([0.4]), np.array([0.5]), np.array([1.0]), 1.0, 0.3,
+            0.01, 0.5, 10, 64, tp.TREEPM_FP64)
+    assert np.all(r.acc == 0.0)
+    r.close()
+    # fewer particles than n_leaf and n_crit: the root is the only node and group
+    x, y, z, m = boxgen.uniform_box(7, 3)
+    r = Run(tp, x, y, z, m, 1.0, 0.3, 0.01, 0.5, 10, 64, tp.TREEPM_FP64)
+    assert r.stats.n_nodes == 1 and r.stats.n_groups == 1
+    ref = np.stack(orc.direct_brute(x, y, z, m, 1.0, 0.3, 0.01))
+    np.testing.assert_allclose(r.acc, ref, rtol=0, atol=1e-13 * np.abs(ref).max())
+    r.close()
+    # many coincident particles: level-21 leaves holding more than n_leaf
+    n = 3000
+    x, y, z, m = boxgen.uniform_box(n, 5)
+    x[:500] = 0.25; y[:500] = 0.5; z[:500] = 0.75
+    r = Run(tp, x, y, z, m, 1.0, 0.1, 0.002, 0.5, 10, 64, tp.TREEPM_FP64)
+    T = orc.Tree(x, y, z, m, 1.0, 0.1, 0.002, 0.5, 10, 64)
+    assert r.stats.max_level == 21
+    ref = np.stack(T.force())
+    assert np.all(np.abs(r.acc - ref) <= 1e-13 * T.error_scale()[None, :] + 1e-300)
+    r.close()
+
+
+def test_error_paths(tp):
+    _say("error paths")
+    p = tp.treepm_params(1.0, 0.1, 0.3, 0.01, 0.5, 10, 64, tp.TREEPM_FP64)
+    ctx = tp.treepm_create(p, 0)
+    x, y, z, m = (torch.from_numpy(a).cuda() for a in boxgen.uniform_box(100, 1))
+    a = [torch.zeros(100, dtype=torch.float64, device="cuda") for _ in range(3)]
+    with pytest.raises(tp.TreePMError) as e:
+        tp.treepm_walk(ctx)
+    assert e.value.code == -5
+    with pytest.raises(tp.TreePMError) as e:
+        tp.treepm_force_short(ctx, *a)
+    assert e.value.code == -5
+    xb = x.clone(); xb[7] = 1.0
+    with pytest.raises(tp.TreePMError) as e:
+        tp.treepm_build(ctx, xb, y, z, m)
+    assert e.value.code == -2
+    xb = x.clone(); xb[3] = -1e-9
+    with pytest.raises(tp.TreePMError) as e:
+        tp.treepm_build(ctx, xb, y, z, m)
+    assert e.value.code == -2
+    mb = m.clone(); mb[5] = float("nan")
+    with pytest.raises(tp.TreePMError) as e:
+        tp.treepm_build(ctx, x, y, z, mb)
+    assert e.value.code == -1
+    mb = m.clone(); mb[5] = 0.0
+    with pytest.raises(tp.TreePMError) as e:
+        tp.treepm_build(ctx, x, y, z, mb)
+    assert e.value.code == -1
+    # a failed build leaves the context empty
+    with pytest.raises(tp.TreePMError) as e:
+        tp.treepm_walk(ctx)
+    assert e.value.code == -5
+    # and a good build afterwards works
+    tp.treepm_build(ctx, x, y, z, m)
+    tp.treepm_walk(ctx)
+    tp.treepm_force_short(ctx, *a)
+    tp.treepm_destroy(ctx)
+    # FP32 path refuses a group too large for one image per entry (root group, r_cut = 0.3)
+    p32 = tp.treepm_params(1.0, 0.1, 0.3, 0.01, 0.5, 10, 64, tp.TREEPM_FP32)
+    ctx = tp.treepm_create(p32, 0)
+    tp.treepm_build(ctx, x, y, z, m)
+    tp.treepm_walk(ctx)
+    with pytest.raises(tp.TreePMError) as e:
+        tp.treepm_force_short(ctx, *a)
+    assert e.value.code == -1
+    tp.treepm_destroy(ctx)
