@@ -1,0 +1,234 @@
+"""Benchmark of the short-range TreePM tree force on one MI355X.
+
+One step = the whole hot path on one box already resident in HBM: build (keys, radix sort,
+gather, octree, moments, groups), walk (interaction lists) and the FP32 force.  The workload
+is the 256^3 clustered box (2000 NFW halos plus a uniform half, mesh 256^3, r_cut = 3/256,
+eps = 1/(20*256), theta = 0.5).  Prints one JSON line.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload nfw256] [--n-crit C]
+                  [--no-cpu-baseline] [--no-fp64]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "particles/s + interactions/s at θ=0.5, FP32 vs FP64 path; ensemble p50/p99"
+K_PP = 38  # flops per pair interaction (FMA = 2, add/mul/rsqrt/sqrt = 1, selects = 0)
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "force_f32_traffic.json")
+FORCE_SRC = os.path.join(ROOT, "paper_0910_0121_amd", "csrc", "k_force.hip")
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="nfw256")
+    ap.add_argument("--n-crit", type=int, default=256)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--cpu-stride", type=int, default=0,
+                    help="oracle sample: every k-th group (0 = choose for ~15 s of work)")
+    return ap.parse_args()
+
+
+def measured_traffic(interactions_unused=None):
+    """HBM bytes per force launch from the committed rocprofv3 counter runs, if they were
+    taken on the current force-kernel source; else None."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+        with open(FORCE_SRC, "rb") as f:
+            sha = hashlib.sha1(f.read()).hexdigest()
+        if t.get("source_sha1") != sha:
+            return None
+        return t
+    except (OSError, ValueError):
+        return None
+
+
+def run_steps(tp, torch, ctx, dev, acc, k):
+    times, st = [], None
+    for _ in range(k):
+        tp.treepm_build(ctx, *dev)
+        tp.treepm_walk(ctx)
+        tp.treepm_force_short(ctx, *acc)
+        st = tp.treepm_get_stats(ctx)
+        times.append(list(st.t_ms))
+    return times, st
+
+
+def cpu_baseline(spec, arrays, n_crit, stride_arg):
+    import numpy as np
+    import oracle
+    x, y, z, m = arrays
+    threads = min(16, os.cpu_count() or 1)
+    t0 = time.perf_counter()
+    T = oracle.Tree(x, y, z, m, spec.L, spec.r_cut, spec.eps, spec.theta, spec.n_leaf, n_crit)
+    t_build = time.perf_counter() - t0
+    G = T.n_groups
+    stride = stride_arg
+    if stride <= 0:
+        # pilot on a sparse sample, then size the real sample for ~15 s of CPU work
+        t1 = time.perf_counter()
+        _, _, _, inter_p, _ = T.walk_force_sample(4096, 0, threads)
+        tp = time.perf_counter() - t1
+        groups_p = len(range(0, G, 4096))
+        per_group = tp / max(1, groups_p)
+        want = max(1, int(15.0 / max(per_group, 1e-9)))
+        stride = max(1, G // want)
+    t2 = time.perf_counter()
+    _, _, _, inter, parts = T.walk_force_sample(stride, 0, threads)
+    t_sample = time.perf_counter() - t2
+    n_sampled = len(range(0, G, stride))
+    t_full = t_build + t_sample * (G / n_sampled)
+    T.close()
+    return {
+        "value": spec.n / t_full,
+        "unit": "particles/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": (f"oracle tree build on all {spec.n} particles ({t_build:.1f} s, 1 thread) + "
+                   f"walk and FP64 list force for every {stride}th group in key order "
+                   f"({n_sampled} of {G} groups, {parts} particles, {inter} interactions, "
+                   f"{t_sample:.1f} s on {threads} threads), extrapolated by group count"),
+        "interactions_per_s": inter / t_sample,
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU only (the tree force of one box on one "
+              f"MI355X); --gpus {args.gpus} is not supported.", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import boxgen
+    import paper_0910_0121_amd as tp
+
+    spec = boxgen.CONFIGS[args.workload]
+    n_crit = args.n_crit
+    log(f"[bench] generating {spec.name} (N={spec.n}) ...")
+    t0 = time.time()
+    arrays = spec.generate()
+    log(f"[bench] generated in {time.time() - t0:.1f} s")
+    dev = [torch.from_numpy(a).cuda() for a in arrays]
+    acc = [torch.empty(spec.n, dtype=torch.float32, device="cuda") for _ in range(3)]
+
+    p32 = tp.treepm_params(spec.L, spec.mesh, spec.r_cut, spec.eps, spec.theta, spec.n_leaf,
+                           n_crit, tp.TREEPM_FP32)
+    ctx = tp.treepm_create(p32, 0)
+    tp.treepm_set_timing(ctx, True)
+    log(f"[bench] warmup {args.warmup} steps")
+    run_steps(tp, torch, ctx, dev, acc, args.warmup)
+    torch.cuda.synchronize()
+    log(f"[bench] timing {args.steps} steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    times, st = run_steps(tp, torch, ctx, dev, acc, args.steps)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    tp.treepm_destroy(ctx)
+    ms_per_step = elapsed / args.steps * 1e3
+    ph = np.array(times)  # per step: build, walk, force, sum (device event times, ms)
+    t_force = float(np.mean(ph[:, 2])) * 1e-3
+    inter = int(st.interactions)
+    evaluated = int(st.evaluated)
+    # The roofline counts the pairs the kernel evaluated: list entries whose source lies at
+    # least r_cut from the group's box add exactly zero and are skipped.
+    achieved = K_PP * evaluated / t_force / 1e12
+    traffic = measured_traffic()
+    result = {
+        "metric": METRIC,
+        "value": spec.n * args.steps / elapsed,
+        "unit": "particles/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"{spec.name}: N={spec.n} clustered box ({spec.n_halos} NFW halos, "
+                         f"c=10, dN/dM~M^-1.9, {int(spec.f_halo * 100)}% in halos), unit "
+                         f"periodic box, mesh {spec.mesh_n}^3, r_cut=3/{spec.mesh_n}, "
+                         f"eps=1/(20*{spec.mesh_n}), theta={spec.theta}, n_leaf={spec.n_leaf}, "
+                         f"n_crit={n_crit}; step = build + walk + FP32 force"),
+            "n": spec.n, "theta": spec.theta, "n_crit": n_crit, "n_leaf": spec.n_leaf,
+            "r_cut": spec.r_cut, "eps": spec.eps,
+        },
+        "interactions_per_s": inter / t_force,
+        "interactions": inter,
+        "interactions_per_particle": inter / spec.n,
+        "evaluated_pairs": evaluated,
+        "evaluated_pairs_per_s": evaluated / t_force,
+        "zero_pairs_skipped_frac": 1.0 - evaluated / inter,
+        "phase_ms": {"build": float(np.mean(ph[:, 0])), "walk": float(np.mean(ph[:, 1])),
+                     "force_f32": float(np.mean(ph[:, 2]))},
+        "tree": {"nodes": int(st.n_nodes), "groups": int(st.n_groups),
+                 "cell_entries": int(st.n_cell_entries), "particle_entries": int(st.n_part_entries),
+                 "max_level": int(st.max_level), "max_group": int(st.max_group)},
+        "roofline": {
+            "kernel": "k_force_f32",
+            "bound": "alu",
+            "achieved": achieved,
+            "peak": FP32_VECTOR_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / FP32_VECTOR_PEAK_TFLOPS,
+            "traffic": (traffic["fetch_bytes"] + traffic["write_bytes"]) if traffic else None,
+            "flops_per_interaction": K_PP,
+            "flops_counted_on": "evaluated pairs",
+        },
+    }
+    if not args.no_fp64:
+        p64 = tp.treepm_params(spec.L, spec.mesh, spec.r_cut, spec.eps, spec.theta, spec.n_leaf,
+                               n_crit, tp.TREEPM_FP64)
+        ctx = tp.treepm_create(p64, 0)
+        tp.treepm_set_timing(ctx, True)
+        log("[bench] FP64 path")
+        run_steps(tp, torch, ctx, dev, acc, 1)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        k64 = max(1, min(3, args.steps))
+        times64, st64 = run_steps(tp, torch, ctx, dev, acc, k64)
+        torch.cuda.synchronize()
+        e64 = time.perf_counter() - t1
+        tp.treepm_destroy(ctx)
+        f64 = float(np.mean(np.array(times64)[:, 2])) * 1e-3
+        result["fp64_path"] = {
+            "particles_per_s": spec.n * k64 / e64,
+            "interactions_per_s": inter / f64,
+            "force_ms": f64 * 1e3,
+            "achieved_tflops": K_PP * inter / f64 / 1e12,
+            "frac_fp64_peak": K_PP * inter / f64 / 1e12 / FP64_VECTOR_PEAK_TFLOPS,
+            "force_speedup_fp32_over_fp64": f64 / t_force,
+        }
+    if not args.no_cpu_baseline:
+        log("[bench] CPU oracle baseline (bounded sample)")
+        result["cpu_baseline"] = cpu_baseline(spec, arrays, n_crit, args.cpu_stride)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -93,6 +93,10 @@ typedef struct {
     int32_t max_group;      /* largest group                                              */
     double t_ms[4];         /* device time of build, walk, force, and their sum (ms);
                                0 unless timing is enabled with treepm_set_timing          */
+    int64_t evaluated;      /* pairs the last force call evaluated: the FP32 kernel skips
+                               list entries whose source lies at least r_cut from the
+                               group's bounding box (they add exactly zero); the FP64
+                               kernel evaluates every pair (= interactions)               */
 } treepm_stats;
 
 /* Create a context for one box on HIP device `device`.  Validates *params (ERR_ARG).  The

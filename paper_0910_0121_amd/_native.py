@@ -36,7 +36,7 @@ class treepm_stats(C.Structure):
     _fields_ = [("n", C.c_int64), ("n_nodes", C.c_int64), ("n_groups", C.c_int64),
                 ("n_cell_entries", C.c_int64), ("n_part_entries", C.c_int64),
                 ("interactions", C.c_int64), ("max_level", C.c_int32),
-                ("max_group", C.c_int32), ("t_ms", C.c_double * 4)]
+                ("max_group", C.c_int32), ("t_ms", C.c_double * 4), ("evaluated", C.c_int64)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "t_ms"}

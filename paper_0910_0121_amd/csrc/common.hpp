@@ -35,6 +35,16 @@ struct NodeArrays {
     double *cnx, *cny, *cnz; // cube centres ((i + 1/2) * L / 2^level)
 };
 
+// Everything the walk reads about one node, in one 64-byte record (one cache line), built
+// once per tree after the moments.
+struct alignas(64) WalkNode {
+    double cn[3];  // cube centre
+    double com[3]; // centre of mass
+    uint32_t first, count, child_first;
+    uint8_t level, nchild, pad0, pad1;
+};
+static_assert(sizeof(WalkNode) == 64, "WalkNode must be one 64-byte line");
+
 struct GroupArrays {
     uint32_t *node, *first, *count;
     double *cgx, *cgy, *cgz;  // bbox centre (lo + hi) / 2
@@ -53,16 +63,17 @@ void scan_u32(uint32_t *data, size_t n, uint32_t *total, uint32_t *tmp, hipStrea
 void scan_u64(uint64_t *data, size_t n, uint64_t *total, uint64_t *tmp, hipStream_t s);
 
 // ------------------------------------------------------------------ launchers (k_build.hip)
+// Also stores each particle's (x, y, z, m) as one 32-byte record for the gather.
 void launch_keys(int64_t n, const double *x, const double *y, const double *z, const double *m,
-                 double L, uint64_t *key, uint32_t *idx, unsigned *flags, hipStream_t s);
+                 double L, uint64_t *key, uint32_t *idx, unsigned *flags, double4 *rec,
+                 hipStream_t s);
 // Stable LSD radix sort of (key, idx) by key; results end in key/idx.  hist holds
 // sort_hist_elems(n) values.
 size_t sort_hist_elems(int64_t n);
 void radix_sort(int64_t n, uint64_t *key, uint32_t *idx, uint64_t *key_alt, uint32_t *idx_alt,
                 uint32_t *hist, uint32_t *scan_tmp, hipStream_t s);
-void launch_permute(int64_t n, const uint32_t *idx, const double *x, const double *y,
-                    const double *z, const double *m, double *px, double *py, double *pz,
-                    double *pm, hipStream_t s);
+void launch_permute(int64_t n, const uint32_t *idx, const double4 *rec, double *px,
+                    double *py, double *pz, double *pm, hipStream_t s);
 void launch_root(NodeArrays nd, uint32_t n, double L, hipStream_t s);
 // Level step: nodes [lo, hi) of level `level`; writes nchild and per-node child counts into
 // cnt (hi - lo values) for the scan.
@@ -73,8 +84,8 @@ void launch_emit(NodeArrays nd, const uint64_t *key, uint32_t lo, uint32_t hi, i
                  uint32_t base, const uint32_t *cnt, double L, hipStream_t s);
 void launch_moments(NodeArrays nd, const double *px, const double *py, const double *pz,
                     const double *pm, uint32_t lo, uint32_t hi, hipStream_t s);
-// com = S / M for every node, after all levels' moments.
-void launch_com_divide(NodeArrays nd, uint32_t n_nodes, hipStream_t s);
+// com = S / M for every node, after all levels' moments; also fills the walk records.
+void launch_com_divide(NodeArrays nd, uint32_t n_nodes, WalkNode *wn, hipStream_t s);
 // Groups: mark in gstart[first] (n values, zeroed here) every maximal node with
 // count <= n_crit or no children; then compact in key order.
 void launch_group_mark(NodeArrays nd, uint32_t n_nodes, int n_crit, uint32_t *gstart,
@@ -93,20 +104,32 @@ struct WalkParams {
     const double *lside; // device table: L / 2^level, level 0..21
 };
 // Count (emit == 0) or write (emit == 1) the interaction list of every group.
-// The emit pass adds (cell entries, particle entries, interactions) into stats[0..2].
-void launch_walk(NodeArrays nd, GroupArrays gr, uint32_t n_groups, WalkParams wp, int emit,
+// The emit pass records each group's cell-entry count in gcells and adds (cell entries,
+// particle entries, interactions) into stats[0..2] (zeroed by the caller).
+void launch_walk(const WalkNode *wn, GroupArrays gr, uint32_t n_groups, WalkParams wp, int emit,
                  uint64_t *counts_or_offsets, uint32_t *entries, unsigned *overflow,
-                 unsigned long long *stats, hipStream_t s);
+                 uint32_t *gcells, unsigned long long *stats, hipStream_t s);
 
 // ------------------------------------------------------------------ launchers (k_force.hip)
 struct ForceParams {
-    double L, eps2, inv_eta, eta;
+    double L, eps2, inv_eta, eta, rc2;
+    uint32_t *kept; // FP32 path: per group, list entries that survived the cutoff cull
 };
-void launch_force_f32(NodeArrays nd, GroupArrays gr, uint32_t n_groups, const uint64_t *off,
+constexpr int kForceClasses = 8; // FP32 force: one class per blocking factor K = 1..8
+// Group ids by blocking class q = ceil(count / 64) - 1 (capped at kForceClasses - 1) into
+// lists[q * stride + ...]; counts[q] (device) receives the class sizes.
+void launch_classify(GroupArrays gr, uint32_t n_groups, uint32_t *lists, uint32_t stride,
+                     uint32_t *counts, hipStream_t s);
+// class_counts: host copy of the class sizes.
+void launch_force_f32(NodeArrays nd, GroupArrays gr, const uint32_t *lists, uint32_t stride,
+                      const uint32_t *class_counts, const uint64_t *off,
                       const uint32_t *entries, const double *px, const double *py,
                       const double *pz, const double *pm, const uint32_t *pidx,
                       ForceParams fp, void *ax, void *ay, void *az, int out_prec,
                       hipStream_t s);
+// sum over groups of count * kept (pairs the FP32 kernel evaluated) into *out (device).
+void launch_kept_stats(GroupArrays gr, uint32_t n_groups, const uint32_t *kept,
+                       unsigned long long *out, hipStream_t s);
 void launch_force_f64(NodeArrays nd, GroupArrays gr, uint32_t n_groups, const uint64_t *off,
                       const uint32_t *entries, const double *px, const double *py,
                       const double *pz, const double *pm, const uint32_t *pidx,

@@ -48,7 +48,8 @@ __global__ __launch_bounds__(256) void k_keys(int64_t n, const double *__restric
                                               const double *__restrict__ z,
                                               const double *__restrict__ m, double L,
                                               double scale, uint64_t *__restrict__ key,
-                                              uint32_t *__restrict__ idx, unsigned *flags)
+                                              uint32_t *__restrict__ idx, unsigned *flags,
+                                              double4 *__restrict__ rec)
 {
     unsigned f = 0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -62,6 +63,7 @@ __global__ __launch_bounds__(256) void k_keys(int64_t n, const double *__restric
                      spread3(quantise(p2, scale));
         key[i] = k;
         idx[i] = (uint32_t)i;
+        rec[i] = make_double4(p0, p1, p2, mi);
     }
     if (f) atomicOr(flags, f);
 }
@@ -83,8 +85,10 @@ __global__ __launch_bounds__(kSortThreads) void k_hist(const uint64_t *__restric
     hist[(size_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
 }
 
-// Stable scatter of one tile: element order inside the tile is (iteration, thread), and each
-// element's rank among equal digits follows that order.
+// Stable scatter of one tile.  Element order inside the tile is (iteration, thread); each
+// element's rank among equal digits follows that order.  The tile is first reordered by
+// digit in LDS, then written out in that order, so elements with equal digits leave as
+// contiguous runs.
 __global__ __launch_bounds__(kSortThreads) void k_scatter(const uint64_t *__restrict__ key,
                                                           const uint32_t *__restrict__ idx,
                                                           int64_t n, int shift,
@@ -94,21 +98,51 @@ __global__ __launch_bounds__(kSortThreads) void k_scatter(const uint64_t *__rest
                                                           uint32_t *__restrict__ idx_out)
 {
     constexpr int kWaves = kSortThreads / 64;
-    __shared__ uint32_t goff[kSortBins];
+    __shared__ uint64_t skey[kSortTile];
+    __shared__ uint32_t sidx[kSortTile];
+    __shared__ uint32_t goff[kSortBins];  // global offset of this tile's digit-d run
+    __shared__ uint32_t loff[kSortBins];  // local offset of digit d inside the tile
+    __shared__ uint32_t run[kSortBins];   // elements of digit d placed so far
     __shared__ uint32_t wcnt[kWaves][kSortBins];
+    __shared__ uint32_t wsum[kWaves];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int64_t base = (int64_t)blockIdx.x * kSortTile;
     goff[tid] = hist[(size_t)tid * nblocks + blockIdx.x];
+    run[tid] = 0;
 #pragma unroll
     for (int q = 0; q < kWaves; ++q) wcnt[q][tid] = 0;
     __syncthreads();
+    // local histogram of the tile (reusing wcnt[0] as the counter array)
+    uint64_t kv[kSortItems];
+    for (int it = 0; it < kSortItems; ++it) {
+        int64_t k = base + (int64_t)it * kSortThreads + tid;
+        kv[it] = k < n ? key[k] : 0ull;
+        if (k < n) atomicAdd(&wcnt[0][(uint32_t)(kv[it] >> shift) & (kSortBins - 1)], 1u);
+    }
+    __syncthreads();
+    {
+        // exclusive scan of the 256 digit counts (one per thread)
+        uint32_t v = wcnt[0][tid];
+        uint32_t inc = v;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            uint32_t o = __shfl_up(inc, d, 64);
+            if (lane >= d) inc += o;
+        }
+        if (lane == 63) wsum[w] = inc;
+        __syncthreads();
+        uint32_t before = 0;
+        for (int q = 0; q < w; ++q) before += wsum[q];
+        loff[tid] = before + inc - v;
+        wcnt[0][tid] = 0;
+    }
+    __syncthreads();
     const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
-    int64_t base = (int64_t)blockIdx.x * kSortTile;
     for (int it = 0; it < kSortItems; ++it) {
         int64_t k = base + (int64_t)it * kSortThreads + tid;
         bool valid = k < n;
-        uint64_t kv = valid ? key[k] : 0ull;
         uint32_t iv = valid ? idx[k] : 0u;
-        uint32_t d = (uint32_t)(kv >> shift) & (kSortBins - 1);
+        uint32_t d = (uint32_t)(kv[it] >> shift) & (kSortBins - 1);
         uint64_t peers = __ballot(valid);
 #pragma unroll
         for (int b = 0; b < kSortBits; ++b) {
@@ -122,9 +156,9 @@ __global__ __launch_bounds__(kSortThreads) void k_scatter(const uint64_t *__rest
         if (valid) {
             uint32_t before = 0;
             for (int q = 0; q < w; ++q) before += wcnt[q][d];
-            uint32_t pos = goff[d] + before + rank;
-            key_out[pos] = kv;
-            idx_out[pos] = iv;
+            uint32_t lp = loff[d] + run[d] + before + rank;
+            skey[lp] = kv[it];
+            sidx[lp] = iv;
         }
         __syncthreads();
         uint32_t add = 0;
@@ -133,27 +167,33 @@ __global__ __launch_bounds__(kSortThreads) void k_scatter(const uint64_t *__rest
             add += wcnt[q][tid];
             wcnt[q][tid] = 0;
         }
-        goff[tid] += add;
+        run[tid] += add;
         __syncthreads();
+    }
+    const int64_t cnt = (n - base) < kSortTile ? (n - base) : kSortTile;
+    for (int e = tid; e < cnt; e += kSortThreads) {
+        uint64_t kk = skey[e];
+        uint32_t d = (uint32_t)(kk >> shift) & (kSortBins - 1);
+        uint32_t pos = goff[d] + ((uint32_t)e - loff[d]);
+        key_out[pos] = kk;
+        idx_out[pos] = sidx[e];
     }
 }
 
+// Gather the (x, y, z, m) records into key order as four FP64 arrays.
 __global__ __launch_bounds__(256) void k_permute(int64_t n, const uint32_t *__restrict__ idx,
-                                                 const double *__restrict__ x,
-                                                 const double *__restrict__ y,
-                                                 const double *__restrict__ z,
-                                                 const double *__restrict__ m,
+                                                 const double4 *__restrict__ rec,
                                                  double *__restrict__ px, double *__restrict__ py,
                                                  double *__restrict__ pz,
                                                  double *__restrict__ pm)
 {
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
          k += (int64_t)gridDim.x * blockDim.x) {
-        uint32_t i = idx[k];
-        px[k] = x[i];
-        py[k] = y[i];
-        pz[k] = z[i];
-        pm[k] = m[i];
+        const double4 r = rec[idx[k]];
+        px[k] = r.x;
+        py[k] = r.y;
+        pz[k] = r.z;
+        pm[k] = r.w;
     }
 }
 
@@ -299,14 +339,30 @@ __global__ __launch_bounds__(256) void k_moments(NodeArrays nd, const double *__
     }
 }
 
-__global__ __launch_bounds__(256) void k_com_divide(NodeArrays nd, uint32_t n_nodes)
+__global__ __launch_bounds__(256) void k_com_divide(NodeArrays nd, uint32_t n_nodes,
+                                                    WalkNode *__restrict__ wn)
 {
     for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < n_nodes;
          u += gridDim.x * blockDim.x) {
         double M = nd.mass[u];
-        nd.comx[u] = nd.comx[u] / M;
-        nd.comy[u] = nd.comy[u] / M;
-        nd.comz[u] = nd.comz[u] / M;
+        double c0 = nd.comx[u] / M, c1 = nd.comy[u] / M, c2 = nd.comz[u] / M;
+        nd.comx[u] = c0;
+        nd.comy[u] = c1;
+        nd.comz[u] = c2;
+        WalkNode w;
+        w.cn[0] = nd.cnx[u];
+        w.cn[1] = nd.cny[u];
+        w.cn[2] = nd.cnz[u];
+        w.com[0] = c0;
+        w.com[1] = c1;
+        w.com[2] = c2;
+        w.first = nd.first[u];
+        w.count = nd.count[u];
+        w.nchild = nd.nchild[u];
+        w.child_first = w.nchild ? nd.child_first[u] : 0u;
+        w.level = nd.level[u];
+        w.pad0 = w.pad1 = 0;
+        wn[u] = w;
     }
 }
 
@@ -343,8 +399,7 @@ __global__ __launch_bounds__(256) void k_group_bbox(NodeArrays nd, GroupArrays g
                                                     uint32_t n_groups,
                                                     const double *__restrict__ px,
                                                     const double *__restrict__ py,
-                                                    const double *__restrict__ pz,
-                                                    unsigned *min_level, unsigned *max_count)
+                                                    const double *__restrict__ pz)
 {
     uint32_t g = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
@@ -369,8 +424,6 @@ __global__ __launch_bounds__(256) void k_group_bbox(NodeArrays nd, GroupArrays g
         }
     }
     if (lane == 0) {
-        atomicMin(min_level, (unsigned)nd.level[u]);
-        atomicMax(max_count, c);
         gr.first[g] = f;
         gr.count[g] = c;
         gr.lox[g] = lo[0]; gr.loy[g] = lo[1]; gr.loz[g] = lo[2];
@@ -387,6 +440,39 @@ __global__ __launch_bounds__(256) void k_group_bbox(NodeArrays nd, GroupArrays g
     }
 }
 
+// Shallowest group level and largest group: block reductions, one atomic per block.
+__global__ __launch_bounds__(256) void k_group_extremes(NodeArrays nd, GroupArrays gr,
+                                                        uint32_t n_groups, unsigned *min_level,
+                                                        unsigned *max_count)
+{
+    unsigned lv = 255u, mc = 0u;
+    for (uint32_t g = blockIdx.x * blockDim.x + threadIdx.x; g < n_groups;
+         g += gridDim.x * blockDim.x) {
+        uint32_t u = gr.node[g];
+        lv = min(lv, (unsigned)nd.level[u]);
+        mc = max(mc, (unsigned)nd.count[u]);
+    }
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) {
+        lv = min(lv, (unsigned)__shfl_xor((int)lv, d, 64));
+        mc = max(mc, (unsigned)__shfl_xor((int)mc, d, 64));
+    }
+    __shared__ unsigned s_lv[4], s_mc[4];
+    if ((threadIdx.x & 63) == 0) {
+        s_lv[threadIdx.x >> 6] = lv;
+        s_mc[threadIdx.x >> 6] = mc;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < 4; ++w) {
+            lv = min(lv, s_lv[w]);
+            mc = max(mc, s_mc[w]);
+        }
+        atomicMin(min_level, lv);
+        atomicMax(max_count, mc);
+    }
+}
+
 inline unsigned grid_for(int64_t n, int threads, int64_t cap = 65536)
 {
     int64_t b = (n + threads - 1) / threads;
@@ -398,10 +484,11 @@ inline unsigned grid_for(int64_t n, int threads, int64_t cap = 65536)
 } // namespace
 
 void launch_keys(int64_t n, const double *x, const double *y, const double *z, const double *m,
-                 double L, uint64_t *key, uint32_t *idx, unsigned *flags, hipStream_t s)
+                 double L, uint64_t *key, uint32_t *idx, unsigned *flags, double4 *rec,
+                 hipStream_t s)
 {
     double scale = 2097152.0 / L;
-    k_keys<<<grid_for(n, 256), 256, 0, s>>>(n, x, y, z, m, L, scale, key, idx, flags);
+    k_keys<<<grid_for(n, 256), 256, 0, s>>>(n, x, y, z, m, L, scale, key, idx, flags, rec);
 }
 
 size_t sort_hist_elems(int64_t n)
@@ -428,11 +515,10 @@ void radix_sort(int64_t n, uint64_t *key, uint32_t *idx, uint64_t *key_alt, uint
     // 64 / kSortBits passes is even: the result is back in key / idx.
 }
 
-void launch_permute(int64_t n, const uint32_t *idx, const double *x, const double *y,
-                    const double *z, const double *m, double *px, double *py, double *pz,
-                    double *pm, hipStream_t s)
+void launch_permute(int64_t n, const uint32_t *idx, const double4 *rec, double *px,
+                    double *py, double *pz, double *pm, hipStream_t s)
 {
-    k_permute<<<grid_for(n, 256), 256, 0, s>>>(n, idx, x, y, z, m, px, py, pz, pm);
+    k_permute<<<grid_for(n, 256), 256, 0, s>>>(n, idx, rec, px, py, pz, pm);
 }
 
 void launch_root(NodeArrays nd, uint32_t n, double L, hipStream_t s)
@@ -458,9 +544,9 @@ void launch_moments(NodeArrays nd, const double *px, const double *py, const dou
     k_moments<<<grid_for(hi - lo, 256), 256, 0, s>>>(nd, px, py, pz, pm, lo, hi);
 }
 
-void launch_com_divide(NodeArrays nd, uint32_t n_nodes, hipStream_t s)
+void launch_com_divide(NodeArrays nd, uint32_t n_nodes, WalkNode *wn, hipStream_t s)
 {
-    k_com_divide<<<grid_for(n_nodes, 256), 256, 0, s>>>(nd, n_nodes);
+    k_com_divide<<<grid_for(n_nodes, 256), 256, 0, s>>>(nd, n_nodes, wn);
 }
 
 void launch_group_mark(NodeArrays nd, uint32_t n_nodes, int n_crit, uint32_t *gstart,
@@ -482,8 +568,9 @@ void launch_group_bbox(NodeArrays nd, GroupArrays gr, uint32_t n_groups, const d
                        unsigned *max_count, hipStream_t s)
 {
     if (!n_groups) return;
-    k_group_bbox<<<(n_groups + 3) / 4, 256, 0, s>>>(nd, gr, n_groups, px, py, pz, min_level,
-                                                    max_count);
+    k_group_bbox<<<(n_groups + 3) / 4, 256, 0, s>>>(nd, gr, n_groups, px, py, pz);
+    k_group_extremes<<<grid_for(n_groups, 256, 256), 256, 0, s>>>(nd, gr, n_groups, min_level,
+                                                                 max_count);
 }
 
 } // namespace tpm

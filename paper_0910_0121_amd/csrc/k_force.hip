@@ -3,9 +3,9 @@
 //
 //   a_i += m_j d g(|d| / eta) / (|d|^2 + eps^2)^(3/2),   d = x_j - x_i.
 //
-// One 64-lane wavefront per group: each lane holds one i-particle (groups larger than 64 are
-// done in chunks of 64), and the group's list is streamed through LDS in tiles; every lane
-// reads the same tile entry (an LDS broadcast) and accumulates into registers.
+// One 64-lane wavefront per group: the group's i-particles sit in registers and its list is
+// streamed through LDS in tiles; lanes of one stream read the same tile entry (an LDS
+// broadcast) and accumulate in registers.
 //
 // FP32 path (Section 3.1.1): positions are passed relative to the group's cube centre x_g,
 // x_i - x_g and wrap(x_j - x_g), each difference taken in FP64 and then rounded to FP32, so
@@ -25,22 +25,6 @@ namespace tpm {
 namespace {
 
 constexpr int kTileJ = 64;
-
-__device__ __forceinline__ float g_p3m_f32(float R)
-{
-    float R2 = R * R;
-    float p = fmaf(0.15f, R, -12.0f / 35.0f);
-    p = fmaf(p, R, -0.5f);
-    p = fmaf(p, R, 1.6f);
-    p = fmaf(p, R2, -1.6f);
-    float g1 = fmaf(p, R2 * R, 1.0f);
-    float u = fmaxf(2.0f - R, 0.0f);
-    float u2 = u * u;
-    float u5 = u2 * u2 * u;
-    float c = fmaf(fmaf(fmaf(0.05f, R, 22.0f / 140.0f), R, 10.0f / 140.0f), R, 4.0f / 140.0f);
-    float g2 = u5 * c;
-    return R < 1.0f ? g1 : g2;
-}
 
 __device__ __forceinline__ double g_p3m_f64(double R)
 {
@@ -89,72 +73,279 @@ __device__ __forceinline__ void store3(void *ax, void *ay, void *az, uint32_t i,
     }
 }
 
-template <int OUT64>
-__global__ __launch_bounds__(64) void k_force_f32(
-    NodeArrays nd, GroupArrays gr, uint32_t n_groups, const uint64_t *__restrict__ off,
-    const uint32_t *__restrict__ entries, const double *__restrict__ px,
-    const double *__restrict__ py, const double *__restrict__ pz, const double *__restrict__ pm,
-    const uint32_t *__restrict__ pidx, ForceParams fp, void *ax, void *ay, void *az)
+// FP32 path.  Lengths are in units of eta (the cutoff scale), so R = |d| and R^2 = |d|^2
+// come for free; the sum is multiplied by 1/eta^2 once per particle:
+//   a_i = (1/eta^2) sum_j m_j d'_ij g(|d'_ij|) / (|d'_ij|^2 + (eps/eta)^2)^(3/2).
+//
+// One tile holds up to kTileF32 sources.  Each lane examines kTileF32 / 64 list entries and
+// drops those whose source is at least r_cut from the group's bounding box: every pair they
+// would form is at least r_cut apart and adds exactly zero (g = 0 for R >= 2).  The survivors
+// are compacted in list order and stored by stream: survivor e goes to stream e % J, slot
+// e / J, so each stream reads a contiguous run.  Slots past the last survivor of a stream
+// are zero-mass padding (they add exactly 0).
+constexpr int kTileF32 = 256;
+
+struct GroupFrame {
+    double xg0, xg1, xg2;   // x_g, origin of the relative coordinates
+    double cg0, cg1, cg2;   // bbox centre
+    double hg0, hg1, hg2;   // bbox half size
+    double L, rc2, inv_eta;
+};
+
+__device__ __forceinline__ int load_tile_f32(float4 *tile, const uint32_t *__restrict__ list,
+                                             uint64_t jb, uint64_t Lg, int J, int per_stream,
+                                             NodeArrays nd, const double *__restrict__ px,
+                                             const double *__restrict__ py,
+                                             const double *__restrict__ pz,
+                                             const double *__restrict__ pm,
+                                             const GroupFrame &F)
 {
-    __shared__ float4 tile[kTileJ];
-    const uint32_t g = blockIdx.x;
     const int lane = threadIdx.x;
-    if (g >= n_groups) return;
+    const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+    int kept = 0;
+#pragma unroll
+    for (int r = 0; r < kTileF32 / 64; ++r) {
+        const uint64_t j = jb + (uint64_t)(r * 64 + lane);
+        bool keep = false;
+        float4 v;
+        if (j < Lg) {
+            uint32_t ent = list[j];
+            double sx, sy, sz, sm;
+            if (ent & kCellTag) {
+                uint32_t u = ent & ~kCellTag;
+                sx = nd.comx[u]; sy = nd.comy[u]; sz = nd.comz[u]; sm = nd.mass[u];
+            } else {
+                sx = px[ent]; sy = py[ent]; sz = pz[ent]; sm = pm[ent];
+            }
+            double w0 = fabs(wrapd(sx - F.cg0, F.L)) - F.hg0;
+            double w1 = fabs(wrapd(sy - F.cg1, F.L)) - F.hg1;
+            double w2 = fabs(wrapd(sz - F.cg2, F.L)) - F.hg2;
+            w0 = w0 > 0.0 ? w0 : 0.0;
+            w1 = w1 > 0.0 ? w1 : 0.0;
+            w2 = w2 > 0.0 ? w2 : 0.0;
+            keep = w0 * w0 + w1 * w1 + w2 * w2 < F.rc2;
+            v = make_float4((float)(wrapd(sx - F.xg0, F.L) * F.inv_eta),
+                            (float)(wrapd(sy - F.xg1, F.L) * F.inv_eta),
+                            (float)(wrapd(sz - F.xg2, F.L) * F.inv_eta), (float)sm);
+        }
+        const uint64_t m = __ballot(keep);
+        if (keep) {
+            const int e = kept + (int)__popcll(m & lt);
+            tile[(e % J) * per_stream + e / J] = v;
+        }
+        kept += (int)__popcll(m);
+    }
+    // zero the padding slots of the last row
+    const int steps = (kept + J - 1) / J;
+    const int e = kept + lane;
+    if (lane < J && e < steps * J) tile[(e % J) * per_stream + e / J] = make_float4(0.f, 0.f, 0.f, 0.f);
+    return kept;
+}
+
+// g(R) of eq. (2) rearranged without cancellation; R2 = R * R is passed in.
+__device__ __forceinline__ float g_p3m_f32s(float R, float R2)
+{
+    float p = fmaf(0.15f, R, -12.0f / 35.0f);
+    p = fmaf(p, R, -0.5f);
+    p = fmaf(p, R, 1.6f);
+    p = fmaf(p, R2, -1.6f);
+    float g1 = fmaf(p, R2 * R, 1.0f);
+    float u = fmaxf(2.0f - R, 0.0f);
+    float u2 = u * u;
+    float u5 = u2 * u2 * u;
+    float c = fmaf(fmaf(fmaf(0.05f, R, 22.0f / 140.0f), R, 10.0f / 140.0f), R, 4.0f / 140.0f);
+    return R < 1.0f ? g1 : u5 * c;
+}
+
+__device__ __forceinline__ void pair_f32(const float4 s, float xi, float yi, float zi,
+                                         float eps2, float &tx, float &ty, float &tz)
+{
+    const float dx = s.x - xi, dy = s.y - yi, dz = s.z - zi;
+    const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+    const float rinv = __builtin_amdgcn_rsqf(r2 + eps2);
+    const float rinv3 = rinv * rinv * rinv;
+    const float R = __builtin_amdgcn_sqrtf(r2);
+    const float fm = s.w * g_p3m_f32s(R, r2) * rinv3;
+    tx = fmaf(fm, dx, tx);
+    ty = fmaf(fm, dy, ty);
+    tz = fmaf(fm, dz, tz);
+}
+
+// One group on one wave: K i-particles per lane, K = ceil(n_g / 64) (at most 8; larger
+// groups are done in chunks of 512).  For groups of at most 32 (K = 1) the wave splits into
+// J = 64 / S streams of S >= n_g lanes, each stream taking every J-th surviving source, and
+// the J partial sums are added at the end in stream order.
+template <int K, int OUT64>
+__device__ __forceinline__ void force_group_f32(float4 *tile, double *red, NodeArrays nd,
+                                                uint32_t n_g, uint32_t f, const uint32_t *list,
+                                                uint64_t Lg, const double *__restrict__ px,
+                                                const double *__restrict__ py,
+                                                const double *__restrict__ pz,
+                                                const double *__restrict__ pm,
+                                                const uint32_t *__restrict__ pidx,
+                                                const GroupFrame &F, float eps2, double scale,
+                                                void *ax, void *ay, void *az, uint32_t *kept_out)
+{
+    const int lane = threadIdx.x;
+    int J = 1;
+    if (K == 1) J = n_g <= 8 ? 8 : n_g <= 16 ? 4 : n_g <= 32 ? 2 : 1;
+    const int S = 64 / J;
+    const int slot = lane % S, stream = lane / S;
+    const int per_stream = kTileF32 / J;
+    uint32_t kept_total = 0;
+    for (uint32_t ib = 0; ib < n_g; ib += 64 * K) {
+        float xi[K], yi[K], zi[K], hx[K], hy[K], hz[K], lx[K], ly[K], lz[K];
+        kept_total = 0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const uint32_t i = ib + slot + S * k;
+            xi[k] = yi[k] = zi[k] = 0.f;
+            if (i < n_g) {
+                xi[k] = (float)((px[f + i] - F.xg0) * F.inv_eta);
+                yi[k] = (float)((py[f + i] - F.xg1) * F.inv_eta);
+                zi[k] = (float)((pz[f + i] - F.xg2) * F.inv_eta);
+            }
+            hx[k] = hy[k] = hz[k] = lx[k] = ly[k] = lz[k] = 0.f;
+        }
+        for (uint64_t jb = 0; jb < Lg; jb += kTileF32) {
+            const int nt = load_tile_f32(tile, list, jb, Lg, J, per_stream, nd, px, py, pz, pm, F);
+            kept_total += (uint32_t)nt;
+            __syncthreads();
+            const int steps = (nt + J - 1) / J;
+            const float4 *ts = tile + stream * per_stream;
+            float tx[K], ty[K], tz[K];
+#pragma unroll
+            for (int k = 0; k < K; ++k) tx[k] = ty[k] = tz[k] = 0.f;
+            int t = 0;
+            for (; t + 2 <= steps; t += 2) {
+                const float4 s0 = ts[t], s1 = ts[t + 1];
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    pair_f32(s0, xi[k], yi[k], zi[k], eps2, tx[k], ty[k], tz[k]);
+                    pair_f32(s1, xi[k], yi[k], zi[k], eps2, tx[k], ty[k], tz[k]);
+                }
+            }
+            if (t < steps) {
+                const float4 s0 = ts[t];
+#pragma unroll
+                for (int k = 0; k < K; ++k)
+                    pair_f32(s0, xi[k], yi[k], zi[k], eps2, tx[k], ty[k], tz[k]);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                two_sum_fold(hx[k], lx[k], tx[k]);
+                two_sum_fold(hy[k], ly[k], ty[k]);
+                two_sum_fold(hz[k], lz[k], tz[k]);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            double vx = (double)hx[k] + (double)lx[k];
+            double vy = (double)hy[k] + (double)ly[k];
+            double vz = (double)hz[k] + (double)lz[k];
+            if (J > 1) {
+                // streams 1..J-1 hand their sums to stream 0 through LDS
+                if (stream > 0) {
+                    red[3 * lane + 0] = vx;
+                    red[3 * lane + 1] = vy;
+                    red[3 * lane + 2] = vz;
+                }
+                __syncthreads();
+                if (stream == 0) {
+                    for (int q = 1; q < J; ++q) {
+                        const int src = q * S + slot;
+                        vx += red[3 * src + 0];
+                        vy += red[3 * src + 1];
+                        vz += red[3 * src + 2];
+                    }
+                }
+                __syncthreads();
+            }
+            const uint32_t i = ib + slot + S * k;
+            if (stream == 0 && i < n_g)
+                store3<OUT64>(ax, ay, az, pidx[f + i], vx * scale, vy * scale, vz * scale);
+        }
+    }
+    if (lane == 0) *kept_out = kept_total;
+}
+
+// One launch per blocking factor K (see k_classify), so each gets its own register budget.
+template <int K, int OUT64>
+__global__ __launch_bounds__(64) void k_force_f32(
+    NodeArrays nd, GroupArrays gr, const uint32_t *__restrict__ ids, uint32_t n_ids,
+    const uint64_t *__restrict__ off, const uint32_t *__restrict__ entries,
+    const double *__restrict__ px, const double *__restrict__ py, const double *__restrict__ pz,
+    const double *__restrict__ pm, const uint32_t *__restrict__ pidx, ForceParams fp, void *ax,
+    void *ay, void *az)
+{
+    __shared__ float4 tile[kTileF32];
+    __shared__ double red[64 * 3];
+    if (blockIdx.x >= n_ids) return;
+    const uint32_t g = ids[blockIdx.x];
     const uint32_t n_g = gr.count[g], f = gr.first[g];
     const uint64_t b = off[g];
     const uint64_t Lg = off[g + 1] - b;
-    const double xg0 = gr.xgx[g], xg1 = gr.xgy[g], xg2 = gr.xgz[g];
-    const double L = fp.L;
-    const float eps2 = (float)fp.eps2, inv_eta = (float)fp.inv_eta;
-    for (uint32_t ib = 0; ib < n_g; ib += 64) {
-        const uint32_t i = ib + lane;
-        const bool act = i < n_g;
-        float xi = 0.f, yi = 0.f, zi = 0.f;
-        if (act) {
-            xi = (float)(px[f + i] - xg0);
-            yi = (float)(py[f + i] - xg1);
-            zi = (float)(pz[f + i] - xg2);
+    GroupFrame F;
+    F.xg0 = gr.xgx[g]; F.xg1 = gr.xgy[g]; F.xg2 = gr.xgz[g];
+    F.cg0 = gr.cgx[g]; F.cg1 = gr.cgy[g]; F.cg2 = gr.cgz[g];
+    F.hg0 = gr.hgx[g]; F.hg1 = gr.hgy[g]; F.hg2 = gr.hgz[g];
+    F.L = fp.L;
+    F.rc2 = fp.rc2;
+    F.inv_eta = fp.inv_eta;
+    const float eps2 = (float)(fp.eps2 * fp.inv_eta * fp.inv_eta);
+    const double scale = fp.inv_eta * fp.inv_eta;
+    force_group_f32<K, OUT64>(tile, red, nd, n_g, f, entries + b, Lg, px, py, pz, pm, pidx, F,
+                              eps2, scale, ax, ay, az, fp.kept + g);
+}
+
+__global__ __launch_bounds__(256) void k_kept_stats(GroupArrays gr, uint32_t n_groups,
+                                                    const uint32_t *__restrict__ kept,
+                                                    unsigned long long *out)
+{
+    unsigned long long v = 0;
+    for (uint32_t g = blockIdx.x * blockDim.x + threadIdx.x; g < n_groups;
+         g += gridDim.x * blockDim.x)
+        v += (unsigned long long)kept[g] * gr.count[g];
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d, 64);
+    __shared__ unsigned long long sm[4];
+    if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) atomicAdd(out, sm[0] + sm[1] + sm[2] + sm[3]);
+}
+
+constexpr int kClasses = 8;
+
+// Blocking class of a group: K - 1 with K = ceil(count / 64), capped at 8.  Each class list
+// is filled with one atomic per wave; the order inside a list does not affect results.
+__global__ __launch_bounds__(256) void k_classify(GroupArrays gr, uint32_t n_groups,
+                                                  uint32_t *__restrict__ lists, uint32_t stride,
+                                                  uint32_t *counts)
+{
+    const int lane = threadIdx.x & 63;
+    for (uint32_t base = blockIdx.x * blockDim.x; base < n_groups;
+         base += gridDim.x * blockDim.x) {
+        const uint32_t g = base + threadIdx.x;
+        int cls = -1;
+        if (g < n_groups) {
+            uint32_t c = gr.count[g];
+            cls = (int)((c + 63) / 64) - 1;
+            cls = cls < 0 ? 0 : cls > kClasses - 1 ? kClasses - 1 : cls;
         }
-        float hx = 0.f, hy = 0.f, hz = 0.f, lx = 0.f, ly = 0.f, lz = 0.f;
-        for (uint64_t jb = 0; jb < Lg; jb += kTileJ) {
-            const uint64_t j = jb + lane;
-            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (j < Lg) {
-                uint32_t e = entries[b + j];
-                double sx, sy, sz, sm;
-                if (e & kCellTag) {
-                    uint32_t u = e & ~kCellTag;
-                    sx = nd.comx[u]; sy = nd.comy[u]; sz = nd.comz[u]; sm = nd.mass[u];
-                } else {
-                    sx = px[e]; sy = py[e]; sz = pz[e]; sm = pm[e];
-                }
-                v = make_float4((float)wrapd(sx - xg0, L), (float)wrapd(sy - xg1, L),
-                                (float)wrapd(sz - xg2, L), (float)sm);
+#pragma unroll
+        for (int q = 0; q < kClasses; ++q) {
+            uint64_t m = __ballot(cls == q);
+            if (!m) continue;
+            uint32_t first_lane = (uint32_t)__ffsll((long long)m) - 1;
+            uint32_t at = 0;
+            if (lane == (int)first_lane) at = atomicAdd(&counts[q], (uint32_t)__popcll(m));
+            at = __shfl(at, first_lane, 64);
+            if (cls == q) {
+                const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+                lists[q * stride + at + __popcll(m & lt)] = g;
             }
-            tile[lane] = v;
-            __syncthreads();
-            const int nt = (Lg - jb) < (uint64_t)kTileJ ? (int)(Lg - jb) : kTileJ;
-            float tx = 0.f, ty = 0.f, tz = 0.f;
-            for (int t = 0; t < nt; ++t) {
-                const float4 s = tile[t];
-                const float dx = s.x - xi, dy = s.y - yi, dz = s.z - zi;
-                const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-                const float rinv = __builtin_amdgcn_rsqf(r2 + eps2);
-                const float rinv3 = rinv * rinv * rinv;
-                const float R = __builtin_amdgcn_sqrtf(r2) * inv_eta;
-                const float fm = s.w * g_p3m_f32(R) * rinv3;
-                tx = fmaf(fm, dx, tx);
-                ty = fmaf(fm, dy, ty);
-                tz = fmaf(fm, dz, tz);
-            }
-            __syncthreads();
-            two_sum_fold(hx, lx, tx);
-            two_sum_fold(hy, ly, ty);
-            two_sum_fold(hz, lz, tz);
         }
-        if (act)
-            store3<OUT64>(ax, ay, az, pidx[f + i], (double)hx + (double)lx,
-                          (double)hy + (double)ly, (double)hz + (double)lz);
     }
 }
 
@@ -223,19 +414,52 @@ __global__ __launch_bounds__(64) void k_force_f64(
 
 } // namespace
 
-void launch_force_f32(NodeArrays nd, GroupArrays gr, uint32_t n_groups, const uint64_t *off,
+void launch_classify(GroupArrays gr, uint32_t n_groups, uint32_t *lists, uint32_t stride,
+                     uint32_t *counts, hipStream_t s)
+{
+    fill_u32(counts, kClasses, 0u, s);
+    if (!n_groups) return;
+    unsigned b = (n_groups + 255) / 256;
+    k_classify<<<b < 1024 ? b : 1024, 256, 0, s>>>(gr, n_groups, lists, stride, counts);
+}
+
+void launch_force_f32(NodeArrays nd, GroupArrays gr, const uint32_t *lists, uint32_t stride,
+                      const uint32_t *class_counts, const uint64_t *off,
                       const uint32_t *entries, const double *px, const double *py,
                       const double *pz, const double *pm, const uint32_t *pidx,
                       ForceParams fp, void *ax, void *ay, void *az, int out_prec,
                       hipStream_t s)
 {
+#define TPM_LAUNCH(KK)                                                                         \
+    if (class_counts[KK - 1]) {                                                                \
+        const uint32_t *ids = lists + (size_t)(KK - 1) * stride;                               \
+        if (out_prec)                                                                          \
+            k_force_f32<KK, 1><<<class_counts[KK - 1], 64, 0, s>>>(                            \
+                nd, gr, ids, class_counts[KK - 1], off, entries, px, py, pz, pm, pidx, fp, ax, \
+                ay, az);                                                                       \
+        else                                                                                   \
+            k_force_f32<KK, 0><<<class_counts[KK - 1], 64, 0, s>>>(                            \
+                nd, gr, ids, class_counts[KK - 1], off, entries, px, py, pz, pm, pidx, fp, ax, \
+                ay, az);                                                                       \
+    }
+    TPM_LAUNCH(8)
+    TPM_LAUNCH(7)
+    TPM_LAUNCH(6)
+    TPM_LAUNCH(5)
+    TPM_LAUNCH(4)
+    TPM_LAUNCH(3)
+    TPM_LAUNCH(2)
+    TPM_LAUNCH(1)
+#undef TPM_LAUNCH
+}
+
+void launch_kept_stats(GroupArrays gr, uint32_t n_groups, const uint32_t *kept,
+                       unsigned long long *out, hipStream_t s)
+{
+    fill_u64((uint64_t *)out, 1, 0ull, s);
     if (!n_groups) return;
-    if (out_prec)
-        k_force_f32<1><<<n_groups, 64, 0, s>>>(nd, gr, n_groups, off, entries, px, py, pz, pm,
-                                              pidx, fp, ax, ay, az);
-    else
-        k_force_f32<0><<<n_groups, 64, 0, s>>>(nd, gr, n_groups, off, entries, px, py, pz, pm,
-                                              pidx, fp, ax, ay, az);
+    unsigned b = (n_groups + 255) / 256;
+    k_kept_stats<<<b < 256 ? b : 256, 256, 0, s>>>(gr, n_groups, kept, out);
 }
 
 void launch_force_f64(NodeArrays nd, GroupArrays gr, uint32_t n_groups, const uint64_t *off,

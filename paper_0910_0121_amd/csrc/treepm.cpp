@@ -50,8 +50,10 @@ struct treepm_ctx {
     bool ev_valid[3] = {false, false, false};
     // particles and sort
     Buf in[4], key, key_alt, idx, idx_alt, pos[4], hist, scan32, flags, levcnt, gstart, gflag;
+    Buf rec; // (x, y, z, m) records in input order, for the gather
     // nodes
     Buf n_code, n_first, n_count, n_cf, n_parent, n_nch, n_level, n_mass, n_com[3], n_cn[3];
+    Buf n_walk; // packed per-node walk records
     size_t node_cap = 0;
     uint32_t n_nodes = 0;
     std::vector<uint32_t> lvl;
@@ -62,7 +64,9 @@ struct treepm_ctx {
     uint32_t n_groups = 0;
     unsigned min_group_level = 0, max_group = 0;
     // lists
-    Buf off, scan64, entries, lside, wstats, overflow, out[3];
+    Buf off, scan64, entries, lside, wstats, overflow, gcells, cls, kept, kept_sum, out[3];
+    int last_force_prec = -1;
+    uint32_t class_counts[kForceClasses] = {};
     uint64_t n_entries = 0;
     uint64_t st[3] = {0, 0, 0};
     Buf host_total; // unused placeholder for alignment of future pinned buffers
@@ -247,7 +251,8 @@ int do_build(treepm_ctx *c, int64_t n, const double *x, const double *y, const d
                {&c->gstart, N * 4},      {&c->gflag, (N + 1) * 4},
                {&c->hist, sort_hist_elems(n) * 4},
                {&c->scan32, (scan_tmp_elems(std::max(sort_hist_elems(n), N + 1)) + 64) * 4},
-               {&c->lside, 32 * 8},      {&c->g_misc, 64}};
+               {&c->lside, 32 * 8},      {&c->g_misc, 64},
+               {&c->rec, N * 32}};
     for (auto &r : res) {
         hipError_t e = reserve(*r.b, std::max<size_t>(r.bytes, 64));
         if (e != hipSuccess) return hip_fail(c, e, "particle buffers");
@@ -264,7 +269,7 @@ int do_build(treepm_ctx *c, int64_t n, const double *x, const double *y, const d
     unsigned *flags = c->flags.as<unsigned>();
     fill_u32(flags, 4, 0u, s);
     launch_keys(n, src[0], src[1], src[2], src[3], P.L, c->key.as<uint64_t>(),
-                c->idx.as<uint32_t>(), flags, s);
+                c->idx.as<uint32_t>(), flags, c->rec.as<double4>(), s);
     unsigned hf = 0;
     if ((rc = d2h(c, &hf, flags, 1, s))) return rc;
     if (hf & kFlagNonFinite)
@@ -274,9 +279,8 @@ int do_build(treepm_ctx *c, int64_t n, const double *x, const double *y, const d
     uint32_t *scan_tmp = c->scan32.as<uint32_t>();
     radix_sort(n, c->key.as<uint64_t>(), c->idx.as<uint32_t>(), c->key_alt.as<uint64_t>(),
                c->idx_alt.as<uint32_t>(), c->hist.as<uint32_t>(), scan_tmp, s);
-    launch_permute(n, c->idx.as<uint32_t>(), src[0], src[1], src[2], src[3],
-                   c->pos[0].as<double>(), c->pos[1].as<double>(), c->pos[2].as<double>(),
-                   c->pos[3].as<double>(), s);
+    launch_permute(n, c->idx.as<uint32_t>(), c->rec.as<double4>(), c->pos[0].as<double>(),
+                   c->pos[1].as<double>(), c->pos[2].as<double>(), c->pos[3].as<double>(), s);
     // octree, level by level
     c->n_nodes = 0;
     if ((rc = ensure_nodes(c, std::max<size_t>(1024, N / 2 + 64), s))) return rc;
@@ -310,7 +314,11 @@ int do_build(treepm_ctx *c, int64_t n, const double *x, const double *y, const d
                  *pz = c->pos[2].as<double>(), *pm = c->pos[3].as<double>();
     for (int l = c->max_level; l >= 0; --l)
         launch_moments(nd, px, py, pz, pm, c->lvl[l], c->lvl[l + 1], s);
-    launch_com_divide(nd, c->n_nodes, s);
+    {
+        hipError_t e = reserve(c->n_walk, (size_t)c->n_nodes * sizeof(WalkNode));
+        if (e != hipSuccess) return hip_fail(c, e, "walk records");
+    }
+    launch_com_divide(nd, c->n_nodes, c->n_walk.as<WalkNode>(), s);
     // groups in key order
     int n_crit = P.n_crit > 0 ? P.n_crit : kDefaultNCrit;
     uint32_t *gstart = c->gstart.as<uint32_t>(), *gflag = c->gflag.as<uint32_t>();
@@ -347,6 +355,8 @@ int do_walk(treepm_ctx *c, hipStream_t s)
         return hip_fail(c, e, "scan buffer");
     if ((e = reserve(c->wstats, 64)) != hipSuccess) return hip_fail(c, e, "stats");
     if ((e = reserve(c->overflow, 64)) != hipSuccess) return hip_fail(c, e, "flags");
+    if ((e = reserve(c->gcells, ((size_t)G + 1) * 4)) != hipSuccess)
+        return hip_fail(c, e, "group stats");
     uint64_t *off = c->off.as<uint64_t>();
     uint64_t *tot = c->scan64.as<uint64_t>();
     unsigned *ovf = c->overflow.as<unsigned>();
@@ -358,7 +368,9 @@ int do_walk(treepm_ctx *c, hipStream_t s)
     WalkParams wp{P.L, P.r_cut * P.r_cut, P.theta * P.theta, c->lside.as<double>()};
     NodeArrays nd = nodes_view(c);
     GroupArrays gr = groups_view(c);
-    launch_walk(nd, gr, G, wp, 0, off, nullptr, ovf, ws, s);
+    uint32_t *gcells = c->gcells.as<uint32_t>();
+    const WalkNode *wn = c->n_walk.as<WalkNode>();
+    launch_walk(wn, gr, G, wp, 0, off, nullptr, ovf, gcells, ws, s);
     scan_u64(off, (size_t)G + 1, tot, tot + 1, s);
     uint64_t total = 0;
     if ((rc = d2h(c, &total, tot, 1, s))) return rc;
@@ -367,7 +379,13 @@ int do_walk(treepm_ctx *c, hipStream_t s)
     if (hov) return fail(c, TREEPM_ERR_OVERFLOW, "walk stack overflow");
     if ((e = reserve(c->entries, std::max<size_t>(total, 1) * 4)) != hipSuccess)
         return hip_fail(c, e, "interaction lists");
-    launch_walk(nd, gr, G, wp, 1, off, c->entries.as<uint32_t>(), ovf, ws, s);
+    launch_walk(wn, gr, G, wp, 1, off, c->entries.as<uint32_t>(), ovf, gcells, ws, s);
+    if ((e = reserve(c->cls, (kForceClasses * ((size_t)G + 1) + kForceClasses) * 4)) !=
+        hipSuccess)
+        return hip_fail(c, e, "group classes");
+    uint32_t *cls = c->cls.as<uint32_t>();
+    launch_classify(gr, G, cls + kForceClasses, G + 1, cls, s);
+    if ((rc = d2h(c, c->class_counts, cls, kForceClasses, s))) return rc;
     unsigned long long hs[3];
     if ((rc = d2h(c, hs, ws, 3, s))) return rc;
     if ((rc = d2h(c, &hov, ovf, 1, s))) return rc;
@@ -433,11 +451,12 @@ TREEPM_API int treepm_destroy(treepm_ctx *c)
                   &c->scan32, &c->flags, &c->levcnt, &c->gstart, &c->gflag, &c->n_code,
                   &c->n_first, &c->n_count, &c->n_cf, &c->n_parent, &c->n_nch, &c->n_level,
                   &c->n_mass, &c->n_com[0], &c->n_com[1], &c->n_com[2], &c->n_cn[0],
-                  &c->n_cn[1], &c->n_cn[2], &c->g_node, &c->g_first, &c->g_count, &c->g_cg[0],
+                  &c->n_cn[1], &c->n_cn[2], &c->n_walk, &c->g_node, &c->g_first, &c->g_count, &c->g_cg[0],
                   &c->g_cg[1], &c->g_cg[2], &c->g_hg[0], &c->g_hg[1], &c->g_hg[2], &c->g_xg[0],
                   &c->g_xg[1], &c->g_xg[2], &c->g_lo[0], &c->g_lo[1], &c->g_lo[2], &c->g_hi[0],
                   &c->g_hi[1], &c->g_hi[2], &c->g_misc, &c->off, &c->scan64, &c->entries,
-                  &c->lside, &c->wstats, &c->overflow, &c->out[0], &c->out[1], &c->out[2]};
+                  &c->lside, &c->wstats, &c->overflow, &c->rec, &c->kept, &c->kept_sum, &c->gcells, &c->cls, &c->out[0],
+                  &c->out[1], &c->out[2]};
     for (Buf *b : all) b->release();
     if (c->ev[0])
         for (hipEvent_t &e : c->ev) hipEventDestroy(e);
@@ -550,13 +569,31 @@ TREEPM_API int treepm_force_short(treepm_ctx *c, void *ax, void *ay, void *az, i
     NodeArrays nd = nodes_view(c);
     GroupArrays gr = groups_view(c);
     double eta = 0.5 * P.r_cut;
-    ForceParams fp{P.L, P.eps * P.eps, 1.0 / eta, eta};
-    auto fn = P.precision == TREEPM_FP32 ? launch_force_f32 : launch_force_f64;
-    fn(nd, gr, c->n_groups, c->off.as<uint64_t>(), c->entries.as<uint32_t>(),
-       c->pos[0].as<double>(), c->pos[1].as<double>(), c->pos[2].as<double>(),
-       c->pos[3].as<double>(), c->idx.as<uint32_t>(), fp, dst[0], dst[1], dst[2], out_prec, s);
+    {
+        hipError_t e = reserve(c->kept, ((size_t)c->n_groups + 1) * 4);
+        if (e == hipSuccess) e = reserve(c->kept_sum, 64);
+        if (e != hipSuccess) return hip_fail(c, e, "force statistics");
+    }
+    ForceParams fp{P.L, P.eps * P.eps, 1.0 / eta, eta, P.r_cut * P.r_cut,
+                   c->kept.as<uint32_t>()};
+    if (P.precision == TREEPM_FP32)
+        launch_force_f32(nd, gr, c->cls.as<uint32_t>() + kForceClasses, c->n_groups + 1,
+                         c->class_counts,
+                         c->off.as<uint64_t>(), c->entries.as<uint32_t>(),
+                         c->pos[0].as<double>(), c->pos[1].as<double>(),
+                         c->pos[2].as<double>(), c->pos[3].as<double>(),
+                         c->idx.as<uint32_t>(), fp, dst[0], dst[1], dst[2], out_prec, s);
+    else
+        launch_force_f64(nd, gr, c->n_groups, c->off.as<uint64_t>(), c->entries.as<uint32_t>(),
+                         c->pos[0].as<double>(), c->pos[1].as<double>(),
+                         c->pos[2].as<double>(), c->pos[3].as<double>(),
+                         c->idx.as<uint32_t>(), fp, dst[0], dst[1], dst[2], out_prec, s);
     HIPCHK(c, hipGetLastError());
     record(c, 5, s);
+    if (P.precision == TREEPM_FP32)
+        launch_kept_stats(gr, c->n_groups, c->kept.as<uint32_t>(),
+                          c->kept_sum.as<unsigned long long>(), s);
+    c->last_force_prec = P.precision;
     c->ev_valid[2] = c->timing;
     if (mem_kind == TREEPM_HOST) {
         void *hdst[3] = {ax, ay, az};
@@ -574,6 +611,14 @@ TREEPM_API int treepm_get_stats(treepm_ctx *c, treepm_stats *stats)
     HIPCHK(c, hipSetDevice(c->device));
     if (c->timing) HIPCHK(c, hipStreamSynchronize(c->last));
     fill_stats(c, stats);
+    if (c->state >= 2 && c->last_force_prec == TREEPM_FP32) {
+        unsigned long long ev = 0;
+        int rc = d2h(c, &ev, c->kept_sum.p, 1, c->last);
+        if (rc) return rc;
+        stats->evaluated = (int64_t)ev;
+    } else if (c->state >= 2 && c->last_force_prec == TREEPM_FP64) {
+        stats->evaluated = stats->interactions;
+    }
     return TREEPM_OK;
 }
 
