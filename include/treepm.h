@@ -158,6 +158,17 @@ int treepm_export_groups(treepm_ctx *ctx, int64_t cap, uint64_t *code, int64_t *
 int treepm_export_lists(treepm_ctx *ctx, int64_t group_cap, int64_t entry_cap, int64_t *offsets,
                         uint8_t *is_cell, uint64_t *value);
 
+/* The FP32 pair routine of treepm_force_short on explicit positions, pair by pair (the
+ * pairwise-accuracy measurement of Section 3.1.1): out[(i n_j + j) 3 + a] is the
+ * acceleration at xi[i] from a mass mj[j] at xj[j], computed exactly as the force kernel
+ * does -- coordinates relative to xg and in units of eta = r_cut / 2, FP32 rsqrt, sqrt and
+ * g -- but without periodic images and without the cull of sources beyond r_cut.
+ * xi: 3 n_i doubles, xj: 3 n_j, mj: n_j, xg: 3, out: 3 n_i n_j (all host memory).
+ * n_i n_j <= 2^28.  Uses params->r_cut and params->eps (validated as for treepm_create). */
+int treepm_pairwise_f32(const treepm_params *params, int device, int64_t n_i, const double *xi,
+                        int64_t n_j, const double *xj, const double *mj, const double *xg,
+                        double *out);
+
 /* Text of the last error on this context ("" if none).  Valid until the next call. */
 const char *treepm_last_error(const treepm_ctx *ctx);
 

@@ -52,7 +52,8 @@ def lib():
         L.orc_tree_force_mag.restype = C.c_int
         L.orc_tree_force_mag.argtypes = [_p, _p, _p, C.c_int]
         L.orc_tree_walk_force_sample.restype = _i64
-        L.orc_tree_walk_force_sample.argtypes = [_p, _i64, _i64, _p, _p, _p, C.c_int, _p]
+        L.orc_tree_walk_force_sample.argtypes = [_p, _i64, _i64, _p, _p, _p, C.c_int, _p, _p,
+                                                 _p]
         for name in ("orc_tree_n_nodes", "orc_tree_n_groups", "orc_tree_n_entries",
                      "orc_tree_interactions"):
             f = getattr(L, name)
@@ -211,13 +212,19 @@ class Tree:
         mag, newt = self.force_mag(nthreads)
         return mag + newt
 
-    def walk_force_sample(self, stride, offset=0, nthreads=0):
+    def walk_force_sample(self, stride, offset=0, nthreads=0, scales=False):
         """Walk + list force for groups offset, offset+stride, ...; returns
-        (ax, ay, az, interactions, particles) with NaN for unsampled particles."""
+        (ax, ay, az, interactions, particles) with NaN for unsampled particles, and with
+        scales=True also (mag, newt), the error scales of force_mag for those particles."""
         ax, ay, az = (np.full(self.n, np.nan) for _ in range(3))
         parts = np.zeros(1, dtype=np.int64)
+        mag = np.full(self.n, np.nan) if scales else None
+        newt = np.full(self.n, np.nan) if scales else None
         inter = lib().orc_tree_walk_force_sample(self.h, stride, offset, _ptr(ax), _ptr(ay),
-                                                 _ptr(az), nthreads, _ptr(parts))
+                                                 _ptr(az), nthreads, _ptr(parts),
+                                                 _ptr(mag) if scales else None,
+                                                 _ptr(newt) if scales else None)
         if inter < 0:
             raise RuntimeError("oracle sampled walk failed")
-        return ax, ay, az, int(inter), int(parts[0])
+        out = (ax, ay, az, int(inter), int(parts[0]))
+        return out + (mag, newt) if scales else out

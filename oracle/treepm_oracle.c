@@ -654,14 +654,17 @@ int orc_tree_force(otree *t, double *ax, double *ay, double *az, int nthreads)
 
 /* Walk and list force for the groups gi = offset, offset+stride, ... only (a stratified
  * sample in key order), each group's list built privately.  Forces of sampled particles are
- * written (input order); others are untouched.  Returns the number of pair interactions
- * (sum over sampled groups of count * list length), or -1. */
+ * written (input order); others are untouched.  If mag and newt are non-NULL they receive,
+ * for the sampled particles, sum_j |f_ij| and the same sum without g (see
+ * orc_tree_force_mag).  Returns the number of pair interactions (sum over sampled groups of
+ * count * list length), or -1. */
 int64_t orc_tree_walk_force_sample(otree *t, int64_t stride, int64_t offset, double *ax,
                                    double *ay, double *az, int nthreads,
-                                   int64_t *particles_out)
+                                   int64_t *particles_out, double *mag, double *newt)
 {
     if (!t || stride < 1 || offset < 0) return -1;
     double rc2 = t->r_cut * t->r_cut, th2 = t->theta * t->theta;
+    double eta = 0.5 * t->r_cut, eps2 = t->eps * t->eps;
     int64_t inter = 0, parts = 0;
     int fail = 0;
 #ifdef _OPENMP
@@ -676,6 +679,21 @@ int64_t orc_tree_walk_force_sample(otree *t, int64_t stride, int64_t offset, dou
             group_force(t, gi, l.e, l.c, l.n, ax, ay, az);
             inter += l.n * t->groups[gi].count;
             parts += t->groups[gi].count;
+            if (mag && newt) {
+                const ogroup *g = &t->groups[gi];
+                for (int64_t k = g->first; k < g->first + g->count; ++k) {
+                    double s = 0.0, sn = 0.0;
+                    for (int64_t q = 0; q < l.n; ++q) {
+                        double p[3], mj;
+                        entry_source(t, l.e[q], l.c[q], p, &mj);
+                        double d[3] = {wrap(p[0] - t->px[k], t->L), wrap(p[1] - t->py[k], t->L),
+                                       wrap(p[2] - t->pz[k], t->L)};
+                        pair_mag(d, mj, eta, eps2, &s, &sn);
+                    }
+                    mag[t->idx[k]] = s;
+                    newt[t->idx[k]] = sn;
+                }
+            }
         }
         free(l.e);
         free(l.c);

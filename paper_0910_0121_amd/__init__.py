@@ -24,6 +24,7 @@ from ._native import (  # noqa: F401
     treepm_force_short,
     treepm_get_stats,
     treepm_last_error,
+    treepm_pairwise_f32,
     treepm_params,
     treepm_set_params,
     treepm_set_timing,

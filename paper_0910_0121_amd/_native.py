@@ -64,6 +64,7 @@ _SIGS = {
     "treepm_export_groups": (_i, [_p, _i64, _p, _p, _p, _p, _p, _p]),
     "treepm_export_lists": (_i, [_p, _i64, _i64, _p, _p, _p]),
     "treepm_last_error": (C.c_char_p, [_p]),
+    "treepm_pairwise_f32": (_i, [C.POINTER(treepm_params), _i, _i64, _p, _i64, _p, _p, _p, _p]),
 }
 
 
@@ -238,3 +239,16 @@ def treepm_export_lists(ctx):
     _check(lib().treepm_export_lists(ctx, st.n_groups + 1, max(ne, 1), off.ctypes.data,
                                      isc.ctypes.data, val.ctypes.data), ctx)
     return off, isc[:ne], val[:ne]
+
+
+def treepm_pairwise_f32(params: treepm_params, xi, xj, mj, xg, device: int = 0):
+    """Per-pair FP32 accelerations, shape (n_i, n_j, 3)."""
+    xi = np.ascontiguousarray(xi, dtype=np.float64).reshape(-1, 3)
+    xj = np.ascontiguousarray(xj, dtype=np.float64).reshape(-1, 3)
+    mj = np.ascontiguousarray(mj, dtype=np.float64).reshape(-1)
+    xg = np.ascontiguousarray(xg, dtype=np.float64).reshape(3)
+    out = np.zeros((xi.shape[0], xj.shape[0], 3))
+    _check(lib().treepm_pairwise_f32(C.byref(params), device, xi.shape[0], xi.ctypes.data,
+                                     xj.shape[0], xj.ctypes.data, mj.ctypes.data, xg.ctypes.data,
+                                     out.ctypes.data))
+    return out

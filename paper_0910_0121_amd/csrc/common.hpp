@@ -127,6 +127,10 @@ void launch_force_f32(NodeArrays nd, GroupArrays gr, const uint32_t *lists, uint
                       const double *pz, const double *pm, const uint32_t *pidx,
                       ForceParams fp, void *ax, void *ay, void *az, int out_prec,
                       hipStream_t s);
+// FP32 pair routine on explicit positions, pair by pair (xg: host, 3 values).
+void launch_pairwise_f32(int64_t n_i, const double *xi, int64_t n_j, const double *xj,
+                         const double *mj, const double *xg, double eta, double eps,
+                         double *out, hipStream_t s);
 // sum over groups of count * kept (pairs the FP32 kernel evaluated) into *out (device).
 void launch_kept_stats(GroupArrays gr, uint32_t n_groups, const uint32_t *kept,
                        unsigned long long *out, hipStream_t s);

@@ -315,6 +315,34 @@ __global__ __launch_bounds__(256) void k_kept_stats(GroupArrays gr, uint32_t n_g
     if (threadIdx.x == 0) atomicAdd(out, sm[0] + sm[1] + sm[2] + sm[3]);
 }
 
+// Pair by pair: out[(i * n_j + j) * 3 + a] = acceleration at x_i from (x_j, m_j) with the
+// FP32 pair routine of the force kernel (same relative coordinates, units and rounding),
+// without the cull and without periodic images.
+__global__ __launch_bounds__(256) void k_pairwise_f32(int64_t n_i, const double *__restrict__ xi,
+                                                      int64_t n_j, const double *__restrict__ xj,
+                                                      const double *__restrict__ mj, double xg0,
+                                                      double xg1, double xg2, double inv_eta,
+                                                      float eps2, double scale,
+                                                      double *__restrict__ out)
+{
+    const int64_t total = n_i * n_j;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = q / n_j, j = q % n_j;
+        const float x = (float)((xi[3 * i + 0] - xg0) * inv_eta);
+        const float y = (float)((xi[3 * i + 1] - xg1) * inv_eta);
+        const float z = (float)((xi[3 * i + 2] - xg2) * inv_eta);
+        const float4 src = make_float4((float)((xj[3 * j + 0] - xg0) * inv_eta),
+                                       (float)((xj[3 * j + 1] - xg1) * inv_eta),
+                                       (float)((xj[3 * j + 2] - xg2) * inv_eta), (float)mj[j]);
+        float tx = 0.f, ty = 0.f, tz = 0.f;
+        pair_f32(src, x, y, z, eps2, tx, ty, tz);
+        out[3 * q + 0] = (double)tx * scale;
+        out[3 * q + 1] = (double)ty * scale;
+        out[3 * q + 2] = (double)tz * scale;
+    }
+}
+
 constexpr int kClasses = 8;
 
 // Blocking class of a group: K - 1 with K = ceil(count / 64), capped at 8.  Each class list
@@ -451,6 +479,18 @@ void launch_force_f32(NodeArrays nd, GroupArrays gr, const uint32_t *lists, uint
     TPM_LAUNCH(2)
     TPM_LAUNCH(1)
 #undef TPM_LAUNCH
+}
+
+void launch_pairwise_f32(int64_t n_i, const double *xi, int64_t n_j, const double *xj,
+                         const double *mj, const double *xg, double eta, double eps,
+                         double *out, hipStream_t s)
+{
+    const double inv_eta = 1.0 / eta;
+    const int64_t total = n_i * n_j;
+    int64_t b = (total + 255) / 256;
+    k_pairwise_f32<<<(unsigned)(b < 65536 ? (b > 0 ? b : 1) : 65536), 256, 0, s>>>(
+        n_i, xi, n_j, xj, mj, xg[0], xg[1], xg[2], inv_eta, (float)(eps * eps * inv_eta * inv_eta),
+        inv_eta * inv_eta, out);
 }
 
 void launch_kept_stats(GroupArrays gr, uint32_t n_groups, const uint32_t *kept,

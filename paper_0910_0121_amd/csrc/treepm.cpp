@@ -728,6 +728,34 @@ TREEPM_API int treepm_export_lists(treepm_ctx *c, int64_t group_cap, int64_t ent
     return TREEPM_OK;
 }
 
+TREEPM_API int treepm_pairwise_f32(const treepm_params *params, int device, int64_t n_i,
+                                   const double *xi, int64_t n_j, const double *xj,
+                                   const double *mj, const double *xg, double *out)
+{
+    int rc = check_params(nullptr, params);
+    if (rc) return rc;
+    if (n_i < 1 || n_j < 1 || n_i * n_j > (int64_t)1 << 28 || !xi || !xj || !mj || !xg || !out)
+        return TREEPM_ERR_ARG;
+    if (hipSetDevice(device) != hipSuccess) return TREEPM_ERR_DEVICE;
+    size_t bi = (size_t)n_i * 3 * 8, bj = (size_t)n_j * 3 * 8, bm = (size_t)n_j * 8,
+           bo = (size_t)n_i * n_j * 3 * 8;
+    char *d = nullptr;
+    if (hipMalloc(&d, bi + bj + bm + bo) != hipSuccess) return TREEPM_ERR_OOM;
+    double *dxi = (double *)d, *dxj = (double *)(d + bi), *dmj = (double *)(d + bi + bj),
+           *dout = (double *)(d + bi + bj + bm);
+    hipError_t e = hipMemcpy(dxi, xi, bi, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(dxj, xj, bj, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(dmj, mj, bm, hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
+        launch_pairwise_f32(n_i, dxi, n_j, dxj, dmj, xg, 0.5 * params->r_cut, params->eps, dout,
+                            nullptr);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpy(out, dout, bo, hipMemcpyDeviceToHost);
+    hipFree(d);
+    return e == hipSuccess ? TREEPM_OK : TREEPM_ERR_DEVICE;
+}
+
 TREEPM_API const char *treepm_last_error(const treepm_ctx *c)
 {
     return c ? c->err.c_str() : "NULL context";

@@ -1,0 +1,90 @@
+"""Parity at the full workload sizes, in the launch configuration the benchmark times.
+
+The 128^3 clustered box (200 NFW halos) and the 256^3 clustered box (2000 halos, the
+benchmark workload) are built, walked and forced on the GPU with n_crit = 256, theta = 0.5.
+The oracle cannot redo the whole box in seconds, so it builds the full tree and computes the
+walk and FP64 list force of a stratified sample of groups (every k-th group in key order);
+the GPU's forces on those groups' particles are checked against it:
+
+  * FP64 path: |a_gpu - a_oracle| <= 1e-13 (sum_j |f_ij| + sum_j N_ij) per particle and
+    component (see test_gpu_parity for the scale), which also fails if a single list entry
+    with a nonzero force were missing or extra;
+  * FP32 path: RMS relative error <= 1e-6 over the sampled particles, and no particle above
+    2e-4 relative (rounding of group-relative positions of very close pairs).
+The 128^3 box also checks the total interaction count against the oracle's full walk.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import boxgen
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+N_CRIT = 256
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def tp():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_0910_0121_amd as t
+    t.lib()
+    return t
+
+
+def _gpu_forces(tp, spec, dev, precision):
+    p = tp.treepm_params(spec.L, spec.mesh, spec.r_cut, spec.eps, spec.theta, spec.n_leaf,
+                         N_CRIT, precision)
+    ctx = tp.treepm_create(p, 0)
+    try:
+        tp.treepm_build(ctx, *dev)
+        st = tp.treepm_walk(ctx)
+        acc = [torch.zeros(spec.n, dtype=torch.float64, device="cuda") for _ in range(3)]
+        tp.treepm_force_short(ctx, *acc)
+        torch.cuda.synchronize()
+        return np.stack([a.cpu().numpy() for a in acc]), st
+    finally:
+        tp.treepm_destroy(ctx)
+
+
+@pytest.mark.parametrize("name,stride", [("nfw128", 40), ("nfw256", 400)])
+def test_full_size_sampled_parity(tp, orc, name, stride):
+    spec, arrays = boxgen.config_box(name)
+    _say(f"{name}: N={spec.n}, n_crit={N_CRIT}, theta={spec.theta}, oracle stride {stride}")
+    dev = [torch.from_numpy(a).cuda() for a in arrays]
+    a64, st64 = _gpu_forces(tp, spec, dev, tp.TREEPM_FP64)
+    a32, st32 = _gpu_forces(tp, spec, dev, tp.TREEPM_FP32)
+    assert st64.interactions == st32.interactions
+    x, y, z, m = arrays
+    T = orc.Tree(x, y, z, m, spec.L, spec.r_cut, spec.eps, spec.theta, spec.n_leaf, N_CRIT)
+    assert T.n_groups == st64.n_groups and T.n_nodes == st64.n_nodes
+    ax, ay, az, inter, parts, mag, newt = T.walk_force_sample(stride, 0, 16, scales=True)
+    s = ~np.isnan(ax)
+    assert s.sum() == parts > 1000
+    ref = np.stack([ax[s], ay[s], az[s]])
+    scale = (mag + newt)[s]
+    err64 = np.abs(a64[:, s] - ref)
+    _say(f"  sampled {parts} particles, {inter} interactions; fp64 max |da|/scale "
+         f"{np.max(err64 / scale):.2e}")
+    assert np.all(err64 <= 1e-13 * scale[None, :])
+    d = np.linalg.norm(a32[:, s] - ref, axis=0)
+    nr = np.linalg.norm(ref, axis=0)
+    nz = nr > 0
+    rel = d[nz] / nr[nz]
+    rms = float(np.sqrt(np.mean(rel ** 2)))
+    _say(f"  fp32 rms rel {rms:.3e} max rel {rel.max():.3e} p99 {np.quantile(rel, 0.99):.3e}")
+    assert rms <= 1e-6
+    assert rel.max() <= 2e-4
+    assert np.all(d[~nz] == 0.0)
+    if name == "nfw128":
+        assert T.interactions() == st64.interactions
+    T.close()
