@@ -97,6 +97,7 @@ typedef struct {
                                list entries whose source lies at least r_cut from the
                                group's bounding box (they add exactly zero); the FP64
                                kernel evaluates every pair (= interactions)               */
+    double latency_ms;      /* ensemble results only: completion minus submission (ms)    */
 } treepm_stats;
 
 /* Create a context for one box on HIP device `device`.  Validates *params (ERR_ARG).  The
@@ -168,6 +169,40 @@ int treepm_export_lists(treepm_ctx *ctx, int64_t group_cap, int64_t entry_cap, i
 int treepm_pairwise_f32(const treepm_params *params, int device, int64_t n_i, const double *xi,
                         int64_t n_j, const double *xj, const double *mj, const double *xg,
                         double *out);
+
+/* ------------------------------------------------------------ ensemble serving */
+
+/* Create a server for force evaluations on many independent boxes on device `device`.
+ * hbm_budget: device bytes the server may keep allocated for resident boxes (particles,
+ * tree, lists; > 0).  max_inflight: requests run at once (1..16), each on its own worker
+ * thread and HIP stream.  A box (identified by the caller's box_id) keeps its device state
+ * between requests until it is evicted, least recently used first, to admit another box. */
+int treepm_ens_create(int device, size_t hbm_budget, int max_inflight, treepm_ens **out);
+
+/* Stop the server: queued requests are dropped, running ones finish, all device memory is
+ * released.  NULL is accepted. */
+int treepm_ens_destroy(treepm_ens *ens);
+
+/* Queue one FP32 force evaluation of box `box_id` with n particles (host arrays, copied
+ * before return; same requirements as treepm_build; params->precision must be FP32).
+ * Thread-safe.  *ticket identifies the request.  ERR_ARG for invalid input, ERR_OOM if the
+ * box alone cannot fit in the budget, ERR_QUEUE_FULL if 4096 requests are queued.  Range
+ * errors in the positions are reported by poll. */
+int treepm_ensemble_submit(treepm_ens *ens, uint64_t box_id, const treepm_params *params,
+                           int64_t n, const double *x, const double *y, const double *z,
+                           const double *m, uint64_t *ticket);
+
+/* Non-blocking: TREEPM_PENDING while the request is queued or running; TREEPM_OK when done,
+ * after copying the n accelerations of each axis (caller's original order, float) into
+ * ax, ay, az (host; NULL skips an axis) and the request's counts and latency into *stats
+ * (NULL allowed).  A finished ticket is released by this call (a second poll gives ERR_ARG);
+ * a failed request returns its error code once.  Thread-safe. */
+int treepm_ensemble_poll(treepm_ens *ens, uint64_t ticket, float *ax, float *ay, float *az,
+                         treepm_stats *stats);
+
+/* Snapshot of the server: queued and running requests, resident bytes and boxes. */
+int treepm_ens_info(treepm_ens *ens, int64_t *queued, int64_t *inflight,
+                    int64_t *resident_bytes, int64_t *resident_boxes);
 
 /* Text of the last error on this context ("" if none).  Valid until the next call. */
 const char *treepm_last_error(const treepm_ctx *ctx);

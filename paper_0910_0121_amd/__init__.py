@@ -11,10 +11,17 @@ from ._native import (  # noqa: F401
     TREEPM_FP32,
     TREEPM_FP64,
     TREEPM_HOST,
+    TREEPM_OK,
+    TREEPM_PENDING,
     TreePMError,
     lib,
     make_params,
     treepm_build,
+    treepm_ens_create,
+    treepm_ens_destroy,
+    treepm_ens_info,
+    treepm_ensemble_poll,
+    treepm_ensemble_submit,
     treepm_create,
     treepm_destroy,
     treepm_export_groups,

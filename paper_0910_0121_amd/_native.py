@@ -36,7 +36,8 @@ class treepm_stats(C.Structure):
     _fields_ = [("n", C.c_int64), ("n_nodes", C.c_int64), ("n_groups", C.c_int64),
                 ("n_cell_entries", C.c_int64), ("n_part_entries", C.c_int64),
                 ("interactions", C.c_int64), ("max_level", C.c_int32),
-                ("max_group", C.c_int32), ("t_ms", C.c_double * 4), ("evaluated", C.c_int64)]
+                ("max_group", C.c_int32), ("t_ms", C.c_double * 4), ("evaluated", C.c_int64),
+                ("latency_ms", C.c_double)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "t_ms"}
@@ -65,6 +66,12 @@ _SIGS = {
     "treepm_export_lists": (_i, [_p, _i64, _i64, _p, _p, _p]),
     "treepm_last_error": (C.c_char_p, [_p]),
     "treepm_pairwise_f32": (_i, [C.POINTER(treepm_params), _i, _i64, _p, _i64, _p, _p, _p, _p]),
+    "treepm_ens_create": (_i, [_i, C.c_size_t, _i, C.POINTER(_p)]),
+    "treepm_ens_destroy": (_i, [_p]),
+    "treepm_ensemble_submit": (_i, [_p, C.c_uint64, C.POINTER(treepm_params), _i64, _p, _p, _p,
+                                    _p, C.POINTER(C.c_uint64)]),
+    "treepm_ensemble_poll": (_i, [_p, C.c_uint64, _p, _p, _p, C.POINTER(treepm_stats)]),
+    "treepm_ens_info": (_i, [_p, _p, _p, _p, _p]),
 }
 
 
@@ -252,3 +259,45 @@ def treepm_pairwise_f32(params: treepm_params, xi, xj, mj, xg, device: int = 0):
                                      xj.shape[0], xj.ctypes.data, mj.ctypes.data, xg.ctypes.data,
                                      out.ctypes.data))
     return out
+
+
+# ----------------------------------------------------------------------------- ensemble
+
+def treepm_ens_create(device: int = 0, hbm_budget: int = 8 << 30, max_inflight: int = 4):
+    h = C.c_void_p()
+    _check(lib().treepm_ens_create(device, hbm_budget, max_inflight, C.byref(h)))
+    return h.value
+
+
+def treepm_ens_destroy(ens) -> None:
+    _check(lib().treepm_ens_destroy(ens))
+
+
+def treepm_ensemble_submit(ens, box_id: int, params: treepm_params, x, y, z, m) -> int:
+    arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (x, y, z, m)]
+    t = C.c_uint64()
+    _check(lib().treepm_ensemble_submit(ens, box_id, C.byref(params), arrs[0].size,
+                                        *(a.ctypes.data for a in arrs), C.byref(t)))
+    return t.value
+
+
+def treepm_ensemble_poll(ens, ticket: int, ax=None, ay=None, az=None):
+    """(TREEPM_OK, stats) when done (results copied into the given float32 arrays),
+    (TREEPM_PENDING, None) while queued or running; raises on an error."""
+    st = treepm_stats()
+    ptr = [None if a is None else a.ctypes.data for a in (ax, ay, az)]
+    for a in (ax, ay, az):
+        if a is not None and (a.dtype != np.float32 or not a.flags.c_contiguous):
+            raise TypeError("poll outputs must be contiguous float32 arrays")
+    rc = lib().treepm_ensemble_poll(ens, ticket, *ptr, C.byref(st))
+    if rc == TREEPM_PENDING:
+        return rc, None
+    _check(rc)
+    return rc, st
+
+
+def treepm_ens_info(ens):
+    v = [C.c_int64() for _ in range(4)]
+    _check(lib().treepm_ens_info(ens, *(C.byref(x) for x in v)))
+    return dict(queued=v[0].value, inflight=v[1].value, resident_bytes=v[2].value,
+                resident_boxes=v[3].value)

@@ -1,0 +1,357 @@
+// Ensemble server: force evaluations for many independent periodic boxes, admitted by an
+// HBM budget, run concurrently on one GPU.
+//
+// submit() copies a request's inputs and queues it.  max_inflight worker threads each own a
+// HIP stream and pinned staging buffers; a worker takes the first queued request that can
+// run now -- its box is not busy with another request, and the box is already resident or
+// its estimated footprint fits in the budget after evicting idle boxes, least recently used
+// first -- and runs build, walk and FP32 force for it on its stream.  A box's context (its
+// device buffers: particles, tree, lists) stays resident between requests until evicted.
+// Requests from different workers overlap on the device.  poll() is non-blocking.
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "common.hpp"
+#include "treepm.h"
+
+#define TREEPM_API extern "C" __attribute__((visibility("default")))
+
+// Device bytes a context currently holds (treepm.cpp).
+size_t treepm_internal_ctx_bytes(const treepm_ctx *c);
+
+namespace {
+
+double now_s()
+{
+    using namespace std::chrono;
+    return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+// Conservative device footprint of one box of n particles before its first build: particle
+// arrays and sort buffers (~100 B), tree (~60 B), groups, and interaction lists (~150 B).
+size_t estimate_bytes(int64_t n) { return (size_t)n * 320 + ((size_t)64 << 20); }
+
+struct Request {
+    uint64_t ticket = 0, box_id = 0;
+    treepm_params prm{};
+    int64_t n = 0;
+    std::vector<double> in; // x, y, z, m blocks
+    std::vector<float> out; // ax, ay, az blocks
+    int state = 0;          // 0 queued, 1 running, 2 done
+    int rc = 0;
+    treepm_stats stats{};
+    double t_submit = 0, t_start = 0, t_done = 0;
+};
+
+struct Box {
+    treepm_ctx *ctx = nullptr;
+    size_t bytes = 0;
+    bool busy = false;
+    uint64_t last_use = 0;
+    treepm_params prm{};
+};
+
+struct Worker {
+    hipStream_t stream = nullptr;
+    double *pin_in = nullptr;
+    float *pin_out = nullptr;
+    int64_t cap = 0;
+};
+
+} // namespace
+
+struct treepm_ens {
+    int device = 0;
+    size_t budget = 0;
+    int max_inflight = 1;
+    size_t queue_cap = 4096;
+    std::mutex mu;
+    std::condition_variable cv;
+    std::deque<std::shared_ptr<Request>> queue;
+    std::unordered_map<uint64_t, std::shared_ptr<Request>> tickets;
+    std::unordered_map<uint64_t, Box> boxes;
+    size_t resident = 0;
+    uint64_t clock = 0, next_ticket = 1;
+    int inflight = 0;
+    bool stop = false;
+    std::vector<std::thread> threads;
+    std::vector<Worker> workers;
+};
+
+namespace {
+
+size_t box_need(const treepm_ens *e, const Request &r)
+{
+    auto it = e->boxes.find(r.box_id);
+    size_t est = estimate_bytes(r.n);
+    if (it == e->boxes.end()) return est;
+    return it->second.bytes >= est ? 0 : est - it->second.bytes;
+}
+
+// With e->mu held: evict idle boxes (least recently used first) until `need` more bytes fit.
+// Returns false if they cannot be made to fit now.
+bool make_room(treepm_ens *e, size_t need, uint64_t keep_box)
+{
+    while (e->resident + need > e->budget) {
+        uint64_t victim = 0;
+        uint64_t oldest = UINT64_MAX;
+        bool found = false;
+        for (auto &kv : e->boxes)
+            if (!kv.second.busy && kv.first != keep_box && kv.second.last_use < oldest) {
+                oldest = kv.second.last_use;
+                victim = kv.first;
+                found = true;
+            }
+        if (!found) return false;
+        Box &b = e->boxes[victim];
+        treepm_destroy(b.ctx);
+        e->resident -= std::min(e->resident, b.bytes);
+        e->boxes.erase(victim);
+    }
+    return true;
+}
+
+// With e->mu held: the first queued request that can start now, or nullptr.
+std::shared_ptr<Request> pick(treepm_ens *e)
+{
+    for (auto it = e->queue.begin(); it != e->queue.end(); ++it) {
+        Request &r = **it;
+        auto bi = e->boxes.find(r.box_id);
+        if (bi != e->boxes.end() && bi->second.busy) continue;
+        size_t need = box_need(e, r);
+        if (!make_room(e, need, r.box_id)) continue;
+        Box &b = e->boxes[r.box_id];
+        b.busy = true;
+        b.last_use = ++e->clock;
+        e->resident += need;
+        b.bytes += need;
+        std::shared_ptr<Request> sel = *it;
+        e->queue.erase(it);
+        return sel;
+    }
+    return nullptr;
+}
+
+int run_request(treepm_ens *e, Worker &w, Request &r, Box &b)
+{
+    int rc;
+    if (!b.ctx) {
+        rc = treepm_create(&r.prm, e->device, &b.ctx);
+        if (rc) return rc;
+        b.prm = r.prm;
+    } else if (memcmp(&b.prm, &r.prm, sizeof r.prm) != 0) {
+        rc = treepm_set_params(b.ctx, &r.prm);
+        if (rc) return rc;
+        b.prm = r.prm;
+    }
+    if (r.n > w.cap) {
+        if (w.pin_in) hipHostFree(w.pin_in);
+        if (w.pin_out) hipHostFree(w.pin_out);
+        w.pin_in = nullptr;
+        w.pin_out = nullptr;
+        w.cap = 0;
+        if (hipHostMalloc((void **)&w.pin_in, (size_t)r.n * 4 * sizeof(double)) != hipSuccess ||
+            hipHostMalloc((void **)&w.pin_out, (size_t)r.n * 3 * sizeof(float)) != hipSuccess)
+            return TREEPM_ERR_OOM;
+        w.cap = r.n;
+    }
+    memcpy(w.pin_in, r.in.data(), (size_t)r.n * 4 * sizeof(double));
+    const double *x = w.pin_in, *y = x + r.n, *z = y + r.n, *m = z + r.n;
+    rc = treepm_build(b.ctx, r.n, x, y, z, m, TREEPM_HOST, w.stream);
+    if (rc) return rc;
+    rc = treepm_walk(b.ctx, w.stream, nullptr);
+    if (rc) return rc;
+    float *ax = w.pin_out, *ay = ax + r.n, *az = ay + r.n;
+    rc = treepm_force_short(b.ctx, ax, ay, az, TREEPM_FP32, TREEPM_HOST, w.stream);
+    if (rc) return rc;
+    rc = treepm_get_stats(b.ctx, &r.stats);
+    if (rc) return rc;
+    r.out.assign(w.pin_out, w.pin_out + (size_t)r.n * 3);
+    return TREEPM_OK;
+}
+
+void worker_main(treepm_ens *e, int wi)
+{
+    hipSetDevice(e->device);
+    Worker &w = e->workers[wi];
+    hipStreamCreateWithFlags(&w.stream, hipStreamNonBlocking);
+    for (;;) {
+        std::shared_ptr<Request> r;
+        {
+            std::unique_lock<std::mutex> lk(e->mu);
+            e->cv.wait(lk, [&] {
+                if (e->stop) return true;
+                r = pick(e);
+                return r != nullptr;
+            });
+            if (e->stop && !r) break;
+            r->state = 1;
+            r->t_start = now_s();
+            ++e->inflight;
+        }
+        Box local;
+        {
+            // ctx pointer and params; nobody else touches the entry while it is busy
+            std::lock_guard<std::mutex> lk(e->mu);
+            local = e->boxes[r->box_id];
+        }
+        int rc = run_request(e, w, *r, local);
+        {
+            std::lock_guard<std::mutex> lk(e->mu);
+            Box &b = e->boxes[r->box_id];
+            b.ctx = local.ctx;
+            b.prm = local.prm;
+            if (b.ctx) {
+                size_t actual = treepm_internal_ctx_bytes(b.ctx);
+                if (actual > b.bytes) {
+                    e->resident += actual - b.bytes;
+                    b.bytes = actual;
+                }
+            }
+            if (rc) { // a failed box is dropped so it cannot poison later requests
+                if (b.ctx) treepm_destroy(b.ctx);
+                e->resident -= std::min(e->resident, b.bytes);
+                e->boxes.erase(r->box_id);
+            } else {
+                b.busy = false;
+                b.last_use = ++e->clock;
+            }
+            r->rc = rc;
+            r->t_done = now_s();
+            r->state = 2;
+            r->in.clear();
+            r->in.shrink_to_fit();
+            --e->inflight;
+        }
+        e->cv.notify_all();
+    }
+    if (w.stream) hipStreamDestroy(w.stream);
+    if (w.pin_in) hipHostFree(w.pin_in);
+    if (w.pin_out) hipHostFree(w.pin_out);
+}
+
+} // namespace
+
+TREEPM_API int treepm_ens_create(int device, size_t hbm_budget, int max_inflight,
+                                 treepm_ens **out)
+{
+    if (!out) return TREEPM_ERR_ARG;
+    *out = nullptr;
+    if (max_inflight < 1 || max_inflight > 16 || hbm_budget == 0) return TREEPM_ERR_ARG;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
+        return TREEPM_ERR_DEVICE;
+    treepm_ens *e = new (std::nothrow) treepm_ens();
+    if (!e) return TREEPM_ERR_OOM;
+    e->device = device;
+    e->budget = hbm_budget;
+    e->max_inflight = max_inflight;
+    e->workers.resize(max_inflight);
+    for (int i = 0; i < max_inflight; ++i) e->threads.emplace_back(worker_main, e, i);
+    *out = e;
+    return TREEPM_OK;
+}
+
+TREEPM_API int treepm_ens_destroy(treepm_ens *e)
+{
+    if (!e) return TREEPM_OK;
+    {
+        std::lock_guard<std::mutex> lk(e->mu);
+        e->stop = true;
+        e->queue.clear();
+    }
+    e->cv.notify_all();
+    for (auto &t : e->threads) t.join();
+    for (auto &kv : e->boxes)
+        if (kv.second.ctx) treepm_destroy(kv.second.ctx);
+    delete e;
+    return TREEPM_OK;
+}
+
+TREEPM_API int treepm_ensemble_submit(treepm_ens *e, uint64_t box_id, const treepm_params *p,
+                                      int64_t n, const double *x, const double *y,
+                                      const double *z, const double *m, uint64_t *ticket)
+{
+    if (!e || !p || !ticket || !x || !y || !z || !m) return TREEPM_ERR_ARG;
+    if (n < 1 || n > 0x7fffffffLL) return TREEPM_ERR_ARG;
+    if (p->precision != TREEPM_FP32) return TREEPM_ERR_ARG;
+    // parameter validation without a device: create fails on a bad parameter block first
+    {
+        treepm_ctx *probe = nullptr;
+        int rc = treepm_create(p, e->device, &probe);
+        if (rc) return rc;
+        treepm_destroy(probe);
+    }
+    if (estimate_bytes(n) > e->budget) return TREEPM_ERR_OOM;
+    auto r = std::make_shared<Request>();
+    r->box_id = box_id;
+    r->prm = *p;
+    r->n = n;
+    try {
+        r->in.resize((size_t)n * 4);
+    } catch (...) {
+        return TREEPM_ERR_OOM;
+    }
+    memcpy(r->in.data(), x, (size_t)n * sizeof(double));
+    memcpy(r->in.data() + n, y, (size_t)n * sizeof(double));
+    memcpy(r->in.data() + 2 * n, z, (size_t)n * sizeof(double));
+    memcpy(r->in.data() + 3 * n, m, (size_t)n * sizeof(double));
+    r->t_submit = now_s();
+    {
+        std::lock_guard<std::mutex> lk(e->mu);
+        if (e->stop) return TREEPM_ERR_STATE;
+        if (e->queue.size() >= e->queue_cap) return TREEPM_ERR_QUEUE_FULL;
+        r->ticket = e->next_ticket++;
+        e->queue.push_back(r);
+        e->tickets[r->ticket] = r;
+        *ticket = r->ticket;
+    }
+    e->cv.notify_all();
+    return TREEPM_OK;
+}
+
+TREEPM_API int treepm_ensemble_poll(treepm_ens *e, uint64_t ticket, float *ax, float *ay,
+                                    float *az, treepm_stats *stats)
+{
+    if (!e) return TREEPM_ERR_ARG;
+    std::shared_ptr<Request> r;
+    {
+        std::lock_guard<std::mutex> lk(e->mu);
+        auto it = e->tickets.find(ticket);
+        if (it == e->tickets.end()) return TREEPM_ERR_ARG;
+        if (it->second->state != 2) return TREEPM_PENDING;
+        r = it->second;
+        e->tickets.erase(it);
+    }
+    if (r->rc) return r->rc;
+    if (ax) memcpy(ax, r->out.data(), (size_t)r->n * sizeof(float));
+    if (ay) memcpy(ay, r->out.data() + r->n, (size_t)r->n * sizeof(float));
+    if (az) memcpy(az, r->out.data() + 2 * r->n, (size_t)r->n * sizeof(float));
+    if (stats) {
+        *stats = r->stats;
+        stats->latency_ms = (r->t_done - r->t_submit) * 1e3;
+    }
+    return TREEPM_OK;
+}
+
+TREEPM_API int treepm_ens_info(treepm_ens *e, int64_t *queued, int64_t *inflight,
+                               int64_t *resident_bytes, int64_t *resident_boxes)
+{
+    if (!e) return TREEPM_ERR_ARG;
+    std::lock_guard<std::mutex> lk(e->mu);
+    if (queued) *queued = (int64_t)e->queue.size();
+    if (inflight) *inflight = e->inflight;
+    if (resident_bytes) *resident_bytes = (int64_t)e->resident;
+    if (resident_boxes) *resident_boxes = (int64_t)e->boxes.size();
+    return TREEPM_OK;
+}

@@ -421,6 +421,26 @@ void fill_stats(treepm_ctx *c, treepm_stats *st)
 
 } // namespace
 
+// Device bytes the context holds (used by the ensemble server's HBM accounting).
+size_t treepm_internal_ctx_bytes(const treepm_ctx *c)
+{
+    const Buf *all[] = {&c->in[0], &c->in[1], &c->in[2], &c->in[3], &c->key, &c->key_alt,
+                        &c->idx, &c->idx_alt, &c->pos[0], &c->pos[1], &c->pos[2], &c->pos[3],
+                        &c->hist, &c->scan32, &c->flags, &c->levcnt, &c->gstart, &c->gflag,
+                        &c->rec, &c->n_code, &c->n_first, &c->n_count, &c->n_cf, &c->n_parent,
+                        &c->n_nch, &c->n_level, &c->n_mass, &c->n_com[0], &c->n_com[1],
+                        &c->n_com[2], &c->n_cn[0], &c->n_cn[1], &c->n_cn[2], &c->n_walk,
+                        &c->g_node, &c->g_first, &c->g_count, &c->g_cg[0], &c->g_cg[1],
+                        &c->g_cg[2], &c->g_hg[0], &c->g_hg[1], &c->g_hg[2], &c->g_xg[0],
+                        &c->g_xg[1], &c->g_xg[2], &c->g_lo[0], &c->g_lo[1], &c->g_lo[2],
+                        &c->g_hi[0], &c->g_hi[1], &c->g_hi[2], &c->g_misc, &c->off, &c->scan64,
+                        &c->entries, &c->lside, &c->wstats, &c->overflow, &c->gcells, &c->cls,
+                        &c->kept, &c->kept_sum, &c->out[0], &c->out[1], &c->out[2]};
+    size_t t = 0;
+    for (const Buf *b : all) t += b->bytes;
+    return t;
+}
+
 TREEPM_API const char *treepm_version(void) { return "treepm-mi355x 0.1"; }
 
 TREEPM_API int treepm_create(const treepm_params *params, int device, treepm_ctx **out)
