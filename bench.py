@@ -45,6 +45,12 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--cpu-stride", type=int, default=0,
                     help="oracle sample: every k-th group (0 = choose for ~15 s of work)")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-boxes", type=int, default=64)
+    ap.add_argument("--serving-requests-per-box", type=int, default=10)
+    ap.add_argument("--serving-inflight", type=int, default=4)
+    ap.add_argument("--serving-budget-frac", type=float, default=0.25)
+    ap.add_argument("--serving-only", action="store_true")
     return ap.parse_args()
 
 
@@ -86,10 +92,11 @@ def cpu_baseline(spec, arrays, n_crit, stride_arg):
     stride = stride_arg
     if stride <= 0:
         # pilot on a sparse sample, then size the real sample for ~15 s of CPU work
+        pilot = max(1, G // (threads * 16))
         t1 = time.perf_counter()
-        _, _, _, inter_p, _ = T.walk_force_sample(4096, 0, threads)
+        _, _, _, inter_p, _ = T.walk_force_sample(pilot, 0, threads)
         tp = time.perf_counter() - t1
-        groups_p = len(range(0, G, 4096))
+        groups_p = len(range(0, G, pilot))
         per_group = tp / max(1, groups_p)
         want = max(1, int(15.0 / max(per_group, 1e-9)))
         stride = max(1, G // want)
@@ -112,6 +119,112 @@ def cpu_baseline(spec, arrays, n_crit, stride_arg):
     }
 
 
+def serving_bench(tp, n_boxes, per_box, inflight, budget_frac=0.25):
+    """The ensemble serving workload: n_boxes independent clustered boxes with N log-uniform
+    in [32^3, 256^3] (seed 999; box i uses seed 1000 + i and max(1, round(N/1e4)) halos),
+    mesh = N^(1/3), r_cut = 3/mesh, eps = mesh/20, theta = 0.5, FP32.  First the closed-loop
+    capacity (2 * inflight requests kept outstanding); then n_boxes * per_box requests in
+    seeded order arriving as a Poisson process at 0.8 x that capacity, with the HBM budget
+    set to 25% of the ensemble's total resident footprint.  Reports p50/p99 latency
+    (completion minus submission) and aggregate particles/s."""
+    import concurrent.futures as cf
+    import threading
+
+    import numpy as np
+
+    import boxgen
+
+    ns, halos = boxgen.serving_sizes(n_boxes, 999)
+    log(f"[serving] generating {n_boxes} boxes, {int(ns.sum())} particles ...")
+    t0 = time.time()
+
+    def gen(i):
+        return boxgen.nfw_box(int(ns[i]), int(halos[i]), 1000 + i)
+
+    with cf.ThreadPoolExecutor(max_workers=8) as ex:
+        boxes = list(ex.map(gen, range(n_boxes)))
+    log(f"[serving] generated in {time.time() - t0:.1f} s")
+    params = []
+    for i in range(n_boxes):
+        mesh_n = round(float(ns[i]) ** (1.0 / 3.0))
+        mesh = 1.0 / mesh_n
+        params.append(tp.treepm_params(1.0, mesh, 3.0 * mesh, mesh / 20.0, 0.5, 10, 256,
+                                       tp.TREEPM_FP32))
+    footprint = int(sum(int(n) * 320 + (64 << 20) for n in ns))
+    budget = max(int(footprint * budget_frac), int(ns.max()) * 320 + (64 << 20))
+    ens = tp.treepm_ens_create(0, budget, inflight)
+    rng = boxgen.SplitMix64(998)
+    order = np.argsort(rng.next_u64(n_boxes * per_box), kind="stable") % n_boxes
+
+    def drain(pending, done, out_lat):
+        for t in list(pending):
+            rc, st = tp.treepm_ensemble_poll(ens, t)
+            if rc == tp.TREEPM_OK:
+                out_lat.append(st.latency_ms)
+                done.append(pending.pop(t))
+
+    try:
+        # closed loop: keep 2 * inflight requests outstanding
+        n_closed = min(len(order), max(4 * inflight, n_boxes))
+        pending, done, lat = {}, [], []
+        t0 = time.perf_counter()
+        k = 0
+        while len(done) < n_closed:
+            while k < n_closed and len(pending) < 2 * inflight:
+                i = int(order[k]); k += 1
+                pending[tp.treepm_ensemble_submit(ens, i, params[i], *boxes[i])] = i
+            drain(pending, done, lat)
+            time.sleep(0.0005)
+        t_closed = time.perf_counter() - t0
+        cap = n_closed / t_closed
+        # open loop: Poisson arrivals at 0.8 x capacity
+        lam = 0.8 * cap
+        gaps = -np.log(1.0 - rng.uniform(len(order))) / lam
+        arrivals = np.cumsum(gaps)
+        pending, done, lat = {}, [], []
+        lock = threading.Lock()
+        t_start = time.perf_counter()
+
+        def submitter():
+            for j, i in enumerate(order):
+                wait = arrivals[j] - (time.perf_counter() - t_start)
+                if wait > 0:
+                    time.sleep(wait)
+                t = tp.treepm_ensemble_submit(ens, int(i), params[int(i)], *boxes[int(i)])
+                with lock:
+                    pending[t] = int(i)
+
+        th = threading.Thread(target=submitter)
+        th.start()
+        while th.is_alive() or pending:
+            with lock:
+                drain(pending, done, lat)
+            time.sleep(0.0005)
+        th.join()
+        makespan = time.perf_counter() - t_start
+        info = tp.treepm_ens_info(ens)
+    finally:
+        tp.treepm_ens_destroy(ens)
+    lat = np.array(lat)
+    parts = float(sum(int(ns[i]) for i in done))
+    return {
+        "boxes": n_boxes,
+        "requests": len(done),
+        "particles": int(ns.sum()),
+        "n_range": [int(ns.min()), int(ns.max())],
+        "hbm_budget_gib": budget / 2 ** 30,
+        "footprint_gib": footprint / 2 ** 30,
+        "max_inflight": inflight,
+        "closed_loop_requests_per_s": cap,
+        "arrival_rate_per_s": lam,
+        "latency_ms_p50": float(np.percentile(lat, 50)),
+        "latency_ms_p99": float(np.percentile(lat, 99)),
+        "latency_ms_max": float(lat.max()),
+        "particles_per_s": parts / makespan,
+        "resident_boxes_at_end": info["resident_boxes"],
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -124,6 +237,11 @@ def main():
     import boxgen
     import paper_0910_0121_amd as tp
 
+    if args.serving_only:
+        print(json.dumps(serving_bench(tp, args.serving_boxes, args.serving_requests_per_box,
+                                       args.serving_inflight, args.serving_budget_frac)),
+              flush=True)
+        return
     spec = boxgen.CONFIGS[args.workload]
     n_crit = args.n_crit
     log(f"[bench] generating {spec.name} (N={spec.n}) ...")
@@ -224,6 +342,10 @@ def main():
             "frac_fp64_peak": K_PP * inter / f64 / 1e12 / FP64_VECTOR_PEAK_TFLOPS,
             "force_speedup_fp32_over_fp64": f64 / t_force,
         }
+    if not args.no_serving:
+        log("[bench] ensemble serving")
+        result["ensemble"] = serving_bench(tp, args.serving_boxes, args.serving_requests_per_box,
+                                           args.serving_inflight, args.serving_budget_frac)
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline (bounded sample)")
         result["cpu_baseline"] = cpu_baseline(spec, arrays, n_crit, args.cpu_stride)

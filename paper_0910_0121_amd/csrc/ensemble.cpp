@@ -14,6 +14,8 @@
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <future>
+#include <map>
 #include <memory>
 #include <mutex>
 #include <new>
@@ -41,17 +43,75 @@ double now_s()
 // arrays and sort buffers (~100 B), tree (~60 B), groups, and interaction lists (~150 B).
 size_t estimate_bytes(int64_t n) { return (size_t)n * 320 + ((size_t)64 << 20); }
 
+// Pinned host blocks, reused across requests (sizes rounded up to a power of two), so a
+// request neither page-faults fresh memory nor needs a second staging copy.
+class PinnedPool {
+  public:
+    ~PinnedPool()
+    {
+        for (auto &kv : free_) hipHostFree(kv.second);
+    }
+    void *get(size_t bytes, size_t *cap)
+    {
+        size_t c = (size_t)1 << 20;
+        while (c < bytes) c <<= 1;
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            auto it = free_.find(c);
+            if (it != free_.end()) {
+                void *p = it->second;
+                free_.erase(it);
+                *cap = c;
+                return p;
+            }
+        }
+        void *p = nullptr;
+        if (hipHostMalloc(&p, c) != hipSuccess) return nullptr;
+        *cap = c;
+        return p;
+    }
+    void put(void *p, size_t cap)
+    {
+        if (!p) return;
+        std::lock_guard<std::mutex> lk(mu_);
+        free_.emplace(cap, p);
+    }
+
+  private:
+    std::mutex mu_;
+    std::multimap<size_t, void *> free_;
+};
+
 struct Request {
     uint64_t ticket = 0, box_id = 0;
     treepm_params prm{};
     int64_t n = 0;
-    std::vector<double> in; // x, y, z, m blocks
-    std::vector<float> out; // ax, ay, az blocks
-    int state = 0;          // 0 queued, 1 running, 2 done
+    double *in = nullptr; // pinned: x, y, z, m blocks
+    size_t in_cap = 0;
+    float *out = nullptr; // pinned: ax, ay, az blocks
+    size_t out_cap = 0;
+    int state = 0; // 0 queued, 1 running, 2 done
     int rc = 0;
     treepm_stats stats{};
     double t_submit = 0, t_start = 0, t_done = 0;
 };
+
+// Copy k arrays of n doubles/floats in parallel (large requests only).
+template <typename T>
+void copy_parallel(T *const *dst, const T *const *src, int k, int64_t n)
+{
+    if ((size_t)n * sizeof(T) < ((size_t)4 << 20)) {
+        for (int a = 0; a < k; ++a) memcpy(dst[a], src[a], (size_t)n * sizeof(T));
+        return;
+    }
+    std::vector<std::future<void>> fs;
+    for (int a = 1; a < k; ++a)
+        fs.push_back(std::async(std::launch::async, [=] {
+            memcpy(dst[a], src[a], (size_t)n * sizeof(T));
+        }));
+    memcpy(dst[0], src[0], (size_t)n * sizeof(T));
+    for (auto &f : fs) f.get();
+}
 
 struct Box {
     treepm_ctx *ctx = nullptr;
@@ -63,9 +123,6 @@ struct Box {
 
 struct Worker {
     hipStream_t stream = nullptr;
-    double *pin_in = nullptr;
-    float *pin_out = nullptr;
-    int64_t cap = 0;
 };
 
 } // namespace
@@ -86,6 +143,7 @@ struct treepm_ens {
     bool stop = false;
     std::vector<std::thread> threads;
     std::vector<Worker> workers;
+    PinnedPool pool;
 };
 
 namespace {
@@ -154,29 +212,23 @@ int run_request(treepm_ens *e, Worker &w, Request &r, Box &b)
         if (rc) return rc;
         b.prm = r.prm;
     }
-    if (r.n > w.cap) {
-        if (w.pin_in) hipHostFree(w.pin_in);
-        if (w.pin_out) hipHostFree(w.pin_out);
-        w.pin_in = nullptr;
-        w.pin_out = nullptr;
-        w.cap = 0;
-        if (hipHostMalloc((void **)&w.pin_in, (size_t)r.n * 4 * sizeof(double)) != hipSuccess ||
-            hipHostMalloc((void **)&w.pin_out, (size_t)r.n * 3 * sizeof(float)) != hipSuccess)
-            return TREEPM_ERR_OOM;
-        w.cap = r.n;
-    }
-    memcpy(w.pin_in, r.in.data(), (size_t)r.n * 4 * sizeof(double));
-    const double *x = w.pin_in, *y = x + r.n, *z = y + r.n, *m = z + r.n;
+    const double *x = r.in, *y = x + r.n, *z = y + r.n, *m = z + r.n;
     rc = treepm_build(b.ctx, r.n, x, y, z, m, TREEPM_HOST, w.stream);
+    // no copy from the pinned inputs may still be in flight when the block is reused
+    hipError_t se = hipStreamSynchronize(w.stream);
+    if (!rc && se != hipSuccess) rc = TREEPM_ERR_DEVICE;
+    e->pool.put(r.in, r.in_cap);
+    r.in = nullptr;
     if (rc) return rc;
     rc = treepm_walk(b.ctx, w.stream, nullptr);
     if (rc) return rc;
-    float *ax = w.pin_out, *ay = ax + r.n, *az = ay + r.n;
+    r.out = (float *)e->pool.get((size_t)r.n * 3 * sizeof(float), &r.out_cap);
+    if (!r.out) return TREEPM_ERR_OOM;
+    float *ax = r.out, *ay = ax + r.n, *az = ay + r.n;
     rc = treepm_force_short(b.ctx, ax, ay, az, TREEPM_FP32, TREEPM_HOST, w.stream);
     if (rc) return rc;
     rc = treepm_get_stats(b.ctx, &r.stats);
     if (rc) return rc;
-    r.out.assign(w.pin_out, w.pin_out + (size_t)r.n * 3);
     return TREEPM_OK;
 }
 
@@ -229,15 +281,17 @@ void worker_main(treepm_ens *e, int wi)
             r->rc = rc;
             r->t_done = now_s();
             r->state = 2;
-            r->in.clear();
-            r->in.shrink_to_fit();
+            if (r->in) e->pool.put(r->in, r->in_cap);
+            r->in = nullptr;
+            if (rc && r->out) {
+                e->pool.put(r->out, r->out_cap);
+                r->out = nullptr;
+            }
             --e->inflight;
         }
         e->cv.notify_all();
     }
-    if (w.stream) hipStreamDestroy(w.stream);
-    if (w.pin_in) hipHostFree(w.pin_in);
-    if (w.pin_out) hipHostFree(w.pin_out);
+    // the stream outlives the thread: resident boxes still name it as their last stream
 }
 
 } // namespace
@@ -274,6 +328,13 @@ TREEPM_API int treepm_ens_destroy(treepm_ens *e)
     for (auto &t : e->threads) t.join();
     for (auto &kv : e->boxes)
         if (kv.second.ctx) treepm_destroy(kv.second.ctx);
+    for (auto &w : e->workers)
+        if (w.stream) (void)hipStreamDestroy(w.stream);
+    for (auto &kv : e->tickets) {
+        if (kv.second->in) e->pool.put(kv.second->in, kv.second->in_cap);
+        if (kv.second->out) e->pool.put(kv.second->out, kv.second->out_cap);
+    }
+    e->tickets.clear();
     delete e;
     return TREEPM_OK;
 }
@@ -294,19 +355,15 @@ TREEPM_API int treepm_ensemble_submit(treepm_ens *e, uint64_t box_id, const tree
     }
     if (estimate_bytes(n) > e->budget) return TREEPM_ERR_OOM;
     auto r = std::make_shared<Request>();
+    r->t_submit = now_s();
     r->box_id = box_id;
     r->prm = *p;
     r->n = n;
-    try {
-        r->in.resize((size_t)n * 4);
-    } catch (...) {
-        return TREEPM_ERR_OOM;
-    }
-    memcpy(r->in.data(), x, (size_t)n * sizeof(double));
-    memcpy(r->in.data() + n, y, (size_t)n * sizeof(double));
-    memcpy(r->in.data() + 2 * n, z, (size_t)n * sizeof(double));
-    memcpy(r->in.data() + 3 * n, m, (size_t)n * sizeof(double));
-    r->t_submit = now_s();
+    r->in = (double *)e->pool.get((size_t)n * 4 * sizeof(double), &r->in_cap);
+    if (!r->in) return TREEPM_ERR_OOM;
+    double *dst[4] = {r->in, r->in + n, r->in + 2 * n, r->in + 3 * n};
+    const double *src[4] = {x, y, z, m};
+    copy_parallel(dst, src, 4, n);
     {
         std::lock_guard<std::mutex> lk(e->mu);
         if (e->stop) return TREEPM_ERR_STATE;
@@ -334,9 +391,22 @@ TREEPM_API int treepm_ensemble_poll(treepm_ens *e, uint64_t ticket, float *ax, f
         e->tickets.erase(it);
     }
     if (r->rc) return r->rc;
-    if (ax) memcpy(ax, r->out.data(), (size_t)r->n * sizeof(float));
-    if (ay) memcpy(ay, r->out.data() + r->n, (size_t)r->n * sizeof(float));
-    if (az) memcpy(az, r->out.data() + 2 * r->n, (size_t)r->n * sizeof(float));
+    {
+        float *dst[3] = {ax, ay, az};
+        const float *src[3] = {r->out, r->out + r->n, r->out + 2 * r->n};
+        int k = 0;
+        float *d2[3];
+        const float *s2[3];
+        for (int a = 0; a < 3; ++a)
+            if (dst[a]) {
+                d2[k] = dst[a];
+                s2[k] = src[a];
+                ++k;
+            }
+        if (k) copy_parallel(d2, s2, k, r->n);
+    }
+    e->pool.put(r->out, r->out_cap);
+    r->out = nullptr;
     if (stats) {
         *stats = r->stats;
         stats->latency_ms = (r->t_done - r->t_submit) * 1e3;

@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -21,12 +22,6 @@ namespace {
 struct Buf {
     void *p = nullptr;
     size_t bytes = 0;
-    void release()
-    {
-        if (p) hipFree(p);
-        p = nullptr;
-        bytes = 0;
-    }
     template <typename T>
     T *as() const
     {
@@ -41,6 +36,12 @@ constexpr int kDefaultNCrit = 128;
 struct treepm_ctx {
     treepm_params prm{};
     int device = 0;
+    // Device memory comes from the stream-ordered allocator on a private stream: freeing a
+    // buffer waits (through `freed`) for the work of the current call's stream and never
+    // synchronises the device, so contexts on other streams are not stalled.
+    hipStream_t own = nullptr;
+    hipEvent_t freed = nullptr;
+    hipStream_t cur = nullptr;
     std::string err;
     int state = 0; // 0 empty, 1 built, 2 walked
     int64_t n = 0;
@@ -98,12 +99,38 @@ int hip_fail(treepm_ctx *c, hipError_t e, const char *what)
         if (e_ != hipSuccess) return hip_fail((ctx), e_, #call);                               \
     } while (0)
 
+// The context whose buffers reserve()/release() manage on this thread (set by each call).
+thread_local treepm_ctx *t_ctx = nullptr;
+
+void release(Buf &b)
+{
+    if (!b.p) return;
+    treepm_ctx *c = t_ctx;
+    if (c && c->own) {
+        // free once the current call's stream has finished with the buffer
+        (void)hipEventRecord(c->freed, c->cur);
+        (void)hipStreamWaitEvent(c->own, c->freed, 0);
+        (void)hipFreeAsync(b.p, c->own);
+    } else {
+        (void)hipFree(b.p);
+    }
+    b.p = nullptr;
+    b.bytes = 0;
+}
+
 hipError_t reserve(Buf &b, size_t bytes)
 {
     if (bytes <= b.bytes && b.p) return hipSuccess;
-    b.release();
+    release(b);
     size_t want = bytes + bytes / 8 + 256;
-    hipError_t e = hipMalloc(&b.p, want);
+    treepm_ctx *c = t_ctx;
+    hipError_t e;
+    if (c && c->own) {
+        e = hipMallocAsync(&b.p, want, c->own);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->own); // ready for any stream
+    } else {
+        e = hipMalloc(&b.p, want);
+    }
     if (e != hipSuccess) {
         b.p = nullptr;
         b.bytes = 0;
@@ -113,6 +140,17 @@ hipError_t reserve(Buf &b, size_t bytes)
     b.bytes = want;
     return hipSuccess;
 }
+
+// Enter an API call on context c with stream s: allocation bookkeeping follows s.
+struct CallScope {
+    treepm_ctx *prev;
+    CallScope(treepm_ctx *c, hipStream_t s) : prev(t_ctx)
+    {
+        t_ctx = c;
+        if (c) c->cur = s;
+    }
+    ~CallScope() { t_ctx = prev; }
+};
 
 int check_params(treepm_ctx *c, const treepm_params *p)
 {
@@ -190,10 +228,8 @@ int ensure_nodes(treepm_ctx *c, size_t need, hipStream_t s)
             e = hipMemcpyAsync(nb.p, f.b->p, (size_t)c->n_nodes * f.elem,
                                hipMemcpyDeviceToDevice, s);
             if (e != hipSuccess) return hip_fail(c, e, "node copy");
-            e = hipStreamSynchronize(s);
-            if (e != hipSuccess) return hip_fail(c, e, "node copy sync");
         }
-        f.b->release();
+        release(*f.b); // stream-ordered after the copy
         *f.b = nb;
     }
     c->node_cap = cap;
@@ -421,6 +457,23 @@ void fill_stats(treepm_ctx *c, treepm_stats *st)
 
 } // namespace
 
+// The device's default memory pool keeps freed blocks for reuse instead of returning them to
+// the driver at each synchronisation.
+void retain_pool(int device)
+{
+    static std::mutex mu;
+    static bool done[64] = {};
+    std::lock_guard<std::mutex> lk(mu);
+    if (device < 0 || device >= 64 || done[device]) return;
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess) {
+        uint64_t thr = UINT64_MAX;
+        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+    }
+    (void)hipGetLastError();
+    done[device] = true;
+}
+
 // Device bytes the context holds (used by the ensemble server's HBM accounting).
 size_t treepm_internal_ctx_bytes(const treepm_ctx *c)
 {
@@ -456,6 +509,19 @@ TREEPM_API int treepm_create(const treepm_params *params, int device, treepm_ctx
     if (!c) return TREEPM_ERR_OOM;
     c->prm = *params;
     c->device = device;
+    if (hipSetDevice(device) != hipSuccess) {
+        delete c;
+        return TREEPM_ERR_DEVICE;
+    }
+    retain_pool(device);
+    if (hipStreamCreateWithFlags(&c->own, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->freed, hipEventDisableTiming) != hipSuccess) {
+        // no private stream: fall back to plain hipMalloc / hipFree
+        if (c->own) (void)hipStreamDestroy(c->own);
+        c->own = nullptr;
+        c->freed = nullptr;
+        (void)hipGetLastError();
+    }
     *out = c;
     return TREEPM_OK;
 }
@@ -477,9 +543,17 @@ TREEPM_API int treepm_destroy(treepm_ctx *c)
                   &c->g_hi[1], &c->g_hi[2], &c->g_misc, &c->off, &c->scan64, &c->entries,
                   &c->lside, &c->wstats, &c->overflow, &c->rec, &c->kept, &c->kept_sum, &c->gcells, &c->cls, &c->out[0],
                   &c->out[1], &c->out[2]};
-    for (Buf *b : all) b->release();
+    {
+        CallScope scope(c, c->last);
+        for (Buf *b : all) release(*b);
+    }
+    if (c->own) {
+        (void)hipStreamSynchronize(c->own);
+        (void)hipStreamDestroy(c->own);
+    }
+    if (c->freed) (void)hipEventDestroy(c->freed);
     if (c->ev[0])
-        for (hipEvent_t &e : c->ev) hipEventDestroy(e);
+        for (hipEvent_t &e : c->ev) (void)hipEventDestroy(e);
     delete c;
     return TREEPM_OK;
 }
@@ -518,6 +592,7 @@ TREEPM_API int treepm_build(treepm_ctx *c, int64_t n, const double *x, const dou
     HIPCHK(c, hipSetDevice(c->device));
     hipStream_t s = (hipStream_t)hip_stream;
     c->last = s;
+    CallScope scope(c, s);
     record(c, 0, s);
     int rc = do_build(c, n, x, y, z, m, mem_kind, s);
     if (rc) return rc;
@@ -537,6 +612,7 @@ TREEPM_API int treepm_walk(treepm_ctx *c, void *hip_stream, treepm_stats *stats)
     HIPCHK(c, hipSetDevice(c->device));
     hipStream_t s = (hipStream_t)hip_stream;
     c->last = s;
+    CallScope scope(c, s);
     record(c, 2, s);
     int rc = do_walk(c, s);
     if (rc) {
@@ -576,6 +652,7 @@ TREEPM_API int treepm_force_short(treepm_ctx *c, void *ax, void *ay, void *az, i
     HIPCHK(c, hipSetDevice(c->device));
     hipStream_t s = (hipStream_t)hip_stream;
     c->last = s;
+    CallScope scope(c, s);
     size_t esz = out_prec == TREEPM_FP64 ? 8 : 4;
     void *dst[3] = {ax, ay, az};
     if (mem_kind == TREEPM_HOST) {
