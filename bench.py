@@ -40,7 +40,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="nfw256")
-    ap.add_argument("--n-crit", type=int, default=256)
+    ap.add_argument("--n-crit", type=int, default=0,
+                    help="group size limit; 0 = autotune over --n-crit-candidates")
+    ap.add_argument("--n-crit-candidates", default="128,192,256,384,512")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--cpu-stride", type=int, default=0,
@@ -251,6 +253,19 @@ def main():
     dev = [torch.from_numpy(a).cuda() for a in arrays]
     acc = [torch.empty(spec.n, dtype=torch.float32, device="cuda") for _ in range(3)]
 
+    autotune = None
+    if n_crit <= 0:
+        cands = [int(v) for v in args.n_crit_candidates.split(",")]
+        p0 = tp.treepm_params(spec.L, spec.mesh, spec.r_cut, spec.eps, spec.theta,
+                              spec.n_leaf, cands[0], tp.TREEPM_FP32)
+        ctx = tp.treepm_create(p0, 0)
+        t0 = time.time()
+        n_crit, best_ms = tp.treepm_autotune(ctx, *dev, cands)
+        tp.treepm_destroy(ctx)
+        autotune = {"candidates": cands, "chosen": n_crit, "step_ms": best_ms,
+                    "seconds": time.time() - t0}
+        log(f"[bench] autotuned n_crit = {n_crit} ({best_ms:.2f} ms)")
+
     p32 = tp.treepm_params(spec.L, spec.mesh, spec.r_cut, spec.eps, spec.theta, spec.n_leaf,
                            n_crit, tp.TREEPM_FP32)
     ctx = tp.treepm_create(p32, 0)
@@ -296,6 +311,7 @@ def main():
             "n": spec.n, "theta": spec.theta, "n_crit": n_crit, "n_leaf": spec.n_leaf,
             "r_cut": spec.r_cut, "eps": spec.eps,
         },
+        "autotune": autotune,
         "interactions_per_s": inter / t_force,
         "interactions": inter,
         "interactions_per_particle": inter / spec.n,

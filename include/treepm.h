@@ -134,6 +134,17 @@ int treepm_walk(treepm_ctx *ctx, void *hip_stream, treepm_stats *stats);
 int treepm_force_short(treepm_ctx *ctx, void *ax, void *ay, void *az, int out_prec,
                        int mem_kind, void *hip_stream);
 
+/* Choose n_crit (Section 3.1.2's N_crit) for this box by measurement: for each of the
+ * n_candidates values (1..64 of them, each >= 1), build, walk and run the FP32 force twice on
+ * the given particles (same arguments as treepm_build) and time the second run with device
+ * events; the fastest is kept.  Afterwards the context's n_crit is the winner (*best; its
+ * time in ms in *best_ms, either may be NULL) and the box is built and walked with it.  Uses
+ * the context's other parameters and the FP32 kernel for the trials. */
+int treepm_autotune(treepm_ctx *ctx, int64_t n, const double *x, const double *y,
+                    const double *z, const double *m, int mem_kind, void *hip_stream,
+                    const int32_t *candidates, int32_t n_candidates, int32_t *best,
+                    double *best_ms);
+
 /* Counts (and timings) of the last calls.  Synchronises the context's last stream. */
 int treepm_get_stats(treepm_ctx *ctx, treepm_stats *stats);
 

@@ -16,6 +16,7 @@ from ._native import (  # noqa: F401
     TreePMError,
     lib,
     make_params,
+    treepm_autotune,
     treepm_build,
     treepm_ens_create,
     treepm_ens_destroy,

@@ -66,6 +66,7 @@ _SIGS = {
     "treepm_export_lists": (_i, [_p, _i64, _i64, _p, _p, _p]),
     "treepm_last_error": (C.c_char_p, [_p]),
     "treepm_pairwise_f32": (_i, [C.POINTER(treepm_params), _i, _i64, _p, _i64, _p, _p, _p, _p]),
+    "treepm_autotune": (_i, [_p, _i64, _p, _p, _p, _p, _i, _p, _p, C.c_int32, _p, _p]),
     "treepm_ens_create": (_i, [_i, C.c_size_t, _i, C.POINTER(_p)]),
     "treepm_ens_destroy": (_i, [_p]),
     "treepm_ensemble_submit": (_i, [_p, C.c_uint64, C.POINTER(treepm_params), _i64, _p, _p, _p,
@@ -195,6 +196,22 @@ def treepm_force_short(ctx, ax, ay, az, stream=None) -> None:
     prec = TREEPM_FP64 if dt == "float64" else TREEPM_FP32
     _check(lib().treepm_force_short(ctx, bufs[0][0], bufs[1][0], bufs[2][0], prec, kind,
                                     _stream(stream, kind)), ctx)
+
+
+def treepm_autotune(ctx, x, y, z, m, candidates, stream=None):
+    """Returns (best n_crit, its build+walk+force time in ms); the context keeps the winner."""
+    bufs = [_buf(a, "float64") for a in (x, y, z, m)]
+    kinds = {b[1] for b in bufs}
+    if len(kinds) != 1:
+        raise ValueError("x, y, z, m must all be host or all be device buffers")
+    kind = kinds.pop()
+    cand = np.ascontiguousarray(candidates, dtype=np.int32)
+    best = C.c_int32()
+    ms = C.c_double()
+    _check(lib().treepm_autotune(ctx, len(bufs[0][2]), bufs[0][0], bufs[1][0], bufs[2][0],
+                                 bufs[3][0], kind, _stream(stream, kind), cand.ctypes.data,
+                                 cand.size, C.byref(best), C.byref(ms)), ctx)
+    return best.value, ms.value
 
 
 def treepm_get_stats(ctx) -> treepm_stats:

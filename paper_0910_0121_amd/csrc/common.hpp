@@ -120,13 +120,14 @@ constexpr int kForceClasses = 8; // FP32 force: one class per blocking factor K 
 // lists[q * stride + ...]; counts[q] (device) receives the class sizes.
 void launch_classify(GroupArrays gr, uint32_t n_groups, uint32_t *lists, uint32_t stride,
                      uint32_t *counts, hipStream_t s);
-// class_counts: host copy of the class sizes.
+// class_counts: host copy of the class sizes.  Classes are launched largest blocking factor
+// first, round-robin over the n_streams streams (the caller forks and joins them).
 void launch_force_f32(NodeArrays nd, GroupArrays gr, const uint32_t *lists, uint32_t stride,
                       const uint32_t *class_counts, const uint64_t *off,
                       const uint32_t *entries, const double *px, const double *py,
                       const double *pz, const double *pm, const uint32_t *pidx,
                       ForceParams fp, void *ax, void *ay, void *az, int out_prec,
-                      hipStream_t s);
+                      const hipStream_t *streams, int n_streams);
 // FP32 pair routine on explicit positions, pair by pair (xg: host, 3 values).
 void launch_pairwise_f32(int64_t n_i, const double *xi, int64_t n_j, const double *xj,
                          const double *mj, const double *xg, double eta, double eps,

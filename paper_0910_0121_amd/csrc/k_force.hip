@@ -456,11 +456,13 @@ void launch_force_f32(NodeArrays nd, GroupArrays gr, const uint32_t *lists, uint
                       const uint32_t *entries, const double *px, const double *py,
                       const double *pz, const double *pm, const uint32_t *pidx,
                       ForceParams fp, void *ax, void *ay, void *az, int out_prec,
-                      hipStream_t s)
+                      const hipStream_t *streams, int n_streams)
 {
+    int next = 0;
 #define TPM_LAUNCH(KK)                                                                         \
     if (class_counts[KK - 1]) {                                                                \
         const uint32_t *ids = lists + (size_t)(KK - 1) * stride;                               \
+        hipStream_t s = streams[next++ % n_streams];                                           \
         if (out_prec)                                                                          \
             k_force_f32<KK, 1><<<class_counts[KK - 1], 64, 0, s>>>(                            \
                 nd, gr, ids, class_counts[KK - 1], off, entries, px, py, pz, pm, pidx, fp, ax, \

@@ -42,6 +42,10 @@ struct treepm_ctx {
     hipStream_t own = nullptr;
     hipEvent_t freed = nullptr;
     hipStream_t cur = nullptr;
+    // The FP32 force's size classes run concurrently on the call's stream and these.
+    static constexpr int kSubStreams = 3;
+    hipStream_t sub[kSubStreams] = {};
+    hipEvent_t fork = nullptr, join[kSubStreams] = {};
     std::string err;
     int state = 0; // 0 empty, 1 built, 2 walked
     int64_t n = 0;
@@ -522,6 +526,21 @@ TREEPM_API int treepm_create(const treepm_params *params, int device, treepm_ctx
         c->freed = nullptr;
         (void)hipGetLastError();
     }
+    bool subs_ok = hipEventCreateWithFlags(&c->fork, hipEventDisableTiming) == hipSuccess;
+    for (int i = 0; subs_ok && i < treepm_ctx::kSubStreams; ++i)
+        subs_ok = hipStreamCreateWithFlags(&c->sub[i], hipStreamNonBlocking) == hipSuccess &&
+                  hipEventCreateWithFlags(&c->join[i], hipEventDisableTiming) == hipSuccess;
+    if (!subs_ok) { // run the classes one after another on the call's stream
+        for (int i = 0; i < treepm_ctx::kSubStreams; ++i) {
+            if (c->sub[i]) (void)hipStreamDestroy(c->sub[i]);
+            if (c->join[i]) (void)hipEventDestroy(c->join[i]);
+            c->sub[i] = nullptr;
+            c->join[i] = nullptr;
+        }
+        if (c->fork) (void)hipEventDestroy(c->fork);
+        c->fork = nullptr;
+        (void)hipGetLastError();
+    }
     *out = c;
     return TREEPM_OK;
 }
@@ -552,6 +571,11 @@ TREEPM_API int treepm_destroy(treepm_ctx *c)
         (void)hipStreamDestroy(c->own);
     }
     if (c->freed) (void)hipEventDestroy(c->freed);
+    for (int i = 0; i < treepm_ctx::kSubStreams; ++i) {
+        if (c->sub[i]) (void)hipStreamDestroy(c->sub[i]);
+        if (c->join[i]) (void)hipEventDestroy(c->join[i]);
+    }
+    if (c->fork) (void)hipEventDestroy(c->fork);
     if (c->ev[0])
         for (hipEvent_t &e : c->ev) (void)hipEventDestroy(e);
     delete c;
@@ -673,14 +697,28 @@ TREEPM_API int treepm_force_short(treepm_ctx *c, void *ax, void *ay, void *az, i
     }
     ForceParams fp{P.L, P.eps * P.eps, 1.0 / eta, eta, P.r_cut * P.r_cut,
                    c->kept.as<uint32_t>()};
-    if (P.precision == TREEPM_FP32)
+    if (P.precision == TREEPM_FP32) {
+        hipStream_t streams[1 + treepm_ctx::kSubStreams] = {s};
+        int ns = 1;
+        if (c->fork) {
+            HIPCHK(c, hipEventRecord(c->fork, s));
+            for (int i = 0; i < treepm_ctx::kSubStreams; ++i) {
+                HIPCHK(c, hipStreamWaitEvent(c->sub[i], c->fork, 0));
+                streams[ns++] = c->sub[i];
+            }
+        }
         launch_force_f32(nd, gr, c->cls.as<uint32_t>() + kForceClasses, c->n_groups + 1,
-                         c->class_counts,
-                         c->off.as<uint64_t>(), c->entries.as<uint32_t>(),
+                         c->class_counts, c->off.as<uint64_t>(), c->entries.as<uint32_t>(),
                          c->pos[0].as<double>(), c->pos[1].as<double>(),
                          c->pos[2].as<double>(), c->pos[3].as<double>(),
-                         c->idx.as<uint32_t>(), fp, dst[0], dst[1], dst[2], out_prec, s);
-    else
+                         c->idx.as<uint32_t>(), fp, dst[0], dst[1], dst[2], out_prec, streams,
+                         ns);
+        if (c->fork)
+            for (int i = 0; i < treepm_ctx::kSubStreams; ++i) {
+                HIPCHK(c, hipEventRecord(c->join[i], c->sub[i]));
+                HIPCHK(c, hipStreamWaitEvent(s, c->join[i], 0));
+            }
+    } else
         launch_force_f64(nd, gr, c->n_groups, c->off.as<uint64_t>(), c->entries.as<uint32_t>(),
                          c->pos[0].as<double>(), c->pos[1].as<double>(),
                          c->pos[2].as<double>(), c->pos[3].as<double>(),
@@ -822,6 +860,75 @@ TREEPM_API int treepm_export_lists(treepm_ctx *c, int64_t group_cap, int64_t ent
             value[q] = idx[e];
         }
     }
+    return TREEPM_OK;
+}
+
+TREEPM_API int treepm_autotune(treepm_ctx *c, int64_t n, const double *x, const double *y,
+                               const double *z, const double *m, int mem_kind, void *hip_stream,
+                               const int32_t *candidates, int32_t n_candidates, int32_t *best,
+                               double *best_ms)
+{
+    if (!c || !candidates || n_candidates < 1 || n_candidates > 64) return TREEPM_ERR_ARG;
+    for (int i = 0; i < n_candidates; ++i)
+        if (candidates[i] < 1) return fail(c, TREEPM_ERR_ARG, "n_crit candidates must be >= 1");
+    int rc;
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)hip_stream;
+    // device outputs for the trial forces (their values are discarded)
+    Buf tmp[3];
+    {
+        CallScope scope(c, s);
+        for (Buf &b : tmp) {
+            hipError_t e = reserve(b, (size_t)n * 4);
+            if (e != hipSuccess) {
+                for (Buf &q : tmp) release(q);
+                return hip_fail(c, e, "autotune outputs");
+            }
+        }
+    }
+    hipEvent_t e0, e1;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    const treepm_params base = c->prm;
+    int32_t win = candidates[0];
+    double win_ms = 1e300;
+    rc = TREEPM_OK;
+    for (int i = 0; i < n_candidates && !rc; ++i) {
+        c->prm.n_crit = candidates[i];
+        float best_t = 1e30f;
+        for (int rep = 0; rep < 2 && !rc; ++rep) {
+            (void)hipEventRecord(e0, s);
+            rc = treepm_build(c, n, x, y, z, m, mem_kind, s);
+            if (!rc) rc = treepm_walk(c, s, nullptr);
+            if (!rc)
+                rc = treepm_force_short(c, tmp[0].p, tmp[1].p, tmp[2].p, TREEPM_FP32,
+                                        TREEPM_DEVICE, s);
+            (void)hipEventRecord(e1, s);
+            if (!rc && hipEventSynchronize(e1) == hipSuccess) {
+                float t = 0.f;
+                if (hipEventElapsedTime(&t, e0, e1) == hipSuccess && rep > 0) best_t = t;
+            }
+        }
+        if (!rc && best_t < win_ms) {
+            win_ms = best_t;
+            win = candidates[i];
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    {
+        CallScope scope(c, s);
+        for (Buf &b : tmp) release(b);
+    }
+    c->prm = base;
+    c->prm.n_crit = win;
+    if (rc) return rc;
+    // leave the context built and walked with the winner
+    rc = treepm_build(c, n, x, y, z, m, mem_kind, s);
+    if (!rc) rc = treepm_walk(c, s, nullptr);
+    if (rc) return rc;
+    if (best) *best = win;
+    if (best_ms) *best_ms = win_ms;
     return TREEPM_OK;
 }
 

@@ -302,3 +302,21 @@ def test_error_paths(tp):
         tp.treepm_force_short(ctx, *a)
     assert e.value.code == -1
     tp.treepm_destroy(ctx)
+
+
+def test_autotune_picks_a_candidate_and_leaves_a_walked_box(tp, orc):
+    _say("autotune")
+    x, y, z, m = boxgen.nfw_box(60000, 100, 13)
+    r_cut, eps = 0.05, 0.05 / 60
+    p = tp.treepm_params(1.0, r_cut / 3, r_cut, eps, 0.5, 10, 64, tp.TREEPM_FP32)
+    ctx = tp.treepm_create(p, 0)
+    dev = [torch.from_numpy(a).cuda() for a in (x, y, z, m)]
+    best, ms = tp.treepm_autotune(ctx, *dev, [32, 96, 200])
+    assert best in (32, 96, 200) and ms > 0
+    a = [torch.zeros(len(x), dtype=torch.float64, device="cuda") for _ in range(3)]
+    tp.treepm_force_short(ctx, *a)      # the box is built and walked with the winner
+    got = np.stack([t.cpu().numpy() for t in a])
+    tp.treepm_destroy(ctx)
+    ref = Run(tp, x, y, z, m, 1.0, r_cut, eps, 0.5, 10, best, tp.TREEPM_FP32)
+    np.testing.assert_array_equal(got, ref.acc)
+    ref.close()
