@@ -53,18 +53,21 @@ def parse():
     ap.add_argument("--serving-inflight", type=int, default=4)
     ap.add_argument("--serving-budget-frac", type=float, default=0.25)
     ap.add_argument("--serving-only", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy (counter calibration)")
     return ap.parse_args()
 
 
-def measured_traffic(interactions_unused=None):
-    """HBM bytes per force launch from the committed rocprofv3 counter runs, if they were
-    taken on the current force-kernel source; else None."""
+def measured_traffic(n_crit, workload):
+    """HBM bytes per force call from the committed rocprofv3 counter runs, if they were taken
+    on the current force-kernel source, the same workload and the same n_crit; else None."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
         with open(FORCE_SRC, "rb") as f:
             sha = hashlib.sha1(f.read()).hexdigest()
-        if t.get("source_sha1") != sha:
+        if (t.get("source_sha1") != sha or t.get("n_crit") != n_crit
+                or not t.get("workload", "").startswith(workload)):
             return None
         return t
     except (OSError, ValueError):
@@ -239,6 +242,15 @@ def main():
     import boxgen
     import paper_0910_0121_amd as tp
 
+    if args.copy_calibration:
+        # a plain copy of known size: reads and writes 2^30 bytes per dispatch
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": 1 << 30, "dispatches": 3}), flush=True)
+        return
     if args.serving_only:
         print(json.dumps(serving_bench(tp, args.serving_boxes, args.serving_requests_per_box,
                                        args.serving_inflight, args.serving_budget_frac)),
@@ -288,7 +300,7 @@ def main():
     # The roofline counts the pairs the kernel evaluated: list entries whose source lies at
     # least r_cut from the group's box add exactly zero and are skipped.
     achieved = K_PP * evaluated / t_force / 1e12
-    traffic = measured_traffic()
+    traffic = measured_traffic(n_crit, spec.name)
     result = {
         "metric": METRIC,
         "value": spec.n * args.steps / elapsed,

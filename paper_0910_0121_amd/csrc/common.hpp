@@ -33,6 +33,9 @@ struct NodeArrays {
     double *mass;          // FP64 moments
     double *comx, *comy, *comz;
     double *cnx, *cny, *cnz; // cube centres ((i + 1/2) * L / 2^level)
+    // Sources as 32-byte records, one cache-line sector per list entry:
+    double4 *nsrc;        // per node: centre of mass and mass
+    const double4 *psrc;  // per particle in key order: position and mass
 };
 
 // Everything the walk reads about one node, in one 64-byte record (one cache line), built
@@ -72,8 +75,9 @@ void launch_keys(int64_t n, const double *x, const double *y, const double *z, c
 size_t sort_hist_elems(int64_t n);
 void radix_sort(int64_t n, uint64_t *key, uint32_t *idx, uint64_t *key_alt, uint32_t *idx_alt,
                 uint32_t *hist, uint32_t *scan_tmp, hipStream_t s);
+// Also writes the key-ordered records psrc (x, y, z, m).
 void launch_permute(int64_t n, const uint32_t *idx, const double4 *rec, double *px,
-                    double *py, double *pz, double *pm, hipStream_t s);
+                    double *py, double *pz, double *pm, double4 *psrc, hipStream_t s);
 void launch_root(NodeArrays nd, uint32_t n, double L, hipStream_t s);
 // Level step: nodes [lo, hi) of level `level`; writes nchild and per-node child counts into
 // cnt (hi - lo values) for the scan.

@@ -185,7 +185,8 @@ __global__ __launch_bounds__(256) void k_permute(int64_t n, const uint32_t *__re
                                                  const double4 *__restrict__ rec,
                                                  double *__restrict__ px, double *__restrict__ py,
                                                  double *__restrict__ pz,
-                                                 double *__restrict__ pm)
+                                                 double *__restrict__ pm,
+                                                 double4 *__restrict__ psrc)
 {
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
          k += (int64_t)gridDim.x * blockDim.x) {
@@ -194,6 +195,7 @@ __global__ __launch_bounds__(256) void k_permute(int64_t n, const uint32_t *__re
         py[k] = r.y;
         pz[k] = r.z;
         pm[k] = r.w;
+        psrc[k] = r;
     }
 }
 
@@ -349,6 +351,7 @@ __global__ __launch_bounds__(256) void k_com_divide(NodeArrays nd, uint32_t n_no
         nd.comx[u] = c0;
         nd.comy[u] = c1;
         nd.comz[u] = c2;
+        nd.nsrc[u] = make_double4(c0, c1, c2, M);
         WalkNode w;
         w.cn[0] = nd.cnx[u];
         w.cn[1] = nd.cny[u];
@@ -516,9 +519,9 @@ void radix_sort(int64_t n, uint64_t *key, uint32_t *idx, uint64_t *key_alt, uint
 }
 
 void launch_permute(int64_t n, const uint32_t *idx, const double4 *rec, double *px,
-                    double *py, double *pz, double *pm, hipStream_t s)
+                    double *py, double *pz, double *pm, double4 *psrc, hipStream_t s)
 {
-    k_permute<<<grid_for(n, 256), 256, 0, s>>>(n, idx, rec, px, py, pz, pm);
+    k_permute<<<grid_for(n, 256), 256, 0, s>>>(n, idx, rec, px, py, pz, pm, psrc);
 }
 
 void launch_root(NodeArrays nd, uint32_t n, double L, hipStream_t s)

@@ -109,14 +109,9 @@ __device__ __forceinline__ int load_tile_f32(float4 *tile, const uint32_t *__res
         bool keep = false;
         float4 v;
         if (j < Lg) {
-            uint32_t ent = list[j];
-            double sx, sy, sz, sm;
-            if (ent & kCellTag) {
-                uint32_t u = ent & ~kCellTag;
-                sx = nd.comx[u]; sy = nd.comy[u]; sz = nd.comz[u]; sm = nd.mass[u];
-            } else {
-                sx = px[ent]; sy = py[ent]; sz = pz[ent]; sm = pm[ent];
-            }
+            const uint32_t ent = list[j];
+            const double4 src = (ent & kCellTag) ? nd.nsrc[ent & ~kCellTag] : nd.psrc[ent];
+            const double sx = src.x, sy = src.y, sz = src.z, sm = src.w;
             double w0 = fabs(wrapd(sx - F.cg0, F.L)) - F.hg0;
             double w1 = fabs(wrapd(sy - F.cg1, F.L)) - F.hg1;
             double w2 = fabs(wrapd(sz - F.cg2, F.L)) - F.hg2;
@@ -410,13 +405,9 @@ __global__ __launch_bounds__(64) void k_force_f64(
             const uint64_t j = jb + lane;
             d4 v = {0.0, 0.0, 0.0, 0.0};
             if (j < Lg) {
-                uint32_t e = entries[b + j];
-                if (e & kCellTag) {
-                    uint32_t u = e & ~kCellTag;
-                    v = {nd.comx[u], nd.comy[u], nd.comz[u], nd.mass[u]};
-                } else {
-                    v = {px[e], py[e], pz[e], pm[e]};
-                }
+                const uint32_t e = entries[b + j];
+                const double4 r = (e & kCellTag) ? nd.nsrc[e & ~kCellTag] : nd.psrc[e];
+                v = {r.x, r.y, r.z, r.w};
             }
             tile[lane] = v;
             __syncthreads();

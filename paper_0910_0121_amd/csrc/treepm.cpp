@@ -59,6 +59,8 @@ struct treepm_ctx {
     // nodes
     Buf n_code, n_first, n_count, n_cf, n_parent, n_nch, n_level, n_mass, n_com[3], n_cn[3];
     Buf n_walk; // packed per-node walk records
+    Buf n_src;  // per-node (com, mass) records
+    Buf psrc;   // key-ordered particle (x, y, z, m) records
     size_t node_cap = 0;
     uint32_t n_nodes = 0;
     std::vector<uint32_t> lvl;
@@ -195,6 +197,8 @@ NodeArrays nodes_view(treepm_ctx *c)
     nd.cnx = c->n_cn[0].as<double>();
     nd.cny = c->n_cn[1].as<double>();
     nd.cnz = c->n_cn[2].as<double>();
+    nd.nsrc = c->n_src.as<double4>();
+    nd.psrc = c->psrc.as<double4>();
     return nd;
 }
 
@@ -292,7 +296,7 @@ int do_build(treepm_ctx *c, int64_t n, const double *x, const double *y, const d
                {&c->hist, sort_hist_elems(n) * 4},
                {&c->scan32, (scan_tmp_elems(std::max(sort_hist_elems(n), N + 1)) + 64) * 4},
                {&c->lside, 32 * 8},      {&c->g_misc, 64},
-               {&c->rec, N * 32}};
+               {&c->rec, N * 32},        {&c->psrc, N * 32}};
     for (auto &r : res) {
         hipError_t e = reserve(*r.b, std::max<size_t>(r.bytes, 64));
         if (e != hipSuccess) return hip_fail(c, e, "particle buffers");
@@ -320,7 +324,8 @@ int do_build(treepm_ctx *c, int64_t n, const double *x, const double *y, const d
     radix_sort(n, c->key.as<uint64_t>(), c->idx.as<uint32_t>(), c->key_alt.as<uint64_t>(),
                c->idx_alt.as<uint32_t>(), c->hist.as<uint32_t>(), scan_tmp, s);
     launch_permute(n, c->idx.as<uint32_t>(), c->rec.as<double4>(), c->pos[0].as<double>(),
-                   c->pos[1].as<double>(), c->pos[2].as<double>(), c->pos[3].as<double>(), s);
+                   c->pos[1].as<double>(), c->pos[2].as<double>(), c->pos[3].as<double>(),
+                   c->psrc.as<double4>(), s);
     // octree, level by level
     c->n_nodes = 0;
     if ((rc = ensure_nodes(c, std::max<size_t>(1024, N / 2 + 64), s))) return rc;
@@ -356,8 +361,10 @@ int do_build(treepm_ctx *c, int64_t n, const double *x, const double *y, const d
         launch_moments(nd, px, py, pz, pm, c->lvl[l], c->lvl[l + 1], s);
     {
         hipError_t e = reserve(c->n_walk, (size_t)c->n_nodes * sizeof(WalkNode));
+        if (e == hipSuccess) e = reserve(c->n_src, (size_t)c->n_nodes * sizeof(double4));
         if (e != hipSuccess) return hip_fail(c, e, "walk records");
     }
+    nd = nodes_view(c);
     launch_com_divide(nd, c->n_nodes, c->n_walk.as<WalkNode>(), s);
     // groups in key order
     int n_crit = P.n_crit > 0 ? P.n_crit : kDefaultNCrit;
@@ -487,6 +494,7 @@ size_t treepm_internal_ctx_bytes(const treepm_ctx *c)
                         &c->rec, &c->n_code, &c->n_first, &c->n_count, &c->n_cf, &c->n_parent,
                         &c->n_nch, &c->n_level, &c->n_mass, &c->n_com[0], &c->n_com[1],
                         &c->n_com[2], &c->n_cn[0], &c->n_cn[1], &c->n_cn[2], &c->n_walk,
+                        &c->n_src, &c->psrc,
                         &c->g_node, &c->g_first, &c->g_count, &c->g_cg[0], &c->g_cg[1],
                         &c->g_cg[2], &c->g_hg[0], &c->g_hg[1], &c->g_hg[2], &c->g_xg[0],
                         &c->g_xg[1], &c->g_xg[2], &c->g_lo[0], &c->g_lo[1], &c->g_lo[2],
@@ -556,7 +564,7 @@ TREEPM_API int treepm_destroy(treepm_ctx *c)
                   &c->scan32, &c->flags, &c->levcnt, &c->gstart, &c->gflag, &c->n_code,
                   &c->n_first, &c->n_count, &c->n_cf, &c->n_parent, &c->n_nch, &c->n_level,
                   &c->n_mass, &c->n_com[0], &c->n_com[1], &c->n_com[2], &c->n_cn[0],
-                  &c->n_cn[1], &c->n_cn[2], &c->n_walk, &c->g_node, &c->g_first, &c->g_count, &c->g_cg[0],
+                  &c->n_cn[1], &c->n_cn[2], &c->n_walk, &c->n_src, &c->psrc, &c->g_node, &c->g_first, &c->g_count, &c->g_cg[0],
                   &c->g_cg[1], &c->g_cg[2], &c->g_hg[0], &c->g_hg[1], &c->g_hg[2], &c->g_xg[0],
                   &c->g_xg[1], &c->g_xg[2], &c->g_lo[0], &c->g_lo[1], &c->g_lo[2], &c->g_hi[0],
                   &c->g_hi[1], &c->g_hi[2], &c->g_misc, &c->off, &c->scan64, &c->entries,
