@@ -40,6 +40,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="nfw256")
+    ap.add_argument("--theta", type=float, default=None, help="override the workload's theta")
     ap.add_argument("--n-crit", type=int, default=0,
                     help="group size limit; 0 = autotune over --n-crit-candidates")
     ap.add_argument("--n-crit-candidates", default="128,192,256,384,512")
@@ -257,6 +258,9 @@ def main():
               flush=True)
         return
     spec = boxgen.CONFIGS[args.workload]
+    if args.theta is not None:
+        import dataclasses
+        spec = dataclasses.replace(spec, theta=args.theta)
     n_crit = args.n_crit
     log(f"[bench] generating {spec.name} (N={spec.n}) ...")
     t0 = time.time()
