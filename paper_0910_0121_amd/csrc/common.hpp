@@ -120,8 +120,8 @@ struct ForceParams {
     uint32_t *kept; // FP32 path: per group, list entries that survived the cutoff cull
 };
 constexpr int kForceClasses = 8; // FP32 force: one class per blocking factor K = 1..8
-// Group ids by blocking class q = ceil(count / 64) - 1 (capped at kForceClasses - 1) into
-// lists[q * stride + ...]; counts[q] (device) receives the class sizes.
+// Group ids by blocking class q = K - 1 (K: i-particles per lane of the group's lane layout)
+// into lists[q * stride + ...]; counts[q] (device) receives the class sizes.
 void launch_classify(GroupArrays gr, uint32_t n_groups, uint32_t *lists, uint32_t stride,
                      uint32_t *counts, hipStream_t s);
 // class_counts: host copy of the class sizes.  Classes are launched largest blocking factor

@@ -77,36 +77,44 @@ __device__ __forceinline__ void store3(void *ax, void *ay, void *az, uint32_t i,
 // come for free; the sum is multiplied by 1/eta^2 once per particle:
 //   a_i = (1/eta^2) sum_j m_j d'_ij g(|d'_ij|) / (|d'_ij|^2 + (eps/eta)^2)^(3/2).
 //
-// One tile holds up to kTileF32 sources.  Each lane examines kTileF32 / 64 list entries and
+// One tile takes up to kTileF32 list entries.  Each lane examines kTileF32 / 64 of them and
 // drops those whose source is at least r_cut from the group's bounding box: every pair they
-// would form is at least r_cut apart and adds exactly zero (g = 0 for R >= 2).  The survivors
-// are compacted in list order and stored by stream: survivor e goes to stream e % J, slot
-// e / J, so each stream reads a contiguous run.  Slots past the last survivor of a stream
-// are zero-mass padding (they add exactly 0).
+// would form is at least r_cut apart and adds exactly zero (g = 0 for R >= 2).  Survivors at
+// least eta from the box ("far": every pair has R >= 1, so only the second branch of g
+// applies) are kept apart from the others ("near").  Both kinds are compacted in list order
+// and stored by stream: near survivor e goes to stream e % J, slot e / J, counting up from
+// the start of the stream's run; far survivor e to stream e % J, slot e / J counting down
+// from its end.  Slots past the last survivor of a stream, in either part, are zero-mass
+// padding (they add exactly 0).
 constexpr int kTileF32 = 256;
 
 struct GroupFrame {
     double xg0, xg1, xg2;   // x_g, origin of the relative coordinates
     double cg0, cg1, cg2;   // bbox centre
     double hg0, hg1, hg2;   // bbox half size
-    double L, rc2, inv_eta;
+    double L, rc2, eta2, inv_eta;
 };
 
-__device__ __forceinline__ int load_tile_f32(float4 *tile, const uint32_t *__restrict__ list,
-                                             uint64_t jb, uint64_t Lg, int J, int per_stream,
-                                             NodeArrays nd, const double *__restrict__ px,
-                                             const double *__restrict__ py,
-                                             const double *__restrict__ pz,
-                                             const double *__restrict__ pm,
-                                             const GroupFrame &F)
+struct TileCounts {
+    int near, far;
+};
+
+// Slots per stream of a tile: n_near + n_far <= kTileF32 survivors need at most
+// kTileF32 / J + 1 rows once both parts are padded to a multiple of J.
+__device__ __forceinline__ int tile_rows(int J) { return kTileF32 / J + 1; }
+
+__device__ __forceinline__ TileCounts load_tile_f32(float4 *tile,
+                                                    const uint32_t *__restrict__ list,
+                                                    uint64_t jb, uint64_t Lg, int J, int rows,
+                                                    NodeArrays nd, const GroupFrame &F)
 {
     const int lane = threadIdx.x;
     const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
-    int kept = 0;
+    int n_near = 0, n_far = 0;
 #pragma unroll
     for (int r = 0; r < kTileF32 / 64; ++r) {
         const uint64_t j = jb + (uint64_t)(r * 64 + lane);
-        bool keep = false;
+        bool keep = false, far = false;
         float4 v;
         if (j < Lg) {
             const uint32_t ent = list[j];
@@ -118,23 +126,77 @@ __device__ __forceinline__ int load_tile_f32(float4 *tile, const uint32_t *__res
             w0 = w0 > 0.0 ? w0 : 0.0;
             w1 = w1 > 0.0 ? w1 : 0.0;
             w2 = w2 > 0.0 ? w2 : 0.0;
-            keep = w0 * w0 + w1 * w1 + w2 * w2 < F.rc2;
+            const double gap2 = w0 * w0 + w1 * w1 + w2 * w2;
+            keep = gap2 < F.rc2;
+            far = gap2 >= F.eta2;
             v = make_float4((float)(wrapd(sx - F.xg0, F.L) * F.inv_eta),
                             (float)(wrapd(sy - F.xg1, F.L) * F.inv_eta),
                             (float)(wrapd(sz - F.xg2, F.L) * F.inv_eta), (float)sm);
         }
-        const uint64_t m = __ballot(keep);
+        const uint64_t mn = __ballot(keep && !far);
+        const uint64_t mf = __ballot(keep && far);
         if (keep) {
-            const int e = kept + (int)__popcll(m & lt);
-            tile[(e % J) * per_stream + e / J] = v;
+            if (far) {
+                const int e = n_far + (int)__popcll(mf & lt);
+                tile[(e % J) * rows + rows - 1 - e / J] = v;
+            } else {
+                const int e = n_near + (int)__popcll(mn & lt);
+                tile[(e % J) * rows + e / J] = v;
+            }
         }
-        kept += (int)__popcll(m);
+        n_near += (int)__popcll(mn);
+        n_far += (int)__popcll(mf);
     }
-    // zero the padding slots of the last row
-    const int steps = (kept + J - 1) / J;
-    const int e = kept + lane;
-    if (lane < J && e < steps * J) tile[(e % J) * per_stream + e / J] = make_float4(0.f, 0.f, 0.f, 0.f);
-    return kept;
+    // zero the padding slots of the last row of each part
+    const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
+    const int en = n_near + lane;
+    if (lane < J && en < (n_near + J - 1) / J * J) tile[(en % J) * rows + en / J] = zero;
+    const int ef = n_far + lane - 32;
+    if (lane >= 32 && lane < 32 + J && ef < (n_far + J - 1) / J * J)
+        tile[(ef % J) * rows + rows - 1 - ef / J] = zero;
+    TileCounts c;
+    c.near = __builtin_amdgcn_readfirstlane(n_near);
+    c.far = __builtin_amdgcn_readfirstlane(n_far);
+    return c;
+}
+
+// Lane layout of a group of n_g particles on one wave: J streams of S = 64 / J lanes, each
+// lane holding K = ceil(n_g / S) i-particles, each stream taking every J-th source.  Among
+// J in {1, 2, 4, 8} with K <= 8 the layout with the fewest lane slots S * K is taken (the
+// smallest J on ties), so few lanes idle: a group of 40 runs as 8 streams of 8 lanes with 5
+// particles each (40 slots) rather than one stream of 64 lanes (64 slots).  Groups above 512
+// run in chunks of 512 with J = 1, K = 8.
+__host__ __device__ __forceinline__ void force_layout(uint32_t n_g, int &J, int &K)
+{
+    J = 1;
+    K = 8;
+    if (n_g > 512) return;
+    uint32_t best = ~0u;
+    for (int j = 1; j <= 8; j *= 2) {
+        const uint32_t s = 64u / (uint32_t)j;
+        uint32_t k = (n_g + s - 1) / s;
+        k = k < 1 ? 1 : k;
+        if (k <= 8 && s * k < best) {
+            best = s * k;
+            J = j;
+            K = (int)k;
+        }
+    }
+}
+
+// Second branch of g (R >= 1, zero from R = 2 on) with u = clamp(1 - R/2, 0, 1), which is
+// (2 - R)/2 exactly on [1, 2]:  (2 - R)^5 (7R^3 + 22R^2 + 10R + 4) / 140
+//   = u^5 (1.6 R^3 + (704/140) R^2 + (320/140) R + 128/140).
+// The factor 32 moved into the coefficients is a power of two, so the value is the same as
+// with (2 - R) itself; the clamp is a modifier of the fma, not an instruction of its own.
+__device__ __forceinline__ float g_far_f32(float R)
+{
+    const float u = fminf(fmaxf(fmaf(R, -0.5f, 1.0f), 0.0f), 1.0f);
+    const float u2 = u * u;
+    const float u5 = u2 * u2 * u;
+    const float c =
+        fmaf(fmaf(fmaf(1.6f, R, 704.0f / 140.0f), R, 320.0f / 140.0f), R, 128.0f / 140.0f);
+    return u5 * c;
 }
 
 // g(R) of eq. (2) rearranged without cancellation; R2 = R * R is passed in.
@@ -144,14 +206,11 @@ __device__ __forceinline__ float g_p3m_f32s(float R, float R2)
     p = fmaf(p, R, -0.5f);
     p = fmaf(p, R, 1.6f);
     p = fmaf(p, R2, -1.6f);
-    float g1 = fmaf(p, R2 * R, 1.0f);
-    float u = fmaxf(2.0f - R, 0.0f);
-    float u2 = u * u;
-    float u5 = u2 * u2 * u;
-    float c = fmaf(fmaf(fmaf(0.05f, R, 22.0f / 140.0f), R, 10.0f / 140.0f), R, 4.0f / 140.0f);
-    return R < 1.0f ? g1 : u5 * c;
+    const float g1 = fmaf(p, R2 * R, 1.0f);
+    return R < 1.0f ? g1 : g_far_f32(R);
 }
 
+template <bool FAR>
 __device__ __forceinline__ void pair_f32(const float4 s, float xi, float yi, float zi,
                                          float eps2, float &tx, float &ty, float &tz)
 {
@@ -160,16 +219,39 @@ __device__ __forceinline__ void pair_f32(const float4 s, float xi, float yi, flo
     const float rinv = __builtin_amdgcn_rsqf(r2 + eps2);
     const float rinv3 = rinv * rinv * rinv;
     const float R = __builtin_amdgcn_sqrtf(r2);
-    const float fm = s.w * g_p3m_f32s(R, r2) * rinv3;
+    const float g = FAR ? g_far_f32(R) : g_p3m_f32s(R, r2);
+    const float fm = s.w * g * rinv3;
     tx = fmaf(fm, dx, tx);
     ty = fmaf(fm, dy, ty);
     tz = fmaf(fm, dz, tz);
 }
 
-// One group on one wave: K i-particles per lane, K = ceil(n_g / 64) (at most 8; larger
-// groups are done in chunks of 512).  For groups of at most 32 (K = 1) the wave splits into
-// J = 64 / S streams of S >= n_g lanes, each stream taking every J-th surviving source, and
-// the J partial sums are added at the end in stream order.
+// steps rows of a stream's tile run, starting at ts, against the lane's K i-particles.
+template <int K, bool FAR>
+__device__ __forceinline__ void tile_pass(const float4 *ts, int steps, const float *xi,
+                                          const float *yi, const float *zi, float eps2,
+                                          float *tx, float *ty, float *tz)
+{
+    int t = 0;
+    for (; t + 2 <= steps; t += 2) {
+        const float4 s0 = ts[t], s1 = ts[t + 1];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            pair_f32<FAR>(s0, xi[k], yi[k], zi[k], eps2, tx[k], ty[k], tz[k]);
+            pair_f32<FAR>(s1, xi[k], yi[k], zi[k], eps2, tx[k], ty[k], tz[k]);
+        }
+    }
+    if (t < steps) {
+        const float4 s0 = ts[t];
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            pair_f32<FAR>(s0, xi[k], yi[k], zi[k], eps2, tx[k], ty[k], tz[k]);
+    }
+}
+
+// One group on one wave in the layout of force_layout (K i-particles per lane, J streams,
+// each stream taking every J-th surviving source); the J partial sums are added at the end
+// in stream order.
 template <int K, int OUT64>
 __device__ __forceinline__ void force_group_f32(float4 *tile, double *red, NodeArrays nd,
                                                 uint32_t n_g, uint32_t f, const uint32_t *list,
@@ -182,13 +264,15 @@ __device__ __forceinline__ void force_group_f32(float4 *tile, double *red, NodeA
                                                 void *ax, void *ay, void *az, uint32_t *kept_out)
 {
     const int lane = threadIdx.x;
-    int J = 1;
-    if (K == 1) J = n_g <= 8 ? 8 : n_g <= 16 ? 4 : n_g <= 32 ? 2 : 1;
+    int J, Kl;
+    force_layout(n_g, J, Kl);
+    (void)Kl;  // equals K: the group was classified with the same layout
     const int S = 64 / J;
+    const int lgJ = J == 1 ? 0 : J == 2 ? 1 : J == 4 ? 2 : 3;
     const int slot = lane % S, stream = lane / S;
-    const int per_stream = kTileF32 / J;
+    const int rows = tile_rows(J);
     uint32_t kept_total = 0;
-    for (uint32_t ib = 0; ib < n_g; ib += 64 * K) {
+    for (uint32_t ib = 0; ib < n_g; ib += (uint32_t)(S * K)) {
         float xi[K], yi[K], zi[K], hx[K], hy[K], hz[K], lx[K], ly[K], lz[K];
         kept_total = 0;
 #pragma unroll
@@ -203,29 +287,17 @@ __device__ __forceinline__ void force_group_f32(float4 *tile, double *red, NodeA
             hx[k] = hy[k] = hz[k] = lx[k] = ly[k] = lz[k] = 0.f;
         }
         for (uint64_t jb = 0; jb < Lg; jb += kTileF32) {
-            const int nt = load_tile_f32(tile, list, jb, Lg, J, per_stream, nd, px, py, pz, pm, F);
-            kept_total += (uint32_t)nt;
+            const TileCounts nt = load_tile_f32(tile, list, jb, Lg, J, rows, nd, F);
+            kept_total += (uint32_t)(nt.near + nt.far);
             __syncthreads();
-            const int steps = (nt + J - 1) / J;
-            const float4 *ts = tile + stream * per_stream;
+            // J is a power of two; the row counts are the same on every lane
+            const int sn = (nt.near + J - 1) >> lgJ, sf = (nt.far + J - 1) >> lgJ;
+            const float4 *ts = tile + stream * rows;
             float tx[K], ty[K], tz[K];
 #pragma unroll
             for (int k = 0; k < K; ++k) tx[k] = ty[k] = tz[k] = 0.f;
-            int t = 0;
-            for (; t + 2 <= steps; t += 2) {
-                const float4 s0 = ts[t], s1 = ts[t + 1];
-#pragma unroll
-                for (int k = 0; k < K; ++k) {
-                    pair_f32(s0, xi[k], yi[k], zi[k], eps2, tx[k], ty[k], tz[k]);
-                    pair_f32(s1, xi[k], yi[k], zi[k], eps2, tx[k], ty[k], tz[k]);
-                }
-            }
-            if (t < steps) {
-                const float4 s0 = ts[t];
-#pragma unroll
-                for (int k = 0; k < K; ++k)
-                    pair_f32(s0, xi[k], yi[k], zi[k], eps2, tx[k], ty[k], tz[k]);
-            }
+            tile_pass<K, false>(ts, sn, xi, yi, zi, eps2, tx, ty, tz);
+            tile_pass<K, true>(ts + rows - sf, sf, xi, yi, zi, eps2, tx, ty, tz);
             __syncthreads();
 #pragma unroll
             for (int k = 0; k < K; ++k) {
@@ -274,7 +346,7 @@ __global__ __launch_bounds__(64) void k_force_f32(
     const double *__restrict__ pm, const uint32_t *__restrict__ pidx, ForceParams fp, void *ax,
     void *ay, void *az)
 {
-    __shared__ float4 tile[kTileF32];
+    __shared__ float4 tile[kTileF32 + 8];
     __shared__ double red[64 * 3];
     if (blockIdx.x >= n_ids) return;
     const uint32_t g = ids[blockIdx.x];
@@ -287,6 +359,7 @@ __global__ __launch_bounds__(64) void k_force_f32(
     F.hg0 = gr.hgx[g]; F.hg1 = gr.hgy[g]; F.hg2 = gr.hgz[g];
     F.L = fp.L;
     F.rc2 = fp.rc2;
+    F.eta2 = fp.eta * fp.eta;
     F.inv_eta = fp.inv_eta;
     const float eps2 = (float)(fp.eps2 * fp.inv_eta * fp.inv_eta);
     const double scale = fp.inv_eta * fp.inv_eta;
@@ -331,7 +404,7 @@ __global__ __launch_bounds__(256) void k_pairwise_f32(int64_t n_i, const double 
                                        (float)((xj[3 * j + 1] - xg1) * inv_eta),
                                        (float)((xj[3 * j + 2] - xg2) * inv_eta), (float)mj[j]);
         float tx = 0.f, ty = 0.f, tz = 0.f;
-        pair_f32(src, x, y, z, eps2, tx, ty, tz);
+        pair_f32<false>(src, x, y, z, eps2, tx, ty, tz);
         out[3 * q + 0] = (double)tx * scale;
         out[3 * q + 1] = (double)ty * scale;
         out[3 * q + 2] = (double)tz * scale;
@@ -340,8 +413,9 @@ __global__ __launch_bounds__(256) void k_pairwise_f32(int64_t n_i, const double 
 
 constexpr int kClasses = 8;
 
-// Blocking class of a group: K - 1 with K = ceil(count / 64), capped at 8.  Each class list
-// is filled with one atomic per wave; the order inside a list does not affect results.
+// Blocking class of a group: K - 1 with K the particles per lane of force_layout.  Each
+// class list is filled with one atomic per wave; the order inside a list does not affect
+// results.
 __global__ __launch_bounds__(256) void k_classify(GroupArrays gr, uint32_t n_groups,
                                                   uint32_t *__restrict__ lists, uint32_t stride,
                                                   uint32_t *counts)
@@ -352,9 +426,9 @@ __global__ __launch_bounds__(256) void k_classify(GroupArrays gr, uint32_t n_gro
         const uint32_t g = base + threadIdx.x;
         int cls = -1;
         if (g < n_groups) {
-            uint32_t c = gr.count[g];
-            cls = (int)((c + 63) / 64) - 1;
-            cls = cls < 0 ? 0 : cls > kClasses - 1 ? kClasses - 1 : cls;
+            int J, K;
+            force_layout(gr.count[g], J, K);
+            cls = K - 1;
         }
 #pragma unroll
         for (int q = 0; q < kClasses; ++q) {
