@@ -115,6 +115,16 @@ void launch_walk(const WalkNode *wn, GroupArrays gr, uint32_t n_groups, WalkPara
                  uint32_t *gcells, unsigned long long *stats, hipStream_t s);
 
 // ------------------------------------------------------------------ launchers (k_force.hip)
+// Workgroups are dealt to the 8 XCDs (each with its own L2) round-robin by block index.
+// xcd_block renumbers block b of n so that each XCD takes a contiguous run: neighbouring
+// groups (key order) then share one L2.  A bijection on [0, n).
+constexpr uint32_t kXcds = 8;
+__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t n)
+{
+    const uint32_t q = n / kXcds, r = n % kXcds, x = b % kXcds;
+    return x * q + (x < r ? x : r) + b / kXcds;
+}
+
 struct ForceParams {
     double L, eps2, inv_eta, eta, rc2;
     uint32_t *kept; // FP32 path: per group, list entries that survived the cutoff cull

@@ -85,10 +85,12 @@ __global__ __launch_bounds__(kSortThreads) void k_hist(const uint64_t *__restric
     hist[(size_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
 }
 
-// Stable scatter of one tile.  Element order inside the tile is (iteration, thread); each
-// element's rank among equal digits follows that order.  The tile is first reordered by
-// digit in LDS, then written out in that order, so elements with equal digits leave as
-// contiguous runs.
+// Stable scatter of one tile.  Wave w takes elements w * 1024 + it * 64 + lane of the tile
+// (iteration it = 0..15), which is also their order for stability.  Each wave ranks its
+// elements among equal digits with ballots and a wave-private running count per digit (no
+// block barrier inside the loop); the per-wave counts then give each wave's base inside
+// each digit's run.  The tile is reordered by digit in LDS and written out in that order,
+// so elements with equal digits leave as contiguous runs.
 __global__ __launch_bounds__(kSortThreads) void k_scatter(const uint64_t *__restrict__ key,
                                                           const uint32_t *__restrict__ idx,
                                                           int64_t n, int shift,
@@ -102,31 +104,56 @@ __global__ __launch_bounds__(kSortThreads) void k_scatter(const uint64_t *__rest
     __shared__ uint32_t sidx[kSortTile];
     __shared__ uint32_t goff[kSortBins];  // global offset of this tile's digit-d run
     __shared__ uint32_t loff[kSortBins];  // local offset of digit d inside the tile
-    __shared__ uint32_t run[kSortBins];   // elements of digit d placed so far
-    __shared__ uint32_t wcnt[kWaves][kSortBins];
+    __shared__ uint32_t wcnt[kWaves][kSortBins]; // per-wave digit counts, then wave bases
     __shared__ uint32_t wsum[kWaves];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int64_t base = (int64_t)blockIdx.x * kSortTile;
     goff[tid] = hist[(size_t)tid * nblocks + blockIdx.x];
-    run[tid] = 0;
 #pragma unroll
     for (int q = 0; q < kWaves; ++q) wcnt[q][tid] = 0;
     __syncthreads();
-    // local histogram of the tile (reusing wcnt[0] as the counter array)
+    const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+    const int64_t wb = base + (int64_t)w * (kSortItems * 64);
     uint64_t kv[kSortItems];
+    uint32_t iv[kSortItems], rk[kSortItems];
+#pragma unroll
     for (int it = 0; it < kSortItems; ++it) {
-        int64_t k = base + (int64_t)it * kSortThreads + tid;
-        kv[it] = k < n ? key[k] : 0ull;
-        if (k < n) atomicAdd(&wcnt[0][(uint32_t)(kv[it] >> shift) & (kSortBins - 1)], 1u);
+        const int64_t k = wb + it * 64 + lane;
+        const bool valid = k < n;
+        kv[it] = valid ? key[k] : 0ull;
+        iv[it] = valid ? idx[k] : 0u;
+    }
+#pragma unroll
+    for (int it = 0; it < kSortItems; ++it) {
+        const bool valid = wb + it * 64 + lane < n;
+        const uint32_t d = (uint32_t)(kv[it] >> shift) & (kSortBins - 1);
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < kSortBits; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t bb = __ballot(bit);
+            peers &= bit ? bb : ~bb;
+        }
+        // LDS operations of one wave complete in order: every lane reads the running
+        // count before the lowest lane of each digit advances it.
+        const uint32_t before = valid ? wcnt[w][d] : 0u;
+        rk[it] = before + (uint32_t)__popcll(peers & lt);
+        if (valid && (peers & lt) == 0) wcnt[w][d] = before + (uint32_t)__popcll(peers);
     }
     __syncthreads();
     {
-        // exclusive scan of the 256 digit counts (one per thread)
-        uint32_t v = wcnt[0][tid];
+        // digit tid: wave bases inside its run, then the exclusive scan over digits
+        uint32_t v = 0;
+#pragma unroll
+        for (int q = 0; q < kWaves; ++q) {
+            const uint32_t c = wcnt[q][tid];
+            wcnt[q][tid] = v;
+            v += c;
+        }
         uint32_t inc = v;
 #pragma unroll
         for (int d = 1; d < 64; d <<= 1) {
-            uint32_t o = __shfl_up(inc, d, 64);
+            const uint32_t o = __shfl_up(inc, d, 64);
             if (lane >= d) inc += o;
         }
         if (lane == 63) wsum[w] = inc;
@@ -134,47 +161,23 @@ __global__ __launch_bounds__(kSortThreads) void k_scatter(const uint64_t *__rest
         uint32_t before = 0;
         for (int q = 0; q < w; ++q) before += wsum[q];
         loff[tid] = before + inc - v;
-        wcnt[0][tid] = 0;
     }
     __syncthreads();
-    const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+#pragma unroll
     for (int it = 0; it < kSortItems; ++it) {
-        int64_t k = base + (int64_t)it * kSortThreads + tid;
-        bool valid = k < n;
-        uint32_t iv = valid ? idx[k] : 0u;
-        uint32_t d = (uint32_t)(kv[it] >> shift) & (kSortBins - 1);
-        uint64_t peers = __ballot(valid);
-#pragma unroll
-        for (int b = 0; b < kSortBits; ++b) {
-            bool bit = (d >> b) & 1u;
-            uint64_t bb = __ballot(bit);
-            peers &= bit ? bb : ~bb;
-        }
-        uint32_t rank = (uint32_t)__popcll(peers & lt);
-        if (valid && (peers & lt) == 0) wcnt[w][d] = (uint32_t)__popcll(peers);
-        __syncthreads();
-        if (valid) {
-            uint32_t before = 0;
-            for (int q = 0; q < w; ++q) before += wcnt[q][d];
-            uint32_t lp = loff[d] + run[d] + before + rank;
+        if (wb + it * 64 + lane < n) {
+            const uint32_t d = (uint32_t)(kv[it] >> shift) & (kSortBins - 1);
+            const uint32_t lp = loff[d] + wcnt[w][d] + rk[it];
             skey[lp] = kv[it];
-            sidx[lp] = iv;
+            sidx[lp] = iv[it];
         }
-        __syncthreads();
-        uint32_t add = 0;
-#pragma unroll
-        for (int q = 0; q < kWaves; ++q) {
-            add += wcnt[q][tid];
-            wcnt[q][tid] = 0;
-        }
-        run[tid] += add;
-        __syncthreads();
     }
+    __syncthreads();
     const int64_t cnt = (n - base) < kSortTile ? (n - base) : kSortTile;
     for (int e = tid; e < cnt; e += kSortThreads) {
-        uint64_t kk = skey[e];
-        uint32_t d = (uint32_t)(kk >> shift) & (kSortBins - 1);
-        uint32_t pos = goff[d] + ((uint32_t)e - loff[d]);
+        const uint64_t kk = skey[e];
+        const uint32_t d = (uint32_t)(kk >> shift) & (kSortBins - 1);
+        const uint32_t pos = goff[d] + ((uint32_t)e - loff[d]);
         key_out[pos] = kk;
         idx_out[pos] = sidx[e];
     }
@@ -397,20 +400,25 @@ __global__ __launch_bounds__(256) void k_group_compact(const uint32_t *__restric
     }
 }
 
-// One wave per group: exact min/max of its particle positions.
+// Eight lanes per group: exact min/max of its particle positions.
 __global__ __launch_bounds__(256) void k_group_bbox(NodeArrays nd, GroupArrays gr,
                                                     uint32_t n_groups,
                                                     const double *__restrict__ px,
                                                     const double *__restrict__ py,
                                                     const double *__restrict__ pz)
 {
-    uint32_t g = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (g >= n_groups) return;
-    uint32_t u = gr.node[g];
-    uint32_t f = nd.first[u], c = nd.count[u];
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t g = t >> 3;
+    const int sub = (int)(t & 7);
+    const bool act = g < n_groups;
+    uint32_t u = 0, f = 0, c = 0;
+    if (act) {
+        u = gr.node[g];
+        f = nd.first[u];
+        c = nd.count[u];
+    }
     double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-    for (uint32_t k = f + lane; k < f + c; k += 64) {
+    for (uint32_t k = f + sub; k < f + c; k += 8) {
         double p[3] = {px[k], py[k], pz[k]};
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
@@ -418,15 +426,16 @@ __global__ __launch_bounds__(256) void k_group_bbox(NodeArrays nd, GroupArrays g
             hi[a] = fmax(hi[a], p[a]);
         }
     }
+    // the eight lanes of a group are an aligned run of the wave
 #pragma unroll
-    for (int d = 32; d > 0; d >>= 1) {
+    for (int d = 4; d > 0; d >>= 1) {
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             lo[a] = fmin(lo[a], __shfl_xor(lo[a], d, 64));
             hi[a] = fmax(hi[a], __shfl_xor(hi[a], d, 64));
         }
     }
-    if (lane == 0) {
+    if (act && sub == 0) {
         gr.first[g] = f;
         gr.count[g] = c;
         gr.lox[g] = lo[0]; gr.loy[g] = lo[1]; gr.loz[g] = lo[2];
@@ -571,7 +580,8 @@ void launch_group_bbox(NodeArrays nd, GroupArrays gr, uint32_t n_groups, const d
                        unsigned *max_count, hipStream_t s)
 {
     if (!n_groups) return;
-    k_group_bbox<<<(n_groups + 3) / 4, 256, 0, s>>>(nd, gr, n_groups, px, py, pz);
+    k_group_bbox<<<(unsigned)(((uint64_t)n_groups * 8 + 255) / 256), 256, 0, s>>>(nd, gr, n_groups,
+                                                                                px, py, pz);
     k_group_extremes<<<grid_for(n_groups, 256, 256), 256, 0, s>>>(nd, gr, n_groups, min_level,
                                                                  max_count);
 }

@@ -338,8 +338,12 @@ __device__ __forceinline__ void force_group_f32(float4 *tile, double *red, NodeA
 }
 
 // One launch per blocking factor K (see k_classify), so each gets its own register budget.
+// Up to K = 4 the kernel fits 128 VGPRs without spilling (4 waves per SIMD); K = 5 runs at
+// 3 waves and larger K at 2.
+constexpr int force_waves_per_simd(int K) { return K <= 4 ? 4 : K == 5 ? 3 : 2; }
+
 template <int K, int OUT64>
-__global__ __launch_bounds__(64) void k_force_f32(
+__global__ __launch_bounds__(64, force_waves_per_simd(K)) void k_force_f32(
     NodeArrays nd, GroupArrays gr, const uint32_t *__restrict__ ids, uint32_t n_ids,
     const uint64_t *__restrict__ off, const uint32_t *__restrict__ entries,
     const double *__restrict__ px, const double *__restrict__ py, const double *__restrict__ pz,
@@ -348,8 +352,9 @@ __global__ __launch_bounds__(64) void k_force_f32(
 {
     __shared__ float4 tile[kTileF32 + 8];
     __shared__ double red[64 * 3];
-    if (blockIdx.x >= n_ids) return;
-    const uint32_t g = ids[blockIdx.x];
+    const uint32_t slot = xcd_block(blockIdx.x, gridDim.x);
+    if (slot >= n_ids) return;
+    const uint32_t g = ids[slot];
     const uint32_t n_g = gr.count[g], f = gr.first[g];
     const uint64_t b = off[g];
     const uint64_t Lg = off[g + 1] - b;
@@ -413,37 +418,43 @@ __global__ __launch_bounds__(256) void k_pairwise_f32(int64_t n_i, const double 
 
 constexpr int kClasses = 8;
 
-// Blocking class of a group: K - 1 with K the particles per lane of force_layout.  Each
-// class list is filled with one atomic per wave; the order inside a list does not affect
-// results.
+// Blocking class of a group: K - 1 with K the particles per lane of force_layout.  A block
+// takes kClassifyItems * 256 consecutive groups, places them with LDS atomics and reserves
+// its part of each class list with one global atomic per class; the order inside a list
+// does not affect results.
+constexpr int kClassifyItems = 8;
+
 __global__ __launch_bounds__(256) void k_classify(GroupArrays gr, uint32_t n_groups,
                                                   uint32_t *__restrict__ lists, uint32_t stride,
                                                   uint32_t *counts)
 {
-    const int lane = threadIdx.x & 63;
-    for (uint32_t base = blockIdx.x * blockDim.x; base < n_groups;
-         base += gridDim.x * blockDim.x) {
-        const uint32_t g = base + threadIdx.x;
-        int cls = -1;
+    __shared__ uint32_t s_cnt[kClasses], s_base[kClasses];
+    if (threadIdx.x < kClasses) s_cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const uint32_t base = blockIdx.x * (256u * kClassifyItems);
+    int cls[kClassifyItems];
+    uint32_t loc[kClassifyItems];
+#pragma unroll
+    for (int r = 0; r < kClassifyItems; ++r) {
+        const uint32_t g = base + (uint32_t)r * 256u + threadIdx.x;
+        cls[r] = -1;
+        loc[r] = 0;
         if (g < n_groups) {
             int J, K;
             force_layout(gr.count[g], J, K);
-            cls = K - 1;
-        }
-#pragma unroll
-        for (int q = 0; q < kClasses; ++q) {
-            uint64_t m = __ballot(cls == q);
-            if (!m) continue;
-            uint32_t first_lane = (uint32_t)__ffsll((long long)m) - 1;
-            uint32_t at = 0;
-            if (lane == (int)first_lane) at = atomicAdd(&counts[q], (uint32_t)__popcll(m));
-            at = __shfl(at, first_lane, 64);
-            if (cls == q) {
-                const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
-                lists[q * stride + at + __popcll(m & lt)] = g;
-            }
+            cls[r] = K - 1;
+            loc[r] = atomicAdd(&s_cnt[K - 1], 1u);
         }
     }
+    __syncthreads();
+    if (threadIdx.x < kClasses && s_cnt[threadIdx.x])
+        s_base[threadIdx.x] = atomicAdd(&counts[threadIdx.x], s_cnt[threadIdx.x]);
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kClassifyItems; ++r)
+        if (cls[r] >= 0)
+            lists[(uint32_t)cls[r] * stride + s_base[cls[r]] + loc[r]] =
+                base + (uint32_t)r * 256u + threadIdx.x;
 }
 
 struct d4 {
@@ -458,7 +469,7 @@ __global__ __launch_bounds__(64) void k_force_f64(
     const uint32_t *__restrict__ pidx, ForceParams fp, void *ax, void *ay, void *az)
 {
     __shared__ d4 tile[kTileJ];
-    const uint32_t g = blockIdx.x;
+    const uint32_t g = xcd_block(blockIdx.x, gridDim.x);
     const int lane = threadIdx.x;
     if (g >= n_groups) return;
     const uint32_t n_g = gr.count[g], f = gr.first[g];
@@ -512,8 +523,8 @@ void launch_classify(GroupArrays gr, uint32_t n_groups, uint32_t *lists, uint32_
 {
     fill_u32(counts, kClasses, 0u, s);
     if (!n_groups) return;
-    unsigned b = (n_groups + 255) / 256;
-    k_classify<<<b < 1024 ? b : 1024, 256, 0, s>>>(gr, n_groups, lists, stride, counts);
+    const unsigned b = (n_groups + 256u * kClassifyItems - 1) / (256u * kClassifyItems);
+    k_classify<<<b, 256, 0, s>>>(gr, n_groups, lists, stride, counts);
 }
 
 void launch_force_f32(NodeArrays nd, GroupArrays gr, const uint32_t *lists, uint32_t stride,

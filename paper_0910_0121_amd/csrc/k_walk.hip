@@ -54,7 +54,7 @@ __global__ __launch_bounds__(64) void k_walk(const WalkNode *__restrict__ wn, Gr
     __shared__ uint32_t stk[kStackCap];
     __shared__ uint32_t s_ex[64], s_val[64];
     __shared__ uint8_t s_cell[64];
-    const uint32_t g = blockIdx.x;
+    const uint32_t g = xcd_block(blockIdx.x, gridDim.x);
     const int lane = threadIdx.x;
     if (g >= n_groups) return;
     const double L = wp.L, rc2 = wp.rc2, th2 = wp.th2;
