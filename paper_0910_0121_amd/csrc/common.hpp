@@ -105,7 +105,7 @@ void launch_group_bbox(NodeArrays nd, GroupArrays gr, uint32_t n_groups, const d
 // ------------------------------------------------------------------ launchers (k_walk.hip)
 struct WalkParams {
     double L, rc2, th2;
-    const double *lside; // device table: L / 2^level, level 0..21
+    uint32_t n_nodes;
 };
 // Count (emit == 0) or write (emit == 1) the interaction list of every group.
 // The emit pass records each group's cell-entry count in gcells and adds (cell entries,

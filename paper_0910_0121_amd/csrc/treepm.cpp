@@ -71,7 +71,7 @@ struct treepm_ctx {
     uint32_t n_groups = 0;
     unsigned min_group_level = 0, max_group = 0;
     // lists
-    Buf off, scan64, entries, lside, wstats, overflow, gcells, cls, kept, kept_sum, out[3];
+    Buf off, scan64, entries, wstats, overflow, gcells, cls, kept, kept_sum, out[3];
     int last_force_prec = -1;
     uint32_t class_counts[kForceClasses] = {};
     uint64_t n_entries = 0;
@@ -295,7 +295,7 @@ int do_build(treepm_ctx *c, int64_t n, const double *x, const double *y, const d
                {&c->gstart, N * 4},      {&c->gflag, (N + 1) * 4},
                {&c->hist, sort_hist_elems(n) * 4},
                {&c->scan32, (scan_tmp_elems(std::max(sort_hist_elems(n), N + 1)) + 64) * 4},
-               {&c->lside, 32 * 8},      {&c->g_misc, 64},
+               {&c->g_misc, 64},
                {&c->rec, N * 32},        {&c->psrc, N * 32}};
     for (auto &r : res) {
         hipError_t e = reserve(*r.b, std::max<size_t>(r.bytes, 64));
@@ -385,9 +385,6 @@ int do_build(treepm_ctx *c, int64_t n, const double *x, const double *y, const d
     c->n_groups = ng;
     c->min_group_level = hm[0];
     c->max_group = hm[1];
-    double ls[kMaxLevel + 1];
-    for (int l = 0; l <= kMaxLevel; ++l) ls[l] = std::ldexp(P.L, -l);
-    HIPCHK(c, hipMemcpyAsync(c->lside.p, ls, sizeof ls, hipMemcpyHostToDevice, s));
     HIPCHK(c, hipStreamSynchronize(s));
     return TREEPM_OK;
 }
@@ -412,7 +409,7 @@ int do_walk(treepm_ctx *c, hipStream_t s)
     fill_u32(ovf, 1, 0u, s);
     fill_u64((uint64_t *)ws, 3, 0ull, s);
     const treepm_params &P = c->prm;
-    WalkParams wp{P.L, P.r_cut * P.r_cut, P.theta * P.theta, c->lside.as<double>()};
+    WalkParams wp{P.L, P.r_cut * P.r_cut, P.theta * P.theta, (uint32_t)c->n_nodes};
     NodeArrays nd = nodes_view(c);
     GroupArrays gr = groups_view(c);
     uint32_t *gcells = c->gcells.as<uint32_t>();
@@ -436,7 +433,8 @@ int do_walk(treepm_ctx *c, hipStream_t s)
     unsigned long long hs[3];
     if ((rc = d2h(c, hs, ws, 3, s))) return rc;
     if ((rc = d2h(c, &hov, ovf, 1, s))) return rc;
-    if (hov) return fail(c, TREEPM_ERR_OVERFLOW, "walk stack overflow");
+    if (hov) return fail(c, TREEPM_ERR_OVERFLOW, hov & 2u ? "walk read a bad node index"
+                                                         : "walk stack overflow");
     c->n_entries = total;
     for (int i = 0; i < 3; ++i) c->st[i] = hs[i];
     return TREEPM_OK;
@@ -499,7 +497,7 @@ size_t treepm_internal_ctx_bytes(const treepm_ctx *c)
                         &c->g_cg[2], &c->g_hg[0], &c->g_hg[1], &c->g_hg[2], &c->g_xg[0],
                         &c->g_xg[1], &c->g_xg[2], &c->g_lo[0], &c->g_lo[1], &c->g_lo[2],
                         &c->g_hi[0], &c->g_hi[1], &c->g_hi[2], &c->g_misc, &c->off, &c->scan64,
-                        &c->entries, &c->lside, &c->wstats, &c->overflow, &c->gcells, &c->cls,
+                        &c->entries, &c->wstats, &c->overflow, &c->gcells, &c->cls,
                         &c->kept, &c->kept_sum, &c->out[0], &c->out[1], &c->out[2]};
     size_t t = 0;
     for (const Buf *b : all) t += b->bytes;
@@ -568,7 +566,7 @@ TREEPM_API int treepm_destroy(treepm_ctx *c)
                   &c->g_cg[1], &c->g_cg[2], &c->g_hg[0], &c->g_hg[1], &c->g_hg[2], &c->g_xg[0],
                   &c->g_xg[1], &c->g_xg[2], &c->g_lo[0], &c->g_lo[1], &c->g_lo[2], &c->g_hi[0],
                   &c->g_hi[1], &c->g_hi[2], &c->g_misc, &c->off, &c->scan64, &c->entries,
-                  &c->lside, &c->wstats, &c->overflow, &c->rec, &c->kept, &c->kept_sum, &c->gcells, &c->cls, &c->out[0],
+                  &c->wstats, &c->overflow, &c->rec, &c->kept, &c->kept_sum, &c->gcells, &c->cls, &c->out[0],
                   &c->out[1], &c->out[2]};
     {
         CallScope scope(c, c->last);
