@@ -79,12 +79,14 @@ void radix_sort(int64_t n, uint64_t *key, uint32_t *idx, uint64_t *key_alt, uint
 void launch_permute(int64_t n, const uint32_t *idx, const double4 *rec, double *px,
                     double *py, double *pz, double *pm, double4 *psrc, hipStream_t s);
 void launch_root(NodeArrays nd, uint32_t n, double L, hipStream_t s);
-// Level step: nodes [lo, hi) of level `level`; writes nchild and per-node child counts into
-// cnt (hi - lo values) for the scan.
+// Level step: nodes [lo, hi) of level `level`; writes nchild, per-node child counts into
+// cnt (hi - lo values) for the scan, and the octant bounds of subdivided nodes into bnd
+// (7 (hi - lo) values).  Levels of at most kWideSplitNodes nodes use one wave per node.
+constexpr uint32_t kWideSplitNodes = 16384;
 void launch_split(NodeArrays nd, const uint64_t *key, uint32_t lo, uint32_t hi, int level,
-                  int n_leaf, uint32_t *cnt, hipStream_t s);
-// Emit children of nodes [lo, hi) at base + exclusive prefix in cnt.
-void launch_emit(NodeArrays nd, const uint64_t *key, uint32_t lo, uint32_t hi, int level,
+                  int n_leaf, uint32_t *cnt, uint32_t *bnd, hipStream_t s);
+// Emit children of nodes [lo, hi) at base + exclusive prefix in cnt, from the bounds in bnd.
+void launch_emit(NodeArrays nd, const uint32_t *bnd, uint32_t lo, uint32_t hi, int level,
                  uint32_t base, const uint32_t *cnt, double L, hipStream_t s);
 void launch_moments(NodeArrays nd, const double *px, const double *py, const double *pz,
                     const double *pm, uint32_t lo, uint32_t hi, hipStream_t s);

@@ -251,9 +251,12 @@ __device__ __forceinline__ void octant_bounds(const uint64_t *__restrict__ key, 
     }
 }
 
+// Octant bounds of subdivided nodes are stored per level, seven per node (b[1..7]; b[0] and
+// b[8] are the node's first and end), by k_split or k_split_wide and read back by k_emit.
 __global__ __launch_bounds__(256) void k_split(NodeArrays nd, const uint64_t *__restrict__ key,
                                                uint32_t lo, uint32_t hi, int level, int n_leaf,
-                                               uint32_t *__restrict__ cnt)
+                                               uint32_t *__restrict__ cnt,
+                                               uint32_t *__restrict__ bnd)
 {
     for (uint32_t u = lo + blockIdx.x * blockDim.x + threadIdx.x; u < hi;
          u += gridDim.x * blockDim.x) {
@@ -263,13 +266,64 @@ __global__ __launch_bounds__(256) void k_split(NodeArrays nd, const uint64_t *__
             uint32_t b[9];
             octant_bounds(key, nd.first[u], c, level, b);
             for (int o = 0; o < 8; ++o) nch += (b[o + 1] > b[o]);
+            uint32_t *q = bnd + (size_t)(u - lo) * 7;
+            for (int o = 1; o < 8; ++o) q[o - 1] = b[o];
         }
         nd.nchild[u] = (uint8_t)nch;
         cnt[u - lo] = nch;
     }
 }
 
-__global__ __launch_bounds__(256) void k_emit(NodeArrays nd, const uint64_t *__restrict__ key,
+// The same for levels of few, large nodes: one wave per node, each octant boundary found by
+// a 64-way search (each round samples 64 keys of the current interval and keeps the gap
+// where the digit reaches the octant), so a node of c particles takes about log64(c) rounds
+// of one parallel load instead of log2(c) dependent loads.
+__global__ __launch_bounds__(256) void k_split_wide(NodeArrays nd,
+                                                    const uint64_t *__restrict__ key,
+                                                    uint32_t lo, uint32_t hi, int level,
+                                                    int n_leaf, uint32_t *__restrict__ cnt,
+                                                    uint32_t *__restrict__ bnd)
+{
+    const uint32_t u = lo + blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const uint32_t lane = threadIdx.x & 63;
+    if (u >= hi) return; // the whole wave leaves together
+    const uint32_t f = nd.first[u], c = nd.count[u];
+    uint32_t nch = 0;
+    if ((int64_t)c >= n_leaf && level < kMaxLevel) {
+        const int shift = 3 * (kMaxLevel - (level + 1));
+        uint32_t prev = f;
+        nch = 0;
+        for (uint32_t o = 1; o <= 8; ++o) {
+            uint32_t bo = f + c;
+            if (o < 8) {
+                // first position in [prev, f + c) whose digit is >= o; it lies in [l, h]
+                uint32_t l = prev, h = f + c;
+                while (h - l > 64) {
+                    const uint32_t sj = l + (uint32_t)((uint64_t)(h - l) * (lane + 1) / 65);
+                    const bool below = (uint32_t)((key[sj] >> shift) & 7u) < o;
+                    const uint32_t t = (uint32_t)__popcll(__ballot(below));
+                    const uint32_t s_lo = l + (uint32_t)((uint64_t)(h - l) * t / 65);
+                    const uint32_t s_hi = l + (uint32_t)((uint64_t)(h - l) * (t + 1) / 65);
+                    // samples 0..t-1 are below o, sample t (if any) is not
+                    if (t > 0) l = s_lo + 1;
+                    if (t < 64) h = s_hi;
+                }
+                const uint32_t p = l + lane;
+                const bool below = p < h && (uint32_t)((key[p] >> shift) & 7u) < o;
+                bo = l + (uint32_t)__popcll(__ballot(below));
+                if (lane == 0) bnd[(size_t)(u - lo) * 7 + (o - 1)] = bo;
+            }
+            nch += (bo > prev);
+            prev = bo;
+        }
+    }
+    if (lane == 0) {
+        nd.nchild[u] = (uint8_t)nch;
+        cnt[u - lo] = nch;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_emit(NodeArrays nd, const uint32_t *__restrict__ bnd,
                                               uint32_t lo, uint32_t hi, int level,
                                               uint32_t base, const uint32_t *__restrict__ cnt,
                                               double L)
@@ -284,7 +338,10 @@ __global__ __launch_bounds__(256) void k_emit(NodeArrays nd, const uint64_t *__r
         uint32_t cf = base + cnt[u - lo];
         nd.child_first[u] = cf;
         uint32_t b[9];
-        octant_bounds(key, nd.first[u], nd.count[u], level, b);
+        b[0] = nd.first[u];
+        b[8] = b[0] + nd.count[u];
+        const uint32_t *q = bnd + (size_t)(u - lo) * 7;
+        for (int o = 1; o < 8; ++o) b[o] = q[o - 1];
         uint64_t pc = nd.code[u];
         uint32_t v = cf;
         for (int o = 0; o < 8; ++o) {
@@ -306,9 +363,6 @@ __global__ __launch_bounds__(256) void k_emit(NodeArrays nd, const uint64_t *__r
     }
 }
 
-// Mass M and mass-weighted position sum S of the nodes of one level; S is kept in com* until
-// k_com_divide.  Leaf: sum over its particles in key order.  Internal node: sum over its
-// children in octant order.
 __global__ __launch_bounds__(256) void k_moments(NodeArrays nd, const double *__restrict__ px,
                                                  const double *__restrict__ py,
                                                  const double *__restrict__ pz,
@@ -539,15 +593,17 @@ void launch_root(NodeArrays nd, uint32_t n, double L, hipStream_t s)
 }
 
 void launch_split(NodeArrays nd, const uint64_t *key, uint32_t lo, uint32_t hi, int level,
-                  int n_leaf, uint32_t *cnt, hipStream_t s)
+                  int n_leaf, uint32_t *cnt, uint32_t *bnd, hipStream_t s)
 {
-    k_split<<<grid_for(hi - lo, 256), 256, 0, s>>>(nd, key, lo, hi, level, n_leaf, cnt);
+    if (hi - lo <= kWideSplitNodes)
+        k_split_wide<<<(hi - lo + 3) / 4, 256, 0, s>>>(nd, key, lo, hi, level, n_leaf, cnt, bnd);
+    else
+        k_split<<<grid_for(hi - lo, 256), 256, 0, s>>>(nd, key, lo, hi, level, n_leaf, cnt, bnd);
 }
-
-void launch_emit(NodeArrays nd, const uint64_t *key, uint32_t lo, uint32_t hi, int level,
+void launch_emit(NodeArrays nd, const uint32_t *bnd, uint32_t lo, uint32_t hi, int level,
                  uint32_t base, const uint32_t *cnt, double L, hipStream_t s)
 {
-    k_emit<<<grid_for(hi - lo, 256), 256, 0, s>>>(nd, key, lo, hi, level, base, cnt, L);
+    k_emit<<<grid_for(hi - lo, 256), 256, 0, s>>>(nd, bnd, lo, hi, level, base, cnt, L);
 }
 
 void launch_moments(NodeArrays nd, const double *px, const double *py, const double *pz,

@@ -71,7 +71,7 @@ struct treepm_ctx {
     uint32_t n_groups = 0;
     unsigned min_group_level = 0, max_group = 0;
     // lists
-    Buf off, scan64, entries, wstats, overflow, gcells, cls, kept, kept_sum, out[3];
+    Buf off, scan64, entries, wstats, overflow, gcells, cls, kept, kept_sum, out[3], bnd;
     int last_force_prec = -1;
     uint32_t class_counts[kForceClasses] = {};
     uint64_t n_entries = 0;
@@ -340,7 +340,11 @@ int do_build(treepm_ctx *c, int64_t n, const double *x, const double *y, const d
     for (int l = 0; l <= kMaxLevel; ++l) {
         uint32_t lo = c->lvl[l], hi = c->lvl[l + 1];
         nd = nodes_view(c);
-        launch_split(nd, c->key.as<uint64_t>(), lo, hi, l, P.n_leaf, cnt, s);
+        {
+            hipError_t e = reserve(c->bnd, (size_t)(hi - lo) * 7 * 4);
+            if (e != hipSuccess) return hip_fail(c, e, "octant bounds");
+        }
+        launch_split(nd, c->key.as<uint64_t>(), lo, hi, l, P.n_leaf, cnt, c->bnd.as<uint32_t>(), s);
         scan_u32(cnt, hi - lo, cnt_total, cnt_tmp, s);
         uint32_t add = 0;
         if ((rc = d2h(c, &add, cnt_total, 1, s))) return rc;
@@ -350,7 +354,7 @@ int do_build(treepm_ctx *c, int64_t n, const double *x, const double *y, const d
             return fail(c, TREEPM_ERR_OVERFLOW, "more than 2^31 tree nodes");
         if ((rc = ensure_nodes(c, (size_t)hi + add, s))) return rc;
         nd = nodes_view(c);
-        launch_emit(nd, c->key.as<uint64_t>(), lo, hi, l, hi, cnt, P.L, s);
+        launch_emit(nd, c->bnd.as<uint32_t>(), lo, hi, l, hi, cnt, P.L, s);
         c->lvl.push_back(hi + add);
         c->n_nodes = hi + add;
     }
@@ -498,7 +502,7 @@ size_t treepm_internal_ctx_bytes(const treepm_ctx *c)
                         &c->g_xg[1], &c->g_xg[2], &c->g_lo[0], &c->g_lo[1], &c->g_lo[2],
                         &c->g_hi[0], &c->g_hi[1], &c->g_hi[2], &c->g_misc, &c->off, &c->scan64,
                         &c->entries, &c->wstats, &c->overflow, &c->gcells, &c->cls,
-                        &c->kept, &c->kept_sum, &c->out[0], &c->out[1], &c->out[2]};
+                        &c->kept, &c->kept_sum, &c->out[0], &c->out[1], &c->out[2], &c->bnd};
     size_t t = 0;
     for (const Buf *b : all) t += b->bytes;
     return t;
@@ -567,7 +571,7 @@ TREEPM_API int treepm_destroy(treepm_ctx *c)
                   &c->g_xg[1], &c->g_xg[2], &c->g_lo[0], &c->g_lo[1], &c->g_lo[2], &c->g_hi[0],
                   &c->g_hi[1], &c->g_hi[2], &c->g_misc, &c->off, &c->scan64, &c->entries,
                   &c->wstats, &c->overflow, &c->rec, &c->kept, &c->kept_sum, &c->gcells, &c->cls, &c->out[0],
-                  &c->out[1], &c->out[2]};
+                  &c->out[1], &c->out[2], &c->bnd};
     {
         CallScope scope(c, c->last);
         for (Buf *b : all) release(*b);
