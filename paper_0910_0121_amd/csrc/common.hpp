@@ -76,8 +76,8 @@ size_t sort_hist_elems(int64_t n);
 void radix_sort(int64_t n, uint64_t *key, uint32_t *idx, uint64_t *key_alt, uint32_t *idx_alt,
                 uint32_t *hist, uint32_t *scan_tmp, hipStream_t s);
 // Also writes the key-ordered records psrc (x, y, z, m).
-void launch_permute(int64_t n, const uint32_t *idx, const double4 *rec, double *px,
-                    double *py, double *pz, double *pm, double4 *psrc, hipStream_t s);
+void launch_permute(int64_t n, const uint32_t *idx, const double4 *rec, double4 *psrc,
+                    hipStream_t s);
 void launch_root(NodeArrays nd, uint32_t n, double L, hipStream_t s);
 // Level step: nodes [lo, hi) of level `level`; writes nchild, per-node child counts into
 // cnt (hi - lo values) for the scan, and the octant bounds of subdivided nodes into bnd
@@ -88,8 +88,7 @@ void launch_split(NodeArrays nd, const uint64_t *key, uint32_t lo, uint32_t hi, 
 // Emit children of nodes [lo, hi) at base + exclusive prefix in cnt, from the bounds in bnd.
 void launch_emit(NodeArrays nd, const uint32_t *bnd, uint32_t lo, uint32_t hi, int level,
                  uint32_t base, const uint32_t *cnt, double L, hipStream_t s);
-void launch_moments(NodeArrays nd, const double *px, const double *py, const double *pz,
-                    const double *pm, uint32_t lo, uint32_t hi, hipStream_t s);
+void launch_moments(NodeArrays nd, const double4 *ps, uint32_t lo, uint32_t hi, hipStream_t s);
 // com = S / M for every node, after all levels' moments; also fills the walk records.
 void launch_com_divide(NodeArrays nd, uint32_t n_nodes, WalkNode *wn, hipStream_t s);
 // Groups: mark in gstart[first] (n values, zeroed here) every maximal node with
@@ -100,8 +99,8 @@ void launch_group_compact(const uint32_t *gstart, const uint32_t *gpos, int64_t 
                           uint32_t *gnode, hipStream_t s);
 // Also lowers *min_level to the shallowest group level and raises *max_count to the
 // largest group.
-void launch_group_bbox(NodeArrays nd, GroupArrays gr, uint32_t n_groups, const double *px,
-                       const double *py, const double *pz, unsigned *min_level,
+void launch_group_bbox(NodeArrays nd, GroupArrays gr, uint32_t n_groups, const double4 *ps,
+                       unsigned *min_level,
                        unsigned *max_count, hipStream_t s);
 
 // ------------------------------------------------------------------ launchers (k_walk.hip)
@@ -140,8 +139,7 @@ void launch_classify(GroupArrays gr, uint32_t n_groups, uint32_t *lists, uint32_
 // first, round-robin over the n_streams streams (the caller forks and joins them).
 void launch_force_f32(NodeArrays nd, GroupArrays gr, const uint32_t *lists, uint32_t stride,
                       const uint32_t *class_counts, const uint64_t *off,
-                      const uint32_t *entries, const double *px, const double *py,
-                      const double *pz, const double *pm, const uint32_t *pidx,
+                      const uint32_t *entries, const double4 *ps, const uint32_t *pidx,
                       ForceParams fp, void *ax, void *ay, void *az, int out_prec,
                       const hipStream_t *streams, int n_streams);
 // FP32 pair routine on explicit positions, pair by pair (xg: host, 3 values).
@@ -152,8 +150,7 @@ void launch_pairwise_f32(int64_t n_i, const double *xi, int64_t n_j, const doubl
 void launch_kept_stats(GroupArrays gr, uint32_t n_groups, const uint32_t *kept,
                        unsigned long long *out, hipStream_t s);
 void launch_force_f64(NodeArrays nd, GroupArrays gr, uint32_t n_groups, const uint64_t *off,
-                      const uint32_t *entries, const double *px, const double *py,
-                      const double *pz, const double *pm, const uint32_t *pidx,
+                      const uint32_t *entries, const double4 *ps, const uint32_t *pidx,
                       ForceParams fp, void *ax, void *ay, void *az, int out_prec,
                       hipStream_t s);
 

@@ -183,23 +183,14 @@ __global__ __launch_bounds__(kSortThreads) void k_scatter(const uint64_t *__rest
     }
 }
 
-// Gather the (x, y, z, m) records into key order as four FP64 arrays.
+// Gather the (x, y, z, m) records into key order.
 __global__ __launch_bounds__(256) void k_permute(int64_t n, const uint32_t *__restrict__ idx,
                                                  const double4 *__restrict__ rec,
-                                                 double *__restrict__ px, double *__restrict__ py,
-                                                 double *__restrict__ pz,
-                                                 double *__restrict__ pm,
                                                  double4 *__restrict__ psrc)
 {
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
-         k += (int64_t)gridDim.x * blockDim.x) {
-        const double4 r = rec[idx[k]];
-        px[k] = r.x;
-        py[k] = r.y;
-        pz[k] = r.z;
-        pm[k] = r.w;
-        psrc[k] = r;
-    }
+         k += (int64_t)gridDim.x * blockDim.x)
+        psrc[k] = rec[idx[k]];
 }
 
 // Cube centre of a node from its code: ((i + 0.5) * L / 2^level) per axis.
@@ -363,11 +354,8 @@ __global__ __launch_bounds__(256) void k_emit(NodeArrays nd, const uint32_t *__r
     }
 }
 
-__global__ __launch_bounds__(256) void k_moments(NodeArrays nd, const double *__restrict__ px,
-                                                 const double *__restrict__ py,
-                                                 const double *__restrict__ pz,
-                                                 const double *__restrict__ pm, uint32_t lo,
-                                                 uint32_t hi)
+__global__ __launch_bounds__(256) void k_moments(NodeArrays nd, const double4 *__restrict__ ps,
+                                                 uint32_t lo, uint32_t hi)
 {
     for (uint32_t u = lo + blockIdx.x * blockDim.x + threadIdx.x; u < hi;
          u += gridDim.x * blockDim.x) {
@@ -376,11 +364,11 @@ __global__ __launch_bounds__(256) void k_moments(NodeArrays nd, const double *__
         if (nch == 0) {
             uint32_t f = nd.first[u], e = f + nd.count[u];
             for (uint32_t k = f; k < e; ++k) {
-                double mk = pm[k];
-                M += mk;
-                Sx += mk * px[k];
-                Sy += mk * py[k];
-                Sz += mk * pz[k];
+                const double4 r = ps[k];
+                M += r.w;
+                Sx += r.w * r.x;
+                Sy += r.w * r.y;
+                Sz += r.w * r.z;
             }
         } else {
             uint32_t cf = nd.child_first[u];
@@ -457,9 +445,7 @@ __global__ __launch_bounds__(256) void k_group_compact(const uint32_t *__restric
 // Eight lanes per group: exact min/max of its particle positions.
 __global__ __launch_bounds__(256) void k_group_bbox(NodeArrays nd, GroupArrays gr,
                                                     uint32_t n_groups,
-                                                    const double *__restrict__ px,
-                                                    const double *__restrict__ py,
-                                                    const double *__restrict__ pz)
+                                                    const double4 *__restrict__ ps)
 {
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t g = t >> 3;
@@ -473,7 +459,8 @@ __global__ __launch_bounds__(256) void k_group_bbox(NodeArrays nd, GroupArrays g
     }
     double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     for (uint32_t k = f + sub; k < f + c; k += 8) {
-        double p[3] = {px[k], py[k], pz[k]};
+        const double4 r = ps[k];
+        double p[3] = {r.x, r.y, r.z};
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             lo[a] = fmin(lo[a], p[a]);
@@ -581,10 +568,10 @@ void radix_sort(int64_t n, uint64_t *key, uint32_t *idx, uint64_t *key_alt, uint
     // 64 / kSortBits passes is even: the result is back in key / idx.
 }
 
-void launch_permute(int64_t n, const uint32_t *idx, const double4 *rec, double *px,
-                    double *py, double *pz, double *pm, double4 *psrc, hipStream_t s)
+void launch_permute(int64_t n, const uint32_t *idx, const double4 *rec, double4 *psrc,
+                    hipStream_t s)
 {
-    k_permute<<<grid_for(n, 256), 256, 0, s>>>(n, idx, rec, px, py, pz, pm, psrc);
+    k_permute<<<grid_for(n, 256), 256, 0, s>>>(n, idx, rec, psrc);
 }
 
 void launch_root(NodeArrays nd, uint32_t n, double L, hipStream_t s)
@@ -606,10 +593,9 @@ void launch_emit(NodeArrays nd, const uint32_t *bnd, uint32_t lo, uint32_t hi, i
     k_emit<<<grid_for(hi - lo, 256), 256, 0, s>>>(nd, bnd, lo, hi, level, base, cnt, L);
 }
 
-void launch_moments(NodeArrays nd, const double *px, const double *py, const double *pz,
-                    const double *pm, uint32_t lo, uint32_t hi, hipStream_t s)
+void launch_moments(NodeArrays nd, const double4 *ps, uint32_t lo, uint32_t hi, hipStream_t s)
 {
-    k_moments<<<grid_for(hi - lo, 256), 256, 0, s>>>(nd, px, py, pz, pm, lo, hi);
+    k_moments<<<grid_for(hi - lo, 256), 256, 0, s>>>(nd, ps, lo, hi);
 }
 
 void launch_com_divide(NodeArrays nd, uint32_t n_nodes, WalkNode *wn, hipStream_t s)
@@ -631,13 +617,12 @@ void launch_group_compact(const uint32_t *gstart, const uint32_t *gpos, int64_t 
     k_group_compact<<<grid_for(n, 256), 256, 0, s>>>(gstart, gpos, n, gnode);
 }
 
-void launch_group_bbox(NodeArrays nd, GroupArrays gr, uint32_t n_groups, const double *px,
-                       const double *py, const double *pz, unsigned *min_level,
-                       unsigned *max_count, hipStream_t s)
+void launch_group_bbox(NodeArrays nd, GroupArrays gr, uint32_t n_groups, const double4 *ps,
+                       unsigned *min_level, unsigned *max_count, hipStream_t s)
 {
     if (!n_groups) return;
     k_group_bbox<<<(unsigned)(((uint64_t)n_groups * 8 + 255) / 256), 256, 0, s>>>(nd, gr, n_groups,
-                                                                                px, py, pz);
+                                                                                ps);
     k_group_extremes<<<grid_for(n_groups, 256, 256), 256, 0, s>>>(nd, gr, n_groups, min_level,
                                                                  max_count);
 }

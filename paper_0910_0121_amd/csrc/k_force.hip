@@ -255,10 +255,7 @@ __device__ __forceinline__ void tile_pass(const float4 *ts, int steps, const flo
 template <int K, int OUT64>
 __device__ __forceinline__ void force_group_f32(float4 *tile, double *red, NodeArrays nd,
                                                 uint32_t n_g, uint32_t f, const uint32_t *list,
-                                                uint64_t Lg, const double *__restrict__ px,
-                                                const double *__restrict__ py,
-                                                const double *__restrict__ pz,
-                                                const double *__restrict__ pm,
+                                                uint64_t Lg, const double4 *__restrict__ ps,
                                                 const uint32_t *__restrict__ pidx,
                                                 const GroupFrame &F, float eps2, double scale,
                                                 void *ax, void *ay, void *az, uint32_t *kept_out)
@@ -280,9 +277,10 @@ __device__ __forceinline__ void force_group_f32(float4 *tile, double *red, NodeA
             const uint32_t i = ib + slot + S * k;
             xi[k] = yi[k] = zi[k] = 0.f;
             if (i < n_g) {
-                xi[k] = (float)((px[f + i] - F.xg0) * F.inv_eta);
-                yi[k] = (float)((py[f + i] - F.xg1) * F.inv_eta);
-                zi[k] = (float)((pz[f + i] - F.xg2) * F.inv_eta);
+                const double4 r = ps[f + i];
+                xi[k] = (float)((r.x - F.xg0) * F.inv_eta);
+                yi[k] = (float)((r.y - F.xg1) * F.inv_eta);
+                zi[k] = (float)((r.z - F.xg2) * F.inv_eta);
             }
             hx[k] = hy[k] = hz[k] = lx[k] = ly[k] = lz[k] = 0.f;
         }
@@ -346,8 +344,7 @@ template <int K, int OUT64>
 __global__ __launch_bounds__(64, force_waves_per_simd(K)) void k_force_f32(
     NodeArrays nd, GroupArrays gr, const uint32_t *__restrict__ ids, uint32_t n_ids,
     const uint64_t *__restrict__ off, const uint32_t *__restrict__ entries,
-    const double *__restrict__ px, const double *__restrict__ py, const double *__restrict__ pz,
-    const double *__restrict__ pm, const uint32_t *__restrict__ pidx, ForceParams fp, void *ax,
+    const double4 *__restrict__ ps, const uint32_t *__restrict__ pidx, ForceParams fp, void *ax,
     void *ay, void *az)
 {
     __shared__ float4 tile[kTileF32 + 8];
@@ -368,7 +365,7 @@ __global__ __launch_bounds__(64, force_waves_per_simd(K)) void k_force_f32(
     F.inv_eta = fp.inv_eta;
     const float eps2 = (float)(fp.eps2 * fp.inv_eta * fp.inv_eta);
     const double scale = fp.inv_eta * fp.inv_eta;
-    force_group_f32<K, OUT64>(tile, red, nd, n_g, f, entries + b, Lg, px, py, pz, pm, pidx, F,
+    force_group_f32<K, OUT64>(tile, red, nd, n_g, f, entries + b, Lg, ps, pidx, F,
                               eps2, scale, ax, ay, az, fp.kept + g);
 }
 
@@ -464,8 +461,7 @@ struct d4 {
 template <int OUT64>
 __global__ __launch_bounds__(64) void k_force_f64(
     NodeArrays nd, GroupArrays gr, uint32_t n_groups, const uint64_t *__restrict__ off,
-    const uint32_t *__restrict__ entries, const double *__restrict__ px,
-    const double *__restrict__ py, const double *__restrict__ pz, const double *__restrict__ pm,
+    const uint32_t *__restrict__ entries, const double4 *__restrict__ ps,
     const uint32_t *__restrict__ pidx, ForceParams fp, void *ax, void *ay, void *az)
 {
     __shared__ d4 tile[kTileJ];
@@ -481,9 +477,10 @@ __global__ __launch_bounds__(64) void k_force_f64(
         const bool act = i < n_g;
         double xi = 0.0, yi = 0.0, zi = 0.0;
         if (act) {
-            xi = px[f + i];
-            yi = py[f + i];
-            zi = pz[f + i];
+            const double4 r = ps[f + i];
+            xi = r.x;
+            yi = r.y;
+            zi = r.z;
         }
         double ax_ = 0.0, ay_ = 0.0, az_ = 0.0;
         for (uint64_t jb = 0; jb < Lg; jb += kTileJ) {
@@ -529,8 +526,7 @@ void launch_classify(GroupArrays gr, uint32_t n_groups, uint32_t *lists, uint32_
 
 void launch_force_f32(NodeArrays nd, GroupArrays gr, const uint32_t *lists, uint32_t stride,
                       const uint32_t *class_counts, const uint64_t *off,
-                      const uint32_t *entries, const double *px, const double *py,
-                      const double *pz, const double *pm, const uint32_t *pidx,
+                      const uint32_t *entries, const double4 *ps, const uint32_t *pidx,
                       ForceParams fp, void *ax, void *ay, void *az, int out_prec,
                       const hipStream_t *streams, int n_streams)
 {
@@ -541,11 +537,11 @@ void launch_force_f32(NodeArrays nd, GroupArrays gr, const uint32_t *lists, uint
         hipStream_t s = streams[next++ % n_streams];                                           \
         if (out_prec)                                                                          \
             k_force_f32<KK, 1><<<class_counts[KK - 1], 64, 0, s>>>(                            \
-                nd, gr, ids, class_counts[KK - 1], off, entries, px, py, pz, pm, pidx, fp, ax, \
+                nd, gr, ids, class_counts[KK - 1], off, entries, ps, pidx, fp, ax, \
                 ay, az);                                                                       \
         else                                                                                   \
             k_force_f32<KK, 0><<<class_counts[KK - 1], 64, 0, s>>>(                            \
-                nd, gr, ids, class_counts[KK - 1], off, entries, px, py, pz, pm, pidx, fp, ax, \
+                nd, gr, ids, class_counts[KK - 1], off, entries, ps, pidx, fp, ax, \
                 ay, az);                                                                       \
     }
     TPM_LAUNCH(8)
@@ -581,18 +577,17 @@ void launch_kept_stats(GroupArrays gr, uint32_t n_groups, const uint32_t *kept,
 }
 
 void launch_force_f64(NodeArrays nd, GroupArrays gr, uint32_t n_groups, const uint64_t *off,
-                      const uint32_t *entries, const double *px, const double *py,
-                      const double *pz, const double *pm, const uint32_t *pidx,
+                      const uint32_t *entries, const double4 *ps, const uint32_t *pidx,
                       ForceParams fp, void *ax, void *ay, void *az, int out_prec,
                       hipStream_t s)
 {
     if (!n_groups) return;
     if (out_prec)
-        k_force_f64<1><<<n_groups, 64, 0, s>>>(nd, gr, n_groups, off, entries, px, py, pz, pm,
-                                              pidx, fp, ax, ay, az);
+        k_force_f64<1><<<n_groups, 64, 0, s>>>(nd, gr, n_groups, off, entries, ps, pidx, fp,
+                                              ax, ay, az);
     else
-        k_force_f64<0><<<n_groups, 64, 0, s>>>(nd, gr, n_groups, off, entries, px, py, pz, pm,
-                                              pidx, fp, ax, ay, az);
+        k_force_f64<0><<<n_groups, 64, 0, s>>>(nd, gr, n_groups, off, entries, ps, pidx, fp,
+                                              ax, ay, az);
 }
 
 } // namespace tpm

@@ -54,7 +54,7 @@ struct treepm_ctx {
     hipEvent_t ev[6] = {};
     bool ev_valid[3] = {false, false, false};
     // particles and sort
-    Buf in[4], key, key_alt, idx, idx_alt, pos[4], hist, scan32, flags, levcnt, gstart, gflag;
+    Buf in[4], key, key_alt, idx, idx_alt, hist, scan32, flags, levcnt, gstart, gflag;
     Buf rec; // (x, y, z, m) records in input order, for the gather
     // nodes
     Buf n_code, n_first, n_count, n_cf, n_parent, n_nch, n_level, n_mass, n_com[3], n_cn[3];
@@ -289,8 +289,7 @@ int do_build(treepm_ctx *c, int64_t n, const double *x, const double *y, const d
         Buf *b;
         size_t bytes;
     } res[] = {{&c->key, N * 8},         {&c->key_alt, N * 8},   {&c->idx, N * 4},
-               {&c->idx_alt, N * 4},     {&c->pos[0], N * 8},    {&c->pos[1], N * 8},
-               {&c->pos[2], N * 8},      {&c->pos[3], N * 8},    {&c->flags, 64},
+               {&c->idx_alt, N * 4},     {&c->flags, 64},
                {&c->levcnt, (N + 1) * 4 + scan_tmp_elems(N + 1) * 4 + 64},
                {&c->gstart, N * 4},      {&c->gflag, (N + 1) * 4},
                {&c->hist, sort_hist_elems(n) * 4},
@@ -323,9 +322,7 @@ int do_build(treepm_ctx *c, int64_t n, const double *x, const double *y, const d
     uint32_t *scan_tmp = c->scan32.as<uint32_t>();
     radix_sort(n, c->key.as<uint64_t>(), c->idx.as<uint32_t>(), c->key_alt.as<uint64_t>(),
                c->idx_alt.as<uint32_t>(), c->hist.as<uint32_t>(), scan_tmp, s);
-    launch_permute(n, c->idx.as<uint32_t>(), c->rec.as<double4>(), c->pos[0].as<double>(),
-                   c->pos[1].as<double>(), c->pos[2].as<double>(), c->pos[3].as<double>(),
-                   c->psrc.as<double4>(), s);
+    launch_permute(n, c->idx.as<uint32_t>(), c->rec.as<double4>(), c->psrc.as<double4>(), s);
     // octree, level by level
     c->n_nodes = 0;
     if ((rc = ensure_nodes(c, std::max<size_t>(1024, N / 2 + 64), s))) return rc;
@@ -359,10 +356,9 @@ int do_build(treepm_ctx *c, int64_t n, const double *x, const double *y, const d
         c->n_nodes = hi + add;
     }
     nd = nodes_view(c);
-    const double *px = c->pos[0].as<double>(), *py = c->pos[1].as<double>(),
-                 *pz = c->pos[2].as<double>(), *pm = c->pos[3].as<double>();
+    const double4 *ps = c->psrc.as<double4>();
     for (int l = c->max_level; l >= 0; --l)
-        launch_moments(nd, px, py, pz, pm, c->lvl[l], c->lvl[l + 1], s);
+        launch_moments(nd, ps, c->lvl[l], c->lvl[l + 1], s);
     {
         hipError_t e = reserve(c->n_walk, (size_t)c->n_nodes * sizeof(WalkNode));
         if (e == hipSuccess) e = reserve(c->n_src, (size_t)c->n_nodes * sizeof(double4));
@@ -383,7 +379,7 @@ int do_build(treepm_ctx *c, int64_t n, const double *x, const double *y, const d
     unsigned *misc = c->g_misc.as<unsigned>();
     fill_u32(misc, 1, 255u, s);
     fill_u32(misc + 1, 1, 0u, s);
-    launch_group_bbox(nd, gr, ng, px, py, pz, misc, misc + 1, s);
+    launch_group_bbox(nd, gr, ng, ps, misc, misc + 1, s);
     unsigned hm[2] = {0, 0};
     if ((rc = d2h(c, hm, misc, 2, s))) return rc;
     c->n_groups = ng;
@@ -491,7 +487,7 @@ void retain_pool(int device)
 size_t treepm_internal_ctx_bytes(const treepm_ctx *c)
 {
     const Buf *all[] = {&c->in[0], &c->in[1], &c->in[2], &c->in[3], &c->key, &c->key_alt,
-                        &c->idx, &c->idx_alt, &c->pos[0], &c->pos[1], &c->pos[2], &c->pos[3],
+                        &c->idx, &c->idx_alt,
                         &c->hist, &c->scan32, &c->flags, &c->levcnt, &c->gstart, &c->gflag,
                         &c->rec, &c->n_code, &c->n_first, &c->n_count, &c->n_cf, &c->n_parent,
                         &c->n_nch, &c->n_level, &c->n_mass, &c->n_com[0], &c->n_com[1],
@@ -562,7 +558,7 @@ TREEPM_API int treepm_destroy(treepm_ctx *c)
     if (c->last) hipStreamSynchronize(c->last);
     else hipDeviceSynchronize();
     Buf *all[] = {&c->in[0], &c->in[1], &c->in[2], &c->in[3], &c->key, &c->key_alt, &c->idx,
-                  &c->idx_alt, &c->pos[0], &c->pos[1], &c->pos[2], &c->pos[3], &c->hist,
+                  &c->idx_alt, &c->hist,
                   &c->scan32, &c->flags, &c->levcnt, &c->gstart, &c->gflag, &c->n_code,
                   &c->n_first, &c->n_count, &c->n_cf, &c->n_parent, &c->n_nch, &c->n_level,
                   &c->n_mass, &c->n_com[0], &c->n_com[1], &c->n_com[2], &c->n_cn[0],
@@ -719,9 +715,8 @@ TREEPM_API int treepm_force_short(treepm_ctx *c, void *ax, void *ay, void *az, i
         }
         launch_force_f32(nd, gr, c->cls.as<uint32_t>() + kForceClasses, c->n_groups + 1,
                          c->class_counts, c->off.as<uint64_t>(), c->entries.as<uint32_t>(),
-                         c->pos[0].as<double>(), c->pos[1].as<double>(),
-                         c->pos[2].as<double>(), c->pos[3].as<double>(),
-                         c->idx.as<uint32_t>(), fp, dst[0], dst[1], dst[2], out_prec, streams,
+                         c->psrc.as<double4>(), c->idx.as<uint32_t>(), fp, dst[0], dst[1],
+                         dst[2], out_prec, streams,
                          ns);
         if (c->fork)
             for (int i = 0; i < treepm_ctx::kSubStreams; ++i) {
@@ -730,9 +725,8 @@ TREEPM_API int treepm_force_short(treepm_ctx *c, void *ax, void *ay, void *az, i
             }
     } else
         launch_force_f64(nd, gr, c->n_groups, c->off.as<uint64_t>(), c->entries.as<uint32_t>(),
-                         c->pos[0].as<double>(), c->pos[1].as<double>(),
-                         c->pos[2].as<double>(), c->pos[3].as<double>(),
-                         c->idx.as<uint32_t>(), fp, dst[0], dst[1], dst[2], out_prec, s);
+                         c->psrc.as<double4>(), c->idx.as<uint32_t>(), fp, dst[0], dst[1],
+                         dst[2], out_prec, s);
     HIPCHK(c, hipGetLastError());
     record(c, 5, s);
     if (P.precision == TREEPM_FP32)
