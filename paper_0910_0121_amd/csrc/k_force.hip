@@ -233,12 +233,21 @@ __device__ __forceinline__ void tile_pass(const float4 *ts, int steps, const flo
                                           float *tx, float *ty, float *tz)
 {
     int t = 0;
-    for (; t + 2 <= steps; t += 2) {
-        const float4 s0 = ts[t], s1 = ts[t + 1];
+    if (K < 4) { // two rows per iteration; larger K has enough independent pairs per row
+        for (; t + 2 <= steps; t += 2) {
+            const float4 s0 = ts[t], s1 = ts[t + 1];
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-            pair_f32<FAR>(s0, xi[k], yi[k], zi[k], eps2, tx[k], ty[k], tz[k]);
-            pair_f32<FAR>(s1, xi[k], yi[k], zi[k], eps2, tx[k], ty[k], tz[k]);
+            for (int k = 0; k < K; ++k) {
+                pair_f32<FAR>(s0, xi[k], yi[k], zi[k], eps2, tx[k], ty[k], tz[k]);
+                pair_f32<FAR>(s1, xi[k], yi[k], zi[k], eps2, tx[k], ty[k], tz[k]);
+            }
+        }
+    } else {
+        for (; t + 1 < steps; ++t) {
+            const float4 s0 = ts[t];
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+                pair_f32<FAR>(s0, xi[k], yi[k], zi[k], eps2, tx[k], ty[k], tz[k]);
         }
     }
     if (t < steps) {
@@ -338,7 +347,7 @@ __device__ __forceinline__ void force_group_f32(float4 *tile, double *red, NodeA
 // One launch per blocking factor K (see k_classify), so each gets its own register budget.
 // Up to K = 4 the kernel fits 128 VGPRs without spilling (4 waves per SIMD); K = 5 runs at
 // 3 waves and larger K at 2.
-constexpr int force_waves_per_simd(int K) { return K <= 4 ? 4 : K == 5 ? 3 : 2; }
+constexpr int force_waves_per_simd(int K) { return K <= 5 ? 4 : K <= 7 ? 3 : 2; }
 
 template <int K, int OUT64>
 __global__ __launch_bounds__(64, force_waves_per_simd(K)) void k_force_f32(
