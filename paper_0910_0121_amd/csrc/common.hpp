@@ -75,6 +75,17 @@ void launch_keys(int64_t n, const double *x, const double *y, const double *z, c
 size_t sort_hist_elems(int64_t n);
 void radix_sort(int64_t n, uint64_t *key, uint32_t *idx, uint64_t *key_alt, uint32_t *idx_alt,
                 uint32_t *hist, uint32_t *scan_tmp, hipStream_t s);
+// The sort in two steps: stable passes over bits [kRunBits, 64) only, then each run of equal
+// high bits sorted by (key, index) in place.  Returns true if the result is in key_alt /
+// idx_alt (an odd number of passes).  long_runs holds long_cap entries; flags (device, two
+// words) ends with flags[1] != 0 if a run could not be sorted this way: the order is then
+// incomplete and radix_sort (on the returned arrays) must follow.
+constexpr int kRunBits = 24;
+constexpr uint32_t kShortRun = 32;
+constexpr uint32_t kLongRun = 2048;
+bool radix_sort_high(int64_t n, uint64_t *key, uint32_t *idx, uint64_t *key_alt,
+                     uint32_t *idx_alt, uint32_t *hist, uint32_t *scan_tmp, uint2 *long_runs,
+                     uint32_t long_cap, unsigned *flags, hipStream_t s);
 // Also writes the key-ordered records psrc (x, y, z, m).
 void launch_permute(int64_t n, const uint32_t *idx, const double4 *rec, double4 *psrc,
                     hipStream_t s);

@@ -183,6 +183,82 @@ __global__ __launch_bounds__(kSortThreads) void k_scatter(const uint64_t *__rest
     }
 }
 
+// Second half of the sort.  After stable passes over the key bits from kRunBits up, equal
+// high parts form runs (cells of about level 13, rarely more than a few particles) in input
+// order; sorting each run by (key, index) completes the order by (key, index).  One thread
+// per run start sorts a run of up to kShortRun elements by insertion; longer runs, up to
+// kLongRun, are listed for k_fix_long_runs; a run longer than that (or a full list) sets
+// *fallback, and the caller then sorts everything by all bits.  Elements of one run share the
+// high part, so reading neighbours while their runs are being reordered is harmless.
+__global__ __launch_bounds__(256) void k_fix_runs(int64_t n, uint64_t *__restrict__ key,
+                                                  uint32_t *__restrict__ idx,
+                                                  uint2 *__restrict__ long_runs,
+                                                  uint32_t long_cap, unsigned *long_count,
+                                                  unsigned *fallback)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t hk = key[i] >> kRunBits;
+        if (i > 0 && (key[i - 1] >> kRunBits) == hk) continue;
+        int64_t e = i + 1;
+        while (e < n && e - i <= (int64_t)kLongRun && (key[e] >> kRunBits) == hk) ++e;
+        const int64_t len = e - i;
+        if (len > (int64_t)kShortRun) {
+            const unsigned slot = len <= (int64_t)kLongRun ? atomicAdd(long_count, 1u) : long_cap;
+            if (slot < long_cap)
+                long_runs[slot] = make_uint2((uint32_t)i, (uint32_t)len);
+            else
+                atomicOr(fallback, 1u);
+            continue;
+        }
+        for (int64_t a = i + 1; a < e; ++a) {
+            const uint64_t k = key[a];
+            const uint32_t v = idx[a];
+            int64_t b = a - 1;
+            while (b >= i && (key[b] > k || (key[b] == k && idx[b] > v))) {
+                key[b + 1] = key[b];
+                idx[b + 1] = idx[b];
+                --b;
+            }
+            key[b + 1] = k;
+            idx[b + 1] = v;
+        }
+    }
+}
+
+// Listed runs, one block each: the run is staged in LDS and every element is written to the
+// position given by its rank, the number of elements before it in (key, index) order.
+__global__ __launch_bounds__(256) void k_fix_long_runs(const uint2 *__restrict__ long_runs,
+                                                       const unsigned *long_count,
+                                                       uint32_t long_cap,
+                                                       uint64_t *__restrict__ key,
+                                                       uint32_t *__restrict__ idx)
+{
+    __shared__ uint64_t sk[kLongRun];
+    __shared__ uint32_t si[kLongRun];
+    unsigned cnt = *long_count;
+    cnt = cnt < long_cap ? cnt : long_cap;
+    for (unsigned r = blockIdx.x; r < cnt; r += gridDim.x) {
+        const uint2 run = long_runs[r];
+        const uint32_t f = run.x, len = run.y;
+        for (uint32_t j = threadIdx.x; j < len; j += blockDim.x) {
+            sk[j] = key[f + j];
+            si[j] = idx[f + j];
+        }
+        __syncthreads();
+        for (uint32_t j = threadIdx.x; j < len; j += blockDim.x) {
+            const uint64_t kj = sk[j];
+            const uint32_t vj = si[j];
+            uint32_t rank = 0;
+            for (uint32_t q = 0; q < len; ++q)
+                rank += (sk[q] < kj || (sk[q] == kj && si[q] < vj)) ? 1u : 0u;
+            key[f + rank] = kj;
+            idx[f + rank] = vj;
+        }
+        __syncthreads();
+    }
+}
+
 // Gather the (x, y, z, m) records into key order.
 __global__ __launch_bounds__(256) void k_permute(int64_t n, const uint32_t *__restrict__ idx,
                                                  const double4 *__restrict__ rec,
@@ -551,21 +627,43 @@ size_t sort_hist_elems(int64_t n)
     return nb * kSortBins;
 }
 
-void radix_sort(int64_t n, uint64_t *key, uint32_t *idx, uint64_t *key_alt, uint32_t *idx_alt,
-                uint32_t *hist, uint32_t *scan_tmp, hipStream_t s)
+// Stable LSD passes over bits [lo_bit, 64) of the keys, 8 bits per pass; an even number of
+// passes leaves the result in key / idx.
+static void radix_passes(int64_t n, int lo_bit, uint64_t *key, uint32_t *idx, uint64_t *key_alt,
+                         uint32_t *idx_alt, uint32_t *hist, uint32_t *scan_tmp, hipStream_t s)
 {
-    if (n <= 1) return;
     uint32_t nb = (uint32_t)((n + kSortTile - 1) / kSortTile);
     uint64_t *kin = key, *kout = key_alt;
     uint32_t *iin = idx, *iout = idx_alt;
-    for (int shift = 0; shift < 64; shift += kSortBits) {
+    for (int shift = lo_bit; shift < 64; shift += kSortBits) {
         k_hist<<<nb, kSortThreads, 0, s>>>(kin, n, shift, hist, nb);
         scan_u32(hist, (size_t)nb * kSortBins, scan_tmp, scan_tmp + 1, s);
         k_scatter<<<nb, kSortThreads, 0, s>>>(kin, iin, n, shift, hist, nb, kout, iout);
         uint64_t *tk = kin; kin = kout; kout = tk;
         uint32_t *ti = iin; iin = iout; iout = ti;
     }
-    // 64 / kSortBits passes is even: the result is back in key / idx.
+}
+
+bool radix_sort_high(int64_t n, uint64_t *key, uint32_t *idx, uint64_t *key_alt,
+                     uint32_t *idx_alt, uint32_t *hist, uint32_t *scan_tmp, uint2 *long_runs,
+                     uint32_t long_cap, unsigned *flags, hipStream_t s)
+{
+    fill_u32(flags, 2, 0u, s); // [0] listed long runs, [1] fallback
+    if (n <= 1) return false;
+    radix_passes(n, kRunBits, key, idx, key_alt, idx_alt, hist, scan_tmp, s);
+    const bool odd = ((64 - kRunBits) / kSortBits) % 2 == 1;
+    uint64_t *k = odd ? key_alt : key;
+    uint32_t *v = odd ? idx_alt : idx;
+    k_fix_runs<<<grid_for(n, 256), 256, 0, s>>>(n, k, v, long_runs, long_cap, flags, flags + 1);
+    k_fix_long_runs<<<256, 256, 0, s>>>(long_runs, flags, long_cap, k, v);
+    return odd;
+}
+
+void radix_sort(int64_t n, uint64_t *key, uint32_t *idx, uint64_t *key_alt, uint32_t *idx_alt,
+                uint32_t *hist, uint32_t *scan_tmp, hipStream_t s)
+{
+    if (n <= 1) return;
+    radix_passes(n, 0, key, idx, key_alt, idx_alt, hist, scan_tmp, s);
 }
 
 void launch_permute(int64_t n, const uint32_t *idx, const double4 *rec, double4 *psrc,

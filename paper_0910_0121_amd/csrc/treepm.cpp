@@ -71,7 +71,7 @@ struct treepm_ctx {
     uint32_t n_groups = 0;
     unsigned min_group_level = 0, max_group = 0;
     // lists
-    Buf off, scan64, entries, wstats, overflow, gcells, cls, kept, kept_sum, out[3], bnd;
+    Buf off, scan64, entries, wstats, overflow, gcells, cls, kept, kept_sum, out[3], bnd, runs;
     int last_force_prec = -1;
     uint32_t class_counts[kForceClasses] = {};
     uint64_t n_entries = 0;
@@ -320,8 +320,27 @@ int do_build(treepm_ctx *c, int64_t n, const double *x, const double *y, const d
     if (hf & kFlagRange)
         return fail(c, TREEPM_ERR_RANGE, "a position lies outside [0, L); wrap it first");
     uint32_t *scan_tmp = c->scan32.as<uint32_t>();
-    radix_sort(n, c->key.as<uint64_t>(), c->idx.as<uint32_t>(), c->key_alt.as<uint64_t>(),
-               c->idx_alt.as<uint32_t>(), c->hist.as<uint32_t>(), scan_tmp, s);
+    {
+        // high key bits first, runs of equal high bits sorted in place; all bits if a run is
+        // too long for that
+        unsigned *sflags = c->flags.as<unsigned>() + 4;
+        const uint32_t long_cap = (uint32_t)(N / (kShortRun + 1) + 1);
+        hipError_t e = reserve(c->runs, (size_t)long_cap * sizeof(uint2));
+        if (e != hipSuccess) return hip_fail(c, e, "sort runs");
+        if (radix_sort_high(n, c->key.as<uint64_t>(), c->idx.as<uint32_t>(),
+                            c->key_alt.as<uint64_t>(), c->idx_alt.as<uint32_t>(),
+                            c->hist.as<uint32_t>(), scan_tmp, c->runs.as<uint2>(), long_cap,
+                            sflags, s)) {
+            std::swap(c->key, c->key_alt);
+            std::swap(c->idx, c->idx_alt);
+        }
+        unsigned fb = 0;
+        if ((rc = d2h(c, &fb, sflags + 1, 1, s))) return rc;
+        if (fb)
+            radix_sort(n, c->key.as<uint64_t>(), c->idx.as<uint32_t>(),
+                       c->key_alt.as<uint64_t>(), c->idx_alt.as<uint32_t>(),
+                       c->hist.as<uint32_t>(), scan_tmp, s);
+    }
     launch_permute(n, c->idx.as<uint32_t>(), c->rec.as<double4>(), c->psrc.as<double4>(), s);
     // octree, level by level
     c->n_nodes = 0;
@@ -498,7 +517,7 @@ size_t treepm_internal_ctx_bytes(const treepm_ctx *c)
                         &c->g_xg[1], &c->g_xg[2], &c->g_lo[0], &c->g_lo[1], &c->g_lo[2],
                         &c->g_hi[0], &c->g_hi[1], &c->g_hi[2], &c->g_misc, &c->off, &c->scan64,
                         &c->entries, &c->wstats, &c->overflow, &c->gcells, &c->cls,
-                        &c->kept, &c->kept_sum, &c->out[0], &c->out[1], &c->out[2], &c->bnd};
+                        &c->kept, &c->kept_sum, &c->out[0], &c->out[1], &c->out[2], &c->bnd, &c->runs};
     size_t t = 0;
     for (const Buf *b : all) t += b->bytes;
     return t;
@@ -567,7 +586,7 @@ TREEPM_API int treepm_destroy(treepm_ctx *c)
                   &c->g_xg[1], &c->g_xg[2], &c->g_lo[0], &c->g_lo[1], &c->g_lo[2], &c->g_hi[0],
                   &c->g_hi[1], &c->g_hi[2], &c->g_misc, &c->off, &c->scan64, &c->entries,
                   &c->wstats, &c->overflow, &c->rec, &c->kept, &c->kept_sum, &c->gcells, &c->cls, &c->out[0],
-                  &c->out[1], &c->out[2], &c->bnd};
+                  &c->out[1], &c->out[2], &c->bnd, &c->runs};
     {
         CallScope scope(c, c->last);
         for (Buf *b : all) release(*b);

@@ -230,6 +230,43 @@ def test_host_buffers_and_fp32_output(tp, orc):
     a.close(); b.close()
 
 
+def _clumped_box(n_uniform, clumps, seed):
+    """Uniform particles plus clumps, each inside one cell of side 2^-11, so each clump's keys
+    share their high bits and differ in the low ones; clump sizes are given.  Every fifth
+    clump member repeats its predecessor's position exactly (equal keys, ordered by index)."""
+    rng = boxgen.SplitMix64(seed)
+    parts = [rng.uniform(3 * n_uniform).reshape(3, n_uniform)]
+    for size in clumps:
+        corner = np.floor(rng.uniform(3) * 2048.0) / 2048.0
+        off = rng.uniform(3 * size).reshape(3, size) * (1.0 / 2048.0)
+        off[:, 4::5] = off[:, 3::5][:, : off[:, 4::5].shape[1]]
+        parts.append(corner[:, None] + off)
+    p = np.concatenate(parts, axis=1)
+    perm = np.argsort(rng.next_u64(p.shape[1]), kind="stable")
+    x, y, z = (np.ascontiguousarray(p[a, perm]) for a in range(3))
+    return x, y, z, np.full(x.size, 1.0 / x.size)
+
+
+@pytest.mark.parametrize("clumps", [[2, 3, 17, 40, 64, 64, 5] * 6, [2, 64, 65, 300]],
+                         ids=["runs-up-to-64", "runs-over-64"])
+def test_sort_order_with_clumps(tp, orc, clumps):
+    """Keys sorted by their high bits, then runs of equal high bits in place (longer runs fall
+    back to sorting all bits): the order must still be (key, input index) exactly."""
+    _say(f"sort order, clumps {sorted(set(clumps))}")
+    x, y, z, m = _clumped_box(3000, clumps, 91)
+    run = Run(tp, x, y, z, m, 1.0, 0.1, 0.002, 0.5, 10, 64, tp.TREEPM_FP64)
+    T = orc.Tree(x, y, z, m, 1.0, 0.1, 0.002, 0.5, 10, 64)
+    gk, gi = tp.treepm_export_sorted(run.ctx)
+    ok, oi = T.sorted()
+    np.testing.assert_array_equal(gk, ok)
+    np.testing.assert_array_equal(gi, oi)
+    gn, on = tp.treepm_export_nodes(run.ctx), T.nodes()
+    go, oo = np.argsort(gn["code"]), np.argsort(on["code"])
+    for k in ("code", "first", "count", "mass", "com"):
+        np.testing.assert_array_equal(gn[k][go], on[k][oo], err_msg=k)
+    run.close()
+
+
 def test_edge_cases(tp, orc):
     _say("edge cases")
     # a single particle feels nothing
