@@ -119,12 +119,26 @@ struct WalkParams {
     double L, rc2, th2;
     uint32_t n_nodes;
 };
-// Count (emit == 0) or write (emit == 1) the interaction list of every group.
-// The emit pass records each group's cell-entry count in gcells and adds (cell entries,
-// particle entries, interactions) into stats[0..2] (zeroed by the caller).
-void launch_walk(const WalkNode *wn, GroupArrays gr, uint32_t n_groups, WalkParams wp, int emit,
-                 uint64_t *counts_or_offsets, uint32_t *entries, unsigned *overflow,
-                 uint32_t *gcells, unsigned long long *stats, hipStream_t s);
+// Group g's interaction list is entries[off[g] .. off[g] + len[g]).
+// Two passes: the count pass writes each list length to counts[g]; after the caller's prefix
+// sum (counts -> off) the emit pass writes the lists, len and gcells (cell entries).
+void launch_walk_count(const WalkNode *wn, GroupArrays gr, uint32_t n_groups, WalkParams wp,
+                       uint64_t *counts, unsigned *overflow, hipStream_t s);
+void launch_walk_emit(const WalkNode *wn, GroupArrays gr, uint32_t n_groups, WalkParams wp,
+                      const uint64_t *off, uint32_t *len, uint32_t *entries, unsigned *overflow,
+                      uint32_t *gcells, hipStream_t s);
+// One pass: n_waves waves write the lists into chunks of `chunk` entries taken from the
+// pool entries[0, pool_cap); a group is walked into the wave's current chunk if at least
+// `reserve` entries are left there, else (or if it did not fit) into a fresh chunk.  Sets bit 4 of *overflow if a list or the pool ran out of room
+// (the lists are then incomplete).  counters holds kXcds + 2 words (8-byte aligned).
+void launch_walk_pool(const WalkNode *wn, GroupArrays gr, uint32_t n_groups, WalkParams wp,
+                      uint32_t n_waves, uint64_t pool_cap, uint64_t chunk, uint64_t reserve,
+                      uint32_t *counters, uint64_t *off, uint32_t *len, uint32_t *entries,
+                      unsigned *overflow, uint32_t *gcells, hipStream_t s);
+// Adds (cell entries, particle entries, interactions) into stats[0..2] and the longest list
+// into stats[3] (all zeroed by the caller).
+void launch_walk_stats(GroupArrays gr, uint32_t n_groups, const uint32_t *len,
+                       const uint32_t *gcells, unsigned long long *stats, hipStream_t s);
 
 // ------------------------------------------------------------------ launchers (k_force.hip)
 // Workgroups are dealt to the 8 XCDs (each with its own L2) round-robin by block index.
@@ -149,7 +163,7 @@ void launch_classify(GroupArrays gr, uint32_t n_groups, uint32_t *lists, uint32_
 // class_counts: host copy of the class sizes.  Classes are launched largest blocking factor
 // first, round-robin over the n_streams streams (the caller forks and joins them).
 void launch_force_f32(NodeArrays nd, GroupArrays gr, const uint32_t *lists, uint32_t stride,
-                      const uint32_t *class_counts, const uint64_t *off,
+                      const uint32_t *class_counts, const uint64_t *off, const uint32_t *len,
                       const uint32_t *entries, const double4 *ps, const uint32_t *pidx,
                       ForceParams fp, void *ax, void *ay, void *az, int out_prec,
                       const hipStream_t *streams, int n_streams);
@@ -161,7 +175,7 @@ void launch_pairwise_f32(int64_t n_i, const double *xi, int64_t n_j, const doubl
 void launch_kept_stats(GroupArrays gr, uint32_t n_groups, const uint32_t *kept,
                        unsigned long long *out, hipStream_t s);
 void launch_force_f64(NodeArrays nd, GroupArrays gr, uint32_t n_groups, const uint64_t *off,
-                      const uint32_t *entries, const double4 *ps, const uint32_t *pidx,
+                      const uint32_t *len, const uint32_t *entries, const double4 *ps, const uint32_t *pidx,
                       ForceParams fp, void *ax, void *ay, void *az, int out_prec,
                       hipStream_t s);
 

@@ -352,7 +352,7 @@ constexpr int force_waves_per_simd(int K) { return K <= 5 ? 4 : K <= 7 ? 3 : 2; 
 template <int K, int OUT64>
 __global__ __launch_bounds__(64, force_waves_per_simd(K)) void k_force_f32(
     NodeArrays nd, GroupArrays gr, const uint32_t *__restrict__ ids, uint32_t n_ids,
-    const uint64_t *__restrict__ off, const uint32_t *__restrict__ entries,
+    const uint64_t *__restrict__ off, const uint32_t *__restrict__ len, const uint32_t *__restrict__ entries,
     const double4 *__restrict__ ps, const uint32_t *__restrict__ pidx, ForceParams fp, void *ax,
     void *ay, void *az)
 {
@@ -363,7 +363,7 @@ __global__ __launch_bounds__(64, force_waves_per_simd(K)) void k_force_f32(
     const uint32_t g = ids[slot];
     const uint32_t n_g = gr.count[g], f = gr.first[g];
     const uint64_t b = off[g];
-    const uint64_t Lg = off[g + 1] - b;
+    const uint64_t Lg = len[g];
     GroupFrame F;
     F.xg0 = gr.xgx[g]; F.xg1 = gr.xgy[g]; F.xg2 = gr.xgz[g];
     F.cg0 = gr.cgx[g]; F.cg1 = gr.cgy[g]; F.cg2 = gr.cgz[g];
@@ -469,7 +469,7 @@ struct d4 {
 
 template <int OUT64>
 __global__ __launch_bounds__(64) void k_force_f64(
-    NodeArrays nd, GroupArrays gr, uint32_t n_groups, const uint64_t *__restrict__ off,
+    NodeArrays nd, GroupArrays gr, uint32_t n_groups, const uint64_t *__restrict__ off, const uint32_t *__restrict__ len,
     const uint32_t *__restrict__ entries, const double4 *__restrict__ ps,
     const uint32_t *__restrict__ pidx, ForceParams fp, void *ax, void *ay, void *az)
 {
@@ -479,7 +479,7 @@ __global__ __launch_bounds__(64) void k_force_f64(
     if (g >= n_groups) return;
     const uint32_t n_g = gr.count[g], f = gr.first[g];
     const uint64_t b = off[g];
-    const uint64_t Lg = off[g + 1] - b;
+    const uint64_t Lg = len[g];
     const double L = fp.L, eps2 = fp.eps2, eta = fp.eta;
     for (uint32_t ib = 0; ib < n_g; ib += 64) {
         const uint32_t i = ib + lane;
@@ -534,7 +534,7 @@ void launch_classify(GroupArrays gr, uint32_t n_groups, uint32_t *lists, uint32_
 }
 
 void launch_force_f32(NodeArrays nd, GroupArrays gr, const uint32_t *lists, uint32_t stride,
-                      const uint32_t *class_counts, const uint64_t *off,
+                      const uint32_t *class_counts, const uint64_t *off, const uint32_t *len,
                       const uint32_t *entries, const double4 *ps, const uint32_t *pidx,
                       ForceParams fp, void *ax, void *ay, void *az, int out_prec,
                       const hipStream_t *streams, int n_streams)
@@ -546,11 +546,11 @@ void launch_force_f32(NodeArrays nd, GroupArrays gr, const uint32_t *lists, uint
         hipStream_t s = streams[next++ % n_streams];                                           \
         if (out_prec)                                                                          \
             k_force_f32<KK, 1><<<class_counts[KK - 1], 64, 0, s>>>(                            \
-                nd, gr, ids, class_counts[KK - 1], off, entries, ps, pidx, fp, ax, \
+                nd, gr, ids, class_counts[KK - 1], off, len, entries, ps, pidx, fp, ax, \
                 ay, az);                                                                       \
         else                                                                                   \
             k_force_f32<KK, 0><<<class_counts[KK - 1], 64, 0, s>>>(                            \
-                nd, gr, ids, class_counts[KK - 1], off, entries, ps, pidx, fp, ax, \
+                nd, gr, ids, class_counts[KK - 1], off, len, entries, ps, pidx, fp, ax, \
                 ay, az);                                                                       \
     }
     TPM_LAUNCH(8)
@@ -586,16 +586,16 @@ void launch_kept_stats(GroupArrays gr, uint32_t n_groups, const uint32_t *kept,
 }
 
 void launch_force_f64(NodeArrays nd, GroupArrays gr, uint32_t n_groups, const uint64_t *off,
-                      const uint32_t *entries, const double4 *ps, const uint32_t *pidx,
+                      const uint32_t *len, const uint32_t *entries, const double4 *ps, const uint32_t *pidx,
                       ForceParams fp, void *ax, void *ay, void *az, int out_prec,
                       hipStream_t s)
 {
     if (!n_groups) return;
     if (out_prec)
-        k_force_f64<1><<<n_groups, 64, 0, s>>>(nd, gr, n_groups, off, entries, ps, pidx, fp,
+        k_force_f64<1><<<n_groups, 64, 0, s>>>(nd, gr, n_groups, off, len, entries, ps, pidx, fp,
                                               ax, ay, az);
     else
-        k_force_f64<0><<<n_groups, 64, 0, s>>>(nd, gr, n_groups, off, entries, ps, pidx, fp,
+        k_force_f64<0><<<n_groups, 64, 0, s>>>(nd, gr, n_groups, off, len, entries, ps, pidx, fp,
                                               ax, ay, az);
 }
 

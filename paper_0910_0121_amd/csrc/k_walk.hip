@@ -13,15 +13,24 @@
 //   else   : push the children.
 //
 // A list entry is a node index with kCellTag set (the node's mass at its centre of mass) or
-// a particle's position in key order.  The count pass records each group's list length;
-// after a prefix sum the emit pass writes the entries.  The traversal order depends only on
-// the tree, so both passes visit the same nodes in the same order.
+// a particle's position in key order.  Group g's list is entries[off[g] .. off[g] + len[g]).
+// Two ways to lay the lists out:
+//   * two passes: the count pass records each group's list length; after a prefix sum the
+//     emit pass writes the lists back to back.  The traversal order depends only on the tree,
+//     so both passes visit the same nodes in the same order.
+//   * one pass: a fixed set of waves takes groups in small batches from per-XCD counters;
+//     each wave writes its lists back to back into chunks it takes from a shared pool with
+//     one atomic per chunk (a list that does not fit the rest of a chunk is walked again into
+//     a fresh one).  Pool and chunk sizes come from the caller (from an earlier walk); if a
+//     list or the pool runs out of room, the pass reports it and the caller falls back to
+//     two passes, so the result never depends on those sizes.
 #include "common.hpp"
 
 namespace tpm {
 namespace {
 
 constexpr int kStackCap = 1024;
+constexpr uint32_t kWalkBatch = 4;
 
 // |wrap(v)| for |v| <= L (both points in [0, L)): min(|v|, L - |v|).  Bit for bit the
 // absolute value of the two-sided wrap (v - L if v >= L/2, v + L if v < -L/2, else v):
@@ -103,22 +112,22 @@ __device__ __forceinline__ Visit visit(const WalkNode &w, const WalkParams &wp, 
     return r;
 }
 
+// Walks group g with the calling wave.  EMIT: writes the list to dst[0 .. cap) (entries past
+// cap are counted but not stored).  Returns the list length; *ncell gets the cell entries.
+// stk (kStackCap) and s_mark (64) are the wave's LDS scratch.
 template <int EMIT>
-__global__ __launch_bounds__(64) void k_walk(const WalkNode *__restrict__ wn, GroupArrays gr,
-                                             uint32_t n_groups,
-                                             WalkParams wp, uint64_t *__restrict__ cnt_off,
-                                             uint32_t *__restrict__ entries,
-                                             unsigned *overflow, uint32_t *__restrict__ gcells)
+__device__ __forceinline__ uint64_t walk_group(const WalkNode *__restrict__ wn,
+                                               const GroupArrays &gr, uint32_t g,
+                                               const WalkParams &wp, uint32_t *stk,
+                                               uint32_t *s_mark, uint32_t *__restrict__ dst,
+                                               uint64_t cap, unsigned *overflow,
+                                               uint64_t *ncell_out)
 {
-    __shared__ uint32_t stk[kStackCap];
-    __shared__ uint32_t s_mark[64];
-    const uint32_t g = xcd_block(blockIdx.x, gridDim.x);
     const int lane = threadIdx.x;
-    if (g >= n_groups) return;
     const double cg0 = gr.cgx[g], cg1 = gr.cgy[g], cg2 = gr.cgz[g];
     const double hg0 = gr.hgx[g], hg1 = gr.hgy[g], hg2 = gr.hgz[g];
-    uint64_t out = EMIT ? cnt_off[g] : 0;
     uint64_t written = 0, ncell = 0;
+    __syncthreads(); // the previous group's last stack reads are done
     if (lane == 0) stk[0] = 0;
     int top = 1;
     __syncthreads();
@@ -148,7 +157,6 @@ __global__ __launch_bounds__(64) void k_walk(const WalkNode *__restrict__ wn, Gr
             // start slot with lane + 1; a running maximum over the chunk's slots then names
             // the owner of every slot (the previous chunk's last owner carries over).
             uint32_t carry = 0;
-            uint32_t *dst = entries + out + written;
             const uint32_t val = a.kind == 1 ? (u | kCellTag) : a.f;
             for (uint32_t base = 0; base < ne_tot; base += 64) {
                 s_mark[lane] = 0u;
@@ -163,7 +171,7 @@ __global__ __launch_bounds__(64) void k_walk(const WalkNode *__restrict__ wn, Gr
                 const uint32_t ex = (uint32_t)__shfl((int)ne_ex, src, 64);
                 const int cell = __shfl(a.kind == 1 ? 1 : 0, src, 64);
                 const uint32_t q = base + lane;
-                if (q < ne_tot) dst[q] = cell ? v : v + (q - ex);
+                if (q < ne_tot && written + q < cap) dst[written + q] = cell ? v : v + (q - ex);
             }
         }
         written += ne_tot;
@@ -177,29 +185,132 @@ __global__ __launch_bounds__(64) void k_walk(const WalkNode *__restrict__ wn, Gr
         top += (int)np_tot;
         __syncthreads(); // pushes visible before the next pops
     }
-    if (lane == 0) {
-        if (!EMIT)
-            cnt_off[g] = written;
-        else
+    *ncell_out = ncell;
+    return written;
+}
+
+// Two passes, one wave per group.  Count: cnt[g] = list length.  Emit: writes the list at
+// entries + off[g], and len[g], gcells[g].
+template <int EMIT>
+__global__ __launch_bounds__(64) void k_walk(const WalkNode *__restrict__ wn, GroupArrays gr,
+                                             uint32_t n_groups, WalkParams wp,
+                                             uint64_t *__restrict__ cnt_off,
+                                             uint32_t *__restrict__ len,
+                                             uint32_t *__restrict__ entries,
+                                             unsigned *overflow, uint32_t *__restrict__ gcells)
+{
+    __shared__ uint32_t stk[kStackCap];
+    __shared__ uint32_t s_mark[64];
+    const uint32_t g = xcd_block(blockIdx.x, gridDim.x);
+    if (g >= n_groups) return;
+    uint64_t ncell = 0;
+    const uint64_t w = walk_group<EMIT>(wn, gr, g, wp, stk, s_mark,
+                                        EMIT ? entries + cnt_off[g] : nullptr, ~0ull, overflow,
+                                        &ncell);
+    if (threadIdx.x == 0) {
+        if (!EMIT) {
+            cnt_off[g] = w;
+        } else {
+            len[g] = (uint32_t)w;
             gcells[g] = (uint32_t)ncell;
+        }
+    }
+}
+
+// One pass: groups are split into kXcds equal ranges with a counter each; a wave takes
+// kWalkBatch groups at a time from its own range (b mod kXcds, the XCD the block is dealt
+// to), then from the others, so every wave ends once all counters have passed their ranges.
+// Lists go into chunks of `chunk` entries taken from the pool (entries[0, pool_cap)) through
+// *pool_next.  A group is walked into the current chunk if at least `reserve` entries are
+// left there; if its list did not fit (or there was no such room) the wave takes a fresh
+// chunk and walks the group into that.  A list longer than a chunk, or an exhausted pool,
+// sets bit 4 of *overflow and ends the wave.
+__global__ __launch_bounds__(64) void k_walk_pool(const WalkNode *__restrict__ wn,
+                                                  GroupArrays gr, uint32_t n_groups,
+                                                  WalkParams wp, uint32_t *counters,
+                                                  unsigned long long *pool_next,
+                                                  uint64_t pool_cap, uint64_t chunk,
+                                                  uint64_t reserve, uint64_t *__restrict__ off,
+                                                  uint32_t *__restrict__ len,
+                                                  uint32_t *__restrict__ entries,
+                                                  unsigned *overflow,
+                                                  uint32_t *__restrict__ gcells)
+{
+    __shared__ uint32_t stk[kStackCap];
+    __shared__ uint32_t s_mark[64];
+    uint64_t cur = 0, end = 0; // the wave's current chunk [cur, end)
+    const uint32_t x0 = blockIdx.x % kXcds;
+    for (uint32_t r = 0; r < kXcds; ++r) {
+        const uint32_t x = (x0 + r) % kXcds;
+        const uint32_t lo = (uint32_t)((uint64_t)n_groups * x / kXcds);
+        const uint32_t hi = (uint32_t)((uint64_t)n_groups * (x + 1) / kXcds);
+        for (;;) {
+            uint32_t t = 0;
+            if (threadIdx.x == 0) t = atomicAdd(&counters[x], kWalkBatch);
+            t = (uint32_t)__builtin_amdgcn_readfirstlane((int)t);
+            if (t >= hi - lo) break;
+            const uint32_t g1 = lo + t + kWalkBatch < hi ? lo + t + kWalkBatch : hi;
+            for (uint32_t g = lo + t; g < g1; ++g) {
+                uint64_t ncell = 0, w = 0;
+                bool fits = false;
+                if (end - cur >= reserve) { // room for a list of typical length: try here
+                    w = walk_group<1>(wn, gr, g, wp, stk, s_mark, entries + cur, end - cur,
+                                      overflow, &ncell);
+                    fits = w <= end - cur;
+                }
+                if (!fits) { // a fresh chunk, and the walk again if it had not fitted
+                    unsigned long long c0 = 0;
+                    if (threadIdx.x == 0) c0 = atomicAdd(pool_next, (unsigned long long)chunk);
+                    const uint32_t c_lo =
+                        (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)c0);
+                    const uint32_t c_hi =
+                        (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(c0 >> 32));
+                    cur = ((uint64_t)c_hi << 32) | c_lo;
+                    end = cur + chunk;
+                    if (end > pool_cap) {
+                        if (threadIdx.x == 0) atomicOr(overflow, 4u);
+                        return;
+                    }
+                    w = walk_group<1>(wn, gr, g, wp, stk, s_mark, entries + cur, chunk,
+                                      overflow, &ncell);
+                    if (w > chunk) {
+                        if (threadIdx.x == 0) atomicOr(overflow, 4u);
+                        return;
+                    }
+                }
+                if (threadIdx.x == 0) {
+                    off[g] = cur;
+                    len[g] = (uint32_t)w;
+                    gcells[g] = (uint32_t)ncell;
+                }
+                cur += w;
+            }
+        }
     }
 }
 
 // (cell entries, particle entries, interactions = sum_g count_g * L_g): block reductions and
 // one atomic per block.
 __global__ __launch_bounds__(256) void k_walk_stats(GroupArrays gr, uint32_t n_groups,
-                                                    const uint64_t *__restrict__ off,
+                                                    const uint32_t *__restrict__ len,
                                                     const uint32_t *__restrict__ gcells,
                                                     unsigned long long *stats)
 {
-    unsigned long long c = 0, p = 0, it = 0;
+    unsigned long long c = 0, p = 0, it = 0, mx = 0;
     for (uint32_t g = blockIdx.x * blockDim.x + threadIdx.x; g < n_groups;
          g += gridDim.x * blockDim.x) {
-        unsigned long long len = off[g + 1] - off[g];
+        const unsigned long long l = len[g];
         c += gcells[g];
-        p += len - gcells[g];
-        it += len * gr.count[g];
+        p += l - gcells[g];
+        it += l * gr.count[g];
+        mx = l > mx ? l : mx;
     }
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) {
+        const unsigned long long o = __shfl_xor(mx, d, 64);
+        mx = o > mx ? o : mx;
+    }
+    if ((threadIdx.x & 63) == 0) atomicMax(&stats[3], mx);
 #pragma unroll
     for (int d = 32; d > 0; d >>= 1) {
         c += __shfl_xor(c, d, 64);
@@ -223,21 +334,41 @@ __global__ __launch_bounds__(256) void k_walk_stats(GroupArrays gr, uint32_t n_g
 
 } // namespace
 
-void launch_walk(const WalkNode *wn, GroupArrays gr, uint32_t n_groups, WalkParams wp, int emit,
-                 uint64_t *counts_or_offsets, uint32_t *entries, unsigned *overflow,
-                 uint32_t *gcells, unsigned long long *stats, hipStream_t s)
+void launch_walk_count(const WalkNode *wn, GroupArrays gr, uint32_t n_groups, WalkParams wp,
+                       uint64_t *counts, unsigned *overflow, hipStream_t s)
 {
     if (!n_groups) return;
-    if (emit) {
-        k_walk<1><<<n_groups, 64, 0, s>>>(wn, gr, n_groups, wp, counts_or_offsets, entries,
-                                         overflow, gcells);
-        unsigned b = (n_groups + 255) / 256;
-        k_walk_stats<<<b < 256 ? b : 256, 256, 0, s>>>(gr, n_groups, counts_or_offsets, gcells,
-                                                       stats);
-    } else {
-        k_walk<0><<<n_groups, 64, 0, s>>>(wn, gr, n_groups, wp, counts_or_offsets, entries,
-                                         overflow, gcells);
-    }
+    k_walk<0><<<n_groups, 64, 0, s>>>(wn, gr, n_groups, wp, counts, nullptr, nullptr, overflow,
+                                     nullptr);
+}
+
+void launch_walk_emit(const WalkNode *wn, GroupArrays gr, uint32_t n_groups, WalkParams wp,
+                      const uint64_t *off, uint32_t *len, uint32_t *entries, unsigned *overflow,
+                      uint32_t *gcells, hipStream_t s)
+{
+    if (!n_groups) return;
+    k_walk<1><<<n_groups, 64, 0, s>>>(wn, gr, n_groups, wp, const_cast<uint64_t *>(off), len,
+                                     entries, overflow, gcells);
+}
+
+void launch_walk_pool(const WalkNode *wn, GroupArrays gr, uint32_t n_groups, WalkParams wp,
+                      uint32_t n_waves, uint64_t pool_cap, uint64_t chunk, uint64_t reserve,
+                      uint32_t *counters, uint64_t *off, uint32_t *len, uint32_t *entries,
+                      unsigned *overflow, uint32_t *gcells, hipStream_t s)
+{
+    if (!n_groups) return;
+    fill_u32(counters, kXcds + 2, 0u, s);
+    k_walk_pool<<<n_waves, 64, 0, s>>>(wn, gr, n_groups, wp, counters,
+                                       (unsigned long long *)(counters + kXcds), pool_cap,
+                                       chunk, reserve, off, len, entries, overflow, gcells);
+}
+
+void launch_walk_stats(GroupArrays gr, uint32_t n_groups, const uint32_t *len,
+                       const uint32_t *gcells, unsigned long long *stats, hipStream_t s)
+{
+    if (!n_groups) return;
+    unsigned b = (n_groups + 255) / 256;
+    k_walk_stats<<<b < 256 ? b : 256, 256, 0, s>>>(gr, n_groups, len, gcells, stats);
 }
 
 } // namespace tpm

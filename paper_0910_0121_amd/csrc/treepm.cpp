@@ -71,10 +71,14 @@ struct treepm_ctx {
     uint32_t n_groups = 0;
     unsigned min_group_level = 0, max_group = 0;
     // lists
-    Buf off, scan64, entries, wstats, overflow, gcells, cls, kept, kept_sum, out[3], bnd, runs;
+    Buf off, glen, wctr, scan64, entries, wstats, overflow, gcells, cls, kept, kept_sum, out[3], bnd, runs;
     int last_force_prec = -1;
     uint32_t class_counts[kForceClasses] = {};
     uint64_t n_entries = 0;
+    // From the last walk on this context: total list entries, the longest list and the number
+    // of groups, used to size the one-pass walk's pool (0: no walk yet, use two passes).
+    uint64_t walk_hint = 0, walk_hint_max = 0;
+    uint32_t walk_hint_groups = 0;
     uint64_t st[3] = {0, 0, 0};
     Buf host_total; // unused placeholder for alignment of future pinned buffers
 };
@@ -408,12 +412,17 @@ int do_build(treepm_ctx *c, int64_t n, const double *x, const double *y, const d
     return TREEPM_OK;
 }
 
+// Waves of the one-pass walk: enough to fill the chip, about 16 groups each at least.
+uint32_t pool_waves(uint32_t G) { return std::max(1u, std::min(8192u, (G + 15) / 16)); }
+
 int do_walk(treepm_ctx *c, hipStream_t s)
 {
     int rc;
     uint32_t G = c->n_groups;
     hipError_t e;
     if ((e = reserve(c->off, ((size_t)G + 1) * 8)) != hipSuccess) return hip_fail(c, e, "offsets");
+    if ((e = reserve(c->glen, ((size_t)G + 1) * 4)) != hipSuccess) return hip_fail(c, e, "lengths");
+    if ((e = reserve(c->wctr, 128)) != hipSuccess) return hip_fail(c, e, "counters");
     if ((e = reserve(c->scan64, (scan_tmp_elems((size_t)G + 1) + 64) * 8)) != hipSuccess)
         return hip_fail(c, e, "scan buffer");
     if ((e = reserve(c->wstats, 64)) != hipSuccess) return hip_fail(c, e, "stats");
@@ -421,40 +430,72 @@ int do_walk(treepm_ctx *c, hipStream_t s)
     if ((e = reserve(c->gcells, ((size_t)G + 1) * 4)) != hipSuccess)
         return hip_fail(c, e, "group stats");
     uint64_t *off = c->off.as<uint64_t>();
+    uint32_t *len = c->glen.as<uint32_t>();
     uint64_t *tot = c->scan64.as<uint64_t>();
     unsigned *ovf = c->overflow.as<unsigned>();
     unsigned long long *ws = c->wstats.as<unsigned long long>();
-    fill_u64(off, (size_t)G + 1, 0ull, s);
     fill_u32(ovf, 1, 0u, s);
-    fill_u64((uint64_t *)ws, 3, 0ull, s);
+    fill_u64((uint64_t *)ws, 4, 0ull, s);
     const treepm_params &P = c->prm;
     WalkParams wp{P.L, P.r_cut * P.r_cut, P.theta * P.theta, (uint32_t)c->n_nodes};
     NodeArrays nd = nodes_view(c);
     GroupArrays gr = groups_view(c);
     uint32_t *gcells = c->gcells.as<uint32_t>();
     const WalkNode *wn = c->n_walk.as<WalkNode>();
-    launch_walk(wn, gr, G, wp, 0, off, nullptr, ovf, gcells, ws, s);
-    scan_u64(off, (size_t)G + 1, tot, tot + 1, s);
-    uint64_t total = 0;
-    if ((rc = d2h(c, &total, tot, 1, s))) return rc;
+    bool done = false;
     unsigned hov = 0;
-    if ((rc = d2h(c, &hov, ovf, 1, s))) return rc;
-    if (hov) return fail(c, TREEPM_ERR_OVERFLOW, "walk stack overflow");
-    if ((e = reserve(c->entries, std::max<size_t>(total, 1) * 4)) != hipSuccess)
-        return hip_fail(c, e, "interaction lists");
-    launch_walk(wn, gr, G, wp, 1, off, c->entries.as<uint32_t>(), ovf, gcells, ws, s);
+    if (c->walk_hint && G) {
+        // One pass, sized from the last walk: chunks of at least four of the longest list,
+        // a group tried in the current chunk if twice the mean list length is left there,
+        // and a pool of 25 % more entries than then plus one chunk per wave.
+        const uint32_t W = pool_waves(G);
+        const uint64_t chunk = std::max<uint64_t>(4 * c->walk_hint_max, 32768);
+        const uint64_t mean = c->walk_hint / std::max<uint32_t>(c->walk_hint_groups, 1);
+        const uint64_t reserve_len = std::min<uint64_t>(std::max<uint64_t>(2 * mean, 64),
+                                                        chunk / 4);
+        const uint64_t pool = c->walk_hint + c->walk_hint / 4 + (uint64_t)W * chunk;
+        if (reserve(c->entries, pool * 4) == hipSuccess) {
+            launch_walk_pool(wn, gr, G, wp, W, pool, chunk, reserve_len, c->wctr.as<uint32_t>(),
+                             off, len, c->entries.as<uint32_t>(), ovf, gcells, s);
+            if ((rc = d2h(c, &hov, ovf, 1, s))) return rc;
+            if (hov & 3u)
+                return fail(c, TREEPM_ERR_OVERFLOW, hov & 2u ? "walk read a bad node index"
+                                                             : "walk stack overflow");
+            done = hov == 0;
+            if (!done) fill_u32(ovf, 1, 0u, s); // lists did not fit: two passes instead
+        }
+    }
+    if (!done) {
+        fill_u64(off, (size_t)G + 1, 0ull, s);
+        launch_walk_count(wn, gr, G, wp, off, ovf, s);
+        scan_u64(off, (size_t)G + 1, tot, tot + 1, s);
+        uint64_t total = 0;
+        if ((rc = d2h(c, &total, tot, 1, s))) return rc;
+        if ((rc = d2h(c, &hov, ovf, 1, s))) return rc;
+        if (hov)
+            return fail(c, TREEPM_ERR_OVERFLOW, hov & 2u ? "walk read a bad node index"
+                                                         : "walk stack overflow");
+        if ((e = reserve(c->entries, std::max<size_t>(total, 1) * 4)) != hipSuccess)
+            return hip_fail(c, e, "interaction lists");
+        launch_walk_emit(wn, gr, G, wp, off, len, c->entries.as<uint32_t>(), ovf, gcells, s);
+    }
+    launch_walk_stats(gr, G, len, gcells, ws, s);
     if ((e = reserve(c->cls, (kForceClasses * ((size_t)G + 1) + kForceClasses) * 4)) !=
         hipSuccess)
         return hip_fail(c, e, "group classes");
     uint32_t *cls = c->cls.as<uint32_t>();
     launch_classify(gr, G, cls + kForceClasses, G + 1, cls, s);
     if ((rc = d2h(c, c->class_counts, cls, kForceClasses, s))) return rc;
-    unsigned long long hs[3];
-    if ((rc = d2h(c, hs, ws, 3, s))) return rc;
+    unsigned long long hs[4];
+    if ((rc = d2h(c, hs, ws, 4, s))) return rc;
     if ((rc = d2h(c, &hov, ovf, 1, s))) return rc;
-    if (hov) return fail(c, TREEPM_ERR_OVERFLOW, hov & 2u ? "walk read a bad node index"
-                                                         : "walk stack overflow");
-    c->n_entries = total;
+    if (hov)
+        return fail(c, TREEPM_ERR_OVERFLOW, hov & 2u ? "walk read a bad node index"
+                                                     : "walk stack overflow");
+    c->n_entries = hs[0] + hs[1];
+    c->walk_hint = c->n_entries;
+    c->walk_hint_max = hs[3];
+    c->walk_hint_groups = G;
     for (int i = 0; i < 3; ++i) c->st[i] = hs[i];
     return TREEPM_OK;
 }
@@ -515,7 +556,7 @@ size_t treepm_internal_ctx_bytes(const treepm_ctx *c)
                         &c->g_node, &c->g_first, &c->g_count, &c->g_cg[0], &c->g_cg[1],
                         &c->g_cg[2], &c->g_hg[0], &c->g_hg[1], &c->g_hg[2], &c->g_xg[0],
                         &c->g_xg[1], &c->g_xg[2], &c->g_lo[0], &c->g_lo[1], &c->g_lo[2],
-                        &c->g_hi[0], &c->g_hi[1], &c->g_hi[2], &c->g_misc, &c->off, &c->scan64,
+                        &c->g_hi[0], &c->g_hi[1], &c->g_hi[2], &c->g_misc, &c->off, &c->glen, &c->wctr, &c->scan64,
                         &c->entries, &c->wstats, &c->overflow, &c->gcells, &c->cls,
                         &c->kept, &c->kept_sum, &c->out[0], &c->out[1], &c->out[2], &c->bnd, &c->runs};
     size_t t = 0;
@@ -584,7 +625,7 @@ TREEPM_API int treepm_destroy(treepm_ctx *c)
                   &c->n_cn[1], &c->n_cn[2], &c->n_walk, &c->n_src, &c->psrc, &c->g_node, &c->g_first, &c->g_count, &c->g_cg[0],
                   &c->g_cg[1], &c->g_cg[2], &c->g_hg[0], &c->g_hg[1], &c->g_hg[2], &c->g_xg[0],
                   &c->g_xg[1], &c->g_xg[2], &c->g_lo[0], &c->g_lo[1], &c->g_lo[2], &c->g_hi[0],
-                  &c->g_hi[1], &c->g_hi[2], &c->g_misc, &c->off, &c->scan64, &c->entries,
+                  &c->g_hi[1], &c->g_hi[2], &c->g_misc, &c->off, &c->glen, &c->wctr, &c->scan64, &c->entries,
                   &c->wstats, &c->overflow, &c->rec, &c->kept, &c->kept_sum, &c->gcells, &c->cls, &c->out[0],
                   &c->out[1], &c->out[2], &c->bnd, &c->runs};
     {
@@ -733,7 +774,8 @@ TREEPM_API int treepm_force_short(treepm_ctx *c, void *ax, void *ay, void *az, i
             }
         }
         launch_force_f32(nd, gr, c->cls.as<uint32_t>() + kForceClasses, c->n_groups + 1,
-                         c->class_counts, c->off.as<uint64_t>(), c->entries.as<uint32_t>(),
+                         c->class_counts, c->off.as<uint64_t>(), c->glen.as<uint32_t>(),
+                         c->entries.as<uint32_t>(),
                          c->psrc.as<double4>(), c->idx.as<uint32_t>(), fp, dst[0], dst[1],
                          dst[2], out_prec, streams,
                          ns);
@@ -743,7 +785,8 @@ TREEPM_API int treepm_force_short(treepm_ctx *c, void *ax, void *ay, void *az, i
                 HIPCHK(c, hipStreamWaitEvent(s, c->join[i], 0));
             }
     } else
-        launch_force_f64(nd, gr, c->n_groups, c->off.as<uint64_t>(), c->entries.as<uint32_t>(),
+        launch_force_f64(nd, gr, c->n_groups, c->off.as<uint64_t>(), c->glen.as<uint32_t>(),
+                         c->entries.as<uint32_t>(),
                          c->psrc.as<double4>(), c->idx.as<uint32_t>(), fp, dst[0], dst[1],
                          dst[2], out_prec, s);
     HIPCHK(c, hipGetLastError());
@@ -867,22 +910,32 @@ TREEPM_API int treepm_export_lists(treepm_ctx *c, int64_t group_cap, int64_t ent
     hipStream_t s = c->last;
     size_t ng = c->n_groups, nn = c->n_nodes, ne = c->n_entries, n = c->n;
     std::vector<uint64_t> off(ng + 1), codes(nn);
-    std::vector<uint32_t> ent(ne), idx(n);
-    if ((rc = d2h(c, off.data(), c->off.p, ng + 1, s))) return rc;
-    if ((rc = d2h(c, ent.data(), c->entries.p, ne, s))) return rc;
+    std::vector<uint32_t> len(ng + 1), idx(n);
+    if ((rc = d2h(c, off.data(), c->off.p, ng, s))) return rc;
+    if ((rc = d2h(c, len.data(), c->glen.p, ng, s))) return rc;
     if ((rc = d2h(c, codes.data(), c->n_code.p, nn, s))) return rc;
     if ((rc = d2h(c, idx.data(), c->idx.p, n, s))) return rc;
-    for (size_t g = 0; g <= ng; ++g) offsets[g] = (int64_t)off[g];
-    for (size_t q = 0; q < ne; ++q) {
-        uint32_t e = ent[q];
-        if (e & kCellTag) {
-            is_cell[q] = 1;
-            value[q] = codes[e & ~kCellTag];
-        } else {
-            is_cell[q] = 0;
-            value[q] = idx[e];
+    // lists may sit anywhere in the entries buffer: copy the used span, write them back to back
+    size_t span = 0;
+    for (size_t g = 0; g < ng; ++g) span = std::max<size_t>(span, off[g] + len[g]);
+    std::vector<uint32_t> ent(span);
+    if (span && (rc = d2h(c, ent.data(), c->entries.p, span, s))) return rc;
+    size_t q = 0;
+    for (size_t g = 0; g < ng; ++g) {
+        offsets[g] = (int64_t)q;
+        for (uint32_t j = 0; j < len[g]; ++j, ++q) {
+            const uint32_t e = ent[off[g] + j];
+            if (e & kCellTag) {
+                is_cell[q] = 1;
+                value[q] = codes[e & ~kCellTag];
+            } else {
+                is_cell[q] = 0;
+                value[q] = idx[e];
+            }
         }
     }
+    offsets[ng] = (int64_t)q;
+    if (q != ne) return fail(c, TREEPM_ERR_STATE, "list lengths do not add up");
     return TREEPM_OK;
 }
 

@@ -230,6 +230,41 @@ def test_host_buffers_and_fp32_output(tp, orc):
     a.close(); b.close()
 
 
+def test_one_pass_walk_on_a_reused_context(tp, orc):
+    """A context's later walks write the lists in one pass, into a pool sized from its previous
+    walk; a box with more interactions than the previous one overflows that pool and is walked
+    again in two passes.  Lists and FP64 forces must match the oracle on every path."""
+    r_cut, theta, n_leaf, n_crit = 0.06, 0.5, 10, 128
+    eps = r_cut / 60
+    boxes = {"small": boxgen.nfw_box(8000, 20, 21), "big": boxgen.nfw_box(40000, 100, 2)}
+    trees = {k: orc.Tree(*b, 1.0, r_cut, eps, theta, n_leaf, n_crit) for k, b in boxes.items()}
+    p = tp.treepm_params(1.0, r_cut / 3.0, r_cut, eps, theta, n_leaf, n_crit, tp.TREEPM_FP64)
+    ctx = tp.treepm_create(p, 0)
+    try:
+        for name in ("small", "small", "big", "big"):
+            _say(f"reused context: {name} box")
+            x, y, z, m = boxes[name]
+            T = trees[name]
+            tp.treepm_build(ctx, *[torch.from_numpy(a).cuda() for a in (x, y, z, m)])
+            st = tp.treepm_walk(ctx)
+            assert st.interactions == T.interactions()
+            goff, gisc, gval = tp.treepm_export_lists(ctx)
+            ooff, oisc, oval = T.lists()
+            np.testing.assert_array_equal(np.diff(goff), np.diff(ooff))
+            for g in range(ooff.size - 1):
+                a = sorted(zip(gisc[goff[g]:goff[g + 1]].tolist(), gval[goff[g]:goff[g + 1]].tolist()))
+                b = sorted(zip(oisc[ooff[g]:ooff[g + 1]].tolist(), oval[ooff[g]:ooff[g + 1]].tolist()))
+                assert a == b, f"{name}: group {g}"
+            acc = [torch.zeros(len(x), dtype=torch.float64, device="cuda") for _ in range(3)]
+            tp.treepm_force_short(ctx, *acc)
+            torch.cuda.synchronize()
+            got = np.stack([t.cpu().numpy() for t in acc])
+            ref = np.stack(T.force())
+            assert np.all(np.abs(got - ref) <= 1e-13 * T.error_scale()[None, :] + 1e-300)
+    finally:
+        tp.treepm_destroy(ctx)
+
+
 def _clumped_box(n_uniform, clumps, seed):
     """Uniform particles plus clumps, each inside one cell of side 2^-11, so each clump's keys
     share their high bits and differ in the low ones; clump sizes are given.  Every fifth
