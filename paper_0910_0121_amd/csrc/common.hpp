@@ -60,6 +60,13 @@ struct GroupArrays {
 // Exclusive prefix sum in place over n values; the total is written to *total (device).
 // tmp must hold scan_tmp_elems(n) values of the same type.
 size_t scan_tmp_elems(size_t n);
+// Host-visible results without a stream synchronisation: copies up to three runs of device
+// words (n0 + n1 + n2 < kMailboxWords in all) into the host-mapped mailbox from word 1 on
+// and then writes seq into word 0; the host waits for word 0 to read seq.
+constexpr uint32_t kMailboxWords = 64;
+void publish_words(const uint32_t *src0, uint32_t n0, const uint32_t *src1, uint32_t n1,
+                   const uint32_t *src2, uint32_t n2, uint32_t *mailbox, uint32_t seq,
+                   hipStream_t s);
 void fill_u32(uint32_t *p, size_t n, uint32_t v, hipStream_t s);
 void fill_u64(uint64_t *p, size_t n, uint64_t v, hipStream_t s);
 void scan_u32(uint32_t *data, size_t n, uint32_t *total, uint32_t *tmp, hipStream_t s);

@@ -109,6 +109,25 @@ void scan_rec(T *data, size_t n, T *total, T *tmp, hipStream_t s)
     k_scan_tile<T><<<(unsigned)nb, kThreads, 0, s>>>(data, n, partials, nullptr);
 }
 
+// Copies up to three runs of words (src0[0..n0), src1[0..n1), src2[0..n2)) into host-mapped
+// memory after word 0, then stores `seq` into word 0 with release order at system scope: a
+// host thread that sees seq there also sees the words.
+__global__ void k_publish(const uint32_t *__restrict__ src0, uint32_t n0,
+                          const uint32_t *__restrict__ src1, uint32_t n1,
+                          const uint32_t *__restrict__ src2, uint32_t n2, uint32_t *mailbox,
+                          uint32_t seq)
+{
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    uint32_t k = 1;
+    for (uint32_t i = 0; i < n0; ++i, ++k)
+        __hip_atomic_store(&mailbox[k], src0[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    for (uint32_t i = 0; i < n1; ++i, ++k)
+        __hip_atomic_store(&mailbox[k], src1[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    for (uint32_t i = 0; i < n2; ++i, ++k)
+        __hip_atomic_store(&mailbox[k], src2[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(&mailbox[0], seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 } // namespace
 
 // Fills with a kernel rather than hipMemsetAsync so the calls can sit inside a captured graph.
@@ -144,6 +163,13 @@ void scan_u32(uint32_t *data, size_t n, uint32_t *total, uint32_t *tmp, hipStrea
 void scan_u64(uint64_t *data, size_t n, uint64_t *total, uint64_t *tmp, hipStream_t s)
 {
     scan_rec<uint64_t>(data, n, total, tmp, s);
+}
+
+void publish_words(const uint32_t *src0, uint32_t n0, const uint32_t *src1, uint32_t n1,
+                   const uint32_t *src2, uint32_t n2, uint32_t *mailbox, uint32_t seq,
+                   hipStream_t s)
+{
+    k_publish<<<1, 64, 0, s>>>(src0, n0, src1, n1, src2, n2, mailbox, seq);
 }
 
 } // namespace tpm

@@ -9,6 +9,7 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "common.hpp"
@@ -78,6 +79,10 @@ struct treepm_ctx {
     // From the last walk on this context: total list entries, the longest list and the number
     // of groups, used to size the one-pass walk's pool (0: no walk yet, use two passes).
     uint64_t walk_hint = 0, walk_hint_max = 0;
+    // Host-mapped words that kernels publish small results into (see fetch); null if the
+    // allocation failed, and then results are copied with a stream synchronisation.
+    uint32_t *mbox_h = nullptr, *mbox_d = nullptr;
+    uint32_t mseq = 0;
     uint32_t walk_hint_groups = 0;
     uint64_t st[3] = {0, 0, 0};
     Buf host_total; // unused placeholder for alignment of future pinned buffers
@@ -277,6 +282,53 @@ int d2h(treepm_ctx *c, T *dst, const void *src, size_t count, hipStream_t s)
     return TREEPM_OK;
 }
 
+// Small device results to the host: up to three runs of 4-byte-multiple objects, published
+// by one kernel into the mapped mailbox, waited for by spinning on its sequence word (with
+// the stream's state checked, so a failed stream ends the wait).  Falls back to d2h.
+struct Run3 {
+    void *dst;
+    const void *src;
+    size_t bytes;
+};
+
+int fetch(treepm_ctx *c, hipStream_t s, Run3 a, Run3 b = {nullptr, nullptr, 0},
+          Run3 d = {nullptr, nullptr, 0})
+{
+    const size_t words = (a.bytes + b.bytes + d.bytes) / 4;
+    if (!c->mbox_h || words >= kMailboxWords) {
+        int rc;
+        for (const Run3 &r : {a, b, d})
+            if (r.bytes && (rc = d2h(c, (uint32_t *)r.dst, r.src, r.bytes / 4, s))) return rc;
+        return TREEPM_OK;
+    }
+    uint32_t seq = ++c->mseq;
+    if (seq == 0) seq = ++c->mseq;
+    publish_words((const uint32_t *)a.src, (uint32_t)(a.bytes / 4), (const uint32_t *)b.src,
+                  (uint32_t)(b.bytes / 4), (const uint32_t *)d.src, (uint32_t)(d.bytes / 4),
+                  c->mbox_d, seq, s);
+    HIPCHK(c, hipGetLastError());
+    for (uint32_t spin = 0;
+         __atomic_load_n(&c->mbox_h[0], __ATOMIC_ACQUIRE) != seq; ++spin) {
+        if (spin < 2048) {
+            __builtin_ia32_pause();
+            continue;
+        }
+        const hipError_t q = hipStreamQuery(s);
+        if (q == hipSuccess) {
+            if (__atomic_load_n(&c->mbox_h[0], __ATOMIC_ACQUIRE) == seq) break;
+            return fail(c, TREEPM_ERR_DEVICE, "a published result did not arrive");
+        }
+        if (q != hipErrorNotReady) return hip_fail(c, q, "stream");
+        std::this_thread::yield();
+    }
+    const uint32_t *w = c->mbox_h + 1;
+    for (const Run3 &r : {a, b, d}) {
+        if (r.bytes) std::memcpy(r.dst, w, r.bytes);
+        w += r.bytes / 4;
+    }
+    return TREEPM_OK;
+}
+
 void record(treepm_ctx *c, int i, hipStream_t s)
 {
     if (c->timing) hipEventRecord(c->ev[i], s);
@@ -317,12 +369,6 @@ int do_build(treepm_ctx *c, int64_t n, const double *x, const double *y, const d
     fill_u32(flags, 4, 0u, s);
     launch_keys(n, src[0], src[1], src[2], src[3], P.L, c->key.as<uint64_t>(),
                 c->idx.as<uint32_t>(), flags, c->rec.as<double4>(), s);
-    unsigned hf = 0;
-    if ((rc = d2h(c, &hf, flags, 1, s))) return rc;
-    if (hf & kFlagNonFinite)
-        return fail(c, TREEPM_ERR_ARG, "non-finite position or mass, or a mass <= 0");
-    if (hf & kFlagRange)
-        return fail(c, TREEPM_ERR_RANGE, "a position lies outside [0, L); wrap it first");
     uint32_t *scan_tmp = c->scan32.as<uint32_t>();
     {
         // high key bits first, runs of equal high bits sorted in place; all bits if a run is
@@ -338,9 +384,15 @@ int do_build(treepm_ctx *c, int64_t n, const double *x, const double *y, const d
             std::swap(c->key, c->key_alt);
             std::swap(c->idx, c->idx_alt);
         }
-        unsigned fb = 0;
-        if ((rc = d2h(c, &fb, sflags + 1, 1, s))) return rc;
-        if (fb)
+        // the input checks of k_keys and the sort's fallback flag in one read (sorting
+        // invalid input first is harmless: keys are clamped)
+        unsigned fl[6] = {};
+        if ((rc = fetch(c, s, {fl, flags, sizeof fl}))) return rc;
+        if (fl[0] & kFlagNonFinite)
+            return fail(c, TREEPM_ERR_ARG, "non-finite position or mass, or a mass <= 0");
+        if (fl[0] & kFlagRange)
+            return fail(c, TREEPM_ERR_RANGE, "a position lies outside [0, L); wrap it first");
+        if (fl[5])
             radix_sort(n, c->key.as<uint64_t>(), c->idx.as<uint32_t>(),
                        c->key_alt.as<uint64_t>(), c->idx_alt.as<uint32_t>(),
                        c->hist.as<uint32_t>(), scan_tmp, s);
@@ -367,7 +419,7 @@ int do_build(treepm_ctx *c, int64_t n, const double *x, const double *y, const d
         launch_split(nd, c->key.as<uint64_t>(), lo, hi, l, P.n_leaf, cnt, c->bnd.as<uint32_t>(), s);
         scan_u32(cnt, hi - lo, cnt_total, cnt_tmp, s);
         uint32_t add = 0;
-        if ((rc = d2h(c, &add, cnt_total, 1, s))) return rc;
+        if ((rc = fetch(c, s, {&add, cnt_total, sizeof add}))) return rc;
         c->max_level = l;
         if (add == 0) break;
         if ((uint64_t)hi + add > 0x7fffffffull)
@@ -395,7 +447,7 @@ int do_build(treepm_ctx *c, int64_t n, const double *x, const double *y, const d
     launch_group_mark(nd, c->n_nodes, n_crit, gstart, gflag, n, s);
     scan_u32(gflag, N + 1, cnt_total, cnt_tmp, s);
     uint32_t ng = 0;
-    if ((rc = d2h(c, &ng, cnt_total, 1, s))) return rc;
+    if ((rc = fetch(c, s, {&ng, cnt_total, sizeof ng}))) return rc;
     if ((rc = ensure_groups(c, ng))) return rc;
     GroupArrays gr = groups_view(c);
     launch_group_compact(gstart, gflag, n, gr.node, s);
@@ -404,7 +456,7 @@ int do_build(treepm_ctx *c, int64_t n, const double *x, const double *y, const d
     fill_u32(misc + 1, 1, 0u, s);
     launch_group_bbox(nd, gr, ng, ps, misc, misc + 1, s);
     unsigned hm[2] = {0, 0};
-    if ((rc = d2h(c, hm, misc, 2, s))) return rc;
+    if ((rc = fetch(c, s, {hm, misc, sizeof hm}))) return rc;
     c->n_groups = ng;
     c->min_group_level = hm[0];
     c->max_group = hm[1];
@@ -442,8 +494,25 @@ int do_walk(treepm_ctx *c, hipStream_t s)
     GroupArrays gr = groups_view(c);
     uint32_t *gcells = c->gcells.as<uint32_t>();
     const WalkNode *wn = c->n_walk.as<WalkNode>();
-    bool done = false;
-    unsigned hov = 0;
+    // The list layout (one pass into the pool, else two passes), then the statistics and
+    // the force classes; everything the host needs comes back in one read.
+    auto two_pass = [&]() -> int {
+        fill_u64(off, (size_t)G + 1, 0ull, s);
+        launch_walk_count(wn, gr, G, wp, off, ovf, s);
+        scan_u64(off, (size_t)G + 1, tot, tot + 1, s);
+        uint64_t total = 0;
+        unsigned ov = 0;
+        int r = fetch(c, s, {&total, tot, sizeof total}, {&ov, ovf, sizeof ov});
+        if (r) return r;
+        if (ov)
+            return fail(c, TREEPM_ERR_OVERFLOW, ov & 2u ? "walk read a bad node index"
+                                                        : "walk stack overflow");
+        hipError_t e2 = reserve(c->entries, std::max<size_t>(total, 1) * 4);
+        if (e2 != hipSuccess) return hip_fail(c, e2, "interaction lists");
+        launch_walk_emit(wn, gr, G, wp, off, len, c->entries.as<uint32_t>(), ovf, gcells, s);
+        return TREEPM_OK;
+    };
+    bool pooled = false;
     if (c->walk_hint && G) {
         // One pass, sized from the last walk: chunks of at least four of the longest list,
         // a group tried in the current chunk if twice the mean list length is left there,
@@ -457,41 +526,31 @@ int do_walk(treepm_ctx *c, hipStream_t s)
         if (reserve(c->entries, pool * 4) == hipSuccess) {
             launch_walk_pool(wn, gr, G, wp, W, pool, chunk, reserve_len, c->wctr.as<uint32_t>(),
                              off, len, c->entries.as<uint32_t>(), ovf, gcells, s);
-            if ((rc = d2h(c, &hov, ovf, 1, s))) return rc;
-            if (hov & 3u)
-                return fail(c, TREEPM_ERR_OVERFLOW, hov & 2u ? "walk read a bad node index"
-                                                             : "walk stack overflow");
-            done = hov == 0;
-            if (!done) fill_u32(ovf, 1, 0u, s); // lists did not fit: two passes instead
+            pooled = true;
         }
     }
-    if (!done) {
-        fill_u64(off, (size_t)G + 1, 0ull, s);
-        launch_walk_count(wn, gr, G, wp, off, ovf, s);
-        scan_u64(off, (size_t)G + 1, tot, tot + 1, s);
-        uint64_t total = 0;
-        if ((rc = d2h(c, &total, tot, 1, s))) return rc;
-        if ((rc = d2h(c, &hov, ovf, 1, s))) return rc;
-        if (hov)
-            return fail(c, TREEPM_ERR_OVERFLOW, hov & 2u ? "walk read a bad node index"
-                                                         : "walk stack overflow");
-        if ((e = reserve(c->entries, std::max<size_t>(total, 1) * 4)) != hipSuccess)
-            return hip_fail(c, e, "interaction lists");
-        launch_walk_emit(wn, gr, G, wp, off, len, c->entries.as<uint32_t>(), ovf, gcells, s);
-    }
-    launch_walk_stats(gr, G, len, gcells, ws, s);
+    if (!pooled && (rc = two_pass())) return rc;
     if ((e = reserve(c->cls, (kForceClasses * ((size_t)G + 1) + kForceClasses) * 4)) !=
         hipSuccess)
         return hip_fail(c, e, "group classes");
     uint32_t *cls = c->cls.as<uint32_t>();
-    launch_classify(gr, G, cls + kForceClasses, G + 1, cls, s);
-    if ((rc = d2h(c, c->class_counts, cls, kForceClasses, s))) return rc;
     unsigned long long hs[4];
-    if ((rc = d2h(c, hs, ws, 4, s))) return rc;
-    if ((rc = d2h(c, &hov, ovf, 1, s))) return rc;
-    if (hov)
-        return fail(c, TREEPM_ERR_OVERFLOW, hov & 2u ? "walk read a bad node index"
-                                                     : "walk stack overflow");
+    unsigned hov = 0;
+    for (;;) {
+        launch_walk_stats(gr, G, len, gcells, ws, s);
+        launch_classify(gr, G, cls + kForceClasses, G + 1, cls, s);
+        if ((rc = fetch(c, s, {&hov, ovf, sizeof hov}, {c->class_counts, cls, sizeof c->class_counts},
+                        {hs, ws, sizeof hs})))
+            return rc;
+        if (hov & 3u)
+            return fail(c, TREEPM_ERR_OVERFLOW, hov & 2u ? "walk read a bad node index"
+                                                         : "walk stack overflow");
+        if (!hov) break;
+        // the pool was too small for these lists: two passes, then the statistics again
+        fill_u32(ovf, 1, 0u, s);
+        fill_u64((uint64_t *)ws, 4, 0ull, s);
+        if ((rc = two_pass())) return rc;
+    }
     c->n_entries = hs[0] + hs[1];
     c->walk_hint = c->n_entries;
     c->walk_hint_max = hs[3];
@@ -607,6 +666,18 @@ TREEPM_API int treepm_create(const treepm_params *params, int device, treepm_ctx
         c->fork = nullptr;
         (void)hipGetLastError();
     }
+    // the mailbox for small results (fetch); without it results are copied and synchronised
+    if (hipHostMalloc((void **)&c->mbox_h, kMailboxWords * 4,
+                      hipHostMallocMapped | hipHostMallocCoherent) == hipSuccess) {
+        std::memset(c->mbox_h, 0, kMailboxWords * 4);
+        if (hipHostGetDevicePointer((void **)&c->mbox_d, c->mbox_h, 0) != hipSuccess) {
+            (void)hipHostFree(c->mbox_h);
+            c->mbox_h = c->mbox_d = nullptr;
+        }
+    } else {
+        c->mbox_h = nullptr;
+    }
+    (void)hipGetLastError();
     *out = c;
     return TREEPM_OK;
 }
@@ -637,6 +708,7 @@ TREEPM_API int treepm_destroy(treepm_ctx *c)
         (void)hipStreamDestroy(c->own);
     }
     if (c->freed) (void)hipEventDestroy(c->freed);
+    if (c->mbox_h) (void)hipHostFree(c->mbox_h);
     for (int i = 0; i < treepm_ctx::kSubStreams; ++i) {
         if (c->sub[i]) (void)hipStreamDestroy(c->sub[i]);
         if (c->join[i]) (void)hipEventDestroy(c->join[i]);
