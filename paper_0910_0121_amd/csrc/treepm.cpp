@@ -282,6 +282,41 @@ int d2h(treepm_ctx *c, T *dst, const void *src, size_t count, hipStream_t s)
     return TREEPM_OK;
 }
 
+// Mailboxes come from slabs of pinned, mapped, coherent host memory that are kept for the
+// life of the process: contexts are created and destroyed often (the ensemble evicts boxes),
+// and pinning or unpinning host memory would stall every stream on the device.
+std::mutex g_mbox_mu;
+std::vector<std::pair<uint32_t *, uint32_t *>> g_mbox_free; // (host, device)
+
+void take_mailbox(uint32_t **h, uint32_t **d)
+{
+    std::lock_guard<std::mutex> lk(g_mbox_mu);
+    *h = *d = nullptr;
+    if (g_mbox_free.empty()) {
+        constexpr int kSlab = 64;
+        uint32_t *hp = nullptr, *dp = nullptr;
+        if (hipHostMalloc((void **)&hp, (size_t)kSlab * kMailboxWords * 4,
+                          hipHostMallocMapped | hipHostMallocCoherent |
+                              hipHostMallocPortable) != hipSuccess ||
+            hipHostGetDevicePointer((void **)&dp, hp, 0) != hipSuccess) {
+            (void)hipGetLastError();
+            return; // the caller copies instead
+        }
+        for (int i = 0; i < kSlab; ++i)
+            g_mbox_free.emplace_back(hp + (size_t)i * kMailboxWords, dp + (size_t)i * kMailboxWords);
+    }
+    *h = g_mbox_free.back().first;
+    *d = g_mbox_free.back().second;
+    g_mbox_free.pop_back();
+    std::memset(*h, 0, kMailboxWords * 4); // no sequence number of a former owner survives
+}
+
+void give_mailbox(uint32_t *h, uint32_t *d)
+{
+    std::lock_guard<std::mutex> lk(g_mbox_mu);
+    g_mbox_free.emplace_back(h, d);
+}
+
 // Small device results to the host: up to three runs of 4-byte-multiple objects, published
 // by one kernel into the mapped mailbox, waited for by spinning on its sequence word (with
 // the stream's state checked, so a failed stream ends the wait).  Falls back to d2h.
@@ -667,17 +702,7 @@ TREEPM_API int treepm_create(const treepm_params *params, int device, treepm_ctx
         (void)hipGetLastError();
     }
     // the mailbox for small results (fetch); without it results are copied and synchronised
-    if (hipHostMalloc((void **)&c->mbox_h, kMailboxWords * 4,
-                      hipHostMallocMapped | hipHostMallocCoherent) == hipSuccess) {
-        std::memset(c->mbox_h, 0, kMailboxWords * 4);
-        if (hipHostGetDevicePointer((void **)&c->mbox_d, c->mbox_h, 0) != hipSuccess) {
-            (void)hipHostFree(c->mbox_h);
-            c->mbox_h = c->mbox_d = nullptr;
-        }
-    } else {
-        c->mbox_h = nullptr;
-    }
-    (void)hipGetLastError();
+    take_mailbox(&c->mbox_h, &c->mbox_d);
     *out = c;
     return TREEPM_OK;
 }
@@ -708,7 +733,7 @@ TREEPM_API int treepm_destroy(treepm_ctx *c)
         (void)hipStreamDestroy(c->own);
     }
     if (c->freed) (void)hipEventDestroy(c->freed);
-    if (c->mbox_h) (void)hipHostFree(c->mbox_h);
+    if (c->mbox_h) give_mailbox(c->mbox_h, c->mbox_d); // the stream is idle: nothing writes it
     for (int i = 0; i < treepm_ctx::kSubStreams; ++i) {
         if (c->sub[i]) (void)hipStreamDestroy(c->sub[i]);
         if (c->join[i]) (void)hipEventDestroy(c->join[i]);
