@@ -24,7 +24,6 @@
 namespace tpm {
 namespace {
 
-constexpr int kTileJ = 64;
 
 __device__ __forceinline__ double g_p3m_f64(double R)
 {
@@ -39,6 +38,16 @@ __device__ __forceinline__ double g_p3m_f64(double R)
     double u5 = u2 * u2 * u;
     double c = fma(fma(fma(0.05, R, 22.0 / 140.0), R, 10.0 / 140.0), R, 4.0 / 140.0);
     return R < 1.0 ? g1 : u5 * c;
+}
+
+// Second branch of eq. (2) alone, for separations known to be at least eta (R >= 1).
+__device__ __forceinline__ double g_far_f64(double R)
+{
+    double u = fmax(2.0 - R, 0.0);
+    double u2 = u * u;
+    double u5 = u2 * u2 * u;
+    double c = fma(fma(fma(0.05, R, 22.0 / 140.0), R, 10.0 / 140.0), R, 4.0 / 140.0);
+    return u5 * c;
 }
 
 __device__ __forceinline__ double wrapd(double v, double L)
@@ -463,59 +472,114 @@ __global__ __launch_bounds__(256) void k_classify(GroupArrays gr, uint32_t n_gro
                 base + (uint32_t)r * 256u + threadIdx.x;
 }
 
-struct d4 {
-    double x, y, z, m;
-};
+// 1/sqrt(x) in FP64 for x > 0: the hardware estimate refined by two Newton steps
+// y <- y + y (1/2 - (x/2) y^2), each of which squares the relative error (to within rounding).
+__device__ __forceinline__ double rsqrt_f64(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    const double h = 0.5 * x;
+    y = fma(y, fma(-h, y * y, 0.5), y);
+    y = fma(y, fma(-h, y * y, 0.5), y);
+    return y;
+}
+
+// FP64 path, one wave per group, 64 i-particles per pass.  Each tile of 64 list entries is
+// culled against the group's box as in the FP32 path (a source at least r_cut from the box
+// adds exactly zero) and the survivors are stored relative to x_g (nearest image, once per
+// entry).  When the group's cube and cutoff fit in half the box (half side + r_cut < L/2)
+// the difference of two relative positions is the nearest-image separation and the pairs
+// need no wrap; otherwise the pair wraps it.  (r^2 + eps^2)^(-1/2) and r^(-1) come from
+// rsqrt_f64 (r = r^2 r^(-1)); a pair at zero separation adds nothing.
+constexpr int kTileF64 = 64;
 
 template <int OUT64>
 __global__ __launch_bounds__(64) void k_force_f64(
-    NodeArrays nd, GroupArrays gr, uint32_t n_groups, const uint64_t *__restrict__ off, const uint32_t *__restrict__ len,
-    const uint32_t *__restrict__ entries, const double4 *__restrict__ ps,
-    const uint32_t *__restrict__ pidx, ForceParams fp, void *ax, void *ay, void *az)
+    NodeArrays nd, GroupArrays gr, uint32_t n_groups, const uint64_t *__restrict__ off,
+    const uint32_t *__restrict__ len, const uint32_t *__restrict__ entries,
+    const double4 *__restrict__ ps, const uint32_t *__restrict__ pidx, ForceParams fp, void *ax,
+    void *ay, void *az)
 {
-    __shared__ d4 tile[kTileJ];
+    __shared__ double4 tile[kTileF64];
     const uint32_t g = xcd_block(blockIdx.x, gridDim.x);
     const int lane = threadIdx.x;
     if (g >= n_groups) return;
     const uint32_t n_g = gr.count[g], f = gr.first[g];
     const uint64_t b = off[g];
     const uint64_t Lg = len[g];
-    const double L = fp.L, eps2 = fp.eps2, eta = fp.eta;
+    const double L = fp.L, eps2 = fp.eps2, inv_eta = fp.inv_eta, eta2 = fp.eta * fp.eta;
+    const double xg0 = gr.xgx[g], xg1 = gr.xgy[g], xg2 = gr.xgz[g];
+    const double cg0 = gr.cgx[g], cg1 = gr.cgy[g], cg2 = gr.cgz[g];
+    const double hg0 = gr.hgx[g], hg1 = gr.hgy[g], hg2 = gr.hgz[g];
+    const double half_side = 0.5 * ldexp(L, -(int)nd.level[gr.node[g]]);
+    const bool pair_wrap = !(half_side + sqrt(fp.rc2) < 0.5 * L);
+    const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
     for (uint32_t ib = 0; ib < n_g; ib += 64) {
         const uint32_t i = ib + lane;
         const bool act = i < n_g;
         double xi = 0.0, yi = 0.0, zi = 0.0;
         if (act) {
             const double4 r = ps[f + i];
-            xi = r.x;
-            yi = r.y;
-            zi = r.z;
+            xi = wrapd(r.x - xg0, L);
+            yi = wrapd(r.y - xg1, L);
+            zi = wrapd(r.z - xg2, L);
         }
         double ax_ = 0.0, ay_ = 0.0, az_ = 0.0;
-        for (uint64_t jb = 0; jb < Lg; jb += kTileJ) {
+        for (uint64_t jb = 0; jb < Lg; jb += kTileF64) {
+            // survivors: near ones (within eta of the box) from the front of the tile, far ones
+            // (every pair has R >= 1: eq. (2)'s second branch only) from the back
             const uint64_t j = jb + lane;
-            d4 v = {0.0, 0.0, 0.0, 0.0};
+            bool keep = false, far = false;
+            double4 v = make_double4(0.0, 0.0, 0.0, 0.0);
             if (j < Lg) {
                 const uint32_t e = entries[b + j];
                 const double4 r = (e & kCellTag) ? nd.nsrc[e & ~kCellTag] : nd.psrc[e];
-                v = {r.x, r.y, r.z, r.w};
+                double w0 = fabs(wrapd(r.x - cg0, L)) - hg0;
+                double w1 = fabs(wrapd(r.y - cg1, L)) - hg1;
+                double w2 = fabs(wrapd(r.z - cg2, L)) - hg2;
+                w0 = w0 > 0.0 ? w0 : 0.0;
+                w1 = w1 > 0.0 ? w1 : 0.0;
+                w2 = w2 > 0.0 ? w2 : 0.0;
+                const double gap2 = w0 * w0 + w1 * w1 + w2 * w2;
+                keep = gap2 < fp.rc2;
+                far = gap2 >= eta2;
+                v = make_double4(wrapd(r.x - xg0, L), wrapd(r.y - xg1, L), wrapd(r.z - xg2, L),
+                                 r.w);
             }
-            tile[lane] = v;
+            const uint64_t mn = __ballot(keep && !far), mf = __ballot(keep && far);
+            if (keep) {
+                if (far)
+                    tile[kTileF64 - 1 - __popcll(mf & lt)] = v;
+                else
+                    tile[__popcll(mn & lt)] = v;
+            }
+            const int nn = __popcll(mn), nf = __popcll(mf);
             __syncthreads();
-            const int nt = (Lg - jb) < (uint64_t)kTileJ ? (int)(Lg - jb) : kTileJ;
-            for (int t = 0; t < nt; ++t) {
-                const d4 s = tile[t];
-                const double dx = wrapd(s.x - xi, L), dy = wrapd(s.y - yi, L),
-                             dz = wrapd(s.z - zi, L);
-                const double r2 = dx * dx + dy * dy + dz * dz;
-                const double r = sqrt(r2);
-                const double s2 = r2 + eps2;
-                double fm = s.m * g_p3m_f64(r / eta) / (s2 * sqrt(s2));
-                fm = r2 > 0.0 ? fm : 0.0;
-                ax_ += fm * dx;
-                ay_ += fm * dy;
-                az_ += fm * dz;
+#define TPM_F64_PAIRS(FAR, WRAP, T0, T1)                                                       \
+    for (int t = (T0); t < (T1); ++t) {                                                        \
+        const double4 s = tile[t];                                                             \
+        double dx = s.x - xi, dy = s.y - yi, dz = s.z - zi;                                    \
+        if (WRAP) {                                                                            \
+            dx = wrapd(dx, L);                                                                 \
+            dy = wrapd(dy, L);                                                                 \
+            dz = wrapd(dz, L);                                                                 \
+        }                                                                                      \
+        const double r2 = dx * dx + dy * dy + dz * dz;                                         \
+        const double is = rsqrt_f64(r2 + eps2);                                                \
+        const double R = r2 * rsqrt_f64(r2) * inv_eta;                                         \
+        double fm = s.w * (FAR ? g_far_f64(R) : g_p3m_f64(R)) * (is * is * is);                \
+        fm = r2 > 0.0 ? fm : 0.0;                                                              \
+        ax_ += fm * dx;                                                                        \
+        ay_ += fm * dy;                                                                        \
+        az_ += fm * dz;                                                                        \
+    }
+            if (pair_wrap) {
+                TPM_F64_PAIRS(false, true, 0, nn)
+                TPM_F64_PAIRS(true, true, kTileF64 - nf, kTileF64)
+            } else {
+                TPM_F64_PAIRS(false, false, 0, nn)
+                TPM_F64_PAIRS(true, false, kTileF64 - nf, kTileF64)
             }
+#undef TPM_F64_PAIRS
             __syncthreads();
         }
         if (act) store3<OUT64>(ax, ay, az, pidx[f + i], ax_, ay_, az_);
