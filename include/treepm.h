@@ -124,7 +124,11 @@ int treepm_build(treepm_ctx *ctx, int64_t n, const double *x, const double *y, c
                  const double *m, int mem_kind, void *hip_stream);
 
 /* Barnes' group walk (Section 2.2 step 5): one interaction list per group.  Requires a
- * build (ERR_STATE).  Fills *stats if non-NULL. */
+ * build (ERR_STATE).  Fills *stats if non-NULL.  The first walk on a context counts the lists
+ * and then writes them (two passes); later walks write them in one pass into device memory
+ * sized from the previous walk (about 1.25x its lists plus a chunk per wave) and fall back to
+ * two passes if that is too small, so the lists never depend on the estimate.  ERR_OVERFLOW
+ * if a group's traversal stack would exceed its capacity (see last_error). */
 int treepm_walk(treepm_ctx *ctx, void *hip_stream, treepm_stats *stats);
 
 /* Short-range force on every particle from its group's list (eq. 1, 2), written in the
