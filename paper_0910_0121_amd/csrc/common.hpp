@@ -88,7 +88,7 @@ void radix_sort(int64_t n, uint64_t *key, uint32_t *idx, uint64_t *key_alt, uint
 // words) ends with flags[1] != 0 if a run could not be sorted this way: the order is then
 // incomplete and radix_sort (on the returned arrays) must follow.
 constexpr int kRunBits = 24;
-constexpr uint32_t kShortRun = 32;
+constexpr uint32_t kShortRun = 8; // the register sorting network in k_fix_runs has 8 inputs
 constexpr uint32_t kLongRun = 2048;
 bool radix_sort_high(int64_t n, uint64_t *key, uint32_t *idx, uint64_t *key_alt,
                      uint32_t *idx_alt, uint32_t *hist, uint32_t *scan_tmp, uint2 *long_runs,

@@ -186,7 +186,7 @@ __global__ __launch_bounds__(kSortThreads) void k_scatter(const uint64_t *__rest
 // Second half of the sort.  After stable passes over the key bits from kRunBits up, equal
 // high parts form runs (cells of about level 13, rarely more than a few particles) in input
 // order; sorting each run by (key, index) completes the order by (key, index).  One thread
-// per run start sorts a run of up to kShortRun elements by insertion; longer runs, up to
+// per run start sorts a run of up to kShortRun elements in registers; longer runs, up to
 // kLongRun, are listed for k_fix_long_runs; a run longer than that (or a full list) sets
 // *fallback, and the caller then sorts everything by all bits.  Elements of one run share the
 // high part, so reading neighbours while their runs are being reordered is harmless.
@@ -211,18 +211,40 @@ __global__ __launch_bounds__(256) void k_fix_runs(int64_t n, uint64_t *__restric
                 atomicOr(fallback, 1u);
             continue;
         }
-        for (int64_t a = i + 1; a < e; ++a) {
-            const uint64_t k = key[a];
-            const uint32_t v = idx[a];
-            int64_t b = a - 1;
-            while (b >= i && (key[b] > k || (key[b] == k && idx[b] > v))) {
-                key[b + 1] = key[b];
-                idx[b + 1] = idx[b];
-                --b;
+        if (len == 1) continue;
+        // up to kShortRun (8) elements: Batcher's odd-even merge network in registers, the
+        // unused slots padded with keys above every real one
+        uint64_t k8[8];
+        uint32_t v8[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            k8[q] = ~0ull;
+            v8[q] = ~0u;
+            if (q < len) {
+                k8[q] = key[i + q];
+                v8[q] = idx[i + q];
             }
-            key[b + 1] = k;
-            idx[b + 1] = v;
         }
+        constexpr int8_t net[19][2] = {{0, 1}, {2, 3}, {4, 5}, {6, 7}, {0, 2}, {1, 3}, {4, 6},
+                                       {5, 7}, {1, 2}, {5, 6}, {0, 4}, {1, 5}, {2, 6}, {3, 7},
+                                       {2, 4}, {3, 5}, {1, 2}, {3, 4}, {5, 6}};
+#pragma unroll
+        for (int c = 0; c < 19; ++c) {
+            const int a = net[c][0], b = net[c][1];
+            const bool swap = k8[a] > k8[b] || (k8[a] == k8[b] && v8[a] > v8[b]);
+            const uint64_t ka = swap ? k8[b] : k8[a], kb = swap ? k8[a] : k8[b];
+            const uint32_t va = swap ? v8[b] : v8[a], vb = swap ? v8[a] : v8[b];
+            k8[a] = ka;
+            k8[b] = kb;
+            v8[a] = va;
+            v8[b] = vb;
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            if (q < len) {
+                key[i + q] = k8[q];
+                idx[i + q] = v8[q];
+            }
     }
 }
 
