@@ -67,6 +67,10 @@ def lib():
         L.orc_tree_groups.argtypes = [_p] * 7
         L.orc_tree_lists.restype = C.c_int
         L.orc_tree_lists.argtypes = [_p, _p, _p, _p]
+        L.orc_theta_r.restype = _d
+        L.orc_theta_r.argtypes = [_d, _d, _d, _d]
+        L.orc_tree_set_opening.restype = C.c_int
+        L.orc_tree_set_opening.argtypes = [_p, C.c_int, _d]
         L.orc_key.restype = C.c_uint64
         L.orc_key.argtypes = [_d, _d, _d, _d]
         _lib = L
@@ -114,6 +118,11 @@ def direct_cells(x, y, z, m, L, r_cut, eps, nthreads=0):
     return _direct(lib().orc_direct_cells, x, y, z, m, L, r_cut, eps, nthreads)
 
 
+def theta_r(r: float, eta: float, theta0: float, theta_max: float) -> float:
+    """Distance-dependent opening angle of eq. (12), r in units of eta, capped."""
+    return float(lib().orc_theta_r(r, eta, theta0, theta_max))
+
+
 def key(x, y, z, L=1.0) -> int:
     return int(lib().orc_key(x, y, z, L))
 
@@ -121,7 +130,10 @@ def key(x, y, z, L=1.0) -> int:
 class Tree:
     """Reference tree, groups, lists and list force for one box."""
 
-    def __init__(self, x, y, z, m, L, r_cut, eps, theta, n_leaf, n_crit):
+    def __init__(self, x, y, z, m, L, r_cut, eps, theta, n_leaf, n_crit, opening=0,
+                 theta_max=0.0):
+        """opening=1 selects the distance-dependent angle of eq. (12): theta is then theta_0
+        and theta_max its upper limit."""
         self._keep = [_f64(a) for a in (x, y, z, m)]
         x, y, z, m = self._keep
         self.n = x.size
@@ -129,6 +141,12 @@ class Tree:
                                       theta, n_leaf, n_crit)
         if not self.h:
             raise ValueError("oracle tree build failed")
+        if opening:
+            self.set_opening(opening, theta_max)
+
+    def set_opening(self, opening, theta_max=0.0):
+        if lib().orc_tree_set_opening(self.h, int(opening), float(theta_max)) != 0:
+            raise ValueError("invalid opening criterion")
 
     def close(self):
         if self.h:

@@ -36,6 +36,11 @@
  *  - prune: periodic gap between the node cube and the group bbox >= r_cut;
  *  - accept: l^2 < theta^2 * d^2, d = distance from the node's centre of mass to the group
  *    bbox, and the node cube does not touch the bbox (gap > 0); a tie opens the node.
+ *  - distance-dependent opening (Section 4.1, eq. 12), when selected: theta is replaced by
+ *    theta(d) = min(theta_max, theta_0 / sqrt(R g_P3M(R))), R = d / eta -- the distance is
+ *    measured in units of eta so that theta_0 is dimensionless, d is the same distance as in
+ *    the fixed test, and theta(d) = theta_max where R g(R) = 0 (the upper limit the paper
+ *    asks for, since the unlimited angle diverges at both ends of the range).
  */
 #include <math.h>
 #include <stdint.h>
@@ -71,6 +76,19 @@ static double wrap(double v, double L)
     if (v >= h) return v - L;
     if (v < -h) return v + L;
     return v;
+}
+
+/* Distance-dependent opening angle of Section 4.1, eq. (12): the uniform-density error of
+ * a node at distance r scales as r theta^2 g(r/eta), so theta_0 / sqrt(R g(R)) spreads it
+ * evenly.  R = r / eta (distance in units of eta), capped at theta_max; where R g(R) = 0
+ * (r = 0, r >= r_cut) the cap is the angle. */
+double orc_theta_r(double r, double eta, double theta0, double theta_max)
+{
+    double R = r / eta;
+    double s = R * orc_g_p3m(R);
+    if (!(s > 0.0)) return theta_max;
+    double th = theta0 / sqrt(s);
+    return th < theta_max ? th : theta_max;
 }
 
 /* Acceleration at the field point from a source of mass m displaced by d (source minus
@@ -231,6 +249,8 @@ typedef struct {
     /* parameters */
     double L, r_cut, eps, theta;
     int n_leaf, n_crit;
+    int opening;        /* 0: fixed theta; 1: theta(d) of eq. (12), theta = theta_0        */
+    double theta_max;   /* upper limit of theta(d) (opening 1)                           */
     /* particles */
     int64_t n;
     uint64_t *key;      /* sorted keys                                                  */
@@ -480,6 +500,21 @@ void orc_tree_free(otree *t)
     free(t);
 }
 
+/* Select the opening criterion: 0 = fixed theta (the build's theta); 1 = theta(d) of
+ * eq. (12) with theta_0 = the build's theta and the cap theta_max.  Drops earlier lists.
+ * Returns 0, or -1 for an invalid choice. */
+int orc_tree_set_opening(otree *t, int opening, double theta_max)
+{
+    if (!t || opening < 0 || opening > 1 || !(theta_max >= 0.0)) return -1;
+    t->opening = opening;
+    t->theta_max = theta_max;
+    free(t->list_off); free(t->list); free(t->list_is_cell);
+    t->list_off = NULL; t->list = NULL; t->list_is_cell = NULL;
+    t->n_entries = 0;
+    t->walked = 0;
+    return 0;
+}
+
 /* ------------------------------------------------ walk: one interaction list per group */
 
 typedef struct {
@@ -509,6 +544,7 @@ static int elist_push(elist *l, int64_t v, uint8_t is_cell)
 /* Visit node u for group g, in depth-first octant order:
  *   prune  : gap_a = max(0, |wrap(cn_a - cg_a)| - (l/2 + hg_a)),  sum gap^2 >= r_cut^2
  *   accept : dc_a  = max(0, |wrap(com_a - cg_a)| - hg_a),   l^2 < theta^2 sum dc^2, gap^2 > 0
+ *            (theta = theta(d), d = sqrt(sum dc^2), under the distance-dependent opening)
  *   leaf   : one particle entry per particle, key order
  *   else   : visit the children. */
 static int walk_rec(const otree *t, const ogroup *g, int64_t u, double rc2, double th2,
@@ -531,6 +567,10 @@ static int walk_rec(const otree *t, const ogroup *g, int64_t u, double rc2, doub
         dc[a] = v > 0.0 ? v : 0.0;
     }
     double D = dc[0] * dc[0] + dc[1] * dc[1] + dc[2] * dc[2];
+    if (t->opening) {
+        double th = orc_theta_r(sqrt(D), 0.5 * t->r_cut, t->theta, t->theta_max);
+        th2 = th * th;
+    }
     if (l * l < th2 * D && G > 0.0) return elist_push(out, u, 1);
     if (nd->nchild == 0) {
         for (int64_t k = nd->first; k < nd->first + nd->count; ++k)

@@ -59,6 +59,25 @@ MUTANTS = [
     ("leaf_particles_skipped", "for (int64_t k = nd->first; k < nd->first + nd->count; ++k)\n            if (elist_push(out, k, 0)) return -1;",
      "for (int64_t k = nd->first + 1; k < nd->first + nd->count; ++k)\n            if (elist_push(out, k, 0)) return -1;",
      TREE + "::test_theta_zero_is_direct_sum"),
+    ("theta_r_inverted", "double th = theta0 / sqrt(s);", "double th = theta0 * sqrt(s);",
+     TREE + "::test_theta_r_closed_forms"),
+    ("theta_r_without_g_cost", "double s = R * orc_g_p3m(R);", "double s = R;",
+     TREE + "::test_distance_opening_beats_fixed_in_uniform_limit"),
+    ("theta_r_zero_where_rg_vanishes", "if (!(s > 0.0)) return theta_max;",
+     "if (!(s > 0.0)) return 0.0;", TREE + "::test_theta_r_cap"),
+    ("theta_r_no_sqrt", "double th = theta0 / sqrt(s);", "double th = theta0 / s;",
+     TREE + "::test_theta_r_closed_forms"),
+    ("theta_r_eta_is_rcut", "double R = r / eta;", "double R = r / (2.0 * eta);",
+     TREE + "::test_theta_r_closed_forms"),
+    ("theta_r_without_g", "double s = R * orc_g_p3m(R);", "double s = R;",
+     TREE + "::test_theta_r_closed_forms"),
+    ("theta_r_uncapped", "return th < theta_max ? th : theta_max;", "return th;",
+     TREE + "::test_theta_r_cap"),
+    ("opening_distance_squared", "orc_theta_r(sqrt(D), 0.5 * t->r_cut,",
+     "orc_theta_r(D, 0.5 * t->r_cut,",
+     TREE + "::test_distance_opening_lists_equal_brute_force_frontier"),
+    ("opening_angle_not_squared", "        th2 = th * th;\n", "        th2 = th;\n",
+     TREE + "::test_distance_opening_lists_equal_brute_force_frontier"),
 ]
 
 

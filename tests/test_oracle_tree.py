@@ -6,7 +6,9 @@ measured from the surface of the receiving region).  The method is an approximat
 pins are: hand-computed keys, structural invariants, a brute-force frontier built from all
 nodes without recursion, geometric checks of every pruned and accepted node against the
 particles themselves, exact coverage of every particle within r_cut, and the theta -> 0
-limit equal to the exact direct sum.
+limit equal to the exact direct sum.  The distance-dependent opening angle of Section 4.1
+(eq. 12) is pinned by closed-form values of the angle, its cap, the same brute-force
+frontier, and the paper's uniform-density claim (less error at no more cost).
 """
 import math
 
@@ -151,9 +153,10 @@ def _min_image(d):
     return d - np.floor(d + 0.5)
 
 
-def _frontier_check(orc, T, pos_in, m_in, theta, r_cut):
+def _frontier_check(orc, T, pos_in, m_in, theta, r_cut, theta_of_d=None):
     """Rebuild each group's list from all nodes without recursion and check every entry
-    geometrically against the particles."""
+    geometrically against the particles.  theta_of_d: the angle as a function of the node's
+    distance d from the group's bbox (distance-dependent opening); None = theta fixed."""
     k, idx = T.sorted()
     pos = pos_in[idx]
     nd = T.nodes()
@@ -181,7 +184,14 @@ def _frontier_check(orc, T, pos_in, m_in, theta, r_cut):
         Gs = (gap * gap).sum(axis=1)
         P = Gs >= rc2
         dc = np.maximum(0.0, np.abs(_min_image(nd["com"] - cg)) - hg)
-        A = (side * side < th2 * (dc * dc).sum(axis=1)) & (Gs > 0.0) & ~P
+        Ds = (dc * dc).sum(axis=1)
+        if theta_of_d is None:
+            thn = np.full(n_nodes, theta)
+            th2n = np.full(n_nodes, th2)
+        else:
+            thn = np.array([theta_of_d(math.sqrt(v)) for v in Ds])
+            th2n = thn * thn
+        A = (side * side < th2n * Ds) & (Gs > 0.0) & ~P
         opened = ~A & ~P
         live = np.array([all(opened[a] for a in ancestors[u]) for u in range(n_nodes)])
         exp_cells = {int(nd["code"][u]) for u in np.nonzero(live & A)[0]}
@@ -202,7 +212,7 @@ def _frontier_check(orc, T, pos_in, m_in, theta, r_cut):
             covered[f:f + c] += 1
             # accepted: side/theta < distance from com to the nearest group particle
             dmin = np.sqrt((_min_image(gpos - nd["com"][u]) ** 2).sum(axis=1)).min()
-            assert side[u] < theta * dmin
+            assert side[u] < thn[u] * dmin
         for u in np.nonzero(live & P)[0]:
             f, c = int(nd["first"][u]), int(nd["count"][u])
             # pruned: every particle of the node is at least r_cut from every group particle
@@ -326,3 +336,93 @@ def test_opening_tie_opens_the_node(orc):
     # level-4 codes (marker 1 << 12) under B = level-3 code 0b1_000_100_000
     b3 = (1 << 9) | (0b000 << 6) | (0b100 << 3) | 0b000
     assert cells == sorted([(b3 << 3) | 0b000, (b3 << 3) | 0b100])
+
+
+# ---------------------------------------------------------------- distance-dependent opening
+
+# g_P3M of eq. (2) at R = 1/2, 1, 3/2, worked out by hand as exact fractions:
+#   R = 1/2: 1 - (28 - 7 + 35/32 + 3/8 - 21/256)/140 = 1 - 5731/35840 = 30109/35840
+#   R = 1  : 1 - (224 - 224 + 70 + 48 - 21)/140      = 43/140
+#   R = 3/2: 1 - (12 - 504 + 3024 - 8505/2 + 1701 + 51030/64 - 6561/8 + 45927/256)/140
+#          = 1 - 35103/35840 = 737/35840
+G_EXACT = {0.5: 30109 / 35840, 1.0: 43 / 140, 1.5: 737 / 35840}
+
+
+@pytest.mark.parametrize("eta", [1.0, 3.0 / 64.0, 0.001])
+def test_theta_r_closed_forms(orc, eta):
+    """theta(r) = theta_0 / sqrt(R g(R)), R = r / eta (eq. 12), below the cap."""
+    for R, g in G_EXACT.items():
+        for th0 in (0.01, 0.05, 0.2):
+            want = th0 / math.sqrt(R * g)
+            assert orc.theta_r(R * eta, eta, th0, 10.0) == pytest.approx(want, rel=1e-14)
+    # the smallest angle sits where R g(R) peaks, near R = 0.65: theta >= theta_0 / 0.673
+    rs = np.linspace(0.01, 1.99, 2000) * eta
+    th = np.array([orc.theta_r(r, eta, 0.1, 10.0) for r in rs])
+    assert 0.1 / math.sqrt(0.4528) < th.min() < 0.1 / math.sqrt(0.4526)
+    assert 0.6 * eta < rs[np.argmin(th)] < 0.7 * eta
+
+
+def test_theta_r_cap(orc):
+    """The angle diverges at r -> 0 and r -> 2 eta (R g -> 0), so it is capped at theta_max;
+    it equals theta_max exactly where R g(R) = 0 (r = 0, r >= r_cut)."""
+    eta = 0.05
+    for r in (0.0, 2 * eta, 3 * eta, 1.0):
+        assert orc.theta_r(r, eta, 0.1, 0.7) == 0.7
+    # near both ends the unlimited angle exceeds any cap
+    assert orc.theta_r(1e-9, eta, 0.1, 0.7) == 0.7
+    assert orc.theta_r(2 * eta * (1 - 1e-6), eta, 0.1, 0.7) == 0.7
+    # in between it is below the cap and continuous across R = 1
+    a, b = orc.theta_r(eta * (1 - 1e-9), eta, 0.1, 0.7), orc.theta_r(eta * (1 + 1e-9), eta,
+                                                                    0.1, 0.7)
+    assert a < 0.7 and b == pytest.approx(a, rel=1e-6)
+    # a cap of 0 never accepts a node: the list force is the direct sum
+    n, r_cut, eps = 3000, 0.1, 0.002
+    x, y, z, m = boxgen.nfw_box(n, 20, 31)
+    T = orc.Tree(x, y, z, m, 1.0, r_cut, eps, 0.1, 10, 64, opening=1, theta_max=0.0)
+    off, isc, val = T.lists()
+    assert not isc.any()
+    a = np.stack(T.force())
+    b = np.stack(orc.direct_cells(x, y, z, m, 1.0, r_cut, eps))
+    assert np.max(np.abs(a - b)) <= 1e-13 * np.max(np.linalg.norm(b, axis=0))
+
+
+@pytest.mark.parametrize("theta0,theta_max", [(0.05, 0.5), (0.15, 1.0), (0.3, 0.6)])
+def test_distance_opening_lists_equal_brute_force_frontier(orc, theta0, theta_max):
+    n, r_cut = 400, 0.2
+    x, y, z, m = boxgen.nfw_box(n, 4, 5)
+    T = orc.Tree(x, y, z, m, 1.0, r_cut, 0.003, theta0, 3, 20, opening=1, theta_max=theta_max)
+    eta = 0.5 * r_cut
+    _frontier_check(orc, T, np.stack([x, y, z], axis=1), m, theta0, r_cut,
+                    theta_of_d=lambda d: orc.theta_r(d, eta, theta0, theta_max))
+
+
+def test_distance_opening_reduces_to_fixed_at_the_cap(orc):
+    """theta_0 so large that theta(r) >= theta_max everywhere: the lists are those of the
+    fixed angle theta_max, entry for entry."""
+    x, y, z, m = boxgen.nfw_box(3000, 20, 32)
+    for tmax in (0.4, 0.8):
+        F = orc.Tree(x, y, z, m, 1.0, 0.1, 0.002, tmax, 8, 48)
+        V = orc.Tree(x, y, z, m, 1.0, 0.1, 0.002, 1.0e6, 8, 48, opening=1, theta_max=tmax)
+        for a, b in zip(F.lists(), V.lists()):
+            assert np.array_equal(a, b)
+
+
+def test_distance_opening_beats_fixed_in_uniform_limit(orc):
+    """Section 4.1: in the uniform-density limit a node's error scales as r theta^2 g(r/eta),
+    so the angle of eq. (12) spreads the error evenly and should minimise it.  On the
+    32^3 uniform box (r_cut = 3/32, eps = 1/640, n_crit = 64) theta_0 = 0.05 with cap 0.6
+    costs fewer interactions than the fixed theta = 0.5 and has a several times smaller RMS
+    relative error against the exact short-range force."""
+    spec, (x, y, z, m) = boxgen.config_box("uniform32k")
+    ex = np.stack(orc.direct_cells(x, y, z, m, spec.L, spec.r_cut, spec.eps), axis=1)
+    mag = np.linalg.norm(ex, axis=1)
+
+    def rms(T):
+        a = np.stack(T.force(), axis=1)
+        return float(np.sqrt(np.mean((np.linalg.norm(a - ex, axis=1) / mag) ** 2)))
+
+    F = orc.Tree(x, y, z, m, spec.L, spec.r_cut, spec.eps, 0.5, spec.n_leaf, spec.n_crit)
+    V = orc.Tree(x, y, z, m, spec.L, spec.r_cut, spec.eps, 0.05, spec.n_leaf, spec.n_crit,
+                 opening=1, theta_max=0.6)
+    assert V.interactions() < F.interactions()
+    assert rms(V) < rms(F) / 4.0
