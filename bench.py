@@ -48,6 +48,12 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--cpu-stride", type=int, default=0,
                     help="oracle sample: every k-th group (0 = choose for ~15 s of work)")
+    ap.add_argument("--no-theta-r", action="store_true",
+                    help="skip the distance-dependent opening angle leg")
+    ap.add_argument("--theta0", type=float, default=0.3,
+                    help="theta_0 of the distance-dependent opening angle leg")
+    ap.add_argument("--theta-max", type=float, default=0.5,
+                    help="cap of the distance-dependent opening angle leg")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-boxes", type=int, default=64)
     ap.add_argument("--serving-requests-per-box", type=int, default=10)
@@ -373,6 +379,34 @@ def main():
             "achieved_tflops": K_PP * inter / f64 / 1e12,
             "frac_fp64_peak": K_PP * inter / f64 / 1e12 / FP64_VECTOR_PEAK_TFLOPS,
             "force_speedup_fp32_over_fp64": f64 / t_force,
+        }
+    if not args.no_theta_r:
+        # The same box and step under the distance-dependent angle of eq. (12).
+        pr = tp.make_params(spec.L, spec.mesh, spec.r_cut, spec.eps, args.theta0, spec.n_leaf,
+                            n_crit, tp.TREEPM_FP32, opening=tp.TREEPM_OPEN_DISTANCE,
+                            theta_max=args.theta_max)
+        ctx = tp.treepm_create(pr, 0)
+        tp.treepm_set_timing(ctx, True)
+        log(f"[bench] theta(r) leg: theta_0={args.theta0}, cap={args.theta_max}")
+        run_steps(tp, torch, ctx, dev, acc, 2)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        kr = max(1, min(5, args.steps))
+        timesr, str_ = run_steps(tp, torch, ctx, dev, acc, kr)
+        torch.cuda.synchronize()
+        er = time.perf_counter() - t1
+        tp.treepm_destroy(ctx)
+        phr = np.array(timesr)
+        fr = float(np.mean(phr[:, 2])) * 1e-3
+        result["theta_r"] = {
+            "theta0": args.theta0, "theta_max": args.theta_max,
+            "ms_per_step": er / kr * 1e3,
+            "particles_per_s": spec.n * kr / er,
+            "interactions": int(str_.interactions),
+            "interactions_per_s": int(str_.interactions) / fr,
+            "cell_entries": int(str_.n_cell_entries),
+            "phase_ms": {"build": float(np.mean(phr[:, 0])), "walk": float(np.mean(phr[:, 1])),
+                         "force_f32": float(np.mean(phr[:, 2]))},
         }
     if not args.no_serving:
         log("[bench] ensemble serving")

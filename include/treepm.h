@@ -51,6 +51,7 @@ enum {
 
 enum { TREEPM_FP32 = 0, TREEPM_FP64 = 1 };   /* pair-kernel / output precision */
 enum { TREEPM_HOST = 0, TREEPM_DEVICE = 1 }; /* memory kind of caller buffers  */
+enum { TREEPM_OPEN_FIXED = 0, TREEPM_OPEN_DISTANCE = 1 }; /* opening criterion        */
 
 /* Parameters of one box (Section 2.2 step 1; Section 2.4; Section 3.1.2).
  *   L        periodic box side, > 0 (the paper normalises it to 1).
@@ -60,13 +61,22 @@ enum { TREEPM_HOST = 0, TREEPM_DEVICE = 1 }; /* memory kind of caller buffers  *
  *   eps      Plummer softening, >= 0; the FP32 kernel requires eps > 0.
  *   theta    opening angle, 0 <= theta <= 1.  A node of side l is used as one source when
  *            l < theta d, d = distance from its centre of mass to the group's bounding box
- *            (minimum image), and its cube does not touch that box.
+ *            (minimum image), and its cube does not touch that box.  Under
+ *            TREEPM_OPEN_DISTANCE this is theta_0 of the distance-dependent angle.
  *   n_leaf   a node is subdivided iff it holds >= n_leaf particles (and level < 21); >= 2.
  *   n_crit   groups are the maximal nodes holding <= n_crit particles (or leaves); >= 1;
  *            0 selects the library default (128).
  *   precision TREEPM_FP32: pair force in FP32 on positions relative to the group's cube
  *            centre with compensated accumulation (Section 3.1.1); TREEPM_FP64: plain FP64.
- *            The tree, moments and every walk decision are FP64 in both cases. */
+ *            The tree, moments and every walk decision are FP64 in both cases.
+ *   opening  TREEPM_OPEN_FIXED (0, the default of a zeroed struct): theta as above.
+ *            TREEPM_OPEN_DISTANCE: the distance-dependent angle of Section 4.1, eq. (12),
+ *            theta(d) = min(theta_max, theta / sqrt(R g_P3M(R))), R = d / eta (distance in
+ *            units of eta), and theta(d) = theta_max where R g(R) = 0 (d = 0 or d >= r_cut);
+ *            the node is used when l < theta(d) d.  sqrt and divisions are correctly rounded,
+ *            so the lists equal a plain FP64 evaluation.
+ *   theta_max the cap of theta(d), 0 <= theta_max <= 1 (read only under
+ *            TREEPM_OPEN_DISTANCE). */
 typedef struct {
     double L;
     double mesh;
@@ -76,6 +86,8 @@ typedef struct {
     int32_t n_leaf;
     int32_t n_crit;
     int32_t precision;
+    int32_t opening;
+    double theta_max;
 } treepm_params;
 
 typedef struct treepm_ctx treepm_ctx; /* one resident box on one GPU */

@@ -11,6 +11,8 @@ from ._native import (  # noqa: F401
     TREEPM_FP32,
     TREEPM_FP64,
     TREEPM_HOST,
+    TREEPM_OPEN_DISTANCE,
+    TREEPM_OPEN_FIXED,
     TREEPM_OK,
     TREEPM_PENDING,
     TreePMError,

@@ -12,6 +12,7 @@ LIB_PATH = os.path.join(PKG, "libtreepm.so")
 TREEPM_OK, TREEPM_PENDING = 0, 1
 TREEPM_FP32, TREEPM_FP64 = 0, 1
 TREEPM_HOST, TREEPM_DEVICE = 0, 1
+TREEPM_OPEN_FIXED, TREEPM_OPEN_DISTANCE = 0, 1
 
 ERROR_NAMES = {
     -1: "TREEPM_ERR_ARG", -2: "TREEPM_ERR_RANGE", -3: "TREEPM_ERR_OOM",
@@ -29,7 +30,8 @@ class TreePMError(RuntimeError):
 class treepm_params(C.Structure):
     _fields_ = [("L", C.c_double), ("mesh", C.c_double), ("r_cut", C.c_double),
                 ("eps", C.c_double), ("theta", C.c_double), ("n_leaf", C.c_int32),
-                ("n_crit", C.c_int32), ("precision", C.c_int32)]
+                ("n_crit", C.c_int32), ("precision", C.c_int32), ("opening", C.c_int32),
+                ("theta_max", C.c_double)]
 
 
 class treepm_stats(C.Structure):
@@ -109,14 +111,18 @@ def _check(rc: int, ctx=None):
 
 
 def make_params(L=1.0, mesh=None, r_cut=None, eps=0.0, theta=0.5, n_leaf=10, n_crit=0,
-                precision=TREEPM_FP32) -> treepm_params:
+                precision=TREEPM_FP32, opening=TREEPM_OPEN_FIXED,
+                theta_max=0.0) -> treepm_params:
+    """opening=TREEPM_OPEN_DISTANCE selects theta(d) of eq. (12): theta is then theta_0 and
+    theta_max its cap."""
     if mesh is None and r_cut is None:
         raise ValueError("give mesh or r_cut")
     if mesh is None:
         mesh = r_cut / 3.0
     if r_cut is None:
         r_cut = 3.0 * mesh
-    return treepm_params(L, mesh, r_cut, eps, theta, n_leaf, n_crit, precision)
+    return treepm_params(L, mesh, r_cut, eps, theta, n_leaf, n_crit, precision, opening,
+                         theta_max)
 
 
 # ----------------------------------------------------------------------------- buffers

@@ -122,9 +122,13 @@ void launch_group_bbox(NodeArrays nd, GroupArrays gr, uint32_t n_groups, const d
                        unsigned *max_count, hipStream_t s);
 
 // ------------------------------------------------------------------ launchers (k_walk.hip)
+// open = 0: fixed angle, th2 = theta^2.  open = 1: theta(d) of eq. (12) from eta = r_cut/2,
+// theta0 and the cap theta_max.
 struct WalkParams {
     double L, rc2, th2;
+    double eta, theta0, theta_max;
     uint32_t n_nodes;
+    uint32_t open;
 };
 // Group g's interaction list is entries[off[g] .. off[g] + len[g]).
 // Two passes: the count pass writes each list length to counts[g]; after the caller's prefix

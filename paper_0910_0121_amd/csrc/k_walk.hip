@@ -9,6 +9,9 @@
 //          gap_a = max(0, |wrap(cn_a - cg_a)| - (l/2 + hg_a)),  gap^2 >= r_cut^2
 //   accept (opening criterion measured from the box surface):
 //          dc_a = max(0, |wrap(com_a - cg_a)| - hg_a),  l^2 < theta^2 dc^2  and gap^2 > 0
+//          theta is fixed, or (distance-dependent opening, Section 4.1 eq. 12) the angle
+//          theta(d) = min(theta_max, theta_0 / sqrt(R g(R))), R = d / eta, d = |dc|, taken
+//          as theta_max where R g(R) = 0
 //   leaf   : one particle entry per particle
 //   else   : push the children.
 //
@@ -71,12 +74,39 @@ __device__ __forceinline__ uint32_t wave_incl_max(uint32_t x)
     return x;
 }
 
+// g_P3M(R) of eq. (2) in its expanded polynomial form, evaluated term by term from the
+// powers R^2 .. R^8 so that the opening decisions it feeds are plain IEEE FP64 operations.
+__device__ __forceinline__ double g_p3m_expanded(double R)
+{
+    const double R2 = R * R, R3 = R2 * R, R4 = R3 * R, R5 = R4 * R, R6 = R5 * R, R7 = R6 * R,
+                 R8 = R7 * R;
+    if (R < 1.0)
+        return 1.0 - (224.0 * R3 - 224.0 * R5 + 70.0 * R6 + 48.0 * R7 - 21.0 * R8) / 140.0;
+    if (R < 2.0)
+        return 1.0 - (12.0 - 224.0 * R2 + 896.0 * R3 - 840.0 * R4 + 224.0 * R5 + 70.0 * R6 -
+                      48.0 * R7 + 7.0 * R8) / 140.0;
+    return 0.0;
+}
+
+// theta(d) of eq. (12) with the distance in units of eta and the cap theta_max.  sqrt and
+// the divisions are the correctly rounded FP64 operations.
+__device__ __forceinline__ double theta_of_d(double d, const WalkParams &wp)
+{
+    const double R = d / wp.eta;
+    const double s = R * g_p3m_expanded(R);
+    if (!(s > 0.0)) return wp.theta_max;
+    const double th = wp.theta0 / sqrt(s);
+    return th < wp.theta_max ? th : wp.theta_max;
+}
+
 struct Visit {
     int kind; // 0 skip, 1 cell entry, 2 leaf particles, 3 open
     uint32_t ne, np, f, cf;
 };
 
-// The decision for a node with record w (see the top of this file).
+// The decision for a node with record w (see the top of this file).  OPEN: 0 fixed theta,
+// 1 distance-dependent theta(d).
+template <int OPEN>
 __device__ __forceinline__ Visit visit(const WalkNode &w, const WalkParams &wp, double cg0,
                                        double cg1, double cg2, double hg0, double hg1,
                                        double hg2)
@@ -95,8 +125,13 @@ __device__ __forceinline__ Visit visit(const WalkNode &w, const WalkParams &wp, 
         double w1 = awrap(w.com[1] - cg1, L) - hg1;
         double w2 = awrap(w.com[2] - cg2, L) - hg2;
         double d0 = w0 > 0.0 ? w0 : 0.0, d1 = w1 > 0.0 ? w1 : 0.0, d2 = w2 > 0.0 ? w2 : 0.0;
-    double D = d0 * d0 + d1 * d1 + d2 * d2;
-        if (l * l < wp.th2 * D && G > 0.0) {
+        const double D = d0 * d0 + d1 * d1 + d2 * d2;
+        double th2 = wp.th2;
+        if (OPEN) {
+            const double th = theta_of_d(sqrt(D), wp);
+            th2 = th * th;
+        }
+        if (l * l < th2 * D && G > 0.0) {
             r.kind = 1;
             r.ne = 1;
         } else if (w.nchild == 0) {
@@ -115,7 +150,7 @@ __device__ __forceinline__ Visit visit(const WalkNode &w, const WalkParams &wp, 
 // Walks group g with the calling wave.  EMIT: writes the list to dst[0 .. cap) (entries past
 // cap are counted but not stored).  Returns the list length; *ncell gets the cell entries.
 // stk (kStackCap) and s_mark (64) are the wave's LDS scratch.
-template <int EMIT>
+template <int EMIT, int OPEN>
 __device__ __forceinline__ uint64_t walk_group(const WalkNode *__restrict__ wn,
                                                const GroupArrays &gr, uint32_t g,
                                                const WalkParams &wp, uint32_t *stk,
@@ -145,7 +180,7 @@ __device__ __forceinline__ uint64_t walk_group(const WalkNode *__restrict__ wn,
             u = 0u;
         }
         const WalkNode rec = wn[u]; // an idle lane reads the root's record (node 0)
-        if (has) a = visit(rec, wp, cg0, cg1, cg2, hg0, hg1, hg2);
+        if (has) a = visit<OPEN>(rec, wp, cg0, cg1, cg2, hg0, hg1, hg2);
         __syncthreads(); // every lane has read its stack slot before the stack is rewritten
         top -= k;
         uint32_t ne_tot, np_tot;
@@ -191,7 +226,7 @@ __device__ __forceinline__ uint64_t walk_group(const WalkNode *__restrict__ wn,
 
 // Two passes, one wave per group.  Count: cnt[g] = list length.  Emit: writes the list at
 // entries + off[g], and len[g], gcells[g].
-template <int EMIT>
+template <int EMIT, int OPEN>
 __global__ __launch_bounds__(64) void k_walk(const WalkNode *__restrict__ wn, GroupArrays gr,
                                              uint32_t n_groups, WalkParams wp,
                                              uint64_t *__restrict__ cnt_off,
@@ -204,7 +239,7 @@ __global__ __launch_bounds__(64) void k_walk(const WalkNode *__restrict__ wn, Gr
     const uint32_t g = xcd_block(blockIdx.x, gridDim.x);
     if (g >= n_groups) return;
     uint64_t ncell = 0;
-    const uint64_t w = walk_group<EMIT>(wn, gr, g, wp, stk, s_mark,
+    const uint64_t w = walk_group<EMIT, OPEN>(wn, gr, g, wp, stk, s_mark,
                                         EMIT ? entries + cnt_off[g] : nullptr, ~0ull, overflow,
                                         &ncell);
     if (threadIdx.x == 0) {
@@ -225,6 +260,7 @@ __global__ __launch_bounds__(64) void k_walk(const WalkNode *__restrict__ wn, Gr
 // left there; if its list did not fit (or there was no such room) the wave takes a fresh
 // chunk and walks the group into that.  A list longer than a chunk, or an exhausted pool,
 // sets bit 4 of *overflow and ends the wave.
+template <int OPEN>
 __global__ __launch_bounds__(64) void k_walk_pool(const WalkNode *__restrict__ wn,
                                                   GroupArrays gr, uint32_t n_groups,
                                                   WalkParams wp, uint32_t *counters,
@@ -254,7 +290,7 @@ __global__ __launch_bounds__(64) void k_walk_pool(const WalkNode *__restrict__ w
                 uint64_t ncell = 0, w = 0;
                 bool fits = false;
                 if (end - cur >= reserve) { // room for a list of typical length: try here
-                    w = walk_group<1>(wn, gr, g, wp, stk, s_mark, entries + cur, end - cur,
+                    w = walk_group<1, OPEN>(wn, gr, g, wp, stk, s_mark, entries + cur, end - cur,
                                       overflow, &ncell);
                     fits = w <= end - cur;
                 }
@@ -271,7 +307,7 @@ __global__ __launch_bounds__(64) void k_walk_pool(const WalkNode *__restrict__ w
                         if (threadIdx.x == 0) atomicOr(overflow, 4u);
                         return;
                     }
-                    w = walk_group<1>(wn, gr, g, wp, stk, s_mark, entries + cur, chunk,
+                    w = walk_group<1, OPEN>(wn, gr, g, wp, stk, s_mark, entries + cur, chunk,
                                       overflow, &ncell);
                     if (w > chunk) {
                         if (threadIdx.x == 0) atomicOr(overflow, 4u);
@@ -338,8 +374,12 @@ void launch_walk_count(const WalkNode *wn, GroupArrays gr, uint32_t n_groups, Wa
                        uint64_t *counts, unsigned *overflow, hipStream_t s)
 {
     if (!n_groups) return;
-    k_walk<0><<<n_groups, 64, 0, s>>>(wn, gr, n_groups, wp, counts, nullptr, nullptr, overflow,
-                                     nullptr);
+    if (wp.open)
+        k_walk<0, 1><<<n_groups, 64, 0, s>>>(wn, gr, n_groups, wp, counts, nullptr, nullptr,
+                                            overflow, nullptr);
+    else
+        k_walk<0, 0><<<n_groups, 64, 0, s>>>(wn, gr, n_groups, wp, counts, nullptr, nullptr,
+                                            overflow, nullptr);
 }
 
 void launch_walk_emit(const WalkNode *wn, GroupArrays gr, uint32_t n_groups, WalkParams wp,
@@ -347,8 +387,12 @@ void launch_walk_emit(const WalkNode *wn, GroupArrays gr, uint32_t n_groups, Wal
                       uint32_t *gcells, hipStream_t s)
 {
     if (!n_groups) return;
-    k_walk<1><<<n_groups, 64, 0, s>>>(wn, gr, n_groups, wp, const_cast<uint64_t *>(off), len,
-                                     entries, overflow, gcells);
+    if (wp.open)
+        k_walk<1, 1><<<n_groups, 64, 0, s>>>(wn, gr, n_groups, wp, const_cast<uint64_t *>(off),
+                                            len, entries, overflow, gcells);
+    else
+        k_walk<1, 0><<<n_groups, 64, 0, s>>>(wn, gr, n_groups, wp, const_cast<uint64_t *>(off),
+                                            len, entries, overflow, gcells);
 }
 
 void launch_walk_pool(const WalkNode *wn, GroupArrays gr, uint32_t n_groups, WalkParams wp,
@@ -358,9 +402,16 @@ void launch_walk_pool(const WalkNode *wn, GroupArrays gr, uint32_t n_groups, Wal
 {
     if (!n_groups) return;
     fill_u32(counters, kXcds + 2, 0u, s);
-    k_walk_pool<<<n_waves, 64, 0, s>>>(wn, gr, n_groups, wp, counters,
-                                       (unsigned long long *)(counters + kXcds), pool_cap,
-                                       chunk, reserve, off, len, entries, overflow, gcells);
+    if (wp.open)
+        k_walk_pool<1><<<n_waves, 64, 0, s>>>(wn, gr, n_groups, wp, counters,
+                                              (unsigned long long *)(counters + kXcds),
+                                              pool_cap, chunk, reserve, off, len, entries,
+                                              overflow, gcells);
+    else
+        k_walk_pool<0><<<n_waves, 64, 0, s>>>(wn, gr, n_groups, wp, counters,
+                                              (unsigned long long *)(counters + kXcds),
+                                              pool_cap, chunk, reserve, off, len, entries,
+                                              overflow, gcells);
 }
 
 void launch_walk_stats(GroupArrays gr, uint32_t n_groups, const uint32_t *len,

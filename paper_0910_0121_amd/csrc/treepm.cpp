@@ -180,6 +180,11 @@ int check_params(treepm_ctx *c, const treepm_params *p)
     if (!std::isfinite(p->eps) || p->eps < 0.0) return fail(c, TREEPM_ERR_ARG, "eps must be >= 0");
     if (!std::isfinite(p->theta) || p->theta < 0.0 || p->theta > 1.0)
         return fail(c, TREEPM_ERR_ARG, "theta must be in [0, 1]");
+    if (p->opening != TREEPM_OPEN_FIXED && p->opening != TREEPM_OPEN_DISTANCE)
+        return fail(c, TREEPM_ERR_ARG, "opening must be TREEPM_OPEN_FIXED or _DISTANCE");
+    if (p->opening == TREEPM_OPEN_DISTANCE &&
+        (!std::isfinite(p->theta_max) || p->theta_max < 0.0 || p->theta_max > 1.0))
+        return fail(c, TREEPM_ERR_ARG, "theta_max must be in [0, 1]");
     if (p->n_leaf < 2) return fail(c, TREEPM_ERR_ARG, "n_leaf must be >= 2");
     if (p->n_crit < 0) return fail(c, TREEPM_ERR_ARG, "n_crit must be >= 1 (0 = default)");
     if (p->precision != TREEPM_FP32 && p->precision != TREEPM_FP64)
@@ -524,7 +529,9 @@ int do_walk(treepm_ctx *c, hipStream_t s)
     fill_u32(ovf, 1, 0u, s);
     fill_u64((uint64_t *)ws, 4, 0ull, s);
     const treepm_params &P = c->prm;
-    WalkParams wp{P.L, P.r_cut * P.r_cut, P.theta * P.theta, (uint32_t)c->n_nodes};
+    WalkParams wp{P.L,         P.r_cut * P.r_cut, P.theta * P.theta,          0.5 * P.r_cut,
+                  P.theta,     P.theta_max,       (uint32_t)c->n_nodes,
+                  P.opening == TREEPM_OPEN_DISTANCE ? 1u : 0u};
     NodeArrays nd = nodes_view(c);
     GroupArrays gr = groups_view(c);
     uint32_t *gcells = c->gcells.as<uint32_t>();

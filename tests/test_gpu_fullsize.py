@@ -11,7 +11,8 @@ the GPU's forces on those groups' particles are checked against it:
     with a nonzero force were missing or extra;
   * FP32 path: RMS relative error <= 1e-6 over the sampled particles, and no particle above
     2e-4 relative (rounding of group-relative positions of very close pairs).
-The 128^3 box also checks the total interaction count against the oracle's full walk.
+The 128^3 box also checks the total interaction count against the oracle's full walk, and
+is run again under the distance-dependent opening angle of eq. (12) with the same bars.
 """
 import sys
 
@@ -41,9 +42,10 @@ def tp():
     return t
 
 
-def _gpu_forces(tp, spec, dev, precision):
-    p = tp.treepm_params(spec.L, spec.mesh, spec.r_cut, spec.eps, spec.theta, spec.n_leaf,
-                         N_CRIT, precision)
+def _gpu_forces(tp, spec, dev, precision, opening=0, theta_max=0.0, theta=None):
+    p = tp.make_params(spec.L, spec.mesh, spec.r_cut, spec.eps,
+                       spec.theta if theta is None else theta, spec.n_leaf, N_CRIT, precision,
+                       opening=opening, theta_max=theta_max)
     ctx = tp.treepm_create(p, 0)
     try:
         tp.treepm_build(ctx, *dev)
@@ -84,6 +86,44 @@ def test_full_size_sampled_parity(tp, orc, name, stride):
     _say(f"  fp32 rms rel {rms:.3e} max rel {rel.max():.3e} p99 {np.quantile(rel, 0.99):.3e}")
     assert rms <= 1e-6
     assert rel.max() <= 2e-4
+    assert np.all(d[~nz] == 0.0)
+    if name == "nfw128":
+        assert T.interactions() == st64.interactions
+    T.close()
+
+
+
+@pytest.mark.parametrize("name,stride", [("nfw128", 40), ("nfw256", 400)])
+def test_distance_opening_full_size(tp, orc, name, stride):
+    """eq. (12) opening at the settings the benchmark times (theta_0 = 0.3, cap 0.5):
+    sampled FP64 and FP32 parity as above; on the 128^3 box also the total interaction
+    count against the oracle's full walk."""
+    spec, arrays = boxgen.config_box(name)
+    th0, tmax = 0.3, 0.5
+    _say(f"{name} theta(r): theta_0={th0}, cap={tmax}, n_crit={N_CRIT}, stride {stride}")
+    dev = [torch.from_numpy(a).cuda() for a in arrays]
+    a64, st64 = _gpu_forces(tp, spec, dev, tp.TREEPM_FP64, 1, tmax, th0)
+    a32, st32 = _gpu_forces(tp, spec, dev, tp.TREEPM_FP32, 1, tmax, th0)
+    assert st64.interactions == st32.interactions
+    x, y, z, m = arrays
+    T = orc.Tree(x, y, z, m, spec.L, spec.r_cut, spec.eps, th0, spec.n_leaf, N_CRIT,
+                 opening=1, theta_max=tmax)
+    assert T.n_groups == st64.n_groups and T.n_nodes == st64.n_nodes
+    ax, ay, az, inter, parts, mag, newt = T.walk_force_sample(stride, 0, 16, scales=True)
+    s = ~np.isnan(ax)
+    assert s.sum() == parts > 1000
+    ref = np.stack([ax[s], ay[s], az[s]])
+    scale = (mag + newt)[s]
+    err64 = np.abs(a64[:, s] - ref)
+    _say(f"  sampled {parts} particles; fp64 max |da|/scale {np.max(err64 / scale):.2e}")
+    assert np.all(err64 <= 1e-13 * scale[None, :])
+    d = np.linalg.norm(a32[:, s] - ref, axis=0)
+    nr = np.linalg.norm(ref, axis=0)
+    nz = nr > 0
+    rel = d[nz] / nr[nz]
+    rms = float(np.sqrt(np.mean(rel ** 2)))
+    _say(f"  fp32 rms rel {rms:.3e} max rel {rel.max():.3e}")
+    assert rms <= 1e-6 and rel.max() <= 2e-4
     assert np.all(d[~nz] == 0.0)
     if name == "nfw128":
         assert T.interactions() == st64.interactions

@@ -265,6 +265,73 @@ def test_one_pass_walk_on_a_reused_context(tp, orc):
         tp.treepm_destroy(ctx)
 
 
+def _assert_lists_equal(tp, ctx, T, what):
+    goff, gisc, gval = tp.treepm_export_lists(ctx)
+    ooff, oisc, oval = T.lists()
+    np.testing.assert_array_equal(np.diff(goff), np.diff(ooff))
+    for g in range(ooff.size - 1):
+        a = sorted(zip(gisc[goff[g]:goff[g + 1]].tolist(), gval[goff[g]:goff[g + 1]].tolist()))
+        b = sorted(zip(oisc[ooff[g]:ooff[g + 1]].tolist(), oval[ooff[g]:ooff[g + 1]].tolist()))
+        assert a == b, f"{what}: group {g}"
+    return int(oisc.sum())
+
+
+OPEN_CASES = [
+    # kind, n, seed, r_cut, theta_0, theta_max, n_leaf, n_crit
+    ("uniform", 32768, 1, 3 / 32, 0.05, 0.6, 10, 64),  # the uniform-limit pin's setting
+    ("nfw", 40000, 2, 0.06, 0.25, 0.8, 10, 128),
+    ("nfw", 20011, 3, 0.08, 0.15, 1.0, 4, 37),        # ragged N, odd n_crit, cap 1
+    ("nfw", 30000, 5, 0.05, 0.3, 0.0, 10, 300),       # cap 0: no cell is ever accepted
+]
+
+
+@pytest.mark.parametrize("case", OPEN_CASES,
+                         ids=[f"{c[0]}-n{c[1]}-th0{c[4]}-max{c[5]}" for c in OPEN_CASES])
+def test_distance_opening_parity(tp, orc, case):
+    """The distance-dependent angle of eq. (12): lists bit-identical to the oracle's on the
+    two-pass walk of a fresh context and on the one-pass walk of the same context; FP64 and
+    FP32 forces to the bars of the fixed-angle tests."""
+    kind, n, seed, r_cut, th0, tmax, n_leaf, n_crit = case
+    x, y, z, m = _box(kind, n, seed)
+    eps = r_cut / 60
+    T = orc.Tree(x, y, z, m, 1.0, r_cut, eps, th0, n_leaf, n_crit, opening=1, theta_max=tmax)
+    dev = [torch.from_numpy(a).cuda() for a in (x, y, z, m)]
+    for prec in (tp.TREEPM_FP64, tp.TREEPM_FP32):
+        p = tp.make_params(1.0, r_cut / 3.0, r_cut, eps, th0, n_leaf, n_crit, prec,
+                           opening=tp.TREEPM_OPEN_DISTANCE, theta_max=tmax)
+        ctx = tp.treepm_create(p, 0)
+        try:
+            for walk in ("two-pass", "one-pass"):
+                _say(f"theta(r) {kind} n={n} th0={th0} max={tmax} prec={prec} {walk}")
+                tp.treepm_build(ctx, *dev)
+                st = tp.treepm_walk(ctx)
+                assert st.interactions == T.interactions()
+                ncell = _assert_lists_equal(tp, ctx, T, walk)
+                assert st.n_cell_entries == ncell
+                if tmax == 0.0:
+                    assert ncell == 0
+                acc = [torch.zeros(n, dtype=torch.float64, device="cuda") for _ in range(3)]
+                tp.treepm_force_short(ctx, *acc)
+                torch.cuda.synchronize()
+                got = np.stack([t.cpu().numpy() for t in acc])
+                ref = np.stack(T.force())
+                if prec == tp.TREEPM_FP64:
+                    assert np.all(np.abs(got - ref) <= 1e-13 * T.error_scale()[None, :] + 1e-300)
+                else:
+                    d = np.linalg.norm(got - ref, axis=0)
+                    nr = np.linalg.norm(ref, axis=0)
+                    nz = nr > 0
+                    rms = float(np.sqrt(np.mean((d[nz] / nr[nz]) ** 2)))
+                    _say(f"  fp32 rms rel {rms:.3e}")
+                    assert rms <= 1e-6
+                    assert np.all(d[~nz] == 0.0)
+                    if walk == "two-pass":
+                        B = fp32_error_scale(T, x, y, z, m, eps)
+                        assert np.all(d <= 8 * 2.0 ** -24 * B)
+        finally:
+            tp.treepm_destroy(ctx)
+
+
 def _clumped_box(n_uniform, clumps, seed):
     """Uniform particles plus clumps, each inside one cell of side 2^-11, so each clump's keys
     share their high bits and differ in the low ones; clump sizes are given.  Every fifth
@@ -374,6 +441,13 @@ def test_error_paths(tp):
         tp.treepm_force_short(ctx, *a)
     assert e.value.code == -1
     tp.treepm_destroy(ctx)
+    # opening criterion: unknown mode, cap outside [0, 1]
+    for bad in (dict(opening=2), dict(opening=1, theta_max=1.5),
+                dict(opening=1, theta_max=float("nan")), dict(opening=1, theta_max=-0.1)):
+        q = tp.make_params(1.0, 0.1, 0.3, 0.01, 0.5, 10, 64, tp.TREEPM_FP64, **bad)
+        with pytest.raises(tp.TreePMError) as e:
+            tp.treepm_create(q, 0)
+        assert e.value.code == -1, bad
 
 
 def test_autotune_picks_a_candidate_and_leaves_a_walked_box(tp, orc):
