@@ -123,9 +123,11 @@ void launch_group_bbox(NodeArrays nd, GroupArrays gr, uint32_t n_groups, const d
 
 // ------------------------------------------------------------------ launchers (k_walk.hip)
 // open = 0: fixed angle, th2 = theta^2.  open = 1: theta(d) of eq. (12) from eta = r_cut/2,
-// theta0 and the cap theta_max.
+// theta0 and the cap theta_max; th2 = theta_max^2 and th2lo = theta_lo^2, where theta_lo =
+// min(theta_max, theta0 / sqrt(0.46)) is below every value theta(d) takes (R g(R) peaks at
+// 0.45273 near R = 0.650).
 struct WalkParams {
-    double L, rc2, th2;
+    double L, rc2, th2, th2lo;
     double eta, theta0, theta_max;
     uint32_t n_nodes;
     uint32_t open;

@@ -126,12 +126,15 @@ __device__ __forceinline__ Visit visit(const WalkNode &w, const WalkParams &wp, 
         double w2 = awrap(w.com[2] - cg2, L) - hg2;
         double d0 = w0 > 0.0 ? w0 : 0.0, d1 = w1 > 0.0 ? w1 : 0.0, d2 = w2 > 0.0 ? w2 : 0.0;
         const double D = d0 * d0 + d1 * d1 + d2 * d2;
-        double th2 = wp.th2;
-        if (OPEN) {
+        const double ll = l * l;
+        bool take = ll < wp.th2 * D;
+        if (OPEN && take && !(ll < wp.th2lo * D)) {
+            // theta_lo <= theta(d) <= theta_max, and rounding is monotone, so only nodes in
+            // the band between the two bounds need the angle itself.
             const double th = theta_of_d(sqrt(D), wp);
-            th2 = th * th;
+            take = ll < (th * th) * D;
         }
-        if (l * l < th2 * D && G > 0.0) {
+        if (take && G > 0.0) {
             r.kind = 1;
             r.ne = 1;
         } else if (w.nchild == 0) {

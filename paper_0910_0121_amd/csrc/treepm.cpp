@@ -529,9 +529,17 @@ int do_walk(treepm_ctx *c, hipStream_t s)
     fill_u32(ovf, 1, 0u, s);
     fill_u64((uint64_t *)ws, 4, 0ull, s);
     const treepm_params &P = c->prm;
-    WalkParams wp{P.L,         P.r_cut * P.r_cut, P.theta * P.theta,          0.5 * P.r_cut,
-                  P.theta,     P.theta_max,       (uint32_t)c->n_nodes,
-                  P.opening == TREEPM_OPEN_DISTANCE ? 1u : 0u};
+    const bool open = P.opening == TREEPM_OPEN_DISTANCE;
+    const double th_lo = std::min(P.theta_max, P.theta / std::sqrt(0.46));
+    WalkParams wp{P.L,
+                  P.r_cut * P.r_cut,
+                  open ? P.theta_max * P.theta_max : P.theta * P.theta,
+                  open ? th_lo * th_lo : 0.0,
+                  0.5 * P.r_cut,
+                  P.theta,
+                  P.theta_max,
+                  (uint32_t)c->n_nodes,
+                  open ? 1u : 0u};
     NodeArrays nd = nodes_view(c);
     GroupArrays gr = groups_view(c);
     uint32_t *gcells = c->gcells.as<uint32_t>();
