@@ -6,6 +6,10 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
+# The mutation tests point this at a directory holding a deliberately broken copy of the
+# oracle package, which must shadow the real one.
+if os.environ.get("TREEPM_ORACLE_PKG"):
+    sys.path.insert(0, os.environ["TREEPM_ORACLE_PKG"])
 
 
 def pytest_configure(config):

@@ -7,6 +7,7 @@ minimum image (v >= L/2 versus v > L/2) is not listed: it is unobservable (the a
 value used by the walk is the same, and the pair force is zero at r = L/2 >= r_cut).
 """
 import os
+import shutil
 import subprocess
 import sys
 
@@ -79,6 +80,44 @@ MUTANTS = [
     ("opening_angle_not_squared", "        th2 = th * th;\n", "        th2 = th;\n",
      TREE + "::test_distance_opening_lists_equal_brute_force_frontier"),
 ]
+
+
+PM = "tests/test_oracle_pm.py"
+PY_MUTANTS = [  # (name, file under oracle/, old, new, pin)
+    ("pm_fd_second_order", "pm.py", "(2.0 / 3.0) * (p1 - m1) - (1.0 / 12.0) * (p2 - m2)",
+     "0.5 * (p1 - m1)", PM + "::test_converges_to_exact_long_range_force"),
+    ("pm_window_once", "pm.py", "/ (W[pos] ** 2)", "/ W[pos]",
+     PM + "::test_accuracy_at_the_papers_split"),
+    ("pm_tsc_centre_weight", "pm.py", "0.75 - d * d", "0.7 - d * d",
+     PM + "::test_tsc_cloud_closed_forms"),
+    ("pm_nearest_point", "pm.py", "i0 = np.floor(u + 0.5)", "i0 = np.floor(u)",
+     PM + "::test_tsc_cloud_closed_forms"),
+    ("pm_interp_mirrored", "pm.py", "wt = w[:, 0, a] * w[:, 1, b] * w[:, 2, c]",
+     "wt = w[:, 0, 2 - a] * w[:, 1, b] * w[:, 2, c]", PM + "::test_momentum_is_conserved"),
+    ("pm_potential_units", "pm.py", "* (n ** 3) / L ** 3", "* (n ** 3) / L ** 2",
+     PM + "::test_scaling_with_box_size"),
+    ("pm_green_sign", "pm.py", "G[pos] = kern.phi_hat(uniq)[inv] / (W[pos] ** 2)",
+     "G[pos] = -kern.phi_hat(uniq)[inv] / (W[pos] ** 2)", PM + "::test_short_plus_pm_is_ewald"),
+    ("pm_mesh_spacing", "pm.py", "    h = L / phi.shape[0]\n", "    h = 2.0 * L / phi.shape[0]\n",
+     PM + "::test_converges_to_exact_long_range_force"),
+]
+
+
+@pytest.mark.parametrize("name,fname,old,new,pin", PY_MUTANTS, ids=[m[0] for m in PY_MUTANTS])
+def test_pin_catches_planted_mistake_py(tmp_path, name, fname, old, new, pin):
+    """The same for the Python parts of the oracle: a mutated copy of the package is put
+    first on the import path of the pin's process."""
+    pkg = tmp_path / "oracle"
+    shutil.copytree(os.path.join(ROOT, "oracle"), pkg,
+                    ignore=shutil.ignore_patterns("__pycache__"))
+    src = (pkg / fname).read_text()
+    assert src.count(old) >= 1, f"mutation site for {name} not found"
+    (pkg / fname).write_text(src.replace(old, new, 1))
+    env = dict(os.environ, TREEPM_ORACLE_PKG=str(tmp_path))
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        os.path.join(ROOT, pin)], cwd=ROOT, env=env, capture_output=True,
+                       text=True, timeout=600)
+    assert r.returncode == 1, f"{name} survived {pin}:\n{r.stdout[-2000:]}"
 
 
 @pytest.mark.parametrize("name,old,new,pin", MUTANTS, ids=[m[0] for m in MUTANTS])
