@@ -150,6 +150,24 @@ int treepm_walk(treepm_ctx *ctx, void *hip_stream, treepm_stats *stats);
 int treepm_force_short(treepm_ctx *ctx, void *ax, void *ay, void *az, int out_prec,
                        int mem_kind, void *hip_stream);
 
+/* Long-range (particle-mesh) acceleration of every particle of the built box (Section 2.2
+ * step 1; the long-range half of the split of Section 2.1), on the mesh N_PM = L / mesh,
+ * which must be a power of two in [16, 1024] (ERR_ARG otherwise):
+ *   - TSC assignment of the masses onto the N_PM^3 mesh points x = i h, h = L / N_PM (the
+ *     nearest point and its two neighbours per axis, periodic), summed in 64-bit fixed point;
+ *   - potential phi = (1/L^3) sum_{k != 0} G(k) M^(k) e^{ikx} by FFT, with
+ *     G(k) = -4 pi S2^(k eta)^2 / (k^2 W(k)^2): the force between two S2 clouds of radius eta
+ *     (the complement of eq. 2's cutoff, eta = r_cut / 2) over the TSC window
+ *     W = prod_a sinc^3(k_a h / 2), divided out for assignment and interpolation;
+ *   - mesh force by fourth-order central differences of -grad phi, then TSC interpolation.
+ * Mesh arithmetic is FP32.  Results go to ax/ay/az in the caller's particle order, as
+ * out_prec (TREEPM_FP32 = float, TREEPM_FP64 = double) of kind mem_kind; accumulate = 1 adds
+ * to the values the arrays hold (so short-range + long-range needs no extra array), 0
+ * overwrites them.  Requires a build (ERR_STATE).  Device memory: about 32 N_PM^3 bytes,
+ * kept by the context. *
+int treepm_force_long(treepm_ctx *ctx, void *ax, void *ay, void *az, int out_prec,
+                      int mem_kind, int accumulate, void *hip_stream);
+
 /* Choose n_crit (Section 3.1.2's N_crit) for this box by measurement: for each of the
  * n_candidates values (1..64 of them, each >= 1), build, walk and run the FP32 force twice on
  * the given particles (same arguments as treepm_build) and time the second run with device

@@ -47,15 +47,17 @@ def assign(pos, m, L, n_pm):
     m = np.asarray(m, dtype=np.float64)
     h = L / n_pm
     i0, w = tsc_cloud(pos / h)                     # (n, 3), (n, 3, 3)
-    M = np.zeros((n_pm, n_pm, n_pm))
+    M = np.zeros(n_pm ** 3)
     for a in range(3):
+        ix = (i0[:, 0] + a - 1) % n_pm
         for b in range(3):
-            for c in range(3):
-                ix = (i0[:, 0] + a - 1) % n_pm
-                iy = (i0[:, 1] + b - 1) % n_pm
-                iz = (i0[:, 2] + c - 1) % n_pm
-                np.add.at(M, (ix, iy, iz), m * w[:, 0, a] * w[:, 1, b] * w[:, 2, c])
-    return M
+            iy = (i0[:, 1] + b - 1) % n_pm
+            row = (ix * n_pm + iy) * n_pm
+            mw = m * w[:, 0, a] * w[:, 1, b]
+            cells = np.concatenate([row + (i0[:, 2] + c - 1) % n_pm for c in range(3)])
+            wts = np.concatenate([mw * w[:, 2, c] for c in range(3)])
+            M += np.bincount(cells, weights=wts, minlength=n_pm ** 3)
+    return M.reshape(n_pm, n_pm, n_pm)
 
 
 def wavenumbers(n_pm, L):

@@ -31,6 +31,7 @@ from ._native import (  # noqa: F401
     treepm_export_lists,
     treepm_export_nodes,
     treepm_export_sorted,
+    treepm_force_long,
     treepm_force_short,
     treepm_get_stats,
     treepm_last_error,

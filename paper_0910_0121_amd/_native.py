@@ -61,6 +61,7 @@ _SIGS = {
     "treepm_build": (_i, [_p, _i64, _p, _p, _p, _p, _i, _p]),
     "treepm_walk": (_i, [_p, _p, C.POINTER(treepm_stats)]),
     "treepm_force_short": (_i, [_p, _p, _p, _p, _i, _i, _p]),
+    "treepm_force_long": (_i, [_p, _p, _p, _p, _i, _i, _i, _p]),
     "treepm_get_stats": (_i, [_p, C.POINTER(treepm_stats)]),
     "treepm_export_sorted": (_i, [_p, _p, _p]),
     "treepm_export_nodes": (_i, [_p, _i64, _p, _p, _p, _p, _p, _p]),
@@ -202,6 +203,18 @@ def treepm_force_short(ctx, ax, ay, az, stream=None) -> None:
     prec = TREEPM_FP64 if dt == "float64" else TREEPM_FP32
     _check(lib().treepm_force_short(ctx, bufs[0][0], bufs[1][0], bufs[2][0], prec, kind,
                                     _stream(stream, kind)), ctx)
+
+
+def treepm_force_long(ctx, ax, ay, az, accumulate=False, stream=None) -> None:
+    dt = "float64" if (str(getattr(ax, "dtype", "")) in ("torch.float64", "float64")) else "float32"
+    bufs = [_buf(a, dt) for a in (ax, ay, az)]
+    kinds = {b[1] for b in bufs}
+    if len(kinds) != 1:
+        raise ValueError("ax, ay, az must all be host or all be device buffers")
+    kind = kinds.pop()
+    prec = TREEPM_FP64 if dt == "float64" else TREEPM_FP32
+    _check(lib().treepm_force_long(ctx, bufs[0][0], bufs[1][0], bufs[2][0], prec, kind,
+                                   1 if accumulate else 0, _stream(stream, kind)), ctx)
 
 
 def treepm_autotune(ctx, x, y, z, m, candidates, stream=None):

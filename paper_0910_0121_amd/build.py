@@ -29,6 +29,7 @@ SOURCES = {
     "k_build.hip": ["-ffp-contract=off"],
     "k_walk.hip": ["-ffp-contract=off"],
     "k_force.hip": [],
+    "k_pm.hip": [],
     "treepm.cpp": ["-ffp-contract=off"],
     "ensemble.cpp": [],
 }

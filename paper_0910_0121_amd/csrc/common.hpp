@@ -192,4 +192,23 @@ void launch_force_f64(NodeArrays nd, GroupArrays gr, uint32_t n_groups, const ui
                       ForceParams fp, void *ax, void *ay, void *az, int out_prec,
                       hipStream_t s);
 
+// Particle-mesh long-range force (k_pm.hip), mesh N^3 with N a power of two in [16, 1024].
+// Lines per FFT workgroup for mesh size N.
+int pm_bundle_lines(int N);
+// Octant table of the Green's function ((N/2+1)^3 floats) and N/2 twiddles.
+void launch_pm_green(int N, double L, double eta, float *green, float2 *tw, hipStream_t s);
+// Clears and fills the fixed-point mass mesh (N^3 words); mx receives the largest mass.
+void launch_pm_assign(const double4 *ps, int64_t n, int N, double L, unsigned long long *mx,
+                      unsigned long long *mass, hipStream_t s);
+// Potential phi (N^3 floats) from the mass mesh, through the complex work mesh grid.
+void launch_pm_potential(const unsigned long long *mass, const unsigned long long *mx,
+                         int64_t n, int N, float2 *grid, float *phi, const float *green,
+                         const float2 *tw, hipStream_t s);
+// Mesh force (N^3 float4: Fx, Fy, Fz, 0) from phi.
+void launch_pm_force(const float *phi, int N, double L, float4 *f, hipStream_t s);
+// Interpolated force per particle (key-ordered ps), written at idx[i] as float or double.
+void launch_pm_interp(const double4 *ps, const uint32_t *idx, int64_t n, int N, double L,
+                      const float4 *f, void *ax, void *ay, void *az, int out_fp64,
+                      int accumulate, hipStream_t s);
+
 } // namespace tpm

@@ -86,6 +86,11 @@ struct treepm_ctx {
     uint32_t walk_hint_groups = 0;
     uint64_t st[3] = {0, 0, 0};
     Buf host_total; // unused placeholder for alignment of future pinned buffers
+    // particle mesh: fixed-point masses (later the potential), the complex work mesh, the
+    // force mesh, the Green's table, twiddles, max mass
+    Buf pm_mass, pm_grid, pm_f, pm_green, pm_tw, pm_mx;
+    int pm_n = 0; // mesh size, box and eta the table was built for
+    double pm_L = 0.0, pm_eta = 0.0;
 };
 
 namespace {
@@ -738,7 +743,8 @@ TREEPM_API int treepm_destroy(treepm_ctx *c)
                   &c->g_xg[1], &c->g_xg[2], &c->g_lo[0], &c->g_lo[1], &c->g_lo[2], &c->g_hi[0],
                   &c->g_hi[1], &c->g_hi[2], &c->g_misc, &c->off, &c->glen, &c->wctr, &c->scan64, &c->entries,
                   &c->wstats, &c->overflow, &c->rec, &c->kept, &c->kept_sum, &c->gcells, &c->cls, &c->out[0],
-                  &c->out[1], &c->out[2], &c->bnd, &c->runs};
+                  &c->out[1], &c->out[2], &c->bnd, &c->runs, &c->pm_mass, &c->pm_grid,
+                  &c->pm_f, &c->pm_green, &c->pm_tw, &c->pm_mx};
     {
         CallScope scope(c, c->last);
         for (Buf *b : all) release(*b);
@@ -913,6 +919,79 @@ TREEPM_API int treepm_force_short(treepm_ctx *c, void *ax, void *ay, void *az, i
         for (int a = 0; a < 3; ++a)
             HIPCHK(c, hipMemcpyAsync(hdst[a], dst[a], (size_t)c->n * esz, hipMemcpyDeviceToHost,
                                      s));
+        HIPCHK(c, hipStreamSynchronize(s));
+    }
+    return TREEPM_OK;
+}
+
+TREEPM_API int treepm_force_long(treepm_ctx *c, void *ax, void *ay, void *az, int out_prec,
+                                 int mem_kind, int accumulate, void *hip_stream)
+{
+    if (!c) return TREEPM_ERR_ARG;
+    if (c->state < 1) return fail(c, TREEPM_ERR_STATE, "treepm_force_long needs a build");
+    c->err.clear();
+    if (!ax || !ay || !az) return fail(c, TREEPM_ERR_ARG, "NULL output buffer");
+    if (out_prec != TREEPM_FP32 && out_prec != TREEPM_FP64)
+        return fail(c, TREEPM_ERR_ARG, "out_prec must be TREEPM_FP32 or TREEPM_FP64");
+    if (mem_kind != TREEPM_HOST && mem_kind != TREEPM_DEVICE)
+        return fail(c, TREEPM_ERR_ARG, "mem_kind must be TREEPM_HOST or TREEPM_DEVICE");
+    if (accumulate != 0 && accumulate != 1)
+        return fail(c, TREEPM_ERR_ARG, "accumulate must be 0 or 1");
+    const treepm_params &P = c->prm;
+    const double q = P.L / P.mesh;
+    const long long N = std::llround(q);
+    if (std::fabs(q - (double)N) > 1e-9 * q || N < 16 || N > 1024 || (N & (N - 1)))
+        return fail(c, TREEPM_ERR_ARG,
+                    "the PM mesh N_PM = L / mesh must be a power of two in [16, 1024] (%.6g)", q);
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)hip_stream;
+    c->last = s;
+    CallScope scope(c, s);
+    const size_t pts = (size_t)N * N * N, H = (size_t)N / 2 + 1;
+    {
+        hipError_t e = reserve(c->pm_mass, pts * 8);
+        if (e == hipSuccess) e = reserve(c->pm_grid, pts * 8);
+        if (e == hipSuccess) e = reserve(c->pm_f, pts * 16);
+        if (e == hipSuccess) e = reserve(c->pm_green, H * H * H * 4);
+        if (e == hipSuccess) e = reserve(c->pm_tw, (size_t)N / 2 * 8);
+        if (e == hipSuccess) e = reserve(c->pm_mx, 8);
+        if (e != hipSuccess) return hip_fail(c, e, "PM meshes");
+    }
+    const double eta = 0.5 * P.r_cut;
+    if (c->pm_n != (int)N || c->pm_L != P.L || c->pm_eta != eta) {
+        launch_pm_green((int)N, P.L, eta, c->pm_green.as<float>(), c->pm_tw.as<float2>(), s);
+        c->pm_n = (int)N;
+        c->pm_L = P.L;
+        c->pm_eta = eta;
+    }
+    size_t esz = out_prec == TREEPM_FP64 ? 8 : 4;
+    void *dst[3] = {ax, ay, az};
+    void *const host_out[3] = {ax, ay, az};
+    if (mem_kind == TREEPM_HOST) {
+        for (int a = 0; a < 3; ++a) {
+            hipError_t e = reserve(c->out[a], (size_t)c->n * esz);
+            if (e != hipSuccess) return hip_fail(c, e, "output staging");
+            dst[a] = c->out[a].p;
+            if (accumulate) // the sum starts from what the caller's arrays hold
+                HIPCHK(c, hipMemcpyAsync(dst[a], host_out[a], (size_t)c->n * esz,
+                                         hipMemcpyHostToDevice, s));
+        }
+    }
+    const double4 *ps = c->psrc.as<double4>();
+    unsigned long long *mass = c->pm_mass.as<unsigned long long>();
+    float2 *grid = c->pm_grid.as<float2>();
+    float *phi = c->pm_mass.as<float>(); // the masses are consumed by the first pass
+    launch_pm_assign(ps, c->n, (int)N, P.L, c->pm_mx.as<unsigned long long>(), mass, s);
+    launch_pm_potential(mass, c->pm_mx.as<unsigned long long>(), c->n, (int)N, grid, phi,
+                        c->pm_green.as<float>(), c->pm_tw.as<float2>(), s);
+    launch_pm_force(phi, (int)N, P.L, c->pm_f.as<float4>(), s);
+    launch_pm_interp(ps, c->idx.as<uint32_t>(), c->n, (int)N, P.L, c->pm_f.as<float4>(), dst[0],
+                     dst[1], dst[2], out_prec == TREEPM_FP64, accumulate, s);
+    HIPCHK(c, hipGetLastError());
+    if (mem_kind == TREEPM_HOST) {
+        for (int a = 0; a < 3; ++a)
+            HIPCHK(c, hipMemcpyAsync(host_out[a], dst[a], (size_t)c->n * esz,
+                                     hipMemcpyDeviceToHost, s));
         HIPCHK(c, hipStreamSynchronize(s));
     }
     return TREEPM_OK;

@@ -128,3 +128,38 @@ def test_distance_opening_full_size(tp, orc, name, stride):
     if name == "nfw128":
         assert T.interactions() == st64.interactions
     T.close()
+
+
+@pytest.mark.parametrize("name", ["nfw128", "nfw256"])
+def test_pm_full_size(tp, name):
+    """The particle-mesh long-range force at the workload's own mesh (N_PM^3 = N, 2 eta =
+    r_cut = 3 h) against the FP64 oracle, which builds the whole mesh and interpolates to every
+    16th particle: RMS |da| at most 2e-6 of the RMS |a| and no particle above 5e-5 of it (the
+    bar of the small-box PM tests)."""
+    from oracle import pm
+    spec, arrays = boxgen.config_box(name)
+    _say(f"{name}: PM at N_PM={spec.mesh_n}")
+    dev = [torch.from_numpy(a).cuda() for a in arrays]
+    p = tp.make_params(spec.L, spec.mesh, spec.r_cut, spec.eps, spec.theta, spec.n_leaf,
+                       N_CRIT, tp.TREEPM_FP32)
+    ctx = tp.treepm_create(p, 0)
+    try:
+        tp.treepm_build(ctx, *dev)
+        acc = [torch.zeros(spec.n, dtype=torch.float64, device="cuda") for _ in range(3)]
+        tp.treepm_force_long(ctx, *acc)
+        torch.cuda.synchronize()
+        got = np.stack([a.cpu().numpy() for a in acc], axis=1)
+    finally:
+        tp.treepm_destroy(ctx)
+    x, y, z, m = arrays
+    pos = np.stack([x, y, z], axis=1)
+    M = pm.assign(pos, m, spec.L, spec.mesh_n)
+    G = pm.green(spec.mesh_n, spec.L, 0.5 * spec.r_cut)
+    F = pm.mesh_force(pm.potential(M, spec.L, G), spec.L)
+    sel = np.arange(0, spec.n, 16)
+    ref = pm.interpolate(F, pos[sel], spec.L)
+    scale = float(np.sqrt(np.mean((ref * ref).sum(axis=1))))
+    d = np.linalg.norm(got[sel] - ref, axis=1)
+    rms, mx = float(np.sqrt(np.mean(d * d))) / scale, float(d.max()) / scale
+    _say(f"  rms |da| / rms |a| = {rms:.2e}, max {mx:.2e}")
+    assert rms <= 2e-6 and mx <= 5e-5
