@@ -25,6 +25,14 @@ if ROOT not in sys.path:
 METRIC = "particles/s + interactions/s at θ=0.5, FP32 vs FP64 path; ensemble p50/p99"
 K_PP = 38  # flops per pair interaction (FMA = 2, add/mul/rsqrt/sqrt = 1, selects = 0)
 FP32_VECTOR_PEAK_TFLOPS = 157.3
+HBM_PEAK_GBS = 8000.0
+# Algorithmic HBM bytes of one particle-mesh call: per mesh point, clearing and filling the
+# fixed-point mass mesh (8 + 8), five FFT passes (16 + 16 + 16 + 16 + 12), the differences
+# (4 read + 16 written) and one read of the force mesh (16); per particle, the key-ordered
+# record read by the max-mass pass, the assignment and the interpolation (3 x 32), its index
+# (4) and three FP32 outputs (12).
+PM_BYTES_PER_POINT = 8 + 8 + 16 + 16 + 16 + 16 + 12 + 4 + 16 + 16
+PM_BYTES_PER_PARTICLE = 3 * 32 + 4 + 12
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "force_f32_traffic.json")
 FORCE_SRC = os.path.join(ROOT, "paper_0910_0121_amd", "csrc", "k_force.hip")
@@ -54,6 +62,8 @@ def parse():
                     help="theta_0 of the distance-dependent opening angle leg")
     ap.add_argument("--theta-max", type=float, default=0.5,
                     help="cap of the distance-dependent opening angle leg")
+    ap.add_argument("--no-pm", action="store_true",
+                    help="skip the particle-mesh long-range leg")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-boxes", type=int, default=64)
     ap.add_argument("--serving-requests-per-box", type=int, default=10)
@@ -407,6 +417,36 @@ def main():
             "cell_entries": int(str_.n_cell_entries),
             "phase_ms": {"build": float(np.mean(phr[:, 0])), "walk": float(np.mean(phr[:, 1])),
                          "force_f32": float(np.mean(phr[:, 2]))},
+        }
+    if not args.no_pm:
+        # The long-range half of the split on the same box and its own mesh (N_PM^3 = N).
+        pp = tp.make_params(spec.L, spec.mesh, spec.r_cut, spec.eps, spec.theta, spec.n_leaf,
+                            n_crit, tp.TREEPM_FP32)
+        ctx = tp.treepm_create(pp, 0)
+        log(f"[bench] particle-mesh leg: N_PM = {spec.mesh_n}")
+        tp.treepm_build(ctx, *dev)
+        for _ in range(2):
+            tp.treepm_force_long(ctx, *acc)
+        torch.cuda.synchronize()
+        kp = max(1, min(10, args.steps))
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(kp):
+            tp.treepm_force_long(ctx, *acc)
+        e1.record()
+        torch.cuda.synchronize()
+        tp.treepm_destroy(ctx)
+        pm_ms = e0.elapsed_time(e1) / kp
+        pm_bytes = PM_BYTES_PER_POINT * spec.mesh_n ** 3 + PM_BYTES_PER_PARTICLE * spec.n
+        result["pm"] = {
+            "n_pm": spec.mesh_n,
+            "ms": pm_ms,
+            "particles_per_s": spec.n / (pm_ms * 1e-3),
+            "short_plus_long_ms_per_step": ms_per_step + pm_ms,
+            "roofline": {"bound": "hbm", "achieved": pm_bytes / (pm_ms * 1e-3) / 1e9,
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": pm_bytes / (pm_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                         "algorithmic_bytes": pm_bytes},
         }
     if not args.no_serving:
         log("[bench] ensemble serving")

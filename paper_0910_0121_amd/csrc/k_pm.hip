@@ -4,7 +4,7 @@
 // interpolation back to the particles.
 //
 // Mesh layout: point (x, y, z) at (x N + y) N + z, z contiguous; N a power of two.
-//  * assignment: a workgroup sums 1024 consecutive particles (key order, so they are close
+//  * assignment: a wave sums 256 consecutive particles (key order, so they are close
 //    together) into an LDS box of mesh points and adds the box to the mesh; masses are summed
 //    as 64-bit fixed point, so the mesh does not depend on the order of the atomics;
 //  * FFT: complex, radix 2, one workgroup per bundle of B lines of one axis held in LDS
@@ -14,7 +14,10 @@
 //    Green's function + z inverse in one kernel (a DIF forward leaves bit-reversed order, which
 //    is what the DIT inverse reads), y inverse, x inverse (writing the real potential);
 //  * mesh force: fourth-order central differences of the potential, one float4 per point;
-//  * interpolation: one thread per particle gathers the 27 points of its cloud.
+//  * interpolation: one thread per particle gathers the 27 points of its cloud (neighbouring
+//    threads hold neighbouring particles, so the gathers share cache lines) into a key-order
+//    stage; a second pass writes it in the caller's order through the inverse permutation,
+//    so no pass writes scattered words.
 #include "common.hpp"
 
 namespace tpm {
@@ -77,80 +80,119 @@ __global__ __launch_bounds__(256) void k_pm_maxmass(const double4 *__restrict__ 
     if ((threadIdx.x & 63) == 0) atomicMax(mx, v);
 }
 
-// One workgroup takes kAssignChunk consecutive particles in key order, which lie close
-// together: if the mesh points their clouds touch fit in an LDS box of kAssignTile words, the
-// contributions are summed there (LDS atomics) and the box is added to the mesh with one global
-// atomic per nonzero point; otherwise (a chunk spread over a large region, or across the
-// periodic seam) each contribution goes to the mesh directly.
-constexpr int kAssignThreads = 256;
+// One wave takes kAssignChunk consecutive particles in key order, kAssignPer consecutive ones
+// per lane.  A lane sums the 27 contributions of a run of particles with the same nearest mesh
+// point in registers and adds them once.  If the mesh points the chunk's clouds touch fit in an
+// LDS box of kAssignTile words (they lie close together in key order), those adds go to the box
+// and the box is added to the mesh with one global atomic per nonzero point; otherwise (a chunk
+// spread over a large region, or across the periodic seam) they go to the mesh directly.
+// Every sum is a fixed sequence of integer adds, so the mesh is the same on every run.
+constexpr int kAssignThreads = 64;
 constexpr int kAssignPer = 4;
 constexpr int kAssignChunk = kAssignThreads * kAssignPer;
 constexpr int kAssignTile = 4096;
+
+__device__ __forceinline__ int wave_min(int v)
+{
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) v = min(v, __shfl_xor(v, d, 64));
+    return v;
+}
+__device__ __forceinline__ int wave_max(int v)
+{
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) v = max(v, __shfl_xor(v, d, 64));
+    return v;
+}
 
 __global__ __launch_bounds__(kAssignThreads) void k_pm_assign(
     const double4 *__restrict__ ps, int64_t n, int N, double inv_h,
     const unsigned long long *__restrict__ mx, unsigned long long *__restrict__ mass)
 {
     __shared__ unsigned long long tile[kAssignTile];
-    __shared__ int box[6]; // lowest and highest nearest-point index per axis
-    const int64_t base = (int64_t)blockIdx.x * kAssignChunk;
-    if (threadIdx.x < 3) {
-        box[threadIdx.x] = 0x7fffffff;
-        box[3 + threadIdx.x] = -0x7fffffff;
-    }
-    __syncthreads();
+    // neighbouring chunks on one XCD, so their mesh points share its L2
+    const int64_t first = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kAssignChunk +
+                          (int64_t)threadIdx.x * kAssignPer;
     int lo[3] = {0x7fffffff, 0x7fffffff, 0x7fffffff}, hi[3] = {-0x7fffffff, -0x7fffffff, -0x7fffffff};
+#pragma unroll
     for (int k = 0; k < kAssignPer; ++k) {
-        const int64_t i = base + threadIdx.x + (int64_t)k * kAssignThreads;
-        if (i >= n) break;
-        const double4 p = ps[i];
-        const int c[3] = {nearest(p.x, inv_h), nearest(p.y, inv_h), nearest(p.z, inv_h)};
-        for (int a = 0; a < 3; ++a) {
-            lo[a] = min(lo[a], c[a]);
-            hi[a] = max(hi[a], c[a]);
+        if (first + k < n) {
+            const double4 p = ps[first + k];
+            const int c[3] = {nearest(p.x, inv_h), nearest(p.y, inv_h), nearest(p.z, inv_h)};
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                lo[a] = min(lo[a], c[a]);
+                hi[a] = max(hi[a], c[a]);
+            }
         }
     }
-    if (base + threadIdx.x < n)
-        for (int a = 0; a < 3; ++a) {
-            atomicMin(&box[a], lo[a]);
-            atomicMax(&box[3 + a], hi[a]);
-        }
-    __syncthreads();
-    const int ox = box[0] - 1, oy = box[1] - 1, oz = box[2] - 1;
-    const int ex = box[3] - box[0] + 3, ey = box[4] - box[1] + 3, ez = box[5] - box[2] + 3;
-    const bool local = (int64_t)ex * ey * ez <= kAssignTile; // the same for the whole group
-    const int cells = local ? ex * ey * ez : 0;
+    int ox = 0, oy = 0, oz = 0, ey = 0, ez = 0, cells = 0;
+    {
+        const int l0 = wave_min(lo[0]), l1 = wave_min(lo[1]), l2 = wave_min(lo[2]);
+        const int h0 = wave_max(hi[0]), h1 = wave_max(hi[1]), h2 = wave_max(hi[2]);
+        const int ex = h0 - l0 + 3;
+        ey = h1 - l1 + 3;
+        ez = h2 - l2 + 3;
+        if ((int64_t)ex * ey * ez <= kAssignTile) cells = ex * ey * ez; // wave-uniform
+        ox = l0 - 1;
+        oy = l1 - 1;
+        oz = l2 - 1;
+    }
+    const bool local = cells > 0;
     for (int t = threadIdx.x; t < cells; t += kAssignThreads) tile[t] = 0ull;
     __syncthreads();
     const double S = pm_scale(*mx, n);
     const int mask = N - 1;
-    for (int k = 0; k < kAssignPer; ++k) {
-        const int64_t i = base + threadIdx.x + (int64_t)k * kAssignThreads;
-        if (i >= n) break;
-        const double4 p = ps[i];
-        double wx[3], wy[3], wz[3];
-        const int ix = tsc(p.x, inv_h, wx), iy = tsc(p.y, inv_h, wy), iz = tsc(p.z, inv_h, wz);
-        const double ms = p.w * S;
+    double acc[27];
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
+    for (int j = 0; j < 27; ++j) acc[j] = 0.0;
+    int cx = 0, cy = 0, cz = 0;
+    bool open = false;
+    auto add_run = [&]() {
 #pragma unroll
-            for (int b = 0; b < 3; ++b) {
-                const double wab = ms * wx[a] * wy[b];
-                if (local) {
-                    const int row = ((ix - 1 + a - ox) * ey + (iy - 1 + b - oy)) * ez + iz - 1 - oz;
+        for (int a = 0; a < 3; ++a)
 #pragma unroll
-                    for (int c = 0; c < 3; ++c)
-                        atomicAdd(&tile[row + c], (unsigned long long)__double2ull_rn(wab * wz[c]));
-                } else {
-                    const size_t row = ((size_t)((ix - 1 + a) & mask) * N + ((iy - 1 + b) & mask)) * N;
+            for (int b = 0; b < 3; ++b)
 #pragma unroll
-                    for (int c = 0; c < 3; ++c)
-                        atomicAdd(&mass[row + ((iz - 1 + c) & mask)],
-                                  (unsigned long long)__double2ull_rn(wab * wz[c]));
+                for (int c = 0; c < 3; ++c) {
+                    const unsigned long long v = __double2ull_rn(acc[(a * 3 + b) * 3 + c]);
+                    if (local)
+                        atomicAdd(&tile[((cx - 1 + a - ox) * ey + (cy - 1 + b - oy)) * ez +
+                                        (cz - 1 + c - oz)],
+                                  v);
+                    else
+                        atomicAdd(&mass[((size_t)((cx - 1 + a) & mask) * N +
+                                         ((cy - 1 + b) & mask)) * N + ((cz - 1 + c) & mask)],
+                                  v);
                 }
+    };
+#pragma unroll
+    for (int k = 0; k < kAssignPer; ++k) {
+        if (first + k < n) {
+            const double4 p = ps[first + k];
+            double wx[3], wy[3], wz[3];
+            const int ix = tsc(p.x, inv_h, wx), iy = tsc(p.y, inv_h, wy), iz = tsc(p.z, inv_h, wz);
+            if (open && (ix != cx || iy != cy || iz != cz)) {
+                add_run();
+#pragma unroll
+                for (int j = 0; j < 27; ++j) acc[j] = 0.0;
             }
+            cx = ix;
+            cy = iy;
+            cz = iz;
+            open = true;
+            const double ms = p.w * S;
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b) {
+                    const double wab = ms * wx[a] * wy[b];
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) acc[(a * 3 + b) * 3 + c] += wab * wz[c];
+                }
         }
     }
+    if (open) add_run();
     if (!local) return;
     __syncthreads();
     for (int t = threadIdx.x; t < cells; t += kAssignThreads) {
@@ -415,7 +457,7 @@ __global__ __launch_bounds__(256) void k_pm_green(int N, double L, double eta,
 __global__ __launch_bounds__(256) void k_pm_fd(const float *__restrict__ phi, int N, int logN,
                                                float inv_h, float4 *__restrict__ f)
 {
-    const size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    const size_t t = xcd_block(blockIdx.x, gridDim.x) * (size_t)blockDim.x + threadIdx.x;
     const size_t NN = (size_t)N * N;
     if (t >= NN * N) return;
     const int m = N - 1;
@@ -435,17 +477,16 @@ __global__ __launch_bounds__(256) void k_pm_fd(const float *__restrict__ phi, in
         0.0f);
 }
 
-// TSC interpolation of the mesh force to each particle (key order in), written to the
-// caller's order idx[i]; ACC adds to what the output holds.
-template <typename T, int ACC>
-__global__ __launch_bounds__(256) void k_pm_interp(const double4 *__restrict__ ps,
-                                                   const uint32_t *__restrict__ idx, int64_t n,
+// TSC interpolation of the mesh force to each particle in key order, into stage[i] =
+// (ax, ay, az, 0).  Neighbouring threads hold neighbouring particles, so the 27-point gathers
+// mostly hit the same cache lines; the writes are contiguous (the caller's order is restored
+// by k_unpermute, whose writes are contiguous too).
+__global__ __launch_bounds__(256) void k_pm_interp(const double4 *__restrict__ ps, int64_t n,
                                                    int N, double inv_h,
                                                    const float4 *__restrict__ f,
-                                                   T *__restrict__ ax, T *__restrict__ ay,
-                                                   T *__restrict__ az)
+                                                   float4 *__restrict__ stage)
 {
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t i = xcd_block(blockIdx.x, gridDim.x) * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
     const double4 p = ps[i];
     double wx[3], wy[3], wz[3];
@@ -454,31 +495,50 @@ __global__ __launch_bounds__(256) void k_pm_interp(const double4 *__restrict__ p
     float sx = 0.0f, sy = 0.0f, sz = 0.0f;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        const size_t xa = (size_t)((ix - 1 + a + N) & mask) * N;
+        const size_t xa = (size_t)((ix - 1 + a) & mask) * N;
 #pragma unroll
         for (int b = 0; b < 3; ++b) {
-            const size_t yb = (xa + ((iy - 1 + b + N) & mask)) * N;
+            const size_t yb = (xa + ((iy - 1 + b) & mask)) * N;
             const double wab = wx[a] * wy[b];
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                const size_t g = yb + ((iz - 1 + c + N) & mask);
                 const float w = (float)(wab * wz[c]);
-                const float4 v = f[g];
+                const float4 v = f[yb + ((iz - 1 + c) & mask)];
                 sx += w * v.x;
                 sy += w * v.y;
                 sz += w * v.z;
             }
         }
     }
-    const uint32_t o = idx[i];
+    stage[i] = make_float4(sx, sy, sz, 0.0f);
+}
+
+// inv[idx[k]] = k: the key-order position of each particle of the caller's order.
+__global__ __launch_bounds__(256) void k_invert(const uint32_t *__restrict__ idx, int64_t n,
+                                                uint32_t *__restrict__ inv)
+{
+    const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k < n) inv[idx[k]] = (uint32_t)k;
+}
+
+// Caller's order o reads stage[inv[o]] and writes (or, ACC, adds to) ax[o], ay[o], az[o].
+template <typename T, int ACC>
+__global__ __launch_bounds__(256) void k_unpermute(const uint32_t *__restrict__ inv,
+                                                   const float4 *__restrict__ stage, int64_t n,
+                                                   T *__restrict__ ax, T *__restrict__ ay,
+                                                   T *__restrict__ az)
+{
+    const int64_t o = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (o >= n) return;
+    const float4 v = stage[inv[o]];
     if (ACC) {
-        ax[o] += (T)sx;
-        ay[o] += (T)sy;
-        az[o] += (T)sz;
+        ax[o] += (T)v.x;
+        ay[o] += (T)v.y;
+        az[o] += (T)v.z;
     } else {
-        ax[o] = (T)sx;
-        ay[o] = (T)sy;
-        az[o] = (T)sz;
+        ax[o] = (T)v.x;
+        ay[o] = (T)v.y;
+        az[o] = (T)v.z;
     }
 }
 
@@ -529,27 +589,38 @@ void launch_pm_force(const float *phi, int N, double L, float4 *f, hipStream_t s
                                                           (float)(N / L), f);
 }
 
-void launch_pm_interp(const double4 *ps, const uint32_t *idx, int64_t n, int N, double L,
-                      const float4 *f, void *ax, void *ay, void *az, int out_fp64,
-                      int accumulate, hipStream_t s)
+void launch_pm_interp(const double4 *ps, int64_t n, int N, double L, const float4 *f,
+                      float4 *stage, hipStream_t s)
+{
+    if (!n) return;
+    k_pm_interp<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(ps, n, N, N / L, f, stage);
+}
+
+void launch_invert(const uint32_t *idx, int64_t n, uint32_t *inv, hipStream_t s)
+{
+    if (!n) return;
+    k_invert<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(idx, n, inv);
+}
+
+void launch_unpermute(const uint32_t *inv, const float4 *stage, int64_t n, void *ax, void *ay,
+                      void *az, int out_fp64, int accumulate, hipStream_t s)
 {
     if (!n) return;
     const unsigned b = (unsigned)((n + 255) / 256);
-    const double inv_h = N / L;
     if (out_fp64) {
         if (accumulate)
-            k_pm_interp<double, 1><<<b, 256, 0, s>>>(ps, idx, n, N, inv_h, f,
-                                                     (double *)ax, (double *)ay, (double *)az);
+            k_unpermute<double, 1><<<b, 256, 0, s>>>(inv, stage, n, (double *)ax, (double *)ay,
+                                                    (double *)az);
         else
-            k_pm_interp<double, 0><<<b, 256, 0, s>>>(ps, idx, n, N, inv_h, f,
-                                                     (double *)ax, (double *)ay, (double *)az);
+            k_unpermute<double, 0><<<b, 256, 0, s>>>(inv, stage, n, (double *)ax, (double *)ay,
+                                                    (double *)az);
     } else {
         if (accumulate)
-            k_pm_interp<float, 1><<<b, 256, 0, s>>>(ps, idx, n, N, inv_h, f,
-                                                    (float *)ax, (float *)ay, (float *)az);
+            k_unpermute<float, 1><<<b, 256, 0, s>>>(inv, stage, n, (float *)ax, (float *)ay,
+                                                   (float *)az);
         else
-            k_pm_interp<float, 0><<<b, 256, 0, s>>>(ps, idx, n, N, inv_h, f,
-                                                    (float *)ax, (float *)ay, (float *)az);
+            k_unpermute<float, 0><<<b, 256, 0, s>>>(inv, stage, n, (float *)ax, (float *)ay,
+                                                   (float *)az);
     }
 }
 

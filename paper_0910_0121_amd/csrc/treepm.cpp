@@ -89,6 +89,10 @@ struct treepm_ctx {
     // particle mesh: fixed-point masses (later the potential), the complex work mesh, the
     // force mesh, the Green's table, twiddles, max mass
     Buf pm_mass, pm_grid, pm_f, pm_green, pm_tw, pm_mx;
+    // per particle: key-order results of the mesh force, and the inverse of the sort
+    // permutation (valid for the current build when inv_valid)
+    Buf pm_stage, inv;
+    bool inv_valid = false;
     int pm_n = 0; // mesh size, box and eta the table was built for
     double pm_L = 0.0, pm_eta = 0.0;
 };
@@ -385,6 +389,7 @@ int do_build(treepm_ctx *c, int64_t n, const double *x, const double *y, const d
     const treepm_params &P = c->prm;
     int rc;
     size_t N = (size_t)n;
+    c->inv_valid = false; // the sort permutation changes
     // particle-sized buffers
     struct R {
         Buf *b;
@@ -744,7 +749,7 @@ TREEPM_API int treepm_destroy(treepm_ctx *c)
                   &c->g_hi[1], &c->g_hi[2], &c->g_misc, &c->off, &c->glen, &c->wctr, &c->scan64, &c->entries,
                   &c->wstats, &c->overflow, &c->rec, &c->kept, &c->kept_sum, &c->gcells, &c->cls, &c->out[0],
                   &c->out[1], &c->out[2], &c->bnd, &c->runs, &c->pm_mass, &c->pm_grid,
-                  &c->pm_f, &c->pm_green, &c->pm_tw, &c->pm_mx};
+                  &c->pm_f, &c->pm_green, &c->pm_tw, &c->pm_mx, &c->pm_stage, &c->inv};
     {
         CallScope scope(c, c->last);
         for (Buf *b : all) release(*b);
@@ -955,6 +960,8 @@ TREEPM_API int treepm_force_long(treepm_ctx *c, void *ax, void *ay, void *az, in
         if (e == hipSuccess) e = reserve(c->pm_green, H * H * H * 4);
         if (e == hipSuccess) e = reserve(c->pm_tw, (size_t)N / 2 * 8);
         if (e == hipSuccess) e = reserve(c->pm_mx, 8);
+        if (e == hipSuccess) e = reserve(c->pm_stage, (size_t)c->n * 16);
+        if (e == hipSuccess && !c->inv_valid) e = reserve(c->inv, (size_t)c->n * 4);
         if (e != hipSuccess) return hip_fail(c, e, "PM meshes");
     }
     const double eta = 0.5 * P.r_cut;
@@ -985,8 +992,13 @@ TREEPM_API int treepm_force_long(treepm_ctx *c, void *ax, void *ay, void *az, in
     launch_pm_potential(mass, c->pm_mx.as<unsigned long long>(), c->n, (int)N, grid, phi,
                         c->pm_green.as<float>(), c->pm_tw.as<float2>(), s);
     launch_pm_force(phi, (int)N, P.L, c->pm_f.as<float4>(), s);
-    launch_pm_interp(ps, c->idx.as<uint32_t>(), c->n, (int)N, P.L, c->pm_f.as<float4>(), dst[0],
-                     dst[1], dst[2], out_prec == TREEPM_FP64, accumulate, s);
+    launch_pm_interp(ps, c->n, (int)N, P.L, c->pm_f.as<float4>(), c->pm_stage.as<float4>(), s);
+    if (!c->inv_valid) {
+        launch_invert(c->idx.as<uint32_t>(), c->n, c->inv.as<uint32_t>(), s);
+        c->inv_valid = true;
+    }
+    launch_unpermute(c->inv.as<uint32_t>(), c->pm_stage.as<float4>(), c->n, dst[0], dst[1],
+                     dst[2], out_prec == TREEPM_FP64, accumulate, s);
     HIPCHK(c, hipGetLastError());
     if (mem_kind == TREEPM_HOST) {
         for (int a = 0; a < 3; ++a)
