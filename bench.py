@@ -76,17 +76,19 @@ def parse():
 
 
 def measured_traffic(n_crit, workload):
-    """HBM bytes per force call from the committed rocprofv3 counter runs, if they were taken
-    on the current force-kernel source, the same workload and the same n_crit; else None."""
+    """HBM bytes per force call from the committed rocprofv3 counter runs (one per n_crit
+    measured), if one was taken on the current force-kernel source, the same workload and the
+    same n_crit; else None."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
         with open(FORCE_SRC, "rb") as f:
             sha = hashlib.sha1(f.read()).hexdigest()
-        if (t.get("source_sha1") != sha or t.get("n_crit") != n_crit
-                or not t.get("workload", "").startswith(workload)):
-            return None
-        return t
+        for run in [t] + t.get("other_runs", []):
+            if (run.get("source_sha1") == sha and run.get("n_crit") == n_crit
+                    and run.get("workload", "").startswith(workload)):
+                return run
+        return None
     except (OSError, ValueError):
         return None
 
