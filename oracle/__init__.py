@@ -71,6 +71,14 @@ def lib():
         L.orc_theta_r.argtypes = [_d, _d, _d, _d]
         L.orc_tree_set_opening.restype = C.c_int
         L.orc_tree_set_opening.argtypes = [_p, C.c_int, _d]
+        L.orc_g_p3m_derivs.restype = None
+        L.orc_g_p3m_derivs.argtypes = [_d, _p, _p]
+        L.orc_cell_acc.restype = None
+        L.orc_cell_acc.argtypes = [_p, _p, _d, _p, _d, _d, _d, C.c_int, _p]
+        L.orc_tree_set_quadrupole.restype = C.c_int
+        L.orc_tree_set_quadrupole.argtypes = [_p, C.c_int]
+        L.orc_tree_nodes_q.restype = None
+        L.orc_tree_nodes_q.argtypes = [_p, _p]
         L.orc_key.restype = C.c_uint64
         L.orc_key.argtypes = [_d, _d, _d, _d]
         _lib = L
@@ -123,6 +131,23 @@ def theta_r(r: float, eta: float, theta0: float, theta_max: float) -> float:
     return float(lib().orc_theta_r(r, eta, theta0, theta_max))
 
 
+def g_p3m_derivs(R: float):
+    """(g'(R), g''(R)) of eq. (2)."""
+    g1, g2 = C.c_double(), C.c_double()
+    lib().orc_g_p3m_derivs(R, C.byref(g1), C.byref(g2))
+    return g1.value, g2.value
+
+
+def cell_acc(xi, com, M, Q, L, r_cut, eps, order=2):
+    """Acceleration at xi from a cell (mass M at com, second moment Q = (xx, yy, zz, xy, xz,
+    yz) about com): order 1 monopole, order 2 with the quadrupole term."""
+    xi, com, Q = _f64(xi), _f64(com), _f64(Q)
+    out = np.zeros(3)
+    lib().orc_cell_acc(_ptr(xi), _ptr(com), float(M), _ptr(Q), L, r_cut, eps, int(order),
+                       _ptr(out))
+    return out
+
+
 def key(x, y, z, L=1.0) -> int:
     return int(lib().orc_key(x, y, z, L))
 
@@ -131,7 +156,7 @@ class Tree:
     """Reference tree, groups, lists and list force for one box."""
 
     def __init__(self, x, y, z, m, L, r_cut, eps, theta, n_leaf, n_crit, opening=0,
-                 theta_max=0.0):
+                 theta_max=0.0, quadrupole=False):
         """opening=1 selects the distance-dependent angle of eq. (12): theta is then theta_0
         and theta_max its upper limit."""
         self._keep = [_f64(a) for a in (x, y, z, m)]
@@ -143,6 +168,18 @@ class Tree:
             raise ValueError("oracle tree build failed")
         if opening:
             self.set_opening(opening, theta_max)
+        if quadrupole:
+            self.set_quadrupole(True)
+
+    def set_quadrupole(self, on=True):
+        if lib().orc_tree_set_quadrupole(self.h, 1 if on else 0) != 0:
+            raise ValueError("invalid quadrupole setting")
+
+    def nodes_q(self):
+        """Second moments of the nodes about their centres of mass, (n_nodes, 6)."""
+        Q = np.zeros((self.n_nodes, 6))
+        lib().orc_tree_nodes_q(self.h, _ptr(Q))
+        return Q
 
     def set_opening(self, opening, theta_max=0.0):
         if lib().orc_tree_set_opening(self.h, int(opening), float(theta_max)) != 0:

@@ -36,6 +36,9 @@
  *  - prune: periodic gap between the node cube and the group bbox >= r_cut;
  *  - accept: l^2 < theta^2 * d^2, d = distance from the node's centre of mass to the group
  *    bbox, and the node cube does not touch the bbox (gap > 0); a tie opens the node.
+ *  - quadrupole cells (Section 4.1), when selected: a cell entry adds the second-order term
+ *    of the expansion of the cut-off pair law about its centre of mass (pair_quad), with the
+ *    node's second moment taken directly from its particles;
  *  - distance-dependent opening (Section 4.1, eq. 12), when selected: theta is replaced by
  *    theta(d) = min(theta_max, theta_0 / sqrt(R g_P3M(R))), R = d / eta -- the distance is
  *    measured in units of eta so that theta_0 is dimensionless, d is the same distance as in
@@ -106,6 +109,68 @@ static void pair_acc(const double d[3], double m, double eta, double eps2, doubl
     acc[0] += f * d[0];
     acc[1] += f * d[1];
     acc[2] += f * d[2];
+}
+
+/* First and second derivatives of g_P3M(R) of eq. (2), differentiated term by term. */
+void orc_g_p3m_derivs(double R, double *g1, double *g2)
+{
+    double R2 = R * R, R3 = R2 * R, R4 = R3 * R, R5 = R4 * R, R6 = R5 * R, R7 = R6 * R;
+    if (R < 1.0) {
+        *g1 = -(672.0 * R2 - 1120.0 * R4 + 420.0 * R5 + 336.0 * R6 - 168.0 * R7) / 140.0;
+        *g2 = -(1344.0 * R - 4480.0 * R3 + 2100.0 * R4 + 2016.0 * R5 - 1176.0 * R6) / 140.0;
+    } else if (R < 2.0) {
+        *g1 = -(-448.0 * R + 2688.0 * R2 - 3360.0 * R3 + 1120.0 * R4 + 420.0 * R5 -
+                336.0 * R6 + 56.0 * R7) / 140.0;
+        *g2 = -(-448.0 + 5376.0 * R - 10080.0 * R2 + 4480.0 * R3 + 2100.0 * R4 - 2016.0 * R5 +
+                392.0 * R6) / 140.0;
+    } else {
+        *g1 = 0.0;
+        *g2 = 0.0;
+    }
+}
+
+/* Second-order (quadrupole) term of a cell whose particles have second moment Q about its
+ * centre of mass, at displacement d = com - field point (Section 4.1: the expansion of the
+ * cut-off force must carry the derivatives of the cutoff function).  With the pair law
+ * F(d) = d h(r), h = g(r/eta) (r^2+eps^2)^(-3/2), the sum over the cell's particles of
+ * F(d + s_j), sum m_j s_j = 0, is M F(d) plus
+ *     (1/2) Q_ab d_a d_b F_c = (Q d)_c u + (1/2) tr(Q) d_c u + (1/2) (d.Q.d) d_c w,
+ *     u = h'/r,  w = (h'/r)'/r,
+ * to second order in the particles' offsets s_j.  Adds into acc[3]. */
+static void pair_quad(const double d[3], const double Q[6], double eta, double eps2,
+                      double acc[3])
+{
+    double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+    if (r2 == 0.0) return;
+    double r = sqrt(r2), R = r / eta;
+    if (R >= 2.0) return;
+    double g = orc_g_p3m(R), g1, g2;
+    orc_g_p3m_derivs(R, &g1, &g2);
+    double s2 = r2 + eps2, s1 = sqrt(s2);
+    double q = 1.0 / (s2 * s1);         /* (r^2+eps^2)^(-3/2) */
+    double p = q / s2;                  /* (r^2+eps^2)^(-5/2) */
+    double s7 = p / s2;                 /* (r^2+eps^2)^(-7/2) */
+    double u = g1 * q / (eta * r) - 3.0 * g * p;
+    double w = g2 * q / (eta * eta * r2) - g1 * q / (eta * r2 * r) - 6.0 * g1 * p / (eta * r) +
+               15.0 * g * s7;
+    double Qd[3] = {Q[0] * d[0] + Q[3] * d[1] + Q[4] * d[2],
+                    Q[3] * d[0] + Q[1] * d[1] + Q[5] * d[2],
+                    Q[4] * d[0] + Q[5] * d[1] + Q[2] * d[2]};
+    double trQ = Q[0] + Q[1] + Q[2];
+    double dQd = d[0] * Qd[0] + d[1] * Qd[1] + d[2] * Qd[2];
+    for (int a = 0; a < 3; ++a) acc[a] += Qd[a] * u + 0.5 * trQ * d[a] * u + 0.5 * dQd * d[a] * w;
+}
+
+/* Public: acceleration at xi from a cell of mass M, centre of mass com and second moment Q
+ * (order 1: monopole only; order 2: with the quadrupole term), minimum image in box L. */
+void orc_cell_acc(const double xi[3], const double com[3], double M, const double Q[6],
+                  double L, double r_cut, double eps, int order, double out[3])
+{
+    double d[3];
+    for (int a = 0; a < 3; ++a) d[a] = wrap(com[a] - xi[a], L);
+    out[0] = out[1] = out[2] = 0.0;
+    pair_acc(d, M, 0.5 * r_cut, eps * eps, out);
+    if (order >= 2) pair_quad(d, Q, 0.5 * r_cut, eps * eps, out);
 }
 
 /* |pair force| of the same pair, and the same magnitude without the cutoff factor g, for
@@ -238,6 +303,7 @@ typedef struct {
     int64_t child_first; /* index of first child in the node array, -1 for a leaf     */
     int nchild;
     double mass, S[3], com[3];
+    double Q[6];        /* second moment about com: xx, yy, zz, xy, xz, yz (quadrupole)  */
 } onode;
 
 typedef struct {
@@ -251,6 +317,7 @@ typedef struct {
     int n_leaf, n_crit;
     int opening;        /* 0: fixed theta; 1: theta(d) of eq. (12), theta = theta_0        */
     double theta_max;   /* upper limit of theta(d) (opening 1)                           */
+    int quadrupole;     /* cell entries also carry their second-order term (Section 4.1) */
     /* particles */
     int64_t n;
     uint64_t *key;      /* sorted keys                                                  */
@@ -500,6 +567,46 @@ void orc_tree_free(otree *t)
     free(t);
 }
 
+/* Second moments of every node about its centre of mass, from its particles directly:
+ * Q = sum_k m_k (x_k - com)(x_k - com)^T over the node's range in key order (a node is a
+ * sub-cube of [0, L), so no image is needed). */
+static void second_moments(otree *t)
+{
+    for (int64_t u = 0; u < t->n_nodes; ++u) {
+        onode *nd = &t->nodes[u];
+        double Q[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        for (int64_t k = nd->first; k < nd->first + nd->count; ++k) {
+            double dx = t->px[k] - nd->com[0], dy = t->py[k] - nd->com[1],
+                   dz = t->pz[k] - nd->com[2], m = t->pm[k];
+            Q[0] += m * dx * dx;
+            Q[1] += m * dy * dy;
+            Q[2] += m * dz * dz;
+            Q[3] += m * dx * dy;
+            Q[4] += m * dx * dz;
+            Q[5] += m * dy * dz;
+        }
+        for (int a = 0; a < 6; ++a) nd->Q[a] = Q[a];
+    }
+}
+
+/* Cell entries with (1) or without (0) their quadrupole term in the list force.  The lists
+ * do not change.  Returns 0, or -1 for an invalid value. */
+int orc_tree_set_quadrupole(otree *t, int on)
+{
+    if (!t || on < 0 || on > 1) return -1;
+    if (on && !t->quadrupole) second_moments(t);
+    t->quadrupole = on;
+    return 0;
+}
+
+/* Second moments of the nodes (n_nodes x 6: xx, yy, zz, xy, xz, yz), node array order. */
+void orc_tree_nodes_q(otree *t, double *Q)
+{
+    second_moments(t);
+    for (int64_t u = 0; u < t->n_nodes; ++u)
+        for (int a = 0; a < 6; ++a) Q[6 * u + a] = t->nodes[u].Q[a];
+}
+
 /* Select the opening criterion: 0 = fixed theta (the build's theta); 1 = theta(d) of
  * eq. (12) with theta_0 = the build's theta and the cap theta_max.  Drops earlier lists.
  * Returns 0, or -1 for an invalid choice. */
@@ -635,6 +742,7 @@ static int64_t group_force(const otree *t, int64_t gi, const int64_t *ent, const
             double d[3] = {wrap(p[0] - xi[0], t->L), wrap(p[1] - xi[1], t->L),
                            wrap(p[2] - xi[2], t->L)};
             pair_acc(d, mj, eta, eps2, acc);
+            if (t->quadrupole && isc[q]) pair_quad(d, t->nodes[ent[q]].Q, eta, eps2, acc);
         }
         int64_t i = t->idx[k];
         ax[i] = acc[0];

@@ -77,6 +77,20 @@ MUTANTS = [
     ("opening_distance_squared", "orc_theta_r(sqrt(D), 0.5 * t->r_cut,",
      "orc_theta_r(D, 0.5 * t->r_cut,",
      TREE + "::test_distance_opening_lists_equal_brute_force_frontier"),
+    ("quad_trace_half_dropped", "0.5 * trQ * d[a] * u", "trQ * d[a] * u",
+     TREE + "::test_quadrupole_cell_is_third_order"),
+    ("quad_w_sign", "- 6.0 * g1 * p / (eta * r)", "+ 6.0 * g1 * p / (eta * r)",
+     TREE + "::test_quadrupole_cell_is_third_order"),
+    ("quad_g2_coefficient", "2016.0 * R5 - 1176.0 * R6", "2016.0 * R5 - 1170.0 * R6",
+     TREE + "::test_cutoff_derivatives"),
+    ("quad_g1_branch2", "336.0 * R6 + 56.0 * R7) / 140.0;", "336.0 * R6 + 57.0 * R7) / 140.0;",
+     TREE + "::test_cutoff_derivatives"),
+    ("quad_eta_power", "g2 * q / (eta * eta * r2)", "g2 * q / (eta * r2)",
+     TREE + "::test_quadrupole_cell_is_third_order"),
+    ("quad_moment_offdiag", "Q[3] += m * dx * dy;", "Q[3] += m * dx * dz;",
+     TREE + "::test_node_second_moments"),
+    ("quad_not_applied", "if (t->quadrupole && isc[q]) pair_quad(",
+     "if (0 && isc[q]) pair_quad(", TREE + "::test_quadrupole_tree_force_is_more_accurate"),
     ("opening_angle_not_squared", "        th2 = th * th;\n", "        th2 = th;\n",
      TREE + "::test_distance_opening_lists_equal_brute_force_frontier"),
 ]
