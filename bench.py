@@ -62,6 +62,8 @@ def parse():
                     help="theta_0 of the distance-dependent opening angle leg")
     ap.add_argument("--theta-max", type=float, default=0.5,
                     help="cap of the distance-dependent opening angle leg")
+    ap.add_argument("--no-quadrupole", action="store_true",
+                    help="skip the quadrupole-cells leg")
     ap.add_argument("--no-pm", action="store_true",
                     help="skip the particle-mesh long-range leg")
     ap.add_argument("--no-serving", action="store_true")
@@ -419,6 +421,29 @@ def main():
             "cell_entries": int(str_.n_cell_entries),
             "phase_ms": {"build": float(np.mean(phr[:, 0])), "walk": float(np.mean(phr[:, 1])),
                          "force_f32": float(np.mean(phr[:, 2]))},
+        }
+    if not args.no_quadrupole:
+        # The same box and step with the cells' second-order terms (Section 4.1).
+        pq = tp.make_params(spec.L, spec.mesh, spec.r_cut, spec.eps, spec.theta, spec.n_leaf,
+                            n_crit, tp.TREEPM_FP32, quadrupole=1)
+        ctx = tp.treepm_create(pq, 0)
+        tp.treepm_set_timing(ctx, True)
+        log("[bench] quadrupole leg")
+        run_steps(tp, torch, ctx, dev, acc, 2)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        kq = max(1, min(5, args.steps))
+        timesq, stq = run_steps(tp, torch, ctx, dev, acc, kq)
+        torch.cuda.synchronize()
+        eq = time.perf_counter() - t1
+        tp.treepm_destroy(ctx)
+        phq = np.array(timesq)
+        result["quadrupole"] = {
+            "ms_per_step": eq / kq * 1e3,
+            "particles_per_s": spec.n * kq / eq,
+            "interactions": int(stq.interactions),
+            "phase_ms": {"build": float(np.mean(phq[:, 0])), "walk": float(np.mean(phq[:, 1])),
+                         "force_f32_with_quadrupole": float(np.mean(phq[:, 2]))},
         }
     if not args.no_pm:
         # The long-range half of the split on the same box and its own mesh (N_PM^3 = N).

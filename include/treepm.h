@@ -76,7 +76,14 @@ enum { TREEPM_OPEN_FIXED = 0, TREEPM_OPEN_DISTANCE = 1 }; /* opening criterion  
  *            the node is used when l < theta(d) d.  sqrt and divisions are correctly rounded,
  *            so the lists equal a plain FP64 evaluation.
  *   theta_max the cap of theta(d), 0 <= theta_max <= 1 (read only under
- *            TREEPM_OPEN_DISTANCE). */
+ *            TREEPM_OPEN_DISTANCE).
+ *   quadrupole 0 (default): a cell entry is its mass at its centre of mass.  1: it also adds
+ *            its second-order term (Section 4.1), (Q d) u + (1/2) tr(Q) d u + (1/2)(d.Q.d) d w
+ *            with Q the node's second moment about its centre of mass (FP64, from the
+ *            build), d the displacement to the centre of mass, u = h'/r, w = (h'/r)'/r and
+ *            h(r) = g_P3M(r/eta) (r^2+eps^2)^(-3/2): the derivatives of the cutoff function
+ *            enter through h.  Computed in the force call's precision; the lists are the
+ *            same.  Costs 48 bytes per node and a second pass over the cell entries. */
 typedef struct {
     double L;
     double mesh;
@@ -88,6 +95,7 @@ typedef struct {
     int32_t precision;
     int32_t opening;
     double theta_max;
+    int32_t quadrupole;
 } treepm_params;
 
 typedef struct treepm_ctx treepm_ctx; /* one resident box on one GPU */

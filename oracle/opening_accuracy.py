@@ -1,4 +1,5 @@
-"""Accuracy against cost of the two opening criteria, from the oracle alone.
+"""Accuracy against cost of the opening criteria and of quadrupole cells, from the oracle
+alone.
 
 TEST INFRASTRUCTURE: it runs the FP64 oracle only (never the HIP library).  For a named
 workload it walks a stratified sample of groups (every k-th in key order) under
@@ -6,6 +7,7 @@ workload it walks a stratified sample of groups (every k-th in key order) under
   * the fixed angle theta of the walk (Section 2.2 step 5), and
   * the distance-dependent angle theta(d) = min(theta_max, theta_0 / sqrt(R g(R))),
     R = d / eta, of Section 4.1 (eq. 12),
+  * the fixed angle with quadrupole cells (the second-order term of Section 4.1),
 
 and prints, per setting, the interactions of the sampled groups and the RMS and 99th
 percentile of |a - a_exact| / |a_exact| over their particles, where a_exact is the exact
@@ -34,6 +36,8 @@ def main():
     ap.add_argument("--fixed", default="0.4,0.5,0.6")
     ap.add_argument("--theta-r", default="0.3:0.5,0.25:0.8,0.2:0.8,0.15:0.6,0.1:0.6",
                     help="theta_0:theta_max pairs")
+    ap.add_argument("--quadrupole", default="0.5,0.7",
+                    help="fixed angles for rows with quadrupole cells (Section 4.1)")
     ap.add_argument("--threads", type=int, default=0)
     a = ap.parse_args()
     spec, (x, y, z, m) = boxgen.config_box(a.workload)
@@ -60,6 +64,8 @@ def main():
 
     for th in (float(v) for v in a.fixed.split(",") if v):
         row(f"fixed {th}", oracle.Tree(*args, th, spec.n_leaf, a.n_crit))
+    for th in (float(v) for v in a.quadrupole.split(",") if v):
+        row(f"quadrupole {th}", oracle.Tree(*args, th, spec.n_leaf, a.n_crit, quadrupole=True))
     for pair in (v for v in a.theta_r.split(",") if v):
         th0, tmax = (float(v) for v in pair.split(":"))
         row(f"theta(r) {th0}/{tmax}",

@@ -31,7 +31,7 @@ class treepm_params(C.Structure):
     _fields_ = [("L", C.c_double), ("mesh", C.c_double), ("r_cut", C.c_double),
                 ("eps", C.c_double), ("theta", C.c_double), ("n_leaf", C.c_int32),
                 ("n_crit", C.c_int32), ("precision", C.c_int32), ("opening", C.c_int32),
-                ("theta_max", C.c_double)]
+                ("theta_max", C.c_double), ("quadrupole", C.c_int32)]
 
 
 class treepm_stats(C.Structure):
@@ -113,9 +113,9 @@ def _check(rc: int, ctx=None):
 
 def make_params(L=1.0, mesh=None, r_cut=None, eps=0.0, theta=0.5, n_leaf=10, n_crit=0,
                 precision=TREEPM_FP32, opening=TREEPM_OPEN_FIXED,
-                theta_max=0.0) -> treepm_params:
+                theta_max=0.0, quadrupole=0) -> treepm_params:
     """opening=TREEPM_OPEN_DISTANCE selects theta(d) of eq. (12): theta is then theta_0 and
-    theta_max its cap."""
+    theta_max its cap.  quadrupole=1 adds the cells' second-order terms."""
     if mesh is None and r_cut is None:
         raise ValueError("give mesh or r_cut")
     if mesh is None:
@@ -123,7 +123,7 @@ def make_params(L=1.0, mesh=None, r_cut=None, eps=0.0, theta=0.5, n_leaf=10, n_c
     if r_cut is None:
         r_cut = 3.0 * mesh
     return treepm_params(L, mesh, r_cut, eps, theta, n_leaf, n_crit, precision, opening,
-                         theta_max)
+                         theta_max, quadrupole)
 
 
 # ----------------------------------------------------------------------------- buffers

@@ -30,6 +30,7 @@ SOURCES = {
     "k_walk.hip": ["-ffp-contract=off"],
     "k_force.hip": [],
     "k_pm.hip": [],
+    "k_quad.hip": [],
     "treepm.cpp": ["-ffp-contract=off"],
     "ensemble.cpp": [],
 }

@@ -215,4 +215,15 @@ void launch_invert(const uint32_t *idx, int64_t n, uint32_t *inv, hipStream_t s)
 void launch_unpermute(const uint32_t *inv, const float4 *stage, int64_t n, void *ax, void *ay,
                       void *az, int out_fp64, int accumulate, hipStream_t s);
 
+// Quadrupole terms of the cell entries (k_quad.hip).  Q: 6 doubles per node (xx, yy, zz,
+// xy, xz, yz about the centre of mass), filled level by level from the deepest.
+void launch_second_moments(NodeArrays nd, const double4 *ps, uint32_t lo, uint32_t hi,
+                           double *Q, hipStream_t s);
+// Adds the cells' second-order terms to ax/ay/az (caller's order, float or double outputs),
+// computed in FP64 (fp64_math) or FP32.
+void launch_quad(NodeArrays nd, GroupArrays gr, uint32_t n_groups, const uint64_t *off,
+                 const uint32_t *len, const uint32_t *entries, const double4 *ps,
+                 const uint32_t *pidx, const double *Q, ForceParams fp, void *ax, void *ay,
+                 void *az, int fp64_math, int out_prec, hipStream_t s);
+
 } // namespace tpm

@@ -93,6 +93,7 @@ struct treepm_ctx {
     // permutation (valid for the current build when inv_valid)
     Buf pm_stage, inv;
     bool inv_valid = false;
+    Buf n_q; // per node second moment (6 doubles), quadrupole boxes only
     int pm_n = 0; // mesh size, box and eta the table was built for
     double pm_L = 0.0, pm_eta = 0.0;
 };
@@ -194,6 +195,8 @@ int check_params(treepm_ctx *c, const treepm_params *p)
     if (p->opening == TREEPM_OPEN_DISTANCE &&
         (!std::isfinite(p->theta_max) || p->theta_max < 0.0 || p->theta_max > 1.0))
         return fail(c, TREEPM_ERR_ARG, "theta_max must be in [0, 1]");
+    if (p->quadrupole != 0 && p->quadrupole != 1)
+        return fail(c, TREEPM_ERR_ARG, "quadrupole must be 0 or 1");
     if (p->n_leaf < 2) return fail(c, TREEPM_ERR_ARG, "n_leaf must be >= 2");
     if (p->n_crit < 0) return fail(c, TREEPM_ERR_ARG, "n_crit must be >= 1 (0 = default)");
     if (p->precision != TREEPM_FP32 && p->precision != TREEPM_FP64)
@@ -491,6 +494,12 @@ int do_build(treepm_ctx *c, int64_t n, const double *x, const double *y, const d
     }
     nd = nodes_view(c);
     launch_com_divide(nd, c->n_nodes, c->n_walk.as<WalkNode>(), s);
+    if (P.quadrupole) {
+        hipError_t e = reserve(c->n_q, (size_t)c->n_nodes * 6 * sizeof(double));
+        if (e != hipSuccess) return hip_fail(c, e, "second moments");
+        for (int l = c->max_level; l >= 0; --l)
+            launch_second_moments(nd, ps, c->lvl[l], c->lvl[l + 1], c->n_q.as<double>(), s);
+    }
     // groups in key order
     int n_crit = P.n_crit > 0 ? P.n_crit : kDefaultNCrit;
     uint32_t *gstart = c->gstart.as<uint32_t>(), *gflag = c->gflag.as<uint32_t>();
@@ -749,7 +758,8 @@ TREEPM_API int treepm_destroy(treepm_ctx *c)
                   &c->g_hi[1], &c->g_hi[2], &c->g_misc, &c->off, &c->glen, &c->wctr, &c->scan64, &c->entries,
                   &c->wstats, &c->overflow, &c->rec, &c->kept, &c->kept_sum, &c->gcells, &c->cls, &c->out[0],
                   &c->out[1], &c->out[2], &c->bnd, &c->runs, &c->pm_mass, &c->pm_grid,
-                  &c->pm_f, &c->pm_green, &c->pm_tw, &c->pm_mx, &c->pm_stage, &c->inv};
+                  &c->pm_f, &c->pm_green, &c->pm_tw, &c->pm_mx, &c->pm_stage, &c->inv,
+                  &c->n_q};
     {
         CallScope scope(c, c->last);
         for (Buf *b : all) release(*b);
@@ -912,6 +922,11 @@ TREEPM_API int treepm_force_short(treepm_ctx *c, void *ax, void *ay, void *az, i
                          c->entries.as<uint32_t>(),
                          c->psrc.as<double4>(), c->idx.as<uint32_t>(), fp, dst[0], dst[1],
                          dst[2], out_prec, s);
+    if (P.quadrupole)
+        launch_quad(nd, gr, c->n_groups, c->off.as<uint64_t>(), c->glen.as<uint32_t>(),
+                    c->entries.as<uint32_t>(), c->psrc.as<double4>(), c->idx.as<uint32_t>(),
+                    c->n_q.as<double>(), fp, dst[0], dst[1], dst[2],
+                    P.precision == TREEPM_FP64, out_prec, s);
     HIPCHK(c, hipGetLastError());
     record(c, 5, s);
     if (P.precision == TREEPM_FP32)

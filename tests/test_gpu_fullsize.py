@@ -163,3 +163,45 @@ def test_pm_full_size(tp, name):
     rms, mx = float(np.sqrt(np.mean(d * d))) / scale, float(d.max()) / scale
     _say(f"  rms |da| / rms |a| = {rms:.2e}, max {mx:.2e}")
     assert rms <= 2e-6 and mx <= 5e-5
+
+
+def test_quadrupole_full_size(tp, orc):
+    """Quadrupole cells on the 256^3 box in the configuration the benchmark times: sampled
+    FP64 and FP32 parity against the oracle's sampled walk and list force with the cells'
+    second-order terms, to the bars above."""
+    spec, arrays = boxgen.config_box("nfw256")
+    stride = 400
+    _say(f"nfw256 quadrupole: n_crit={N_CRIT}, stride {stride}")
+    dev = [torch.from_numpy(a).cuda() for a in arrays]
+    out = {}
+    for prec in (tp.TREEPM_FP64, tp.TREEPM_FP32):
+        p = tp.make_params(spec.L, spec.mesh, spec.r_cut, spec.eps, spec.theta, spec.n_leaf,
+                           N_CRIT, prec, quadrupole=1)
+        ctx = tp.treepm_create(p, 0)
+        try:
+            tp.treepm_build(ctx, *dev)
+            tp.treepm_walk(ctx)
+            acc = [torch.zeros(spec.n, dtype=torch.float64, device="cuda") for _ in range(3)]
+            tp.treepm_force_short(ctx, *acc)
+            torch.cuda.synchronize()
+            out[prec] = np.stack([a.cpu().numpy() for a in acc])
+        finally:
+            tp.treepm_destroy(ctx)
+    x, y, z, m = arrays
+    T = orc.Tree(x, y, z, m, spec.L, spec.r_cut, spec.eps, spec.theta, spec.n_leaf, N_CRIT,
+                 quadrupole=True)
+    ax, ay, az, inter, parts, mag, newt = T.walk_force_sample(stride, 0, 16, scales=True)
+    T.close()
+    s = ~np.isnan(ax)
+    ref = np.stack([ax[s], ay[s], az[s]])
+    scale = (mag + newt)[s]
+    err64 = np.abs(out[tp.TREEPM_FP64][:, s] - ref)
+    _say(f"  sampled {parts} particles; fp64 max |da|/scale {np.max(err64 / scale):.2e}")
+    assert np.all(err64 <= 1e-13 * scale[None, :])
+    d = np.linalg.norm(out[tp.TREEPM_FP32][:, s] - ref, axis=0)
+    nr = np.linalg.norm(ref, axis=0)
+    nz = nr > 0
+    rel = d[nz] / nr[nz]
+    rms = float(np.sqrt(np.mean(rel ** 2)))
+    _say(f"  fp32 rms rel {rms:.3e} max rel {rel.max():.3e}")
+    assert rms <= 1e-6 and rel.max() <= 2e-4
