@@ -64,6 +64,8 @@ def parse():
                     help="cap of the distance-dependent opening angle leg")
     ap.add_argument("--no-quadrupole", action="store_true",
                     help="skip the quadrupole-cells leg")
+    ap.add_argument("--no-time-step", action="store_true",
+                    help="skip the full TreePM time-step leg")
     ap.add_argument("--no-pm", action="store_true",
                     help="skip the particle-mesh long-range leg")
     ap.add_argument("--no-serving", action="store_true")
@@ -474,6 +476,42 @@ def main():
                          "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": pm_bytes / (pm_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                          "algorithmic_bytes": pm_bytes},
+        }
+    if not args.no_time_step:
+        # Whole TreePM time steps on copies of the box: short- and long-range forces into one
+        # FP32 array, the shared step of eq. (7) and a kick and drift (Section 2.2, 2.4).
+        ps_ = tp.make_params(spec.L, spec.mesh, spec.r_cut, spec.eps, spec.theta, spec.n_leaf,
+                             n_crit, tp.TREEPM_FP32)
+        ctx = tp.treepm_create(ps_, 0)
+        pos = [t.clone() for t in dev[:3]]
+        vel = [torch.zeros(spec.n, dtype=torch.float64, device="cuda") for _ in range(3)]
+        log("[bench] time-step leg")
+
+        def one_step(first):
+            tp.treepm_build(ctx, *pos, dev[3])
+            tp.treepm_walk(ctx)
+            tp.treepm_force_short(ctx, *acc)
+            tp.treepm_force_long(ctx, *acc, accumulate=True)
+            dt = tp.treepm_timestep(ctx, *vel, *acc, spec.eps, 1.0)
+            tp.treepm_kick_drift(ctx, *pos, *vel, *acc, 0.5 * dt if first else dt, dt)
+            return dt
+
+        for k in range(2):
+            one_step(k == 0)
+        torch.cuda.synchronize()
+        ks = max(1, min(5, args.steps))
+        t1 = time.perf_counter()
+        dts = [one_step(False) for _ in range(ks)]
+        torch.cuda.synchronize()
+        es = time.perf_counter() - t1
+        tp.treepm_destroy(ctx)
+        del pos, vel
+        result["time_step"] = {
+            "ms_per_step": es / ks * 1e3,
+            "particles_per_s": spec.n * ks / es,
+            "dt_last": dts[-1],
+            "content": "build + walk + FP32 short-range + PM long-range + eq. (7) step + "
+                       "kick-drift",
         }
     if not args.no_serving:
         log("[bench] ensemble serving")

@@ -176,6 +176,31 @@ int treepm_force_short(treepm_ctx *ctx, void *ax, void *ay, void *az, int out_pr
 int treepm_force_long(treepm_ctx *ctx, void *ax, void *ay, void *az, int out_prec,
                       int mem_kind, int accumulate, void *hip_stream);
 
+/* ------------------------------------------------------------ time stepping
+ * Section 2.2 kicks the velocities with the forces and drifts the positions; Section 2.4 gives
+ * the shared adaptive step (eq. 7) and the softening schedule (eq. 6).  Positions, velocities
+ * (double) and accelerations (float or double, acc_prec) are device arrays of n particles in
+ * the caller's order; these calls use the context's device and L and do not need a build.
+ * Arithmetic is FP64 without contraction (plain IEEE evaluation of each formula). */
+
+/* Physical Plummer softening at redshift z, eq. (6): eps_fin (1 + z_crit) / (1 + z) for
+ * z >= z_crit, else eps_fin (so the comoving softening is constant before z_crit). */
+double treepm_eps_of_z(double z, double eps_fin, double z_crit);
+
+/* Shared time step, eq. (7): *dt = zeta min_i(sqrt(eps / |a_i|), eps / |v_i|), where a term
+ * with a zero denominator does not bind (+inf if none does).  eps, zeta finite and > 0.
+ * Synchronises the stream. */
+int treepm_timestep(treepm_ctx *ctx, int64_t n, const double *vx, const double *vy,
+                    const double *vz, const void *ax, const void *ay, const void *az,
+                    int acc_prec, double eps, double zeta, void *hip_stream, double *dt);
+
+/* One kick and drift, in place: v += a dt_kick, then x += v dt_drift, and each coordinate is
+ * wrapped back into [0, L) by one box length (one that rounds to L is set to 0).  A leapfrog
+ * starts with dt_kick = dt / 2.  Stream-ordered; does not synchronise. */
+int treepm_kick_drift(treepm_ctx *ctx, int64_t n, double *x, double *y, double *z, double *vx,
+                      double *vy, double *vz, const void *ax, const void *ay, const void *az,
+                      int acc_prec, double dt_kick, double dt_drift, void *hip_stream);
+
 /* Choose n_crit (Section 3.1.2's N_crit) for this box by measurement: for each of the
  * n_candidates values (1..64 of them, each >= 1), build, walk and run the FP32 force twice on
  * the given particles (same arguments as treepm_build) and time the second run with device

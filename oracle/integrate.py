@@ -8,8 +8,9 @@ TEST INFRASTRUCTURE ONLY.
     denominator is zero does not bind);
   * one step, as in Section 2.2 (velocities kicked by the forces, then positions drifted):
         v <- v + a dt_kick,   x <- x + v dt_drift,
-    and x wrapped back into [0, L) by one box length (a value that rounds to L is 0).  The caller chooses dt_kick (half a step
-    to start a leapfrog, the mean of two consecutive steps afterwards) and dt_drift.
+    and x wrapped back into [0, L) by one box length (a value that rounds to L is 0).  The
+    caller chooses dt_kick (half a step to start a leapfrog, the mean of two consecutive steps
+    afterwards) and dt_drift.
 
 Plain FP64 numpy in the order written.  The forces come from the oracle's tree and PM code.
 """

@@ -31,7 +31,10 @@ from ._native import (  # noqa: F401
     treepm_export_lists,
     treepm_export_nodes,
     treepm_export_sorted,
+    treepm_eps_of_z,
     treepm_force_long,
+    treepm_kick_drift,
+    treepm_timestep,
     treepm_force_short,
     treepm_get_stats,
     treepm_last_error,

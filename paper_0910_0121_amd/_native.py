@@ -62,6 +62,11 @@ _SIGS = {
     "treepm_walk": (_i, [_p, _p, C.POINTER(treepm_stats)]),
     "treepm_force_short": (_i, [_p, _p, _p, _p, _i, _i, _p]),
     "treepm_force_long": (_i, [_p, _p, _p, _p, _i, _i, _i, _p]),
+    "treepm_eps_of_z": (C.c_double, [C.c_double, C.c_double, C.c_double]),
+    "treepm_timestep": (_i, [_p, _i64, _p, _p, _p, _p, _p, _p, _i, C.c_double, C.c_double, _p,
+                             C.POINTER(C.c_double)]),
+    "treepm_kick_drift": (_i, [_p, _i64, _p, _p, _p, _p, _p, _p, _p, _p, _p, _i, C.c_double,
+                               C.c_double, _p]),
     "treepm_get_stats": (_i, [_p, C.POINTER(treepm_stats)]),
     "treepm_export_sorted": (_i, [_p, _p, _p]),
     "treepm_export_nodes": (_i, [_p, _i64, _p, _p, _p, _p, _p, _p]),
@@ -215,6 +220,41 @@ def treepm_force_long(ctx, ax, ay, az, accumulate=False, stream=None) -> None:
     prec = TREEPM_FP64 if dt == "float64" else TREEPM_FP32
     _check(lib().treepm_force_long(ctx, bufs[0][0], bufs[1][0], bufs[2][0], prec, kind,
                                    1 if accumulate else 0, _stream(stream, kind)), ctx)
+
+
+def treepm_eps_of_z(z, eps_fin, z_crit) -> float:
+    return float(lib().treepm_eps_of_z(z, eps_fin, z_crit))
+
+
+def _dev_ptrs(arrs, dtypes):
+    out = []
+    for a, dt in zip(arrs, dtypes):
+        p, kind, _ = _buf(a, dt)
+        if kind != TREEPM_DEVICE:
+            raise ValueError("time-stepping calls take device tensors")
+        out.append(p)
+    return out
+
+
+def treepm_timestep(ctx, vx, vy, vz, ax, ay, az, eps, zeta, stream=None) -> float:
+    """Shared step of eq. (7) from device velocities (float64) and accelerations."""
+    adt = "float64" if str(ax.dtype) == "torch.float64" else "float32"
+    ptr = _dev_ptrs((vx, vy, vz, ax, ay, az), ("float64",) * 3 + (adt,) * 3)
+    dt = C.c_double()
+    _check(lib().treepm_timestep(ctx, vx.shape[0], *ptr,
+                                 TREEPM_FP64 if adt == "float64" else TREEPM_FP32, eps, zeta,
+                                 _stream(stream, TREEPM_DEVICE), C.byref(dt)), ctx)
+    return dt.value
+
+
+def treepm_kick_drift(ctx, x, y, z, vx, vy, vz, ax, ay, az, dt_kick, dt_drift,
+                      stream=None) -> None:
+    """In place on device tensors: v += a dt_kick, x += v dt_drift (wrapped into [0, L))."""
+    adt = "float64" if str(ax.dtype) == "torch.float64" else "float32"
+    ptr = _dev_ptrs((x, y, z, vx, vy, vz, ax, ay, az), ("float64",) * 6 + (adt,) * 3)
+    _check(lib().treepm_kick_drift(ctx, x.shape[0], *ptr,
+                                   TREEPM_FP64 if adt == "float64" else TREEPM_FP32, dt_kick,
+                                   dt_drift, _stream(stream, TREEPM_DEVICE)), ctx)
 
 
 def treepm_autotune(ctx, x, y, z, m, candidates, stream=None):

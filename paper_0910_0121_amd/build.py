@@ -31,6 +31,7 @@ SOURCES = {
     "k_force.hip": [],
     "k_pm.hip": [],
     "k_quad.hip": [],
+    "k_step.hip": ["-ffp-contract=off"],
     "treepm.cpp": ["-ffp-contract=off"],
     "ensemble.cpp": [],
 }

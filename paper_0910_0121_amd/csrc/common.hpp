@@ -226,4 +226,14 @@ void launch_quad(NodeArrays nd, GroupArrays gr, uint32_t n_groups, const uint64_
                  const uint32_t *pidx, const double *Q, ForceParams fp, void *ax, void *ay,
                  void *az, int fp64_math, int out_prec, hipStream_t s);
 
+// Time stepping (k_step.hip).  Accelerations are float (acc_fp64 = 0) or double arrays.
+// out receives the bit pattern of min_i(sqrt(eps / |a_i|), eps / |v_i|) (+inf if none binds).
+void launch_timestep(int64_t n, const double *vx, const double *vy, const double *vz,
+                     const void *ax, const void *ay, const void *az, int acc_fp64, double eps,
+                     unsigned long long *out, hipStream_t s);
+// v += a dt_kick, then x += v dt_drift wrapped into [0, L), in place.
+void launch_kick_drift(int64_t n, double *x, double *y, double *z, double *vx, double *vy,
+                       double *vz, const void *ax, const void *ay, const void *az, int acc_fp64,
+                       double dt_kick, double dt_drift, double L, hipStream_t s);
+
 } // namespace tpm

@@ -94,6 +94,7 @@ struct treepm_ctx {
     Buf pm_stage, inv;
     bool inv_valid = false;
     Buf n_q; // per node second moment (6 doubles), quadrupole boxes only
+    Buf step_min; // time-step reduction result
     int pm_n = 0; // mesh size, box and eta the table was built for
     double pm_L = 0.0, pm_eta = 0.0;
 };
@@ -759,7 +760,7 @@ TREEPM_API int treepm_destroy(treepm_ctx *c)
                   &c->wstats, &c->overflow, &c->rec, &c->kept, &c->kept_sum, &c->gcells, &c->cls, &c->out[0],
                   &c->out[1], &c->out[2], &c->bnd, &c->runs, &c->pm_mass, &c->pm_grid,
                   &c->pm_f, &c->pm_green, &c->pm_tw, &c->pm_mx, &c->pm_stage, &c->inv,
-                  &c->n_q};
+                  &c->n_q, &c->step_min};
     {
         CallScope scope(c, c->last);
         for (Buf *b : all) release(*b);
@@ -1021,6 +1022,88 @@ TREEPM_API int treepm_force_long(treepm_ctx *c, void *ax, void *ay, void *az, in
                                      hipMemcpyDeviceToHost, s));
         HIPCHK(c, hipStreamSynchronize(s));
     }
+    return TREEPM_OK;
+}
+
+// True if p is device (or managed) memory of device `device`: the time-stepping kernels read
+// and write their arrays directly, so a host pointer is refused before any launch.
+static bool device_array(const void *p, int device)
+{
+    hipPointerAttribute_t a{};
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return (a.type == hipMemoryTypeDevice || a.isManaged) && a.device == device;
+}
+
+TREEPM_API double treepm_eps_of_z(double z, double eps_fin, double z_crit)
+{
+    return z >= z_crit ? (1.0 + z_crit) / (1.0 + z) * eps_fin : eps_fin;
+}
+
+TREEPM_API int treepm_timestep(treepm_ctx *c, int64_t n, const double *vx, const double *vy,
+                               const double *vz, const void *ax, const void *ay, const void *az,
+                               int acc_prec, double eps, double zeta, void *hip_stream,
+                               double *dt)
+{
+    if (!c) return TREEPM_ERR_ARG;
+    c->err.clear();
+    if (!dt) return fail(c, TREEPM_ERR_ARG, "dt is NULL");
+    if (n < 1 || n > 0x7fffffffLL) return fail(c, TREEPM_ERR_ARG, "n must be in [1, 2^31)");
+    if (!vx || !vy || !vz || !ax || !ay || !az) return fail(c, TREEPM_ERR_ARG, "NULL buffer");
+    if (acc_prec != TREEPM_FP32 && acc_prec != TREEPM_FP64)
+        return fail(c, TREEPM_ERR_ARG, "acc_prec must be TREEPM_FP32 or TREEPM_FP64");
+    if (!std::isfinite(eps) || !(eps > 0.0) || !std::isfinite(zeta) || !(zeta > 0.0))
+        return fail(c, TREEPM_ERR_ARG, "eps and zeta must be finite and > 0");
+    HIPCHK(c, hipSetDevice(c->device));
+    for (const void *p : {(const void *)vx, (const void *)vy, (const void *)vz, ax, ay, az})
+        if (!device_array(p, c->device))
+            return fail(c, TREEPM_ERR_ARG, "treepm_timestep takes device arrays");
+    hipStream_t s = (hipStream_t)hip_stream;
+    c->last = s;
+    CallScope scope(c, s);
+    {
+        hipError_t e = reserve(c->step_min, 8);
+        if (e != hipSuccess) return hip_fail(c, e, "time step");
+    }
+    launch_timestep(n, vx, vy, vz, ax, ay, az, acc_prec == TREEPM_FP64, eps,
+                    c->step_min.as<unsigned long long>(), s);
+    HIPCHK(c, hipGetLastError());
+    unsigned long long bits = 0;
+    int rc = d2h(c, &bits, c->step_min.p, 1, s);
+    if (rc) return rc;
+    double m;
+    std::memcpy(&m, &bits, sizeof m);
+    *dt = zeta * m;
+    return TREEPM_OK;
+}
+
+TREEPM_API int treepm_kick_drift(treepm_ctx *c, int64_t n, double *x, double *y, double *z,
+                                 double *vx, double *vy, double *vz, const void *ax,
+                                 const void *ay, const void *az, int acc_prec, double dt_kick,
+                                 double dt_drift, void *hip_stream)
+{
+    if (!c) return TREEPM_ERR_ARG;
+    c->err.clear();
+    if (n < 1 || n > 0x7fffffffLL) return fail(c, TREEPM_ERR_ARG, "n must be in [1, 2^31)");
+    if (!x || !y || !z || !vx || !vy || !vz || !ax || !ay || !az)
+        return fail(c, TREEPM_ERR_ARG, "NULL buffer");
+    if (acc_prec != TREEPM_FP32 && acc_prec != TREEPM_FP64)
+        return fail(c, TREEPM_ERR_ARG, "acc_prec must be TREEPM_FP32 or TREEPM_FP64");
+    if (!std::isfinite(dt_kick) || !std::isfinite(dt_drift))
+        return fail(c, TREEPM_ERR_ARG, "dt_kick and dt_drift must be finite");
+    HIPCHK(c, hipSetDevice(c->device));
+    for (const void *p : {(const void *)x, (const void *)y, (const void *)z, (const void *)vx,
+                          (const void *)vy, (const void *)vz, ax, ay, az})
+        if (!device_array(p, c->device))
+            return fail(c, TREEPM_ERR_ARG, "treepm_kick_drift takes device arrays");
+    hipStream_t s = (hipStream_t)hip_stream;
+    c->last = s;
+    CallScope scope(c, s);
+    launch_kick_drift(n, x, y, z, vx, vy, vz, ax, ay, az, acc_prec == TREEPM_FP64, dt_kick,
+                      dt_drift, c->prm.L, s);
+    HIPCHK(c, hipGetLastError());
     return TREEPM_OK;
 }
 
