@@ -256,7 +256,7 @@ def serving_bench(tp, n_boxes, per_box, inflight, budget_frac=0.25):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only (the tree force of one box on one "
+        print(f"bench.py: measures one GPU only (the tree force of one box on one "
               f"MI355X); --gpus {args.gpus} is not supported.", file=sys.stderr)
         sys.exit(2)
     import numpy as np
