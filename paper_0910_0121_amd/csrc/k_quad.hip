@@ -109,11 +109,12 @@ __device__ __forceinline__ void g_derivs140_far(T R, T &g, T &g1, T &g2)
 __device__ __forceinline__ float rsqrt_t(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ double rsqrt_t(double x) { return 1.0 / sqrt(x); }
 
-// A cell as the kernel uses it: centre of mass relative to the group's cube centre and the
-// six moments, in the arithmetic type.
+// A cell as the kernel uses it: centre of mass relative to the group's cube centre, half the
+// trace of the moments, and the six moments, in the arithmetic type (three 16-byte LDS reads
+// in FP32).
 template <typename T>
-struct QuadCell {
-    T x, y, z, q0, q1, q2, q3, q4, q5;
+struct alignas(4 * sizeof(T)) QuadCell {
+    T x, y, z, htr, q0, q1, q2, q3, q4, q5, pad0, pad1;
 };
 
 // One wave per group.  The lanes are S = 64 / J particle slots times J cell phases, J the
@@ -148,7 +149,7 @@ __global__ __launch_bounds__(64) void k_quad(NodeArrays nd, GroupArrays gr, uint
     // unless half the group cube plus r_cut reaches L/2; then each pair takes its own (only
     // the FP64 path: the FP32 force call refuses such boxes)
     const bool pair_wrap = WRAP && !(half_side + sqrt(fp.rc2) < 0.5 * L);
-    const T inv_eta = T(fp.inv_eta), rc2 = T(fp.rc2), eps2 = T(fp.eps2);
+    const T inv_eta = T(fp.inv_eta), eps2 = T(fp.eps2);
     const T inv_eta2 = inv_eta * inv_eta;
     int lj = 0; // log2 J
     while (lj < 6 && (uint64_t)n_g << (lj + 1) <= 64u * kQuadK) ++lj;
@@ -193,9 +194,18 @@ __global__ __launch_bounds__(64) void k_quad(NodeArrays nd, GroupArrays gr, uint
                     const double *q = Q + 6 * (size_t)c;
                     // the moments carry the 1/140 of g and its derivatives below
                     const double k = 1.0 / 140.0;
-                    v = QuadCell<T>{T(wrapq(r.x - xg0, L)), T(wrapq(r.y - xg1, L)),
-                                    T(wrapq(r.z - xg2, L)), T(q[0] * k), T(q[1] * k),
-                                    T(q[2] * k), T(q[3] * k), T(q[4] * k), T(q[5] * k)};
+                    v = QuadCell<T>{T(wrapq(r.x - xg0, L)),
+                                    T(wrapq(r.y - xg1, L)),
+                                    T(wrapq(r.z - xg2, L)),
+                                    T(0.5 * (q[0] + q[1] + q[2]) * k),
+                                    T(q[0] * k),
+                                    T(q[1] * k),
+                                    T(q[2] * k),
+                                    T(q[3] * k),
+                                    T(q[4] * k),
+                                    T(q[5] * k),
+                                    T(0),
+                                    T(0)};
                 }
             }
             // near cells from the front of the tile, far ones from the back
@@ -215,9 +225,9 @@ __global__ __launch_bounds__(64) void k_quad(NodeArrays nd, GroupArrays gr, uint
                     dy = T(wrapq(double(dy), L));
                     dz = T(wrapq(double(dz), L));
                 }
+                // pairs at or beyond r_cut get g = g' = g'' = 0 from the polynomials (R >= 2)
                 const T r2 = dx * dx + dy * dy + dz * dz;
-                if (!(r2 < rc2) || r2 == T(0)) return;
-                const T ir = rsqrt_t(r2), r = r2 * ir, R = r * inv_eta;
+                const T ir = r2 > T(0) ? rsqrt_t(r2) : T(0), r = r2 * ir, R = r * inv_eta;
                 T gv, g1, g2;
                 if (far_cell)
                     g_derivs140_far<T>(R, gv, g1, g2);
@@ -228,13 +238,14 @@ __global__ __launch_bounds__(64) void k_quad(NodeArrays nd, GroupArrays gr, uint
                 const T ir2 = ir * ir;
                 // 140 u = 140 h'/r and 140 w = 140 (h'/r)'/r (the moments carry 1/140)
                 const T A = g1 * inv_eta * ir;
-                const T ur = A * q3 - T(3) * gv * p5;
-                const T wr = (g2 * inv_eta2 - A) * ir2 * q3 - T(6) * A * p5 + T(15) * gv * s7;
+                const bool live = r2 > T(0); // a cell never sits on a particle; kept safe
+                const T ur = live ? A * q3 - T(3) * gv * p5 : T(0);
+                const T wr =
+                    live ? (g2 * inv_eta2 - A) * ir2 * q3 - T(6) * A * p5 + T(15) * gv * s7 : T(0);
                 const T qx = s.q0 * dx + s.q3 * dy + s.q4 * dz;
                 const T qy = s.q3 * dx + s.q1 * dy + s.q5 * dz;
                 const T qz = s.q4 * dx + s.q5 * dy + s.q2 * dz;
-                const T sc = T(0.5) * ((s.q0 + s.q1 + s.q2) * ur +
-                                       (dx * qx + dy * qy + dz * qz) * wr);
+                const T sc = s.htr * ur + T(0.5) * (dx * qx + dy * qy + dz * qz) * wr;
                 ax_[k] += qx * ur + sc * dx;
                 ay_[k] += qy * ur + sc * dy;
                 az_[k] += qz * ur + sc * dz;

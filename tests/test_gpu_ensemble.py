@@ -96,6 +96,48 @@ def test_mix_equals_alone(tp, budget_boxes, inflight):
         tp.treepm_ens_destroy(ens)
 
 
+def test_modes_mix_equals_alone(tp):
+    """Boxes with the distance-dependent opening angle and with quadrupole cells, served in one
+    mix, give exactly what each gives alone with the same parameters."""
+    print("[gpu-case] ensemble with opening and quadrupole modes", flush=True)
+    boxes = _boxes()
+
+    def params(i, mesh):
+        return tp.make_params(1.0, mesh, 3 * mesh, mesh / 20, 0.3 if i % 2 == 0 else 0.5, 10,
+                              128, tp.TREEPM_FP32,
+                              opening=tp.TREEPM_OPEN_DISTANCE if i % 2 == 0 else 0,
+                              theta_max=0.5 if i % 2 == 0 else 0.0, quadrupole=i // 2)
+
+    ref = {}
+    for i, arr, mesh in boxes:
+        ctx = tp.treepm_create(params(i, mesh), 0)
+        try:
+            tp.treepm_build(ctx, *arr)
+            tp.treepm_walk(ctx)
+            a = [np.zeros(len(arr[0]), dtype=np.float32) for _ in range(3)]
+            tp.treepm_force_short(ctx, *a)
+            ref[i] = (np.stack(a), tp.treepm_get_stats(ctx).interactions)
+        finally:
+            tp.treepm_destroy(ctx)
+    biggest = max(len(arr[0]) for _, arr, _ in boxes)
+    ens = tp.treepm_ens_create(0, int(100 * (biggest * 320 + (64 << 20))), 4)
+    try:
+        tickets, sizes, which = [], {}, {}
+        for rep in range(2):
+            for i, arr, mesh in boxes:
+                t = tp.treepm_ensemble_submit(ens, i, params(i, mesh), *arr)
+                tickets.append(t)
+                sizes[t] = len(arr[0])
+                which[t] = i
+        res = _drain(tp, ens, tickets, sizes)
+        for t in tickets:
+            a, st = res[t]
+            np.testing.assert_array_equal(a, ref[which[t]][0])
+            assert st.interactions == ref[which[t]][1]
+    finally:
+        tp.treepm_ens_destroy(ens)
+
+
 def test_errors(tp):
     print("[gpu-case] ensemble errors", flush=True)
     ens = tp.treepm_ens_create(0, 256 << 20, 2)

@@ -515,3 +515,39 @@ def test_quadrupole_parity(tp, orc, case):
             _say(f"  fp32 rms rel {rms:.3e}")
             assert rms <= 1e-6
             assert np.all(d[~nz] == 0.0)
+
+
+def test_quadrupole_with_distance_opening(tp, orc):
+    """Both Section 4.1 options at once: lists under theta(d) (theta_0 = 0.25, cap 0.8) with the
+    cells' second-order terms; FP64 and FP32 bars as above."""
+    x, y, z, m = _box("nfw", 40000, 2)
+    r_cut, th0, tmax = 0.06, 0.25, 0.8
+    eps = r_cut / 60
+    T = orc.Tree(x, y, z, m, 1.0, r_cut, eps, th0, 10, 128, opening=1, theta_max=tmax,
+                 quadrupole=True)
+    ref = np.stack(T.force())
+    scale = T.error_scale()
+    dev = [torch.from_numpy(a).cuda() for a in (x, y, z, m)]
+    for prec in (tp.TREEPM_FP64, tp.TREEPM_FP32):
+        _say(f"quadrupole + theta(r) prec={prec}")
+        p = tp.make_params(1.0, r_cut / 3.0, r_cut, eps, th0, 10, 128, prec,
+                           opening=tp.TREEPM_OPEN_DISTANCE, theta_max=tmax, quadrupole=1)
+        ctx = tp.treepm_create(p, 0)
+        try:
+            tp.treepm_build(ctx, *dev)
+            st = tp.treepm_walk(ctx)
+            assert st.interactions == T.interactions()
+            _assert_lists_equal(tp, ctx, T, "theta(r) + quadrupole")
+            acc = [torch.zeros(len(x), dtype=torch.float64, device="cuda") for _ in range(3)]
+            tp.treepm_force_short(ctx, *acc)
+            torch.cuda.synchronize()
+            got = np.stack([t.cpu().numpy() for t in acc])
+        finally:
+            tp.treepm_destroy(ctx)
+        if prec == tp.TREEPM_FP64:
+            assert np.all(np.abs(got - ref) <= 1e-13 * scale[None, :] + 1e-300)
+        else:
+            d = np.linalg.norm(got - ref, axis=0)
+            nr = np.linalg.norm(ref, axis=0)
+            nz = nr > 0
+            assert float(np.sqrt(np.mean((d[nz] / nr[nz]) ** 2))) <= 1e-6

@@ -92,6 +92,23 @@ def test_pm_force_matches_oracle(tp, case):
     np.testing.assert_array_equal(got32, got.astype(np.float32).astype(np.float64))
 
 
+def test_pm_particles_on_the_seams(tp):
+    """Clouds that wrap around the periodic boundary: particles at 0, just below L and at
+    half-cell offsets from the seam on every axis, among a clustered box."""
+    x, y, z, m = boxgen.nfw_box(20000, 40, 6)
+    L, n_pm = 1.0, 32
+    h = L / n_pm
+    seam = np.array([0.0, np.nextafter(L, 0.0), 0.5 * h, L - 0.5 * h, 0.25 * h, L - 0.25 * h])
+    k = seam.size
+    x[:k], y[:k], z[:k] = seam, seam[::-1].copy(), np.roll(seam, 2)
+    got = _long(tp, x, y, z, m, n_pm)
+    ref = pm.pm_force(np.stack([x, y, z], axis=1), m, L, n_pm, 1.5 * h)
+    _check(got, ref, "seam particles")
+    d = np.linalg.norm(got[:k] - ref[:k], axis=1)
+    scale = float(np.sqrt(np.mean((ref * ref).sum(axis=1))))
+    assert np.all(d <= 5e-5 * scale)
+
+
 def test_pm_box_size_and_host_buffers(tp):
     """L = 2.5 with host output buffers, and accumulation onto existing values."""
     x, y, z, m = boxgen.nfw_box(30000, 60, 5)
