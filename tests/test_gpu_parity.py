@@ -551,3 +551,24 @@ def test_quadrupole_with_distance_opening(tp, orc):
             nr = np.linalg.norm(ref, axis=0)
             nz = nr > 0
             assert float(np.sqrt(np.mean((d[nz] / nr[nz]) ** 2))) <= 1e-6
+
+
+@pytest.mark.parametrize("n", [1, 2, 9])
+def test_quadrupole_tiny_boxes(tp, orc, n):
+    """Quadrupole cells on boxes of a few particles (few or no cell entries), FP64 output."""
+    x, y, z, m = boxgen.uniform_box(n, 60 + n)
+    r_cut = 0.3
+    T = orc.Tree(x, y, z, m, 1.0, r_cut, 0.002, 0.8, 2, 2, quadrupole=True)
+    ref = np.stack(T.force())
+    p = tp.make_params(1.0, r_cut / 3, r_cut, 0.002, 0.8, 2, 2, tp.TREEPM_FP64, quadrupole=1)
+    ctx = tp.treepm_create(p, 0)
+    try:
+        tp.treepm_build(ctx, *[torch.from_numpy(a).cuda() for a in (x, y, z, m)])
+        tp.treepm_walk(ctx)
+        acc = [torch.zeros(n, dtype=torch.float64, device="cuda") for _ in range(3)]
+        tp.treepm_force_short(ctx, *acc)
+        torch.cuda.synchronize()
+        got = np.stack([t.cpu().numpy() for t in acc])
+    finally:
+        tp.treepm_destroy(ctx)
+    assert np.all(np.abs(got - ref) <= 1e-13 * T.error_scale()[None, :] + 1e-300)

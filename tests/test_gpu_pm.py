@@ -174,3 +174,18 @@ def test_pm_errors(tp):
         assert e.value.code == -5
     finally:
         tp.treepm_destroy(ctx)
+
+
+@pytest.mark.parametrize("n", [1, 2, 7])
+def test_pm_tiny_boxes(tp, n):
+    """A handful of particles (one wave's chunk partly empty, most of the mesh empty).  The
+    forces can nearly vanish (one particle: only its mesh self-force), so the bar is relative
+    to the mesh's own force scale M / h^2: 1e-6 of it."""
+    rng = boxgen.SplitMix64(40 + n)
+    pos = rng.uniform(3 * n).reshape(n, 3)
+    m = np.full(n, 1.0 / n)
+    x, y, z = (np.ascontiguousarray(pos[:, a]) for a in range(3))
+    got = _long(tp, x, y, z, m, 16)
+    ref = pm.pm_force(pos, m, 1.0, 16, 1.5 / 16)
+    scale = m.sum() / (1.0 / 16) ** 2
+    assert np.abs(got - ref).max() <= 1e-6 * scale
