@@ -152,9 +152,9 @@ def serving_bench(tp, n_boxes, per_box, inflight, budget_frac=0.25):
     in [32^3, 256^3] (seed 999; box i uses seed 1000 + i and max(1, round(N/1e4)) halos),
     mesh = N^(1/3), r_cut = 3/mesh, eps = mesh/20, theta = 0.5, FP32.  First the closed-loop
     capacity (2 * inflight requests kept outstanding); then n_boxes * per_box requests in
-    seeded order arriving as a Poisson process at 0.8 x that capacity, with the HBM budget
-    set to 25% of the ensemble's total resident footprint.  Reports p50/p99 latency
-    (completion minus submission) and aggregate particles/s."""
+    seeded order arriving as a Poisson process at 0.8 x that capacity, then again at 0.5 x,
+    with the HBM budget set to 25% of the ensemble's total resident footprint.  Reports p50/p99
+    latency (completion minus submission) and aggregate particles/s for both rates."""
     import concurrent.futures as cf
     import threading
 
@@ -205,36 +205,41 @@ def serving_bench(tp, n_boxes, per_box, inflight, budget_frac=0.25):
             time.sleep(0.0005)
         t_closed = time.perf_counter() - t0
         cap = n_closed / t_closed
-        # open loop: Poisson arrivals at 0.8 x capacity
-        lam = 0.8 * cap
-        gaps = -np.log(1.0 - rng.uniform(len(order))) / lam
-        arrivals = np.cumsum(gaps)
-        pending, done, lat = {}, [], []
-        lock = threading.Lock()
-        t_start = time.perf_counter()
+        def open_loop(frac):
+            """Poisson arrivals at frac x capacity: (latencies, requests done, makespan)."""
+            lam = frac * cap
+            gaps = -np.log(1.0 - rng.uniform(len(order))) / lam
+            arrivals = np.cumsum(gaps)
+            pending, done, lat = {}, [], []
+            lock = threading.Lock()
+            t_start = time.perf_counter()
 
-        def submitter():
-            for j, i in enumerate(order):
-                wait = arrivals[j] - (time.perf_counter() - t_start)
-                if wait > 0:
-                    time.sleep(wait)
-                t = tp.treepm_ensemble_submit(ens, int(i), params[int(i)], *boxes[int(i)])
+            def submitter():
+                for j, i in enumerate(order):
+                    wait = arrivals[j] - (time.perf_counter() - t_start)
+                    if wait > 0:
+                        time.sleep(wait)
+                    t = tp.treepm_ensemble_submit(ens, int(i), params[int(i)],
+                                                  *boxes[int(i)])
+                    with lock:
+                        pending[t] = int(i)
+
+            th = threading.Thread(target=submitter)
+            th.start()
+            while th.is_alive() or pending:
                 with lock:
-                    pending[t] = int(i)
+                    drain(pending, done, lat)
+                time.sleep(0.0005)
+            th.join()
+            return lam, np.array(lat), done, time.perf_counter() - t_start
 
-        th = threading.Thread(target=submitter)
-        th.start()
-        while th.is_alive() or pending:
-            with lock:
-                drain(pending, done, lat)
-            time.sleep(0.0005)
-        th.join()
-        makespan = time.perf_counter() - t_start
+        lam, lat, done, makespan = open_loop(0.8)
         info = tp.treepm_ens_info(ens)
+        lam5, lat5, done5, makespan5 = open_loop(0.5)
     finally:
         tp.treepm_ens_destroy(ens)
-    lat = np.array(lat)
     parts = float(sum(int(ns[i]) for i in done))
+    parts5 = float(sum(int(ns[i]) for i in done5))
     return {
         "boxes": n_boxes,
         "requests": len(done),
@@ -250,6 +255,13 @@ def serving_bench(tp, n_boxes, per_box, inflight, budget_frac=0.25):
         "latency_ms_max": float(lat.max()),
         "particles_per_s": parts / makespan,
         "resident_boxes_at_end": info["resident_boxes"],
+        "at_half_capacity": {
+            "arrival_rate_per_s": lam5,
+            "requests": len(done5),
+            "latency_ms_p50": float(np.percentile(lat5, 50)),
+            "latency_ms_p99": float(np.percentile(lat5, 99)),
+            "particles_per_s": parts5 / makespan5,
+        },
     }
 
 
