@@ -96,20 +96,35 @@ struct Request {
     double t_submit = 0, t_start = 0, t_done = 0;
 };
 
-// Copy k arrays of n doubles/floats in parallel (large requests only).
+// Copy k arrays of n doubles/floats.  Large requests are cut into pieces of at least 4 MiB
+// spread over up to kCopyThreads threads (one thread's memcpy reaches only a fraction of the
+// host's memory bandwidth).
+constexpr int kCopyThreads = 8;
+
 template <typename T>
 void copy_parallel(T *const *dst, const T *const *src, int k, int64_t n)
 {
-    if ((size_t)n * sizeof(T) < ((size_t)4 << 20)) {
-        for (int a = 0; a < k; ++a) memcpy(dst[a], src[a], (size_t)n * sizeof(T));
+    const size_t bytes = (size_t)n * sizeof(T), piece_min = (size_t)4 << 20;
+    const size_t total = bytes * (size_t)k;
+    if (total < 2 * piece_min) {
+        for (int a = 0; a < k; ++a) memcpy(dst[a], src[a], bytes);
         return;
     }
+    size_t pieces = total / piece_min;
+    if (pieces > (size_t)kCopyThreads) pieces = kCopyThreads;
+    const size_t share = (total + pieces - 1) / pieces;
+    // piece p copies bytes [p share, (p + 1) share) of the k arrays laid end to end
+    auto run = [=](size_t p) {
+        size_t lo = p * share, hi = std::min(total, lo + share);
+        while (lo < hi) {
+            const size_t a = lo / bytes, off = lo % bytes, len = std::min(hi - lo, bytes - off);
+            memcpy((char *)dst[a] + off, (const char *)src[a] + off, len);
+            lo += len;
+        }
+    };
     std::vector<std::future<void>> fs;
-    for (int a = 1; a < k; ++a)
-        fs.push_back(std::async(std::launch::async, [=] {
-            memcpy(dst[a], src[a], (size_t)n * sizeof(T));
-        }));
-    memcpy(dst[0], src[0], (size_t)n * sizeof(T));
+    for (size_t p = 1; p < pieces; ++p) fs.push_back(std::async(std::launch::async, run, p));
+    run(0);
     for (auto &f : fs) f.get();
 }
 
