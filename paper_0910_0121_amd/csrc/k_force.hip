@@ -25,14 +25,20 @@ namespace tpm {
 namespace {
 
 
-__device__ __forceinline__ double g_p3m_f64(double R)
+// First branch of eq. (2) alone, for separations known to be below eta (R < 1).
+__device__ __forceinline__ double g_in_f64(double R)
 {
     double R2 = R * R;
     double p = fma(0.15, R, -12.0 / 35.0);
     p = fma(p, R, -0.5);
     p = fma(p, R, 1.6);
     p = fma(p, R2, -1.6);
-    double g1 = fma(p, R2 * R, 1.0);
+    return fma(p, R2 * R, 1.0);
+}
+
+__device__ __forceinline__ double g_p3m_f64(double R)
+{
+    double g1 = g_in_f64(R);
     double u = fmax(2.0 - R, 0.0);
     double u2 = u * u;
     double u5 = u2 * u2 * u;
@@ -486,11 +492,18 @@ __device__ __forceinline__ double rsqrt_f64(double x)
 // FP64 path, one wave per group, 64 i-particles per pass.  Each tile of 64 list entries is
 // culled against the group's box as in the FP32 path (a source at least r_cut from the box
 // adds exactly zero) and the survivors are stored relative to x_g (nearest image, once per
-// entry).  When the group's cube and cutoff fit in half the box (half side + r_cut < L/2)
-// the difference of two relative positions is the nearest-image separation and the pairs
-// need no wrap; otherwise the pair wraps it.  (r^2 + eps^2)^(-1/2) and r^(-1) come from
+// entry) in three runs: "inner" sources, whose farthest point of the box is within eta (every
+// pair has R < 1: eq. (2)'s first branch only), from the front of the tile; "far" ones, at
+// least eta from the box (every pair has R >= 1: the second branch only), from the back; the
+// others ("near", both branches and a select) in between.  The FP64 pair evaluates both
+// branches of g for a near source, so the inner run saves the second branch and the select.
+// When the group's cube and cutoff fit in half the box (half side + r_cut < L/2) the
+// difference of two relative positions is the nearest-image separation and the pairs need no
+// wrap; otherwise the pair wraps it.  (r^2 + eps^2)^(-1/2) and r^(-1) come from
 // rsqrt_f64 (r = r^2 r^(-1)); a pair at zero separation adds nothing.
 constexpr int kTileF64 = 64;
+
+enum F64Kind { kF64Near = 0, kF64Far = 1, kF64Inner = 2 };
 
 template <int OUT64>
 __global__ __launch_bounds__(64) void k_force_f64(
@@ -525,36 +538,40 @@ __global__ __launch_bounds__(64) void k_force_f64(
         }
         double ax_ = 0.0, ay_ = 0.0, az_ = 0.0;
         for (uint64_t jb = 0; jb < Lg; jb += kTileF64) {
-            // survivors: near ones (within eta of the box) from the front of the tile, far ones
-            // (every pair has R >= 1: eq. (2)'s second branch only) from the back
             const uint64_t j = jb + lane;
-            bool keep = false, far = false;
+            bool keep = false, far = false, inner = false;
             double4 v = make_double4(0.0, 0.0, 0.0, 0.0);
             if (j < Lg) {
                 const uint32_t e = entries[b + j];
                 const double4 r = (e & kCellTag) ? nd.nsrc[e & ~kCellTag] : nd.psrc[e];
-                double w0 = fabs(wrapd(r.x - cg0, L)) - hg0;
-                double w1 = fabs(wrapd(r.y - cg1, L)) - hg1;
-                double w2 = fabs(wrapd(r.z - cg2, L)) - hg2;
+                const double a0 = fabs(wrapd(r.x - cg0, L));
+                const double a1 = fabs(wrapd(r.y - cg1, L));
+                const double a2 = fabs(wrapd(r.z - cg2, L));
+                double w0 = a0 - hg0, w1 = a1 - hg1, w2 = a2 - hg2;
                 w0 = w0 > 0.0 ? w0 : 0.0;
                 w1 = w1 > 0.0 ? w1 : 0.0;
                 w2 = w2 > 0.0 ? w2 : 0.0;
                 const double gap2 = w0 * w0 + w1 * w1 + w2 * w2;
+                const double e0 = a0 + hg0, e1 = a1 + hg1, e2 = a2 + hg2;
                 keep = gap2 < fp.rc2;
                 far = gap2 >= eta2;
+                inner = e0 * e0 + e1 * e1 + e2 * e2 < eta2;
                 v = make_double4(wrapd(r.x - xg0, L), wrapd(r.y - xg1, L), wrapd(r.z - xg2, L),
                                  r.w);
             }
-            const uint64_t mn = __ballot(keep && !far), mf = __ballot(keep && far);
+            const uint64_t mi = __ballot(keep && inner), mn = __ballot(keep && !far && !inner),
+                           mf = __ballot(keep && far);
+            const int ni = __popcll(mi), nn = __popcll(mn), nf = __popcll(mf);
             if (keep) {
                 if (far)
                     tile[kTileF64 - 1 - __popcll(mf & lt)] = v;
+                else if (inner)
+                    tile[__popcll(mi & lt)] = v;
                 else
-                    tile[__popcll(mn & lt)] = v;
+                    tile[ni + __popcll(mn & lt)] = v;
             }
-            const int nn = __popcll(mn), nf = __popcll(mf);
             __syncthreads();
-#define TPM_F64_PAIRS(FAR, WRAP, T0, T1)                                                       \
+#define TPM_F64_PAIRS(KIND, WRAP, T0, T1)                                                       \
     for (int t = (T0); t < (T1); ++t) {                                                        \
         const double4 s = tile[t];                                                             \
         double dx = s.x - xi, dy = s.y - yi, dz = s.z - zi;                                    \
@@ -566,18 +583,23 @@ __global__ __launch_bounds__(64) void k_force_f64(
         const double r2 = dx * dx + dy * dy + dz * dz;                                         \
         const double is = rsqrt_f64(r2 + eps2);                                                \
         const double R = r2 * rsqrt_f64(r2) * inv_eta;                                         \
-        double fm = s.w * (FAR ? g_far_f64(R) : g_p3m_f64(R)) * (is * is * is);                \
+        const double g = KIND == kF64Far     ? g_far_f64(R)                                   \
+                         : KIND == kF64Inner ? g_in_f64(R)                                    \
+                                             : g_p3m_f64(R);                                  \
+        double fm = s.w * g * (is * is * is);                                                  \
         fm = r2 > 0.0 ? fm : 0.0;                                                              \
         ax_ += fm * dx;                                                                        \
         ay_ += fm * dy;                                                                        \
         az_ += fm * dz;                                                                        \
     }
             if (pair_wrap) {
-                TPM_F64_PAIRS(false, true, 0, nn)
-                TPM_F64_PAIRS(true, true, kTileF64 - nf, kTileF64)
+                TPM_F64_PAIRS(kF64Inner, true, 0, ni)
+                TPM_F64_PAIRS(kF64Near, true, ni, ni + nn)
+                TPM_F64_PAIRS(kF64Far, true, kTileF64 - nf, kTileF64)
             } else {
-                TPM_F64_PAIRS(false, false, 0, nn)
-                TPM_F64_PAIRS(true, false, kTileF64 - nf, kTileF64)
+                TPM_F64_PAIRS(kF64Inner, false, 0, ni)
+                TPM_F64_PAIRS(kF64Near, false, ni, ni + nn)
+                TPM_F64_PAIRS(kF64Far, false, kTileF64 - nf, kTileF64)
             }
 #undef TPM_F64_PAIRS
             __syncthreads();
