@@ -82,37 +82,30 @@ __global__ __launch_bounds__(256) void k_pm_maxmass(const double4 *__restrict__ 
 
 // One wave takes kAssignChunk consecutive particles in key order, kAssignPer consecutive ones
 // per lane.  A lane sums the 27 contributions of a run of particles with the same nearest mesh
-// point in registers and adds them once.  If the mesh points the chunk's clouds touch fit in an
-// LDS box of kAssignTile words (they lie close together in key order), those adds go to the box
-// and the box is added to the mesh with one global atomic per nonzero point; otherwise (a chunk
-// spread over a large region, or across the periodic seam) they go to the mesh directly.
-// Every sum is a fixed sequence of integer adds, so the mesh is the same on every run.
+// point in registers and adds them once.  The adds go to an LDS box of mesh points, which is
+// then added to the mesh with one global atomic per nonzero point.  The box is chosen per group
+// of lanes: the whole wave's particles if the mesh points their clouds touch fit kAssignTile
+// words; otherwise each half-wave's in a box of kAssignTile / 2 words, then each quarter's and
+// each eighth's, taking for every group the largest one that fits.  A group of 8 << l lanes
+// (level l) owns words [g, g + 1) * (kAssignTile / 8 << l) of the tile, g = lane / (8 << l),
+// so the boxes of one wave never overlap.  An eighth that still does not fit (particles
+// spread over a large region, or across the periodic seam) adds to the mesh directly.  Every
+// sum is a fixed sequence of integer adds, so the mesh is the same on every run.
 constexpr int kAssignThreads = 64;
 constexpr int kAssignPer = 4;
 constexpr int kAssignChunk = kAssignThreads * kAssignPer;
 constexpr int kAssignTile = 4096;
-
-__device__ __forceinline__ int wave_min(int v)
-{
-#pragma unroll
-    for (int d = 32; d > 0; d >>= 1) v = min(v, __shfl_xor(v, d, 64));
-    return v;
-}
-__device__ __forceinline__ int wave_max(int v)
-{
-#pragma unroll
-    for (int d = 32; d > 0; d >>= 1) v = max(v, __shfl_xor(v, d, 64));
-    return v;
-}
+constexpr int kAssignSlot = kAssignTile / 8;  // words owned by eight lanes
 
 __global__ __launch_bounds__(kAssignThreads) void k_pm_assign(
     const double4 *__restrict__ ps, int64_t n, int N, double inv_h,
     const unsigned long long *__restrict__ mx, unsigned long long *__restrict__ mass)
 {
     __shared__ unsigned long long tile[kAssignTile];
+    const int lane = threadIdx.x;
     // neighbouring chunks on one XCD, so their mesh points share its L2
     const int64_t first = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kAssignChunk +
-                          (int64_t)threadIdx.x * kAssignPer;
+                          (int64_t)lane * kAssignPer;
     int lo[3] = {0x7fffffff, 0x7fffffff, 0x7fffffff}, hi[3] = {-0x7fffffff, -0x7fffffff, -0x7fffffff};
 #pragma unroll
     for (int k = 0; k < kAssignPer; ++k) {
@@ -126,20 +119,71 @@ __global__ __launch_bounds__(kAssignThreads) void k_pm_assign(
             }
         }
     }
-    int ox = 0, oy = 0, oz = 0, ey = 0, ez = 0, cells = 0;
+    // Bounding boxes of the lane's groups of 8, 16, 32 and 64 lanes (one butterfly), and the
+    // largest group whose box fits its share of the tile.  All lanes of a group see the same
+    // boxes for it and for every larger group, so they agree on the level.
+    int base = 0, ox = 0, oy = 0, oz = 0, ey = 1, ez = 1, cells = 0;
+    bool local = false;
     {
-        const int l0 = wave_min(lo[0]), l1 = wave_min(lo[1]), l2 = wave_min(lo[2]);
-        const int h0 = wave_max(hi[0]), h1 = wave_max(hi[1]), h2 = wave_max(hi[2]);
-        const int ex = h0 - l0 + 3;
-        ey = h1 - l1 + 3;
-        ez = h2 - l2 + 3;
-        if ((int64_t)ex * ey * ez <= kAssignTile) cells = ex * ey * ez; // wave-uniform
-        ox = l0 - 1;
-        oy = l1 - 1;
-        oz = l2 - 1;
+#pragma unroll
+        for (int d = 1; d < 8; d <<= 1)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                lo[a] = min(lo[a], __shfl_xor(lo[a], d, 64));
+                hi[a] = max(hi[a], __shfl_xor(hi[a], d, 64));
+            }
+        int glo[4][3], ghi[4][3];
+#pragma unroll
+        for (int l = 0; l < 4; ++l) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                glo[l][a] = lo[a];
+                ghi[l][a] = hi[a];
+            }
+            if (l < 3) {
+                const int d = 8 << l;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    lo[a] = min(lo[a], __shfl_xor(lo[a], d, 64));
+                    hi[a] = max(hi[a], __shfl_xor(hi[a], d, 64));
+                }
+            }
+        }
+#pragma unroll
+        for (int l = 3; l >= 0; --l) {
+            if (local) continue;
+            const int cap = kAssignSlot << l;
+            if (glo[l][0] > ghi[l][0]) {  // no particles in this group (ragged tail)
+                local = true;
+                base = (lane >> (3 + l)) * cap;
+                cells = 0;
+                continue;
+            }
+            const int ex = ghi[l][0] - glo[l][0] + 3, fy = ghi[l][1] - glo[l][1] + 3,
+                      fz = ghi[l][2] - glo[l][2] + 3;
+            if ((int64_t)ex * fy * fz <= cap) {
+                local = true;
+                base = (lane >> (3 + l)) * cap;
+                cells = ex * fy * fz;
+                ox = glo[l][0] - 1;
+                oy = glo[l][1] - 1;
+                oz = glo[l][2] - 1;
+                ey = fy;
+                ez = fz;
+            }
+        }
     }
-    const bool local = cells > 0;
-    for (int t = threadIdx.x; t < cells; t += kAssignThreads) tile[t] = 0ull;
+    // Word t of slot q (words q * kAssignSlot ...) belongs to the box of lane 8 q's group: it is
+    // used iff t - base < cells there (base and cells of a direct group are 0).
+#pragma unroll 1
+    for (int q = 0; q < 8; ++q) {
+        const int qb = __shfl(base, 8 * q, 64), qc = __shfl(cells, 8 * q, 64);
+#pragma unroll
+        for (int j = 0; j < kAssignSlot / kAssignThreads; ++j) {
+            const int t = q * kAssignSlot + j * kAssignThreads + lane;
+            if (t - qb < qc) tile[t] = 0ull;
+        }
+    }
     __syncthreads();
     const double S = pm_scale(*mx, n);
     const int mask = N - 1;
@@ -157,7 +201,7 @@ __global__ __launch_bounds__(kAssignThreads) void k_pm_assign(
                 for (int c = 0; c < 3; ++c) {
                     const unsigned long long v = __double2ull_rn(acc[(a * 3 + b) * 3 + c]);
                     if (local)
-                        atomicAdd(&tile[((cx - 1 + a - ox) * ey + (cy - 1 + b - oy)) * ez +
+                        atomicAdd(&tile[base + ((cx - 1 + a - ox) * ey + (cy - 1 + b - oy)) * ez +
                                         (cz - 1 + c - oz)],
                                   v);
                     else
@@ -193,15 +237,24 @@ __global__ __launch_bounds__(kAssignThreads) void k_pm_assign(
         }
     }
     if (open) add_run();
-    if (!local) return;
     __syncthreads();
-    for (int t = threadIdx.x; t < cells; t += kAssignThreads) {
-        const unsigned long long v = tile[t];
-        if (!v) continue;
-        const int lz = t % ez, ly = (t / ez) % ey, lx = t / (ez * ey);
-        atomicAdd(&mass[((size_t)((ox + lx) & mask) * N + ((oy + ly) & mask)) * N +
-                        ((oz + lz) & mask)],
-                  v);
+#pragma unroll 1
+    for (int q = 0; q < 8; ++q) {
+        const int qb = __shfl(base, 8 * q, 64), qc = __shfl(cells, 8 * q, 64);
+        const int qx = __shfl(ox, 8 * q, 64), qy = __shfl(oy, 8 * q, 64),
+                  qz = __shfl(oz, 8 * q, 64), qey = __shfl(ey, 8 * q, 64),
+                  qez = __shfl(ez, 8 * q, 64);
+        for (int j = 0; j < kAssignSlot / kAssignThreads; ++j) {
+            const int t = q * kAssignSlot + j * kAssignThreads + lane;
+            const int u = t - qb;
+            if (u >= qc) continue;
+            const unsigned long long v = tile[t];
+            if (!v) continue;
+            const int lz = u % qez, ly = (u / qez) % qey, lx = u / (qez * qey);
+            atomicAdd(&mass[((size_t)((qx + lx) & mask) * N + ((qy + ly) & mask)) * N +
+                            ((qz + lz) & mask)],
+                      v);
+        }
     }
 }
 
