@@ -93,9 +93,10 @@ constexpr uint32_t kLongRun = 2048;
 bool radix_sort_high(int64_t n, uint64_t *key, uint32_t *idx, uint64_t *key_alt,
                      uint32_t *idx_alt, uint32_t *hist, uint32_t *scan_tmp, uint2 *long_runs,
                      uint32_t long_cap, unsigned *flags, hipStream_t s);
-// Also writes the key-ordered records psrc (x, y, z, m).
+// Writes the key-ordered records psrc (x, y, z, m) and the bit pattern of the largest mass
+// into *mmax (the particle mesh scales its fixed-point sums by it).
 void launch_permute(int64_t n, const uint32_t *idx, const double4 *rec, double4 *psrc,
-                    hipStream_t s);
+                    unsigned long long *mmax, hipStream_t s);
 void launch_root(NodeArrays nd, uint32_t n, double L, hipStream_t s);
 // Level step: nodes [lo, hi) of level `level`; writes nchild, per-node child counts into
 // cnt (hi - lo values) for the scan, and the octant bounds of subdivided nodes into bnd

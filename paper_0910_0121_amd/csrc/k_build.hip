@@ -282,13 +282,34 @@ __global__ __launch_bounds__(256) void k_fix_long_runs(const uint2 *__restrict__
 }
 
 // Gather the (x, y, z, m) records into key order.
+// Records in key order, and the largest mass (its bit pattern: masses are positive, so the
+// patterns order like the values) into *mmax, which the caller has zeroed.  A block adds its
+// maximum only when it exceeds the value already there, so equal masses cost one atomic.
 __global__ __launch_bounds__(256) void k_permute(int64_t n, const uint32_t *__restrict__ idx,
                                                  const double4 *__restrict__ rec,
-                                                 double4 *__restrict__ psrc)
+                                                 double4 *__restrict__ psrc,
+                                                 unsigned long long *mmax)
 {
+    unsigned long long v = 0;
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
-         k += (int64_t)gridDim.x * blockDim.x)
-        psrc[k] = rec[idx[k]];
+         k += (int64_t)gridDim.x * blockDim.x) {
+        const double4 r = rec[idx[k]];
+        psrc[k] = r;
+        const unsigned long long b = (unsigned long long)__double_as_longlong(r.w);
+        v = b > v ? b : v;
+    }
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) {
+        const unsigned long long o = __shfl_xor(v, d, 64);
+        v = o > v ? o : v;
+    }
+    __shared__ unsigned long long wm[4];
+    if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < 4; ++w) v = wm[w] > v ? wm[w] : v;
+        if (v > *(volatile unsigned long long *)mmax) atomicMax(mmax, v);
+    }
 }
 
 // Cube centre of a node from its code: ((i + 0.5) * L / 2^level) per axis.
@@ -689,9 +710,10 @@ void radix_sort(int64_t n, uint64_t *key, uint32_t *idx, uint64_t *key_alt, uint
 }
 
 void launch_permute(int64_t n, const uint32_t *idx, const double4 *rec, double4 *psrc,
-                    hipStream_t s)
+                    unsigned long long *mmax, hipStream_t s)
 {
-    k_permute<<<grid_for(n, 256), 256, 0, s>>>(n, idx, rec, psrc);
+    fill_u64((uint64_t *)mmax, 1, 0ull, s);
+    if (n) k_permute<<<grid_for(n, 256), 256, 0, s>>>(n, idx, rec, psrc, mmax);
 }
 
 void launch_root(NodeArrays nd, uint32_t n, double L, hipStream_t s)

@@ -62,24 +62,6 @@ __device__ __forceinline__ double pm_scale(unsigned long long mmax_bits, int64_t
     return ldexp(1.0, 61 - ilogb(t));
 }
 
-__global__ __launch_bounds__(256) void k_pm_maxmass(const double4 *__restrict__ ps, int64_t n,
-                                                    unsigned long long *mx)
-{
-    unsigned long long v = 0;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        // masses are positive, so their bit patterns order like the values
-        const unsigned long long b = (unsigned long long)__double_as_longlong(ps[i].w);
-        v = b > v ? b : v;
-    }
-#pragma unroll
-    for (int d = 32; d > 0; d >>= 1) {
-        const unsigned long long o = __shfl_xor(v, d, 64);
-        v = o > v ? o : v;
-    }
-    if ((threadIdx.x & 63) == 0) atomicMax(mx, v);
-}
-
 // One wave takes kAssignChunk consecutive particles in key order, kAssignPer consecutive ones
 // per lane.  A lane sums the 27 contributions of a run of particles with the same nearest mesh
 // point in registers and adds them once.  The adds go to an LDS box of mesh points, which is
@@ -610,10 +592,7 @@ void launch_pm_assign(const double4 *ps, int64_t n, int N, double L, unsigned lo
                       unsigned long long *mass, hipStream_t s)
 {
     fill_u64((uint64_t *)mass, (size_t)N * N * N, 0ull, s);
-    fill_u64((uint64_t *)mx, 1, 0ull, s);
     if (!n) return;
-    const int64_t b = (n + 255) / 256;
-    k_pm_maxmass<<<(unsigned)(b < 1024 ? b : 1024), 256, 0, s>>>(ps, n, mx);
     k_pm_assign<<<(unsigned)((n + kAssignChunk - 1) / kAssignChunk), kAssignThreads, 0, s>>>(
         ps, n, N, N / L, mx, mass);
 }

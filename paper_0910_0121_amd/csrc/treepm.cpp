@@ -451,7 +451,12 @@ int do_build(treepm_ctx *c, int64_t n, const double *x, const double *y, const d
                        c->key_alt.as<uint64_t>(), c->idx_alt.as<uint32_t>(),
                        c->hist.as<uint32_t>(), scan_tmp, s);
     }
-    launch_permute(n, c->idx.as<uint32_t>(), c->rec.as<double4>(), c->psrc.as<double4>(), s);
+    {
+        hipError_t e = reserve(c->pm_mx, 8);
+        if (e != hipSuccess) return hip_fail(c, e, "largest-mass word");
+    }
+    launch_permute(n, c->idx.as<uint32_t>(), c->rec.as<double4>(), c->psrc.as<double4>(),
+                   c->pm_mx.as<unsigned long long>(), s);
     // octree, level by level
     c->n_nodes = 0;
     if ((rc = ensure_nodes(c, std::max<size_t>(1024, N / 2 + 64), s))) return rc;
@@ -975,7 +980,6 @@ TREEPM_API int treepm_force_long(treepm_ctx *c, void *ax, void *ay, void *az, in
         if (e == hipSuccess) e = reserve(c->pm_f, pts * 16);
         if (e == hipSuccess) e = reserve(c->pm_green, H * H * H * 4);
         if (e == hipSuccess) e = reserve(c->pm_tw, (size_t)N / 2 * 8);
-        if (e == hipSuccess) e = reserve(c->pm_mx, 8);
         if (e == hipSuccess) e = reserve(c->pm_stage, (size_t)c->n * 16);
         if (e == hipSuccess && !c->inv_valid) e = reserve(c->inv, (size_t)c->n * 4);
         if (e != hipSuccess) return hip_fail(c, e, "PM meshes");
