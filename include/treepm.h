@@ -172,7 +172,7 @@ int treepm_force_short(treepm_ctx *ctx, void *ax, void *ay, void *az, int out_pr
  * out_prec (TREEPM_FP32 = float, TREEPM_FP64 = double) of kind mem_kind; accumulate = 1 adds
  * to the values the arrays hold (so short-range + long-range needs no extra array), 0
  * overwrites them.  Requires a build (ERR_STATE).  Device memory: about 32 N_PM^3 bytes,
- * kept by the context. *
+ * kept by the context. */
 int treepm_force_long(treepm_ctx *ctx, void *ax, void *ay, void *az, int out_prec,
                       int mem_kind, int accumulate, void *hip_stream);
 

@@ -3,6 +3,8 @@ host-side argument checks behave as documented (no GPU needed: no compute call i
 import ctypes as C
 import os
 import re
+import shutil
+import subprocess
 
 import pytest
 
@@ -13,7 +15,7 @@ HEADER = os.path.join(ROOT, "include", "treepm.h")
 def declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(treepm_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(treepm_[a-z0-9_]+)\s*\(", text)))
 
 
 @pytest.fixture(scope="module")
@@ -26,8 +28,30 @@ def native():
 def test_header_declares_the_boundary():
     names = declared_functions()
     for must in ("treepm_create", "treepm_destroy", "treepm_build", "treepm_walk",
-                 "treepm_force_short", "treepm_export_lists", "treepm_last_error"):
+                 "treepm_force_short", "treepm_force_long", "treepm_export_lists",
+                 "treepm_timestep", "treepm_kick_drift", "treepm_last_error"):
         assert must in names
+
+
+def test_header_compiles_cleanly_as_c_and_cxx(tmp_path):
+    """The header is valid C99 and C++17 with every warning an error (an unclosed comment
+    would hide the declarations after it)."""
+    src = tmp_path / "use_header.c"
+    src.write_text('#include "treepm.h"\nint main(void) { return 0; }\n')
+    for comp, flags in (("gcc", ["-std=c99"]), ("g++", ["-std=c++17", "-x", "c++"])):
+        if shutil.which(comp) is None:
+            pytest.skip(f"{comp} not available")
+        r = subprocess.run([comp, *flags, "-Wall", "-Wextra", "-Werror", "-I",
+                            os.path.dirname(HEADER), "-c", str(src), "-o", os.devnull],
+                           capture_output=True, text=True)
+        assert r.returncode == 0, r.stderr
+
+
+def test_binding_names_only_declared_functions(native):
+    """Every C function the Python binding calls is declared in the header."""
+    declared = set(declared_functions())
+    bound = set(native._native._SIGS)
+    assert bound <= declared, sorted(bound - declared)
 
 
 def test_library_exports_every_declared_symbol(native):
