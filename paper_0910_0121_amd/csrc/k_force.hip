@@ -118,22 +118,45 @@ struct TileCounts {
 // kTileF32 / J + 1 rows once both parts are padded to a multiple of J.
 __device__ __forceinline__ int tile_rows(int J) { return kTileF32 / J + 1; }
 
-__device__ __forceinline__ TileCounts load_tile_f32(float4 *tile,
-                                                    const uint32_t *__restrict__ list,
+constexpr int kTileRounds = kTileF32 / 64;
+
+// The list entries of the tile starting at jb (jb < Lg), one per lane and round.  Slots past
+// the list's end read its last entry and are dropped by load_tile_f32.  The caller issues
+// these reads one tile ahead, so they are in flight while the previous tile is evaluated.
+__device__ __forceinline__ void fetch_entries(const uint32_t *__restrict__ list, uint64_t jb,
+                                              uint64_t Lg, uint32_t *ent)
+{
+    const int lane = threadIdx.x;
+#pragma unroll
+    for (int r = 0; r < kTileRounds; ++r) {
+        const uint64_t j = jb + (uint64_t)(r * 64 + lane);
+        ent[r] = list[j < Lg ? j : Lg - 1];
+    }
+}
+
+__device__ __forceinline__ TileCounts load_tile_f32(float4 *tile, const uint32_t *ent,
                                                     uint64_t jb, uint64_t Lg, int J, int rows,
                                                     NodeArrays nd, const GroupFrame &F)
 {
+    constexpr int kR = kTileRounds;
     const int lane = threadIdx.x;
     const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
     int n_near = 0, n_far = 0;
+    // All source reads are issued before any is used, with no branch between them, so a tile
+    // waits for one memory latency rather than one per round.
+    double4 srcs[kR];
 #pragma unroll
-    for (int r = 0; r < kTileF32 / 64; ++r) {
+    for (int r = 0; r < kR; ++r) {
+        const double4 *base = (ent[r] & kCellTag) ? nd.nsrc : nd.psrc;
+        srcs[r] = base[ent[r] & ~kCellTag];
+    }
+#pragma unroll
+    for (int r = 0; r < kR; ++r) {
         const uint64_t j = jb + (uint64_t)(r * 64 + lane);
         bool keep = false, far = false;
         float4 v;
         if (j < Lg) {
-            const uint32_t ent = list[j];
-            const double4 src = (ent & kCellTag) ? nd.nsrc[ent & ~kCellTag] : nd.psrc[ent];
+            const double4 src = srcs[r];
             const double sx = src.x, sy = src.y, sz = src.z, sm = src.w;
             double w0 = fabs(wrapd(sx - F.cg0, F.L)) - F.hg0;
             double w1 = fabs(wrapd(sy - F.cg1, F.L)) - F.hg1;
@@ -273,6 +296,11 @@ __device__ __forceinline__ void tile_pass(const float4 *ts, int steps, const flo
     }
 }
 
+// Whether the next tile's list entries are read while the current tile is evaluated: only
+// where the four extra registers do not push the class past its register budget (K = 5 and
+// K = 7 sit at theirs).
+__host__ __device__ constexpr bool force_prefetch(int K) { return K <= 4 || K == 6 || K == 8; }
+
 // One group on one wave in the layout of force_layout (K i-particles per lane, J streams,
 // each stream taking every J-th surviving source); the J partial sums are added at the end
 // in stream order.
@@ -308,10 +336,15 @@ __device__ __forceinline__ void force_group_f32(float4 *tile, double *red, NodeA
             }
             hx[k] = hy[k] = hz[k] = lx[k] = ly[k] = lz[k] = 0.f;
         }
+        uint32_t ent[kTileRounds];
+        if (force_prefetch(K) && Lg) fetch_entries(list, 0, Lg, ent);
         for (uint64_t jb = 0; jb < Lg; jb += kTileF32) {
-            const TileCounts nt = load_tile_f32(tile, list, jb, Lg, J, rows, nd, F);
+            if (!force_prefetch(K)) fetch_entries(list, jb, Lg, ent);
+            const TileCounts nt = load_tile_f32(tile, ent, jb, Lg, J, rows, nd, F);
             kept_total += (uint32_t)(nt.near + nt.far);
             __syncthreads();
+            if (force_prefetch(K) && jb + kTileF32 < Lg)
+                fetch_entries(list, jb + kTileF32, Lg, ent);
             // J is a power of two; the row counts are the same on every lane
             const int sn = (nt.near + J - 1) >> lgJ, sf = (nt.far + J - 1) >> lgJ;
             const float4 *ts = tile + stream * rows;
