@@ -75,6 +75,22 @@ CASES = [
 ]
 
 
+def test_pm_unequal_masses(tp):
+    """Masses spread over more than three decades, the heaviest particle last in the caller's
+    order: the fixed-point scale of the assignment comes from the largest mass, which the
+    build reduces over many blocks while it permutes the records.  A scale taken from the
+    wrong maximum would overflow the 64-bit sums or lose their precision."""
+    _say("pm unequal masses")
+    n = 100003
+    x, y, z, _ = boxgen.nfw_box(n, 200, 7)
+    m = np.exp(boxgen.SplitMix64(8).uniform(n) * np.log(1e3))
+    m[-1] = 5e3
+    m /= m.sum()
+    got = _long(tp, x, y, z, m, 64)
+    ref = pm.pm_force(np.stack([x, y, z], axis=1), m, 1.0, 64, 1.5 / 64)
+    _check(got, ref, "unequal masses")
+
+
 @pytest.mark.parametrize("case", CASES, ids=[f"{c[0]}-n{c[1]}-pm{c[3]}" for c in CASES])
 def test_pm_force_matches_oracle(tp, case):
     kind, n, seed, n_pm = case
