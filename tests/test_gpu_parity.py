@@ -167,6 +167,44 @@ def test_fp32_force_error_vs_fp64_oracle(tp, orc, case):
     run.close()
 
 
+def test_unequal_masses(tp, orc):
+    """Masses over three decades on a clustered box with ragged N: node masses and centres of
+    mass bit-identical, the same lists (the opening criterion measures from the centre of
+    mass), the FP64 force to 1e-13 of the summed magnitudes and the FP32 force within its
+    bound.  Every other parity case has equal masses."""
+    _say("unequal masses")
+    n, r_cut, theta, n_leaf, n_crit = 20011, 3 / 32, 0.5, 10, 64
+    x, y, z, _ = boxgen.nfw_box(n, 50, 12)
+    m = np.exp(boxgen.SplitMix64(13).uniform(n) * np.log(1e3))
+    m /= m.sum()
+    eps = r_cut / 60
+    T = orc.Tree(x, y, z, m, 1.0, r_cut, eps, theta, n_leaf, n_crit)
+    run = Run(tp, x, y, z, m, 1.0, r_cut, eps, theta, n_leaf, n_crit, tp.TREEPM_FP64)
+    gn, on = tp.treepm_export_nodes(run.ctx), T.nodes()
+    go, oo = np.argsort(gn["code"]), np.argsort(on["code"])
+    for k in ("code", "count", "mass", "com"):
+        np.testing.assert_array_equal(gn[k][go], on[k][oo], err_msg=k)
+    goff, gisc, gval = tp.treepm_export_lists(run.ctx)
+    ooff, oisc, oval = T.lists()
+    np.testing.assert_array_equal(np.diff(goff), np.diff(ooff))
+    for g in range(len(ooff) - 1):
+        a = sorted(zip(gisc[goff[g]:goff[g + 1]].tolist(), gval[goff[g]:goff[g + 1]].tolist()))
+        b = sorted(zip(oisc[ooff[g]:ooff[g + 1]].tolist(), oval[ooff[g]:ooff[g + 1]].tolist()))
+        assert a == b, f"group {g}"
+    ref = np.stack(T.force())
+    scale = T.error_scale()
+    err = np.abs(run.acc - ref)
+    assert np.all(err <= 1e-13 * scale[None, :] + 1e-300), float(np.max(err / (scale + 1e-300)))
+    run.close()
+    run = Run(tp, x, y, z, m, 1.0, r_cut, eps, theta, n_leaf, n_crit, tp.TREEPM_FP32,
+              out64=True)
+    B = fp32_error_scale(T, x, y, z, m, eps)
+    d = np.linalg.norm(run.acc - ref, axis=0)
+    _say(f"  fp32 max |da|/(u B) {np.max(d / (2.0 ** -24 * B)):.3f}")
+    assert np.all(d <= 8 * 2.0 ** -24 * B)
+    run.close()
+
+
 def fp32_error_scale(T, x, y, z, m, eps):
     """B_i of the FP32 bound, from the oracle's groups and lists (FP64, numpy)."""
     k, idx = T.sorted()
