@@ -75,7 +75,11 @@ class Run:
 def _box(kind, n, seed):
     if kind == "uniform":
         return boxgen.uniform_box(n, seed)
-    return boxgen.nfw_box(n, max(1, n // 400), seed)
+    x, y, z, m = boxgen.nfw_box(n, max(1, n // 400), seed)
+    if kind == "nfw-masses":  # masses over three decades
+        m = np.exp(boxgen.SplitMix64(seed + 1).uniform(n) * np.log(1e3))
+        m /= m.sum()
+    return x, y, z, m
 
 
 CASES = [
@@ -510,6 +514,7 @@ QUAD_CASES = [
     ("uniform", 32768, 1, 3 / 32, 0.5, 10, 64),
     ("nfw", 40000, 2, 0.06, 0.5, 10, 128),
     ("nfw", 20011, 3, 0.08, 0.8, 4, 37),
+    ("nfw-masses", 20011, 14, 3 / 32, 0.6, 10, 64),  # second moments weighted by mass
 ]
 
 
