@@ -207,14 +207,13 @@ void launch_pm_potential(const unsigned long long *mass, const unsigned long lon
                          const float2 *tw, hipStream_t s);
 // Mesh force (N^3 float4: Fx, Fy, Fz, 0) from phi.
 void launch_pm_force(const float *phi, int N, double L, float4 *f, hipStream_t s);
-// Interpolated force per particle (key-ordered ps) into stage[i] = (ax, ay, az, 0).
+// Interpolated force of key-ordered particle k (ps[k]) into stage[idx[k]] = (ax, ay, az, 0),
+// i.e. in the caller's order (idx is the sort permutation).
 void launch_pm_interp(const double4 *ps, int64_t n, int N, double L, const float4 *f,
-                      float4 *stage, hipStream_t s);
-// inv[idx[k]] = k.
-void launch_invert(const uint32_t *idx, int64_t n, uint32_t *inv, hipStream_t s);
-// ax[o] = stage[inv[o]].x etc. (float or double; accumulate adds).
-void launch_unpermute(const uint32_t *inv, const float4 *stage, int64_t n, void *ax, void *ay,
-                      void *az, int out_fp64, int accumulate, hipStream_t s);
+                      const uint32_t *idx, float4 *stage, hipStream_t s);
+// ax[o] = stage[o].x etc. (float or double; accumulate adds).
+void launch_pm_split(const float4 *stage, int64_t n, void *ax, void *ay, void *az,
+                     int out_fp64, int accumulate, hipStream_t s);
 
 // Quadrupole terms of the cell entries (k_quad.hip).  Q: 6 doubles per node (xx, yy, zz,
 // xy, xz, yz about the centre of mass), filled level by level from the deepest.

@@ -512,13 +512,15 @@ __global__ __launch_bounds__(256) void k_pm_fd(const float *__restrict__ phi, in
         0.0f);
 }
 
-// TSC interpolation of the mesh force to each particle in key order, into stage[i] =
-// (ax, ay, az, 0).  Neighbouring threads hold neighbouring particles, so the 27-point gathers
-// mostly hit the same cache lines; the writes are contiguous (the caller's order is restored
-// by k_unpermute, whose writes are contiguous too).
+// TSC interpolation of the mesh force to each particle, taken in key order, written to
+// stage[idx[i]] = (ax, ay, az, 0), i.e. already in the caller's order.  Neighbouring threads
+// hold neighbouring particles, so the 27-point gathers mostly hit the same cache lines; each
+// thread writes one whole 16-byte record (k_pm_split then writes the three arrays
+// contiguously).
 __global__ __launch_bounds__(256) void k_pm_interp(const double4 *__restrict__ ps, int64_t n,
                                                    int N, double inv_h,
                                                    const float4 *__restrict__ f,
+                                                   const uint32_t *__restrict__ idx,
                                                    float4 *__restrict__ stage)
 {
     const int64_t i = xcd_block(blockIdx.x, gridDim.x) * (int64_t)blockDim.x + threadIdx.x;
@@ -545,27 +547,18 @@ __global__ __launch_bounds__(256) void k_pm_interp(const double4 *__restrict__ p
             }
         }
     }
-    stage[i] = make_float4(sx, sy, sz, 0.0f);
+    stage[idx[i]] = make_float4(sx, sy, sz, 0.0f);
 }
 
-// inv[idx[k]] = k: the key-order position of each particle of the caller's order.
-__global__ __launch_bounds__(256) void k_invert(const uint32_t *__restrict__ idx, int64_t n,
-                                                uint32_t *__restrict__ inv)
-{
-    const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (k < n) inv[idx[k]] = (uint32_t)k;
-}
-
-// Caller's order o reads stage[inv[o]] and writes (or, ACC, adds to) ax[o], ay[o], az[o].
+// The caller's order o: ax[o], ay[o], az[o] = stage[o] (written, or added to with ACC).
 template <typename T, int ACC>
-__global__ __launch_bounds__(256) void k_unpermute(const uint32_t *__restrict__ inv,
-                                                   const float4 *__restrict__ stage, int64_t n,
-                                                   T *__restrict__ ax, T *__restrict__ ay,
-                                                   T *__restrict__ az)
+__global__ __launch_bounds__(256) void k_pm_split(const float4 *__restrict__ stage, int64_t n,
+                                               T *__restrict__ ax, T *__restrict__ ay,
+                                               T *__restrict__ az)
 {
     const int64_t o = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (o >= n) return;
-    const float4 v = stage[inv[o]];
+    const float4 v = stage[o];
     if (ACC) {
         ax[o] += (T)v.x;
         ay[o] += (T)v.y;
@@ -622,37 +615,29 @@ void launch_pm_force(const float *phi, int N, double L, float4 *f, hipStream_t s
 }
 
 void launch_pm_interp(const double4 *ps, int64_t n, int N, double L, const float4 *f,
-                      float4 *stage, hipStream_t s)
+                      const uint32_t *idx, float4 *stage, hipStream_t s)
 {
     if (!n) return;
-    k_pm_interp<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(ps, n, N, N / L, f, stage);
+    k_pm_interp<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(ps, n, N, N / L, f, idx, stage);
 }
 
-void launch_invert(const uint32_t *idx, int64_t n, uint32_t *inv, hipStream_t s)
-{
-    if (!n) return;
-    k_invert<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(idx, n, inv);
-}
-
-void launch_unpermute(const uint32_t *inv, const float4 *stage, int64_t n, void *ax, void *ay,
-                      void *az, int out_fp64, int accumulate, hipStream_t s)
+void launch_pm_split(const float4 *stage, int64_t n, void *ax, void *ay, void *az,
+                     int out_fp64, int accumulate, hipStream_t s)
 {
     if (!n) return;
     const unsigned b = (unsigned)((n + 255) / 256);
     if (out_fp64) {
         if (accumulate)
-            k_unpermute<double, 1><<<b, 256, 0, s>>>(inv, stage, n, (double *)ax, (double *)ay,
-                                                    (double *)az);
+            k_pm_split<double, 1><<<b, 256, 0, s>>>(stage, n, (double *)ax, (double *)ay,
+                                                (double *)az);
         else
-            k_unpermute<double, 0><<<b, 256, 0, s>>>(inv, stage, n, (double *)ax, (double *)ay,
-                                                    (double *)az);
+            k_pm_split<double, 0><<<b, 256, 0, s>>>(stage, n, (double *)ax, (double *)ay,
+                                                (double *)az);
     } else {
         if (accumulate)
-            k_unpermute<float, 1><<<b, 256, 0, s>>>(inv, stage, n, (float *)ax, (float *)ay,
-                                                   (float *)az);
+            k_pm_split<float, 1><<<b, 256, 0, s>>>(stage, n, (float *)ax, (float *)ay, (float *)az);
         else
-            k_unpermute<float, 0><<<b, 256, 0, s>>>(inv, stage, n, (float *)ax, (float *)ay,
-                                                   (float *)az);
+            k_pm_split<float, 0><<<b, 256, 0, s>>>(stage, n, (float *)ax, (float *)ay, (float *)az);
     }
 }
 

@@ -89,10 +89,8 @@ struct treepm_ctx {
     // particle mesh: fixed-point masses (later the potential), the complex work mesh, the
     // force mesh, the Green's table, twiddles, max mass
     Buf pm_mass, pm_grid, pm_f, pm_green, pm_tw, pm_mx;
-    // per particle: key-order results of the mesh force, and the inverse of the sort
-    // permutation (valid for the current build when inv_valid)
-    Buf pm_stage, inv;
-    bool inv_valid = false;
+    // per particle: the mesh force in the caller's order (x, y, z, 0)
+    Buf pm_stage;
     Buf n_q; // per node second moment (6 doubles), quadrupole boxes only
     Buf step_min; // time-step reduction result
     int pm_n = 0; // mesh size, box and eta the table was built for
@@ -393,7 +391,6 @@ int do_build(treepm_ctx *c, int64_t n, const double *x, const double *y, const d
     const treepm_params &P = c->prm;
     int rc;
     size_t N = (size_t)n;
-    c->inv_valid = false; // the sort permutation changes
     // particle-sized buffers
     struct R {
         Buf *b;
@@ -764,7 +761,7 @@ TREEPM_API int treepm_destroy(treepm_ctx *c)
                   &c->g_hi[1], &c->g_hi[2], &c->g_misc, &c->off, &c->glen, &c->wctr, &c->scan64, &c->entries,
                   &c->wstats, &c->overflow, &c->rec, &c->kept, &c->kept_sum, &c->gcells, &c->cls, &c->out[0],
                   &c->out[1], &c->out[2], &c->bnd, &c->runs, &c->pm_mass, &c->pm_grid,
-                  &c->pm_f, &c->pm_green, &c->pm_tw, &c->pm_mx, &c->pm_stage, &c->inv,
+                  &c->pm_f, &c->pm_green, &c->pm_tw, &c->pm_mx, &c->pm_stage,
                   &c->n_q, &c->step_min};
     {
         CallScope scope(c, c->last);
@@ -981,7 +978,6 @@ TREEPM_API int treepm_force_long(treepm_ctx *c, void *ax, void *ay, void *az, in
         if (e == hipSuccess) e = reserve(c->pm_green, H * H * H * 4);
         if (e == hipSuccess) e = reserve(c->pm_tw, (size_t)N / 2 * 8);
         if (e == hipSuccess) e = reserve(c->pm_stage, (size_t)c->n * 16);
-        if (e == hipSuccess && !c->inv_valid) e = reserve(c->inv, (size_t)c->n * 4);
         if (e != hipSuccess) return hip_fail(c, e, "PM meshes");
     }
     const double eta = 0.5 * P.r_cut;
@@ -1012,13 +1008,10 @@ TREEPM_API int treepm_force_long(treepm_ctx *c, void *ax, void *ay, void *az, in
     launch_pm_potential(mass, c->pm_mx.as<unsigned long long>(), c->n, (int)N, grid, phi,
                         c->pm_green.as<float>(), c->pm_tw.as<float2>(), s);
     launch_pm_force(phi, (int)N, P.L, c->pm_f.as<float4>(), s);
-    launch_pm_interp(ps, c->n, (int)N, P.L, c->pm_f.as<float4>(), c->pm_stage.as<float4>(), s);
-    if (!c->inv_valid) {
-        launch_invert(c->idx.as<uint32_t>(), c->n, c->inv.as<uint32_t>(), s);
-        c->inv_valid = true;
-    }
-    launch_unpermute(c->inv.as<uint32_t>(), c->pm_stage.as<float4>(), c->n, dst[0], dst[1],
-                     dst[2], out_prec == TREEPM_FP64, accumulate, s);
+    launch_pm_interp(ps, c->n, (int)N, P.L, c->pm_f.as<float4>(), c->idx.as<uint32_t>(),
+                     c->pm_stage.as<float4>(), s);
+    launch_pm_split(c->pm_stage.as<float4>(), c->n, dst[0], dst[1], dst[2],
+                    out_prec == TREEPM_FP64, accumulate, s);
     HIPCHK(c, hipGetLastError());
     if (mem_kind == TREEPM_HOST) {
         for (int a = 0; a < 3; ++a)
