@@ -122,8 +122,16 @@ def _nfw_radius_units(u: np.ndarray, c: float = 10.0) -> np.ndarray:
 
     Bracketed Newton iteration: the bracket [lo, hi] always holds the root, a Newton step that
     leaves it is replaced by bisection, and an element stops once its step falls below
-    2^-50 of its value (a few FP64 ulps).
+    2^-50 of its value (a few FP64 ulps).  Each element's iteration depends on that element
+    alone, so the variates are solved in cache-sized chunks.
     """
+    out = np.empty_like(u)
+    for s in range(0, u.size, _CHUNK):
+        out[s:s + _CHUNK] = _nfw_radius_chunk(u[s:s + _CHUNK], c)
+    return out
+
+
+def _nfw_radius_chunk(u: np.ndarray, c: float) -> np.ndarray:
     target = u * _nfw_mu(np.float64(c))
     lo = np.zeros_like(u)
     hi = np.full_like(u, c)
@@ -148,6 +156,16 @@ def _nfw_radius_units(u: np.ndarray, c: float = 10.0) -> np.ndarray:
         x[idx] = xn
         idx = idx[~conv]
     return x
+
+
+def _stable_argsort_u64(k: np.ndarray) -> np.ndarray:
+    """The stable argsort of k.  Without repeated values every sort gives the same order, so
+    the faster unstable sort is used and the stable one only if two values are equal."""
+    perm = np.argsort(k)
+    ks = k[perm]
+    if np.any(ks[1:] == ks[:-1]):
+        perm = np.argsort(k, kind="stable")
+    return perm
 
 
 def nfw_box(n: int, n_halos: int, seed: int, f_halo: float = 0.5, L: float = 1.0,
@@ -197,7 +215,7 @@ def nfw_box(n: int, n_halos: int, seed: int, f_halo: float = 0.5, L: float = 1.0
     x = _wrap_unit(np.concatenate([hx, ux]), L)
     y = _wrap_unit(np.concatenate([hy, uy]), L)
     z = _wrap_unit(np.concatenate([hz, uz]), L)
-    perm = np.argsort(rng.next_u64(n), kind="stable")
+    perm = _stable_argsort_u64(rng.next_u64(n))
     m = np.full(n, 1.0 / n)
     return (np.ascontiguousarray(x[perm]), np.ascontiguousarray(y[perm]),
             np.ascontiguousarray(z[perm]), m)

@@ -71,6 +71,8 @@ def lib():
         L.orc_theta_r.argtypes = [_d, _d, _d, _d]
         L.orc_tree_set_opening.restype = C.c_int
         L.orc_tree_set_opening.argtypes = [_p, C.c_int, _d]
+        L.orc_tree_set_theta.restype = C.c_int
+        L.orc_tree_set_theta.argtypes = [_p, _d]
         L.orc_g_p3m_derivs.restype = None
         L.orc_g_p3m_derivs.argtypes = [_d, _p, _p]
         L.orc_cell_acc.restype = None
@@ -184,6 +186,11 @@ class Tree:
     def set_opening(self, opening, theta_max=0.0):
         if lib().orc_tree_set_opening(self.h, int(opening), float(theta_max)) != 0:
             raise ValueError("invalid opening criterion")
+
+    def set_theta(self, theta):
+        """A new opening angle on the same tree and groups (earlier lists are dropped)."""
+        if lib().orc_tree_set_theta(self.h, float(theta)) != 0:
+            raise ValueError("invalid theta")
 
     def close(self):
         if self.h:

@@ -622,6 +622,20 @@ int orc_tree_set_opening(otree *t, int opening, double theta_max)
     return 0;
 }
 
+/* Replace the opening angle theta (theta_0 under the distance-dependent opening); the tree and
+ * groups do not depend on it.  Drops earlier lists.  Returns 0, or -1 for theta outside
+ * [0, 1]. */
+int orc_tree_set_theta(otree *t, double theta)
+{
+    if (!t || !(theta >= 0.0 && theta <= 1.0)) return -1;
+    t->theta = theta;
+    free(t->list_off); free(t->list); free(t->list_is_cell);
+    t->list_off = NULL; t->list = NULL; t->list_is_cell = NULL;
+    t->n_entries = 0;
+    t->walked = 0;
+    return 0;
+}
+
 /* ------------------------------------------------ walk: one interaction list per group */
 
 typedef struct {

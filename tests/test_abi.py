@@ -105,3 +105,21 @@ def test_ensemble_argument_checks_without_gpu(native):
     assert lib.treepm_ensemble_poll(None, 1, None, None, None, None) == -1
     t = C.c_uint64()
     assert lib.treepm_ensemble_submit(None, 0, None, 1, None, None, None, None, C.byref(t)) == -1
+
+
+def test_eps_of_z_equals_the_oracle(native):
+    """treepm_eps_of_z (eq. 6, host arithmetic) equals the oracle's schedule bit for bit on
+    both sides of z_crit, at z_crit itself and far from it; a host call, so no GPU."""
+    from oracle import integrate as it
+    eps_fin, z_crit = 1.0 / 5120.0, 10.0
+    zs = [0.0, 0.5, 1.0, 9.999999, z_crit, 10.000001, 15.0, 30.0, 99.0, 400.0, 1e6]
+    zs += [z_crit * (1 + k * 2.0 ** -52) for k in (-2, -1, 1, 2)]
+    for zc in (z_crit, 0.0, 3.5):
+        for z in zs:
+            got = native.treepm_eps_of_z(z, eps_fin, zc)
+            ref = float(it.eps_of_z(z, eps_fin, zc))
+            assert got == ref, (z, zc, got, ref)
+    # the comoving softening is constant before z_crit, the physical one after
+    assert native.treepm_eps_of_z(30.0, eps_fin, z_crit) * 31.0 == pytest.approx(
+        eps_fin * 11.0, rel=1e-15)
+    assert native.treepm_eps_of_z(3.0, eps_fin, z_crit) == eps_fin

@@ -91,6 +91,17 @@ MUTANTS = [
      TREE + "::test_node_second_moments"),
     ("quad_not_applied", "if (t->quadrupole && isc[q]) pair_quad(",
      "if (0 && isc[q]) pair_quad(", TREE + "::test_quadrupole_tree_force_is_more_accurate"),
+    ("sample_interactions_without_count", "inter += l.n * t->groups[gi].count;",
+     "inter += l.n;", TREE + "::test_walk_force_sample_equals_full_walk_and_force"),
+    ("sample_theta_not_squared",
+     "double rc2 = t->r_cut * t->r_cut, th2 = t->theta * t->theta;\n    double eta = 0.5 * t->r_cut, eps2 = t->eps * t->eps;\n    int64_t inter = 0, parts = 0;",
+     "double rc2 = t->r_cut * t->r_cut, th2 = t->theta;\n    double eta = 0.5 * t->r_cut, eps2 = t->eps * t->eps;\n    int64_t inter = 0, parts = 0;",
+     TREE + "::test_walk_force_sample_equals_full_walk_and_force"),
+    ("sample_scale_without_g", "                        pair_mag(d, mj, eta, eps2, &s, &sn);\n                    }\n                    mag[t->idx[k]] = s;\n                    newt[t->idx[k]] = sn;\n                }\n            }",
+     "                        pair_mag(d, mj, eta, eps2, &sn, &s);\n                    }\n                    mag[t->idx[k]] = s;\n                    newt[t->idx[k]] = sn;\n                }\n            }",
+     TREE + "::test_walk_force_sample_equals_full_walk_and_force"),
+    ("set_theta_keeps_lists", "    t->theta = theta;\n    free(t->list_off);", "    t->theta = theta;\n    return 0;\n    free(t->list_off);",
+     TREE + "::test_walk_force_sample_equals_full_walk_and_force"),
     ("opening_angle_not_squared", "        th2 = th * th;\n", "        th2 = th;\n",
      TREE + "::test_distance_opening_lists_equal_brute_force_frontier"),
 ]

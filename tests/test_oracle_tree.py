@@ -531,3 +531,48 @@ def test_quadrupole_tree_force_is_more_accurate(orc):
         err[q] = (float(np.sqrt(np.mean(e ** 2))), float(np.quantile(e, 0.99)))
     assert err[True][0] < err[False][0] / 1.8
     assert err[True][1] < err[False][1] / 5.0
+
+
+@pytest.mark.parametrize("opening,quad", [(0, False), (1, False), (0, True)],
+                         ids=["fixed", "distance", "quadrupole"])
+def test_walk_force_sample_equals_full_walk_and_force(orc, opening, quad):
+    """The sampled walk + list force (the reference of the full-size parity tests and of the
+    CPU baseline) against the whole-box walk, lists and list force: with stride 1 every
+    particle's force and error scales equal the full computation bit for bit and the
+    interaction count equals sum_g n_g L_g; with stride 7 and offset 3 exactly the particles
+    of groups 3, 10, 17, ... are written, each equal to the full result, the others stay
+    untouched, and the count is that of the sampled groups' lists."""
+    x, y, z, m = boxgen.nfw_box(12000, 30, 77)
+    T = orc.Tree(x, y, z, m, 1.0, 0.06, 0.001, 0.5, 10, 40, opening=opening,
+                 theta_max=0.6 if opening else 0.0, quadrupole=quad)
+    full = np.stack(T.force(nthreads=4))
+    mag, newt = T.force_mag(nthreads=4)
+    off, isc, val = T.lists()
+    G = T.groups()
+    lens = np.diff(off)
+    ax, ay, az, inter, parts, ms, ns = T.walk_force_sample(1, 0, 4, scales=True)
+    np.testing.assert_array_equal(np.stack([ax, ay, az]), full)
+    np.testing.assert_array_equal(ms, mag)
+    np.testing.assert_array_equal(ns, newt)
+    assert inter == T.interactions() == int((G["count"] * lens).sum())
+    assert parts == len(x)
+    _, idx = T.sorted()
+    sel = np.arange(3, T.n_groups, 7)
+    want = np.zeros(len(x), dtype=bool)
+    for g in sel:
+        want[idx[G["first"][g]:G["first"][g] + G["count"][g]]] = True
+    ax, ay, az, inter, parts, ms, ns = T.walk_force_sample(7, 3, 4, scales=True)
+    got = np.stack([ax, ay, az])
+    assert np.array_equal(~np.isnan(ax), want)
+    np.testing.assert_array_equal(got[:, want], full[:, want])
+    np.testing.assert_array_equal(ms[want], mag[want])
+    np.testing.assert_array_equal(ns[want], newt[want])
+    assert parts == int(want.sum()) == int(G["count"][sel].sum())
+    assert inter == int((G["count"][sel] * lens[sel]).sum())
+    # a new angle on the same tree gives the lists of a tree built with that angle
+    T.set_theta(0.4)
+    T2 = orc.Tree(x, y, z, m, 1.0, 0.06, 0.001, 0.4, 10, 40, opening=opening,
+                  theta_max=0.6 if opening else 0.0, quadrupole=quad)
+    for a, b in zip(T.lists(), T2.lists()):
+        np.testing.assert_array_equal(a, b)
+    np.testing.assert_array_equal(np.stack(T.force(nthreads=4)), np.stack(T2.force(nthreads=4)))
