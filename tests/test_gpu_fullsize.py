@@ -1,7 +1,8 @@
-"""Parity at the full workload sizes, in the launch configuration the benchmark times.
+"""Parity at the full workload sizes, in the launch configurations the benchmark times.
 
 The 128^3 clustered box (200 NFW halos) and the 256^3 clustered box (2000 halos, the
-benchmark workload) are built, walked and forced on the GPU with n_crit = 256, theta = 0.5.
+benchmark workload) are built, walked and forced on the GPU at theta = 0.5; the 256^3 box at
+each n_crit the benchmark's autotuner chooses from (128, 192, 256), the 128^3 box at 256.
 The oracle cannot redo the whole box in seconds, so it builds the full tree and computes the
 walk and FP64 list force of a stratified sample of groups (every k-th group in key order);
 the GPU's forces on those groups' particles are checked against it:
@@ -26,6 +27,15 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 N_CRIT = 256
+# the benchmark autotunes n_crit over these on the 256^3 box
+BENCH_N_CRITS = (128, 192, 256)
+_BOXES = {}
+
+
+def _config_box(name):
+    if name not in _BOXES:
+        _BOXES[name] = boxgen.config_box(name)
+    return _BOXES[name]
 
 
 def _say(msg):
@@ -42,9 +52,10 @@ def tp():
     return t
 
 
-def _gpu_forces(tp, spec, dev, precision, opening=0, theta_max=0.0, theta=None):
+def _gpu_forces(tp, spec, dev, precision, opening=0, theta_max=0.0, theta=None,
+                n_crit=N_CRIT):
     p = tp.make_params(spec.L, spec.mesh, spec.r_cut, spec.eps,
-                       spec.theta if theta is None else theta, spec.n_leaf, N_CRIT, precision,
+                       spec.theta if theta is None else theta, spec.n_leaf, n_crit, precision,
                        opening=opening, theta_max=theta_max)
     ctx = tp.treepm_create(p, 0)
     try:
@@ -58,16 +69,17 @@ def _gpu_forces(tp, spec, dev, precision, opening=0, theta_max=0.0, theta=None):
         tp.treepm_destroy(ctx)
 
 
-@pytest.mark.parametrize("name,stride", [("nfw128", 40), ("nfw256", 400)])
-def test_full_size_sampled_parity(tp, orc, name, stride):
-    spec, arrays = boxgen.config_box(name)
-    _say(f"{name}: N={spec.n}, n_crit={N_CRIT}, theta={spec.theta}, oracle stride {stride}")
+@pytest.mark.parametrize("name,n_crit,stride",
+                         [("nfw128", N_CRIT, 40)] + [("nfw256", c, 400) for c in BENCH_N_CRITS])
+def test_full_size_sampled_parity(tp, orc, name, n_crit, stride):
+    spec, arrays = _config_box(name)
+    _say(f"{name}: N={spec.n}, n_crit={n_crit}, theta={spec.theta}, oracle stride {stride}")
     dev = [torch.from_numpy(a).cuda() for a in arrays]
-    a64, st64 = _gpu_forces(tp, spec, dev, tp.TREEPM_FP64)
-    a32, st32 = _gpu_forces(tp, spec, dev, tp.TREEPM_FP32)
+    a64, st64 = _gpu_forces(tp, spec, dev, tp.TREEPM_FP64, n_crit=n_crit)
+    a32, st32 = _gpu_forces(tp, spec, dev, tp.TREEPM_FP32, n_crit=n_crit)
     assert st64.interactions == st32.interactions
     x, y, z, m = arrays
-    T = orc.Tree(x, y, z, m, spec.L, spec.r_cut, spec.eps, spec.theta, spec.n_leaf, N_CRIT)
+    T = orc.Tree(x, y, z, m, spec.L, spec.r_cut, spec.eps, spec.theta, spec.n_leaf, n_crit)
     assert T.n_groups == st64.n_groups and T.n_nodes == st64.n_nodes
     ax, ay, az, inter, parts, mag, newt = T.walk_force_sample(stride, 0, 16, scales=True)
     s = ~np.isnan(ax)
@@ -98,7 +110,7 @@ def test_distance_opening_full_size(tp, orc, name, stride):
     """eq. (12) opening at the settings the benchmark times (theta_0 = 0.3, cap 0.5):
     sampled FP64 and FP32 parity as above; on the 128^3 box also the total interaction
     count against the oracle's full walk."""
-    spec, arrays = boxgen.config_box(name)
+    spec, arrays = _config_box(name)
     th0, tmax = 0.3, 0.5
     _say(f"{name} theta(r): theta_0={th0}, cap={tmax}, n_crit={N_CRIT}, stride {stride}")
     dev = [torch.from_numpy(a).cuda() for a in arrays]
@@ -137,7 +149,7 @@ def test_pm_full_size(tp, name):
     16th particle: RMS |da| at most 2e-6 of the RMS |a| and no particle above 5e-5 of it (the
     bar of the small-box PM tests)."""
     from oracle import pm
-    spec, arrays = boxgen.config_box(name)
+    spec, arrays = _config_box(name)
     _say(f"{name}: PM at N_PM={spec.mesh_n}")
     dev = [torch.from_numpy(a).cuda() for a in arrays]
     p = tp.make_params(spec.L, spec.mesh, spec.r_cut, spec.eps, spec.theta, spec.n_leaf,
@@ -169,7 +181,7 @@ def test_quadrupole_full_size(tp, orc):
     """Quadrupole cells on the 256^3 box in the configuration the benchmark times: sampled
     FP64 and FP32 parity against the oracle's sampled walk and list force with the cells'
     second-order terms, to the bars above."""
-    spec, arrays = boxgen.config_box("nfw256")
+    spec, arrays = _config_box("nfw256")
     stride = 400
     _say(f"nfw256 quadrupole: n_crit={N_CRIT}, stride {stride}")
     dev = [torch.from_numpy(a).cuda() for a in arrays]

@@ -615,3 +615,88 @@ def test_quadrupole_tiny_boxes(tp, orc, n):
     finally:
         tp.treepm_destroy(ctx)
     assert np.all(np.abs(got - ref) <= 1e-13 * T.error_scale()[None, :] + 1e-300)
+
+
+def test_sort_fallback_run_over_2048(tp, orc):
+    """More than 2048 particles share one level-13 cell (the same key bits 24-62), which is
+    longer than the in-place sort of runs handles, so the build sorts all key bits instead:
+    the order, the nodes and the FP64 force must still equal the oracle's."""
+    rng = boxgen.SplitMix64(4242)
+    n_bg, n_cl = 3000, 2600
+    bg = rng.uniform(3 * n_bg).reshape(3, n_bg)
+    corner = np.array([1234.0, 4321.0, 777.0]) / 8192.0
+    cl = corner[:, None] + rng.uniform(3 * n_cl).reshape(3, n_cl) * (1.0 / 8192.0)
+    cl[:, 5::7] = cl[:, 4::7][:, : cl[:, 5::7].shape[1]]  # some exactly equal keys too
+    p = np.concatenate([bg, cl], axis=1)
+    perm = np.argsort(rng.next_u64(p.shape[1]), kind="stable")
+    x, y, z = (np.ascontiguousarray(p[a, perm]) for a in range(3))
+    m = np.full(x.size, 1.0 / x.size)
+    T = orc.Tree(x, y, z, m, 1.0, 0.1, 0.002, 0.5, 10, 64)
+    ok, oi = T.sorted()
+    hi = ok >> np.uint64(24)
+    runs = np.diff(np.flatnonzero(np.concatenate([[True], hi[1:] != hi[:-1], [True]])))
+    _say(f"sort fallback: longest run of equal high key bits {runs.max()}")
+    assert runs.max() > 2048  # the case the in-place run sort does not take
+    run = Run(tp, x, y, z, m, 1.0, 0.1, 0.002, 0.5, 10, 64, tp.TREEPM_FP64)
+    gk, gi = tp.treepm_export_sorted(run.ctx)
+    np.testing.assert_array_equal(gk, ok)
+    np.testing.assert_array_equal(gi, oi)
+    gn, on = tp.treepm_export_nodes(run.ctx), T.nodes()
+    go, oo = np.argsort(gn["code"]), np.argsort(on["code"])
+    for k in ("code", "first", "count", "nchild", "mass", "com"):
+        np.testing.assert_array_equal(gn[k][go], on[k][oo], err_msg=k)
+    assert run.stats.interactions == T.interactions()
+    ref = np.stack(T.force())
+    assert np.all(np.abs(run.acc - ref) <= 1e-13 * T.error_scale()[None, :] + 1e-300)
+    run.close()
+
+
+def _check_fp32(run, T, x, y, z, m, eps):
+    ref = np.stack(T.force())
+    B = fp32_error_scale(T, x, y, z, m, eps)
+    d = np.linalg.norm(run.acc - ref, axis=0)
+    nr = np.linalg.norm(ref, axis=0)
+    nz = nr > 0
+    rel = d[nz] / nr[nz]
+    rms = float(np.sqrt(np.mean(rel ** 2)))
+    _say(f"  rms rel {rms:.3e} max rel {rel.max():.3e} "
+         f"max |da|/(u B) {np.max(d / (2.0 ** -24 * B)):.3f}")
+    assert rms <= 1e-6
+    assert np.all(d[~nz] == 0.0)
+    assert np.all(d <= 8 * 2.0 ** -24 * B)
+
+
+def test_fp32_groups_over_512(tp, orc):
+    """n_crit = 600: groups of 513-600 particles take the FP32 kernel's widest layout (one
+    stream, eight particles per lane) in chunks of 512 particles; lists and forces as for
+    every other group."""
+    n, seed, r_cut, n_crit = 60000, 7, 0.06, 600
+    x, y, z, m = boxgen.nfw_box(n, n // 400, seed)
+    eps = r_cut / 60
+    T = orc.Tree(x, y, z, m, 1.0, r_cut, eps, 0.5, 10, n_crit)
+    big = int((T.groups()["count"] > 512).sum())
+    _say(f"fp32 groups over 512: {big} of {T.n_groups} groups")
+    assert big > 10
+    run = Run(tp, x, y, z, m, 1.0, r_cut, eps, 0.5, 10, n_crit, tp.TREEPM_FP32)
+    assert run.stats.interactions == T.interactions()
+    assert run.stats.max_group == int(T.groups()["count"].max())
+    _check_fp32(run, T, x, y, z, m, eps)
+    run.close()
+
+
+def test_fp32_coincident_clump_of_700(tp, orc):
+    """700 particles at one position make a level-21 leaf of 700 (a group above n_crit and
+    above 512): the FP32 kernel runs it in two chunks; pairs at zero separation add
+    nothing."""
+    n = 6000
+    x, y, z, m = boxgen.uniform_box(n, 17)
+    x[100:800] = 0.3125; y[100:800] = 0.6; z[100:800] = 0.9
+    r_cut, eps = 0.1, 0.002
+    T = orc.Tree(x, y, z, m, 1.0, r_cut, eps, 0.5, 10, 64)
+    assert int(T.groups()["count"].max()) == 700
+    _say("fp32 coincident clump of 700")
+    run = Run(tp, x, y, z, m, 1.0, r_cut, eps, 0.5, 10, 64, tp.TREEPM_FP32)
+    assert run.stats.max_group == 700 and run.stats.max_level == 21
+    assert run.stats.interactions == T.interactions()
+    _check_fp32(run, T, x, y, z, m, eps)
+    run.close()
