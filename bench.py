@@ -51,7 +51,9 @@ def parse():
     ap.add_argument("--theta", type=float, default=None, help="override the workload's theta")
     ap.add_argument("--n-crit", type=int, default=0,
                     help="group size limit; 0 = autotune over --n-crit-candidates")
-    ap.add_argument("--n-crit-candidates", default="128,192,256,384,512")
+    ap.add_argument("--n-crit-candidates", default="128,192,256",
+                    help="the n_crit values the autotuner tries (each is parity-tested at full "
+                         "size on the 256^3 box)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--cpu-stride", type=int, default=0,
@@ -69,6 +71,11 @@ def parse():
     ap.add_argument("--no-pm", action="store_true",
                     help="skip the particle-mesh long-range leg")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-accuracy", action="store_true",
+                    help="skip the force-accuracy leg on the 128^3 box")
+    ap.add_argument("--no-scale", action="store_true",
+                    help="skip the 512^3 clustered box at theta 0.5 and 0.4")
+    ap.add_argument("--scale-n-crit", type=int, default=192)
     ap.add_argument("--serving-boxes", type=int, default=64)
     ap.add_argument("--serving-requests-per-box", type=int, default=10)
     ap.add_argument("--serving-inflight", type=int, default=4)
@@ -108,8 +115,22 @@ def run_steps(tp, torch, ctx, dev, acc, k):
     return times, st
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(spec, arrays, n_crit, stride_arg):
-    import numpy as np
+    """The oracle's tree build (one thread) and its walk + FP64 list force on a stratified
+    sample of groups (every k-th group in key order), once on all the host's threads (up to
+    16) and once on one thread, each sample sized for about 15 s of work; the full-box time is
+    extrapolated from the sampled groups' share."""
     import oracle
     x, y, z, m = arrays
     threads = min(16, os.cpu_count() or 1)
@@ -117,33 +138,47 @@ def cpu_baseline(spec, arrays, n_crit, stride_arg):
     T = oracle.Tree(x, y, z, m, spec.L, spec.r_cut, spec.eps, spec.theta, spec.n_leaf, n_crit)
     t_build = time.perf_counter() - t0
     G = T.n_groups
-    stride = stride_arg
-    if stride <= 0:
-        # pilot on a sparse sample, then size the real sample for ~15 s of CPU work
-        pilot = max(1, G // (threads * 16))
+
+    def sized(nthreads, budget_s):
+        # pilot on a sparse sample, then a stride for about budget_s of work
+        pilot = max(1, G // (nthreads * 16))
         t1 = time.perf_counter()
-        _, _, _, inter_p, _ = T.walk_force_sample(pilot, 0, threads)
-        tp = time.perf_counter() - t1
-        groups_p = len(range(0, G, pilot))
-        per_group = tp / max(1, groups_p)
-        want = max(1, int(15.0 / max(per_group, 1e-9)))
-        stride = max(1, G // want)
-    t2 = time.perf_counter()
-    _, _, _, inter, parts = T.walk_force_sample(stride, 0, threads)
-    t_sample = time.perf_counter() - t2
-    n_sampled = len(range(0, G, stride))
-    t_full = t_build + t_sample * (G / n_sampled)
+        T.walk_force_sample(pilot, 0, nthreads)
+        per_group = (time.perf_counter() - t1) / max(1, len(range(0, G, pilot)))
+        return max(1, G // max(1, int(budget_s / max(per_group, 1e-9))))
+
+    out = {}
+    for label, nth in (("all", threads), ("one", 1)):
+        stride = stride_arg if (stride_arg > 0 and label == "all") else sized(nth, 15.0)
+        t2 = time.perf_counter()
+        _, _, _, inter, parts = T.walk_force_sample(stride, 0, nth)
+        t_sample = time.perf_counter() - t2
+        n_sampled = len(range(0, G, stride))
+        out[label] = (stride, n_sampled, parts, inter, t_sample,
+                      t_build + t_sample * (G / n_sampled))
     T.close()
+    stride, n_s, parts, inter, t_s, t_full = out["all"]
+    stride1, n_s1, parts1, inter1, t_s1, t_full1 = out["one"]
+    # per core: the one-thread walk + force rate with the (one-thread) build included
     return {
         "value": spec.n / t_full,
         "unit": "particles/s",
         "cores": threads,
         "kind": "oracle",
+        "cpu_model": cpu_model(),
         "sample": (f"oracle tree build on all {spec.n} particles ({t_build:.1f} s, 1 thread) + "
                    f"walk and FP64 list force for every {stride}th group in key order "
-                   f"({n_sampled} of {G} groups, {parts} particles, {inter} interactions, "
-                   f"{t_sample:.1f} s on {threads} threads), extrapolated by group count"),
-        "interactions_per_s": inter / t_sample,
+                   f"({n_s} of {G} groups, {parts} particles, {inter} interactions, "
+                   f"{t_s:.1f} s on {threads} threads), extrapolated by group count"),
+        "interactions_per_s": inter / t_s,
+        "one_core": {
+            "particles_per_s": spec.n / t_full1,
+            "interactions_per_s": inter1 / t_s1,
+            "sample": (f"the same build + every {stride1}th group ({n_s1} groups, {parts1} "
+                       f"particles, {inter1} interactions, {t_s1:.1f} s on 1 thread), "
+                       f"extrapolated by group count"),
+            "paper_per_core_particles_per_s": 5.0e4,
+        },
     }
 
 
@@ -265,6 +300,110 @@ def serving_bench(tp, n_boxes, per_box, inflight, budget_frac=0.25):
     }
 
 
+def accuracy_bench(tp, torch, np, n_crit):
+    """Force accuracy on the 128^3 clustered box, all computed by the library: the reference is
+    the FP64 path at theta = 0, whose lists hold every particle within r_cut of each group (the
+    exact short-range sum).  For each setting: interactions and the RMS, median and 99th
+    percentile over particles of |a - a_exact| / |a_exact|.  The FP32 path at theta = 0 gives
+    the kernel's own rounding against FP64 on the same lists."""
+    import boxgen
+    spec = boxgen.CONFIGS["nfw128"]
+    arrays = spec.generate()
+    dev = [torch.from_numpy(a).cuda() for a in arrays]
+    log("[bench] accuracy leg (nfw128)")
+
+    def run(prec, theta, opening=0, theta_max=0.0, quad=0):
+        p = tp.make_params(spec.L, spec.mesh, spec.r_cut, spec.eps, theta, spec.n_leaf, n_crit,
+                           prec, opening=opening, theta_max=theta_max, quadrupole=quad)
+        ctx = tp.treepm_create(p, 0)
+        try:
+            tp.treepm_build(ctx, *dev)
+            st = tp.treepm_walk(ctx)
+            acc = [torch.empty(spec.n, dtype=torch.float64, device="cuda") for _ in range(3)]
+            tp.treepm_force_short(ctx, *acc)
+            torch.cuda.synchronize()
+            return torch.stack(acc), int(st.interactions)
+        finally:
+            tp.treepm_destroy(ctx)
+
+    ref, inter0 = run(tp.TREEPM_FP64, 0.0)
+    nr = torch.linalg.norm(ref, dim=0)
+    nz = nr > 0
+
+    def err(a):
+        rel = (torch.linalg.norm(a - ref, dim=0)[nz] / nr[nz]).cpu().numpy()
+        return {"rms": float(np.sqrt(np.mean(rel * rel))), "p50": float(np.median(rel)),
+                "p99": float(np.quantile(rel, 0.99))}
+
+    out = {"workload": f"{spec.name}, n_crit={n_crit}", "exact_interactions": inter0}
+    a, i = run(tp.TREEPM_FP32, 0.0)
+    out["fp32_kernel_theta_0"] = dict(err(a), interactions=i)
+    for name, kw in (("monopole_theta_0.5", dict(theta=0.5)),
+                     ("monopole_theta_0.4", dict(theta=0.4)),
+                     ("quadrupole_theta_0.5", dict(theta=0.5, quad=1)),
+                     ("quadrupole_theta_0.7", dict(theta=0.7, quad=1)),
+                     ("theta_r_0.3_cap_0.5", dict(theta=0.3, opening=1, theta_max=0.5))):
+        a, i = run(tp.TREEPM_FP32, **kw)
+        out[name] = dict(err(a), interactions=i)
+    del dev
+    torch.cuda.empty_cache()
+    return out
+
+
+def scale_bench(tp, torch, np, n_crit, steps=4, warmup=2):
+    """The scale workload: the 512^3 clustered box (10,000 halos holding 70 % of the particles,
+    mesh 512^3, r_cut = 3/512, eps = 1/(20*512)), FP32 path, n_crit fixed (parity-tested at
+    this size), at theta = 0.5 (Table 2's setting) and theta = 0.4.  Step = build + walk +
+    force on the resident box, as in the main leg."""
+    import boxgen
+    spec = boxgen.CONFIGS["nfw512"]
+    log(f"[bench] scale leg: generating {spec.name} (N={spec.n}) ...")
+    t0 = time.time()
+    arrays = spec.generate()
+    log(f"[bench] generated in {time.time() - t0:.1f} s")
+    dev = [torch.from_numpy(a).cuda() for a in arrays]
+    del arrays
+    acc = [torch.empty(spec.n, dtype=torch.float32, device="cuda") for _ in range(3)]
+    out = {"workload": (f"{spec.name}: N={spec.n} clustered box ({spec.n_halos} NFW halos, "
+                        f"{int(spec.f_halo * 100)}% in halos), mesh {spec.mesh_n}^3, "
+                        f"r_cut=3/{spec.mesh_n}, eps=1/(20*{spec.mesh_n}), n_leaf={spec.n_leaf}, "
+                        f"n_crit={n_crit}, FP32; step = build + walk + force"),
+           "n": spec.n, "n_crit": n_crit}
+    for theta in (0.5, 0.4):
+        p = tp.treepm_params(spec.L, spec.mesh, spec.r_cut, spec.eps, theta, spec.n_leaf,
+                             n_crit, tp.TREEPM_FP32)
+        ctx = tp.treepm_create(p, 0)
+        tp.treepm_set_timing(ctx, True)
+        log(f"[bench] scale leg: theta = {theta}")
+        run_steps(tp, torch, ctx, dev, acc, warmup)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        times, st = run_steps(tp, torch, ctx, dev, acc, steps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t1
+        tp.treepm_destroy(ctx)
+        ph = np.array(times)
+        tf = float(np.mean(ph[:, 2])) * 1e-3
+        inter = int(st.interactions)
+        pps = spec.n * steps / el
+        out[f"theta_{theta}"] = {
+            "ms_per_step": el / steps * 1e3,
+            "particles_per_s": pps,
+            "interactions": inter,
+            "interactions_per_particle": inter / spec.n,
+            "interactions_per_s": inter / tf,
+            "evaluated_pairs": int(st.evaluated),
+            "phase_ms": {"build": float(np.mean(ph[:, 0])), "walk": float(np.mean(ph[:, 1])),
+                         "force_f32": float(np.mean(ph[:, 2]))},
+            "groups": int(st.n_groups),
+            "force_roofline_frac": K_PP * inter / tf / 1e12 / FP32_VECTOR_PEAK_TFLOPS,
+            "paper_core_equivalents": pps / 5.0e4,
+        }
+    del dev, acc
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -335,9 +474,12 @@ def main():
     t_force = float(np.mean(ph[:, 2])) * 1e-3
     inter = int(st.interactions)
     evaluated = int(st.evaluated)
-    # The roofline counts the pairs the kernel evaluated: list entries whose source lies at
-    # least r_cut from the group's box add exactly zero and are skipped.
-    achieved = K_PP * evaluated / t_force / 1e12
+    # Achieved FLOP/s in the survey's unit: K_pp flops per list interaction (sum over groups of
+    # n_g L_g, the paper's N_int x N), over the force call's device time.  The kernel skips
+    # the pairs whose source lies at least r_cut from the group's box (they add exactly zero);
+    # the same rate counted on the pairs it evaluated is reported beside it.
+    achieved = K_PP * inter / t_force / 1e12
+    achieved_eval = K_PP * evaluated / t_force / 1e12
     traffic = measured_traffic(n_crit, spec.name)
     result = {
         "metric": METRIC,
@@ -382,7 +524,9 @@ def main():
             "frac": achieved / FP32_VECTOR_PEAK_TFLOPS,
             "traffic": (traffic["fetch_bytes"] + traffic["write_bytes"]) if traffic else None,
             "flops_per_interaction": K_PP,
-            "flops_counted_on": "evaluated pairs",
+            "flops_counted_on": "list interactions (sum over groups of n_g L_g)",
+            "achieved_on_evaluated_pairs": achieved_eval,
+            "frac_on_evaluated_pairs": achieved_eval / FP32_VECTOR_PEAK_TFLOPS,
         },
     }
     if not args.no_fp64:
@@ -400,12 +544,15 @@ def main():
         e64 = time.perf_counter() - t1
         tp.treepm_destroy(ctx)
         f64 = float(np.mean(np.array(times64)[:, 2])) * 1e-3
+        ev64 = int(st64.evaluated)
         result["fp64_path"] = {
             "particles_per_s": spec.n * k64 / e64,
             "interactions_per_s": inter / f64,
             "force_ms": f64 * 1e3,
+            "evaluated_pairs": ev64,
             "achieved_tflops": K_PP * inter / f64 / 1e12,
             "frac_fp64_peak": K_PP * inter / f64 / 1e12 / FP64_VECTOR_PEAK_TFLOPS,
+            "achieved_tflops_on_evaluated_pairs": K_PP * ev64 / f64 / 1e12,
             "force_speedup_fp32_over_fp64": f64 / t_force,
         }
     if not args.no_theta_r:
@@ -530,6 +677,10 @@ def main():
             "content": "build + walk + FP32 short-range + PM long-range + eq. (7) step + "
                        "kick-drift",
         }
+    if not args.no_accuracy:
+        result["accuracy"] = accuracy_bench(tp, torch, np, n_crit)
+    if not args.no_scale:
+        result["scale"] = scale_bench(tp, torch, np, args.scale_n_crit)
     if not args.no_serving:
         log("[bench] ensemble serving")
         result["ensemble"] = serving_bench(tp, args.serving_boxes, args.serving_requests_per_box,

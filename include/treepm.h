@@ -58,7 +58,8 @@ enum { TREEPM_OPEN_FIXED = 0, TREEPM_OPEN_DISTANCE = 1 }; /* opening criterion  
  *   mesh     PM mesh spacing L / N_PM, > 0.
  *   r_cut    cutoff radius, 0 < r_cut <= L/2, and r_cut = 3 mesh to relative 1e-12
  *            (2 eta = r_cut = 3 / N_PM).
- *   eps      Plummer softening, >= 0; the FP32 kernel requires eps > 0.
+ *   eps      Plummer softening, >= 0; the FP32 kernel requires eps >= 2^-12 r_cut / 2
+ *            (its pair law is tabulated per box for eps / eta, eta = r_cut / 2).
  *   theta    opening angle, 0 <= theta <= 1.  A node of side l is used as one source when
  *            l < theta d, d = distance from its centre of mass to the group's bounding box
  *            (minimum image), and its cube does not touch that box.  Under
@@ -113,10 +114,10 @@ typedef struct {
     int32_t max_group;      /* largest group                                              */
     double t_ms[4];         /* device time of build, walk, force, and their sum (ms);
                                0 unless timing is enabled with treepm_set_timing          */
-    int64_t evaluated;      /* pairs the last force call evaluated: the FP32 kernel skips
-                               list entries whose source lies at least r_cut from the
-                               group's bounding box (they add exactly zero); the FP64
-                               kernel evaluates every pair (= interactions)               */
+    int64_t evaluated;      /* pairs the last force call evaluated: both force kernels
+                               skip list entries whose source lies at least r_cut from
+                               the group's bounding box (every pair they form adds
+                               exactly zero), so this is at most interactions            */
     double latency_ms;      /* ensemble results only: completion minus submission (ms)    */
 } treepm_stats;
 
@@ -152,7 +153,11 @@ int treepm_build(treepm_ctx *ctx, int64_t n, const double *x, const double *y, c
 int treepm_walk(treepm_ctx *ctx, void *hip_stream, treepm_stats *stats);
 
 /* Short-range force on every particle from its group's list (eq. 1, 2), written in the
- * caller's original particle order.  ax, ay, az: n values each of type out_prec
+ * caller's original particle order.  TREEPM_FP32 boxes evaluate the pair law
+ * G(s) = g_P3M(sqrt(s)) / (s + (eps/eta)^2)^(3/2), s = (r/eta)^2, from a table of cubic pieces
+ * built on the host for the box (32 per octave of s + c, c a power of two below
+ * (eps/eta)^2 / 64; least-squares fits within about 1.3e-7 of the uncut law), and the pair
+ * arithmetic in FP32 on coordinates relative to the group's cube centre.  ax, ay, az: n values each of type out_prec
  * (TREEPM_FP32 = float, TREEPM_FP64 = double) and kind mem_kind.  Requires a walk
  * (ERR_STATE). */
 int treepm_force_short(treepm_ctx *ctx, void *ax, void *ay, void *az, int out_prec,

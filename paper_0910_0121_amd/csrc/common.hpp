@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <vector>
 
 namespace tpm {
 
@@ -167,25 +168,55 @@ __device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t n)
 
 struct ForceParams {
     double L, eps2, inv_eta, eta, rc2;
-    uint32_t *kept; // FP32 path: per group, list entries that survived the cutoff cull
+    uint32_t *kept; // per group, list entries that survived the cutoff cull
 };
+
+// The FP32 pair law G(s) = g(sqrt(s)) / (s + (eps/eta)^2)^(3/2) (s = r^2 in units of eta^2) as
+// cubic pieces in u = s + c: 2^kTabSegBits pieces per octave of u, located by the bit
+// pattern of u (index = (bits >> kTabShift) - base, position = the low kTabShift bits), from
+// u = c up to u = 4 (R = 2); the last entry is zero and takes every u >= 4.
+constexpr int kTabSegBits = 5;
+constexpr int kTabShift = 23 - kTabSegBits;
+constexpr uint32_t kTabMaxEntries = 1025; // 32 octaves: eps / eta down to 2^-12
+struct ForceTable {
+    const float4 *coef; // entries x (c0, c1, c2, c3), device
+    uint32_t entries;
+    uint32_t base;      // (bit pattern of c) >> kTabShift
+    float c;            // a power of two at most (eps/eta)^2 / 64
+};
+// Fills the table for eps / eta (host, FP64 fit, rounded to float); false if eps / eta is
+// not positive or too small for kTabMaxEntries entries.
+bool build_force_table(double eps_over_eta, std::vector<float4> &coef, uint32_t &base, float &c);
+
 constexpr int kForceClasses = 8; // FP32 force: one class per blocking factor K = 1..8
-// Group ids by blocking class q = K - 1 (K: i-particles per lane of the group's lane layout)
-// into lists[q * stride + ...]; counts[q] (device) receives the class sizes.
-void launch_classify(GroupArrays gr, uint32_t n_groups, uint32_t *lists, uint32_t stride,
-                     uint32_t *counts, hipStream_t s);
+// Layout of the class buffer (u32 words): the class sizes, per class the kXcds + 1 part
+// starts (absolute word positions in the buffer), the per-(class, part) queue counters, the
+// (class, part, cost bucket) cursors, then per class its group ids (stride words apart),
+// each part longest first.
+constexpr uint32_t kClsCounts = 0;
+constexpr uint32_t kClsStarts = kClsCounts + kForceClasses;
+constexpr uint32_t kClsQueue = kClsStarts + kForceClasses * (kXcds + 1);
+constexpr uint32_t kClsBins = kClsQueue + kForceClasses * kXcds;
+constexpr uint32_t kClsLists = kClsBins + kForceClasses * kXcds * 64;
+// Classes, parts and longest-first order of the groups (len: list lengths), into cls.
+void launch_classify(GroupArrays gr, uint32_t n_groups, const uint32_t *len, uint32_t *cls,
+                     uint32_t stride, hipStream_t s);
+// Empties the force queues (a fill kernel): on the call's stream before the class launches
+// fork onto the other streams.
+void launch_force_f32_prep(uint32_t *cls, hipStream_t s);
 // class_counts: host copy of the class sizes.  Classes are launched largest blocking factor
-// first, round-robin over the n_streams streams (the caller forks and joins them).
-void launch_force_f32(NodeArrays nd, GroupArrays gr, const uint32_t *lists, uint32_t stride,
-                      const uint32_t *class_counts, const uint64_t *off, const uint32_t *len,
-                      const uint32_t *entries, const double4 *ps, const uint32_t *pidx,
-                      ForceParams fp, void *ax, void *ay, void *az, int out_prec,
+// first, round-robin over the n_streams streams (the caller forks and joins them); each is a
+// persistent kernel of at most n_cu x (its waves per SIMD) workgroups.
+void launch_force_f32(NodeArrays nd, GroupArrays gr, uint32_t *cls, const uint32_t *class_counts,
+                      const uint64_t *off, const uint32_t *len, const uint32_t *entries,
+                      const double4 *ps, const uint32_t *pidx, ForceParams fp, ForceTable ft,
+                      void *ax, void *ay, void *az, int out_prec, int n_cu,
                       const hipStream_t *streams, int n_streams);
 // FP32 pair routine on explicit positions, pair by pair (xg: host, 3 values).
 void launch_pairwise_f32(int64_t n_i, const double *xi, int64_t n_j, const double *xj,
-                         const double *mj, const double *xg, double eta, double eps,
+                         const double *mj, const double *xg, double eta, ForceTable ft,
                          double *out, hipStream_t s);
-// sum over groups of count * kept (pairs the FP32 kernel evaluated) into *out (device).
+// sum over groups of count * kept (pairs the force kernel evaluated) into *out (device).
 void launch_kept_stats(GroupArrays gr, uint32_t n_groups, const uint32_t *kept,
                        unsigned long long *out, hipStream_t s);
 void launch_force_f64(NodeArrays nd, GroupArrays gr, uint32_t n_groups, const uint64_t *off,

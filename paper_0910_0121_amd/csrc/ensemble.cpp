@@ -28,8 +28,10 @@
 
 #define TREEPM_API extern "C" __attribute__((visibility("default")))
 
-// Device bytes a context currently holds (treepm.cpp).
+// Device bytes a context currently holds, and the parameter checks of treepm_create, without
+// a device (treepm.cpp).
 size_t treepm_internal_ctx_bytes(const treepm_ctx *c);
+int treepm_internal_check_params(const treepm_params *p);
 
 namespace {
 
@@ -358,19 +360,17 @@ TREEPM_API int treepm_ensemble_submit(treepm_ens *e, uint64_t box_id, const tree
                                       int64_t n, const double *x, const double *y,
                                       const double *z, const double *m, uint64_t *ticket)
 {
+    const double t_submit = now_s(); // latency counts from here
     if (!e || !p || !ticket || !x || !y || !z || !m) return TREEPM_ERR_ARG;
     if (n < 1 || n > 0x7fffffffLL) return TREEPM_ERR_ARG;
     if (p->precision != TREEPM_FP32) return TREEPM_ERR_ARG;
-    // parameter validation without a device: create fails on a bad parameter block first
     {
-        treepm_ctx *probe = nullptr;
-        int rc = treepm_create(p, e->device, &probe);
+        const int rc = treepm_internal_check_params(p);
         if (rc) return rc;
-        treepm_destroy(probe);
     }
     if (estimate_bytes(n) > e->budget) return TREEPM_ERR_OOM;
     auto r = std::make_shared<Request>();
-    r->t_submit = now_s();
+    r->t_submit = t_submit;
     r->box_id = box_id;
     r->prm = *p;
     r->n = n;
@@ -381,8 +381,16 @@ TREEPM_API int treepm_ensemble_submit(treepm_ens *e, uint64_t box_id, const tree
     copy_parallel(dst, src, 4, n);
     {
         std::lock_guard<std::mutex> lk(e->mu);
-        if (e->stop) return TREEPM_ERR_STATE;
-        if (e->queue.size() >= e->queue_cap) return TREEPM_ERR_QUEUE_FULL;
+        int rc = TREEPM_OK;
+        if (e->stop)
+            rc = TREEPM_ERR_STATE;
+        else if (e->queue.size() >= e->queue_cap)
+            rc = TREEPM_ERR_QUEUE_FULL;
+        if (rc) { // the pinned block goes back to the pool
+            e->pool.put(r->in, r->in_cap);
+            r->in = nullptr;
+            return rc;
+        }
         r->ticket = e->next_ticket++;
         e->queue.push_back(r);
         e->tickets[r->ticket] = r;

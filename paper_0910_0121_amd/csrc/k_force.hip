@@ -5,21 +5,29 @@
 //
 // One 64-lane wavefront per group: the group's i-particles sit in registers and its list is
 // streamed through LDS in tiles; lanes of one stream read the same tile entry (an LDS
-// broadcast) and accumulate in registers.
+// broadcast) and accumulate in registers.  List entries whose source lies at least r_cut from
+// the group's bounding box are dropped while a tile is loaded (every pair they form adds
+// exactly zero).
 //
 // FP32 path (Section 3.1.1): positions are passed relative to the group's cube centre x_g,
 // x_i - x_g and wrap(x_j - x_g), each difference taken in FP64 and then rounded to FP32, so
-// the rounding error of the subtraction scales with the group size, not the box.  The
-// per-tile FP32 partial sums are folded into an FP32 (hi, lo) pair with TwoSum.
+// the rounding error of the subtraction scales with the group size, not the box.  The pair
+// law is read from a per-box table of cubic pieces (see the FP32 section).  The per-tile FP32
+// partial sums are folded into an FP32 (hi, lo) pair with TwoSum.  Persistent workgroups
+// take the groups from per-XCD queues, longest lists first.
 //
-// FP64 path: plain FP64 on absolute positions with the nearest image per pair, IEEE square
-// root and division.
-//
-// g is evaluated in a form with no cancellation: for R < 1,
+// FP64 path: the same relative coordinates in FP64 (nearest image once per entry, or per pair
+// when the group's cube plus r_cut reaches half the box), (r^2 + eps^2)^(-1/2) and r^(-1)
+// from the hardware estimate refined by two Newton steps, and eq. (2) evaluated directly in a
+// form with no cancellation: for R < 1,
 //   g = 1 + R^3 (-8/5 + R^2 (8/5 + R (-1/2 + R (-12/35 + 3R/20)))),
 // and for R >= 1, g = max(2 - R, 0)^5 (7R^3 + 22R^2 + 10R + 4) / 140 (zero from R = 2 on).
 // Both are eq. (2) rearranged.
 #include "common.hpp"
+
+#include <cmath>
+#include <utility>
+#include <vector>
 
 namespace tpm {
 namespace {
@@ -88,37 +96,39 @@ __device__ __forceinline__ void store3(void *ax, void *ay, void *az, uint32_t i,
     }
 }
 
-// FP32 path.  Lengths are in units of eta (the cutoff scale), so R = |d| and R^2 = |d|^2
-// come for free; the sum is multiplied by 1/eta^2 once per particle:
-//   a_i = (1/eta^2) sum_j m_j d'_ij g(|d'_ij|) / (|d'_ij|^2 + (eps/eta)^2)^(3/2).
+// FP32 path.  Lengths are in units of eta (the cutoff scale), and the pair law is
+//   a_i = (1/eta^2) sum_j m_j d'_ij G(|d'_ij|^2),   G(s) = g(sqrt(s)) / (s + (eps/eta)^2)^(3/2),
+// so the 1/eta^2 is applied once per particle.  G is read from a table of cubic pieces built
+// on the host for the box's eps/eta (build_force_table): the variable u = s + c (c a power of
+// two far below (eps/eta)^2, added inside the fused sum of squares) is cut into 32 pieces per
+// octave by its own bit pattern, so the piece index is the exponent and top five mantissa
+// bits of u and the position inside the piece is the remaining 18 mantissa bits, both exact.
+// u >= 4 (R >= 2) falls on a zero piece.  A pair costs 19 vector instructions and one LDS
+// read and needs no square root, reciprocal square root or branch.
 //
 // One tile takes up to kTileF32 list entries.  Each lane examines kTileF32 / 64 of them and
 // drops those whose source is at least r_cut from the group's bounding box: every pair they
-// would form is at least r_cut apart and adds exactly zero (g = 0 for R >= 2).  Survivors at
-// least eta from the box ("far": every pair has R >= 1, so only the second branch of g
-// applies) are kept apart from the others ("near").  Both kinds are compacted in list order
-// and stored by stream: near survivor e goes to stream e % J, slot e / J, counting up from
-// the start of the stream's run; far survivor e to stream e % J, slot e / J counting down
-// from its end.  Slots past the last survivor of a stream, in either part, are zero-mass
-// padding (they add exactly 0).
+// would form is at least r_cut apart and adds exactly zero (g = 0 for R >= 2).  Survivors are
+// compacted in list order and dealt to the J streams: survivor e goes to stream e % J, row
+// e / J.  Rows past the last survivor of a stream are zero-mass padding (they add exactly 0).
 constexpr int kTileF32 = 256;
+constexpr int kTileRounds = kTileF32 / 64;
+constexpr int kForceWaves = 4; // waves per workgroup; each runs its own groups, sharing the table
 
 struct GroupFrame {
     double xg0, xg1, xg2;   // x_g, origin of the relative coordinates
     double cg0, cg1, cg2;   // bbox centre
     double hg0, hg1, hg2;   // bbox half size
-    double L, rc2, eta2, inv_eta;
+    double L, rc2, inv_eta;
 };
 
-struct TileCounts {
-    int near, far;
-};
-
-// Slots per stream of a tile: n_near + n_far <= kTileF32 survivors need at most
-// kTileF32 / J + 1 rows once both parts are padded to a multiple of J.
-__device__ __forceinline__ int tile_rows(int J) { return kTileF32 / J + 1; }
-
-constexpr int kTileRounds = kTileF32 / 64;
+// The LDS writes of this wave are complete before any of its lanes reads LDS again (the
+// waves of a workgroup work on different groups, so a workgroup barrier is not wanted).
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_s_waitcnt(0xc07f); // lgkmcnt(0); vector memory counters untouched
+    __builtin_amdgcn_wave_barrier();
+}
 
 // The list entries of the tile starting at jb (jb < Lg), one per lane and round.  Slots past
 // the list's end read its last entry and are dropped by load_tile_f32.  The caller issues
@@ -126,7 +136,7 @@ constexpr int kTileRounds = kTileF32 / 64;
 __device__ __forceinline__ void fetch_entries(const uint32_t *__restrict__ list, uint64_t jb,
                                               uint64_t Lg, uint32_t *ent)
 {
-    const int lane = threadIdx.x;
+    const int lane = __lane_id();
 #pragma unroll
     for (int r = 0; r < kTileRounds; ++r) {
         const uint64_t j = jb + (uint64_t)(r * 64 + lane);
@@ -134,14 +144,16 @@ __device__ __forceinline__ void fetch_entries(const uint32_t *__restrict__ list,
     }
 }
 
-__device__ __forceinline__ TileCounts load_tile_f32(float4 *tile, const uint32_t *ent,
-                                                    uint64_t jb, uint64_t Lg, int J, int rows,
-                                                    NodeArrays nd, const GroupFrame &F)
+// Culls and packs one tile; returns the number of survivors (the same on every lane).
+__device__ __forceinline__ int load_tile_f32(float4 *tile, const uint32_t *ent, uint64_t jb,
+                                             uint64_t Lg, int J, int lgJ, NodeArrays nd,
+                                             const GroupFrame &F)
 {
     constexpr int kR = kTileRounds;
-    const int lane = threadIdx.x;
+    const int lane = __lane_id();
+    const int rows = kTileF32 >> lgJ;
     const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
-    int n_near = 0, n_far = 0;
+    int n = 0;
     // All source reads are issued before any is used, with no branch between them, so a tile
     // waits for one memory latency rather than one per round.
     double4 srcs[kR];
@@ -153,7 +165,7 @@ __device__ __forceinline__ TileCounts load_tile_f32(float4 *tile, const uint32_t
 #pragma unroll
     for (int r = 0; r < kR; ++r) {
         const uint64_t j = jb + (uint64_t)(r * 64 + lane);
-        bool keep = false, far = false;
+        bool keep = false;
         float4 v;
         if (j < Lg) {
             const double4 src = srcs[r];
@@ -164,38 +176,23 @@ __device__ __forceinline__ TileCounts load_tile_f32(float4 *tile, const uint32_t
             w0 = w0 > 0.0 ? w0 : 0.0;
             w1 = w1 > 0.0 ? w1 : 0.0;
             w2 = w2 > 0.0 ? w2 : 0.0;
-            const double gap2 = w0 * w0 + w1 * w1 + w2 * w2;
-            keep = gap2 < F.rc2;
-            far = gap2 >= F.eta2;
+            keep = w0 * w0 + w1 * w1 + w2 * w2 < F.rc2;
             v = make_float4((float)(wrapd(sx - F.xg0, F.L) * F.inv_eta),
                             (float)(wrapd(sy - F.xg1, F.L) * F.inv_eta),
                             (float)(wrapd(sz - F.xg2, F.L) * F.inv_eta), (float)sm);
         }
-        const uint64_t mn = __ballot(keep && !far);
-        const uint64_t mf = __ballot(keep && far);
+        const uint64_t mk = __ballot(keep);
         if (keep) {
-            if (far) {
-                const int e = n_far + (int)__popcll(mf & lt);
-                tile[(e % J) * rows + rows - 1 - e / J] = v;
-            } else {
-                const int e = n_near + (int)__popcll(mn & lt);
-                tile[(e % J) * rows + e / J] = v;
-            }
+            const int e = n + (int)__popcll(mk & lt);
+            tile[(e & (J - 1)) * rows + (e >> lgJ)] = v;
         }
-        n_near += (int)__popcll(mn);
-        n_far += (int)__popcll(mf);
+        n += (int)__popcll(mk);
     }
-    // zero the padding slots of the last row of each part
-    const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
-    const int en = n_near + lane;
-    if (lane < J && en < (n_near + J - 1) / J * J) tile[(en % J) * rows + en / J] = zero;
-    const int ef = n_far + lane - 32;
-    if (lane >= 32 && lane < 32 + J && ef < (n_far + J - 1) / J * J)
-        tile[(ef % J) * rows + rows - 1 - ef / J] = zero;
-    TileCounts c;
-    c.near = __builtin_amdgcn_readfirstlane(n_near);
-    c.far = __builtin_amdgcn_readfirstlane(n_far);
-    return c;
+    // zero the padding slots of the last row
+    const int e = n + lane;
+    if (lane < J && e < ((n + J - 1) >> lgJ) << lgJ)
+        tile[(e & (J - 1)) * rows + (e >> lgJ)] = make_float4(0.f, 0.f, 0.f, 0.f);
+    return __builtin_amdgcn_readfirstlane(n);
 }
 
 // Lane layout of a group of n_g particles on one wave: J streams of S = 64 / J lanes, each
@@ -222,52 +219,39 @@ __host__ __device__ __forceinline__ void force_layout(uint32_t n_g, int &J, int 
     }
 }
 
-// Second branch of g (R >= 1, zero from R = 2 on) with u = clamp(1 - R/2, 0, 1), which is
-// (2 - R)/2 exactly on [1, 2]:  (2 - R)^5 (7R^3 + 22R^2 + 10R + 4) / 140
-//   = u^5 (1.6 R^3 + (704/140) R^2 + (320/140) R + 128/140).
-// The factor 32 moved into the coefficients is a power of two, so the value is the same as
-// with (2 - R) itself; the clamp is a modifier of the fma, not an instruction of its own.
-__device__ __forceinline__ float g_far_f32(float R)
-{
-    const float u = fminf(fmaxf(fmaf(R, -0.5f, 1.0f), 0.0f), 1.0f);
-    const float u2 = u * u;
-    const float u5 = u2 * u2 * u;
-    const float c =
-        fmaf(fmaf(fmaf(1.6f, R, 704.0f / 140.0f), R, 320.0f / 140.0f), R, 128.0f / 140.0f);
-    return u5 * c;
-}
+struct TabView {
+    const float4 *t; // the table in LDS
+    uint32_t base;   // bit pattern of c >> kTabShift
+    uint32_t last;   // base + index of the zero piece
+    float c;
+    float c4;        // 4 + c
+};
 
-// g(R) of eq. (2) rearranged without cancellation; R2 = R * R is passed in.
-__device__ __forceinline__ float g_p3m_f32s(float R, float R2)
-{
-    float p = fmaf(0.15f, R, -12.0f / 35.0f);
-    p = fmaf(p, R, -0.5f);
-    p = fmaf(p, R, 1.6f);
-    p = fmaf(p, R2, -1.6f);
-    const float g1 = fmaf(p, R2 * R, 1.0f);
-    return R < 1.0f ? g1 : g_far_f32(R);
-}
-
-template <bool FAR>
+// One pair from the table: s = (x_j', m_j), lane particle (xi, yi, zi), all in units of eta.
 __device__ __forceinline__ void pair_f32(const float4 s, float xi, float yi, float zi,
-                                         float eps2, float &tx, float &ty, float &tz)
+                                         const TabView &T, float &tx, float &ty, float &tz)
 {
     const float dx = s.x - xi, dy = s.y - yi, dz = s.z - zi;
-    const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-    const float rinv = __builtin_amdgcn_rsqf(r2 + eps2);
-    const float rinv3 = rinv * rinv * rinv;
-    const float R = __builtin_amdgcn_sqrtf(r2);
-    const float g = FAR ? g_far_f32(R) : g_p3m_f32s(R, r2);
-    const float fm = s.w * g * rinv3;
+    const float u = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, T.c)));
+    const uint32_t b = __float_as_uint(u);
+    const uint32_t k = min(b >> kTabShift, T.last) - T.base;
+    const float4 q = T.t[k];
+    // position inside the piece, in [-1/2, 1/2): the low mantissa bits as a float in [1, 2)
+    const float t = __uint_as_float(((b << kTabSegBits) & 0x007fffffu) | 0x3f800000u) - 1.5f;
+    const float H = fmaf(fmaf(fmaf(q.w, t, q.z), t, q.y), t, q.x);
+    // G = (4 - s)^5 H: the factor carries eq. (2)'s fifth-order zero at R = 2, so G keeps its
+    // relative accuracy up to the cutoff; 4 - s = (4 + c) - u is exact for u >= 2
+    const float w = T.c4 - u, w2 = w * w;
+    const float fm = s.w * (w2 * w2 * w) * H;
     tx = fmaf(fm, dx, tx);
     ty = fmaf(fm, dy, ty);
     tz = fmaf(fm, dz, tz);
 }
 
 // steps rows of a stream's tile run, starting at ts, against the lane's K i-particles.
-template <int K, bool FAR>
+template <int K>
 __device__ __forceinline__ void tile_pass(const float4 *ts, int steps, const float *xi,
-                                          const float *yi, const float *zi, float eps2,
+                                          const float *yi, const float *zi, const TabView &T,
                                           float *tx, float *ty, float *tz)
 {
     int t = 0;
@@ -276,50 +260,41 @@ __device__ __forceinline__ void tile_pass(const float4 *ts, int steps, const flo
             const float4 s0 = ts[t], s1 = ts[t + 1];
 #pragma unroll
             for (int k = 0; k < K; ++k) {
-                pair_f32<FAR>(s0, xi[k], yi[k], zi[k], eps2, tx[k], ty[k], tz[k]);
-                pair_f32<FAR>(s1, xi[k], yi[k], zi[k], eps2, tx[k], ty[k], tz[k]);
+                pair_f32(s0, xi[k], yi[k], zi[k], T, tx[k], ty[k], tz[k]);
+                pair_f32(s1, xi[k], yi[k], zi[k], T, tx[k], ty[k], tz[k]);
             }
         }
-    } else {
-        for (; t + 1 < steps; ++t) {
-            const float4 s0 = ts[t];
-#pragma unroll
-            for (int k = 0; k < K; ++k)
-                pair_f32<FAR>(s0, xi[k], yi[k], zi[k], eps2, tx[k], ty[k], tz[k]);
-        }
     }
-    if (t < steps) {
+    for (; t < steps; ++t) {
         const float4 s0 = ts[t];
 #pragma unroll
-        for (int k = 0; k < K; ++k)
-            pair_f32<FAR>(s0, xi[k], yi[k], zi[k], eps2, tx[k], ty[k], tz[k]);
+        for (int k = 0; k < K; ++k) pair_f32(s0, xi[k], yi[k], zi[k], T, tx[k], ty[k], tz[k]);
     }
 }
 
 // Whether the next tile's list entries are read while the current tile is evaluated: only
-// where the four extra registers do not push the class past its register budget (K = 5 and
-// K = 7 sit at theirs).
+// where the four extra registers do not push the class past its register budget.
 __host__ __device__ constexpr bool force_prefetch(int K) { return K <= 4 || K == 6 || K == 8; }
 
 // One group on one wave in the layout of force_layout (K i-particles per lane, J streams,
 // each stream taking every J-th surviving source); the J partial sums are added at the end
-// in stream order.
+// in stream order.  tile: this wave's kTileF32 LDS slots (also used for that reduction).
 template <int K, int OUT64>
-__device__ __forceinline__ void force_group_f32(float4 *tile, double *red, NodeArrays nd,
+__device__ __forceinline__ void force_group_f32(float4 *tile, const TabView &T, NodeArrays nd,
                                                 uint32_t n_g, uint32_t f, const uint32_t *list,
                                                 uint64_t Lg, const double4 *__restrict__ ps,
                                                 const uint32_t *__restrict__ pidx,
-                                                const GroupFrame &F, float eps2, double scale,
-                                                void *ax, void *ay, void *az, uint32_t *kept_out)
+                                                const GroupFrame &F, double scale, void *ax,
+                                                void *ay, void *az, uint32_t *kept_out)
 {
-    const int lane = threadIdx.x;
+    const int lane = __lane_id();
     int J, Kl;
     force_layout(n_g, J, Kl);
-    (void)Kl;  // equals K: the group was classified with the same layout
+    (void)Kl; // equals K: the group was classified with the same layout
     const int S = 64 / J;
     const int lgJ = J == 1 ? 0 : J == 2 ? 1 : J == 4 ? 2 : 3;
     const int slot = lane % S, stream = lane / S;
-    const int rows = tile_rows(J);
+    const int rows = kTileF32 >> lgJ;
     uint32_t kept_total = 0;
     for (uint32_t ib = 0; ib < n_g; ib += (uint32_t)(S * K)) {
         float xi[K], yi[K], zi[K], hx[K], hy[K], hz[K], lx[K], ly[K], lz[K];
@@ -340,20 +315,17 @@ __device__ __forceinline__ void force_group_f32(float4 *tile, double *red, NodeA
         if (force_prefetch(K) && Lg) fetch_entries(list, 0, Lg, ent);
         for (uint64_t jb = 0; jb < Lg; jb += kTileF32) {
             if (!force_prefetch(K)) fetch_entries(list, jb, Lg, ent);
-            const TileCounts nt = load_tile_f32(tile, ent, jb, Lg, J, rows, nd, F);
-            kept_total += (uint32_t)(nt.near + nt.far);
-            __syncthreads();
+            const int nt = load_tile_f32(tile, ent, jb, Lg, J, lgJ, nd, F);
+            kept_total += (uint32_t)nt;
+            wave_lds_sync();
             if (force_prefetch(K) && jb + kTileF32 < Lg)
                 fetch_entries(list, jb + kTileF32, Lg, ent);
-            // J is a power of two; the row counts are the same on every lane
-            const int sn = (nt.near + J - 1) >> lgJ, sf = (nt.far + J - 1) >> lgJ;
-            const float4 *ts = tile + stream * rows;
+            const int steps = (nt + J - 1) >> lgJ; // the same on every lane
             float tx[K], ty[K], tz[K];
 #pragma unroll
             for (int k = 0; k < K; ++k) tx[k] = ty[k] = tz[k] = 0.f;
-            tile_pass<K, false>(ts, sn, xi, yi, zi, eps2, tx, ty, tz);
-            tile_pass<K, true>(ts + rows - sf, sf, xi, yi, zi, eps2, tx, ty, tz);
-            __syncthreads();
+            tile_pass<K>(tile + stream * rows, steps, xi, yi, zi, T, tx, ty, tz);
+            wave_lds_sync();
 #pragma unroll
             for (int k = 0; k < K; ++k) {
                 two_sum_fold(hx[k], lx[k], tx[k]);
@@ -361,6 +333,7 @@ __device__ __forceinline__ void force_group_f32(float4 *tile, double *red, NodeA
                 two_sum_fold(hz[k], lz[k], tz[k]);
             }
         }
+        double *red = reinterpret_cast<double *>(tile); // 64 x 3 doubles fit the tile
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             double vx = (double)hx[k] + (double)lx[k];
@@ -373,7 +346,7 @@ __device__ __forceinline__ void force_group_f32(float4 *tile, double *red, NodeA
                     red[3 * lane + 1] = vy;
                     red[3 * lane + 2] = vz;
                 }
-                __syncthreads();
+                wave_lds_sync();
                 if (stream == 0) {
                     for (int q = 1; q < J; ++q) {
                         const int src = q * S + slot;
@@ -382,48 +355,64 @@ __device__ __forceinline__ void force_group_f32(float4 *tile, double *red, NodeA
                         vz += red[3 * src + 2];
                     }
                 }
-                __syncthreads();
+                wave_lds_sync();
             }
             const uint32_t i = ib + slot + S * k;
             if (stream == 0 && i < n_g)
                 store3<OUT64>(ax, ay, az, pidx[f + i], vx * scale, vy * scale, vz * scale);
         }
     }
-    if (lane == 0) *kept_out = kept_total;
+    *kept_out = kept_total; // the same value on every lane
 }
 
-// One launch per blocking factor K (see k_classify), so each gets its own register budget.
-// Up to K = 4 the kernel fits 128 VGPRs without spilling (4 waves per SIMD); K = 5 runs at
-// 3 waves and larger K at 2.
+// One kernel per blocking factor K, so each gets its own register budget.  Up to K = 4 the
+// kernel fits 128 VGPRs without spilling (4 waves per SIMD); K = 5 runs at 4, 6-7 at 3 and 8
+// at 2.
 constexpr int force_waves_per_simd(int K) { return K <= 5 ? 4 : K <= 7 ? 3 : 2; }
 
+// Persistent: each workgroup copies the table into LDS once and its waves then take groups
+// from the class's queues until all are empty.  The class's groups are split into kXcds
+// parts, each a contiguous range of groups in key order (neighbouring groups share sources),
+// sorted by decreasing cost n_g L_g (the longest lists first, so the last groups to finish
+// are short).  A workgroup starts on the part of its own XCD (workgroups are dealt to the
+// XCDs round-robin by block index) and then takes from the others'.
 template <int K, int OUT64>
-__global__ __launch_bounds__(64, force_waves_per_simd(K)) void k_force_f32(
-    NodeArrays nd, GroupArrays gr, const uint32_t *__restrict__ ids, uint32_t n_ids,
-    const uint64_t *__restrict__ off, const uint32_t *__restrict__ len, const uint32_t *__restrict__ entries,
-    const double4 *__restrict__ ps, const uint32_t *__restrict__ pidx, ForceParams fp, void *ax,
-    void *ay, void *az)
+__global__ __launch_bounds__(64 * kForceWaves, force_waves_per_simd(K)) void k_force_f32(
+    NodeArrays nd, GroupArrays gr, const uint32_t *__restrict__ ids,
+    const uint32_t *__restrict__ part_start, uint32_t *queue, const uint64_t *__restrict__ off,
+    const uint32_t *__restrict__ len, const uint32_t *__restrict__ entries,
+    const double4 *__restrict__ ps, const uint32_t *__restrict__ pidx, ForceParams fp,
+    ForceTable ft, void *ax, void *ay, void *az)
 {
-    __shared__ float4 tile[kTileF32 + 8];
-    __shared__ double red[64 * 3];
-    const uint32_t slot = xcd_block(blockIdx.x, gridDim.x);
-    if (slot >= n_ids) return;
-    const uint32_t g = ids[slot];
-    const uint32_t n_g = gr.count[g], f = gr.first[g];
-    const uint64_t b = off[g];
-    const uint64_t Lg = len[g];
+    extern __shared__ float4 smem[];
+    for (uint32_t i = threadIdx.x; i < ft.entries; i += blockDim.x) smem[i] = ft.coef[i];
+    __syncthreads();
+    const TabView T{smem, ft.base, ft.base + ft.entries - 1, ft.c, 4.0f + ft.c};
+    float4 *tile = smem + ft.entries + (threadIdx.x >> 6) * kTileF32;
+    const uint32_t lane = __lane_id();
     GroupFrame F;
-    F.xg0 = gr.xgx[g]; F.xg1 = gr.xgy[g]; F.xg2 = gr.xgz[g];
-    F.cg0 = gr.cgx[g]; F.cg1 = gr.cgy[g]; F.cg2 = gr.cgz[g];
-    F.hg0 = gr.hgx[g]; F.hg1 = gr.hgy[g]; F.hg2 = gr.hgz[g];
     F.L = fp.L;
     F.rc2 = fp.rc2;
-    F.eta2 = fp.eta * fp.eta;
     F.inv_eta = fp.inv_eta;
-    const float eps2 = (float)(fp.eps2 * fp.inv_eta * fp.inv_eta);
     const double scale = fp.inv_eta * fp.inv_eta;
-    force_group_f32<K, OUT64>(tile, red, nd, n_g, f, entries + b, Lg, ps, pidx, F,
-                              eps2, scale, ax, ay, az, fp.kept + g);
+    const uint32_t xcd = blockIdx.x % kXcds;
+    for (uint32_t p = 0; p < kXcds; ++p) {
+        const uint32_t part = (xcd + p) % kXcds;
+        const uint32_t lo = part_start[part], size = part_start[part + 1] - lo;
+        for (;;) {
+            // One slot per wave: every lane takes part in the atomic (lane 0 adds 1, the others
+            // 0) and the wave reads lane 0's result, so no branch depends on the lane here.
+            const uint32_t q =
+                __builtin_amdgcn_readfirstlane(atomicAdd(&queue[part], lane == 0 ? 1u : 0u));
+            if (q >= size) break;
+            const uint32_t g = ids[lo + q];
+            F.xg0 = gr.xgx[g]; F.xg1 = gr.xgy[g]; F.xg2 = gr.xgz[g];
+            F.cg0 = gr.cgx[g]; F.cg1 = gr.cgy[g]; F.cg2 = gr.cgz[g];
+            F.hg0 = gr.hgx[g]; F.hg1 = gr.hgy[g]; F.hg2 = gr.hgz[g];
+            force_group_f32<K, OUT64>(tile, T, nd, gr.count[g], gr.first[g], entries + off[g],
+                                      len[g], ps, pidx, F, scale, ax, ay, az, fp.kept + g);
+        }
+    }
 }
 
 __global__ __launch_bounds__(256) void k_kept_stats(GroupArrays gr, uint32_t n_groups,
@@ -443,15 +432,16 @@ __global__ __launch_bounds__(256) void k_kept_stats(GroupArrays gr, uint32_t n_g
 }
 
 // Pair by pair: out[(i * n_j + j) * 3 + a] = acceleration at x_i from (x_j, m_j) with the
-// FP32 pair routine of the force kernel (same relative coordinates, units and rounding),
-// without the cull and without periodic images.
+// FP32 pair routine of the force kernel (same relative coordinates, units, table and
+// rounding), without the cull and without periodic images.
 __global__ __launch_bounds__(256) void k_pairwise_f32(int64_t n_i, const double *__restrict__ xi,
                                                       int64_t n_j, const double *__restrict__ xj,
                                                       const double *__restrict__ mj, double xg0,
                                                       double xg1, double xg2, double inv_eta,
-                                                      float eps2, double scale,
+                                                      ForceTable ft, double scale,
                                                       double *__restrict__ out)
 {
+    const TabView T{ft.coef, ft.base, ft.base + ft.entries - 1, ft.c, 4.0f + ft.c};
     const int64_t total = n_i * n_j;
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total;
          q += (int64_t)gridDim.x * blockDim.x) {
@@ -463,52 +453,104 @@ __global__ __launch_bounds__(256) void k_pairwise_f32(int64_t n_i, const double 
                                        (float)((xj[3 * j + 1] - xg1) * inv_eta),
                                        (float)((xj[3 * j + 2] - xg2) * inv_eta), (float)mj[j]);
         float tx = 0.f, ty = 0.f, tz = 0.f;
-        pair_f32<false>(src, x, y, z, eps2, tx, ty, tz);
+        pair_f32(src, x, y, z, T, tx, ty, tz);
         out[3 * q + 0] = (double)tx * scale;
         out[3 * q + 1] = (double)ty * scale;
         out[3 * q + 2] = (double)tz * scale;
     }
 }
 
-constexpr int kClasses = 8;
-
-// Blocking class of a group: K - 1 with K the particles per lane of force_layout.  A block
-// takes kClassifyItems * 256 consecutive groups, places them with LDS atomics and reserves
-// its part of each class list with one global atomic per class; the order inside a list
-// does not affect results.
+// Classes and queues of the FP32 force.  Group g belongs to class q = K - 1 (K of its lane
+// layout), to XCD part p = floor(8 g / G) (contiguous key ranges) and to a cost bucket of
+// n_g L_g on a half-octave scale; the bins (q, p, bucket) are laid out with the costliest
+// bucket first, so each part of each class lists its groups longest first.  Three passes:
+// count the bins, scan them into cursors and part starts, scatter.  Blocks take
+// kClassifyItems * 256 consecutive groups and aggregate their bins in LDS first.
 constexpr int kClassifyItems = 8;
+constexpr int kCostBuckets = 64;
+constexpr int kBins = kForceClasses * kXcds * kCostBuckets;
 
-__global__ __launch_bounds__(256) void k_classify(GroupArrays gr, uint32_t n_groups,
-                                                  uint32_t *__restrict__ lists, uint32_t stride,
-                                                  uint32_t *counts)
+__device__ __forceinline__ uint32_t cost_bin(uint32_t g, uint32_t n_groups, uint32_t n_g,
+                                             uint32_t L_g)
 {
-    __shared__ uint32_t s_cnt[kClasses], s_base[kClasses];
-    if (threadIdx.x < kClasses) s_cnt[threadIdx.x] = 0;
+    int J, K;
+    force_layout(n_g, J, K);
+    const uint32_t part = (uint32_t)(((uint64_t)g * kXcds) / n_groups);
+    const uint64_t cost = (uint64_t)n_g * L_g;
+    uint32_t b = 0;
+    if (cost > 1) {
+        const uint32_t lg = 63u - (uint32_t)__clzll((long long)cost);
+        b = 2u * lg + (uint32_t)((cost >> (lg - 1)) & 1u);
+        b = b < kCostBuckets ? b : kCostBuckets - 1;
+    }
+    return ((uint32_t)(K - 1) * kXcds + part) * kCostBuckets + (kCostBuckets - 1 - b);
+}
+
+__global__ __launch_bounds__(256) void k_class_count(GroupArrays gr, uint32_t n_groups,
+                                                     const uint32_t *__restrict__ len,
+                                                     uint32_t *hist)
+{
+    __shared__ uint32_t s_cnt[kBins];
+    for (int i = threadIdx.x; i < kBins; i += 256) s_cnt[i] = 0;
     __syncthreads();
     const uint32_t base = blockIdx.x * (256u * kClassifyItems);
-    int cls[kClassifyItems];
-    uint32_t loc[kClassifyItems];
 #pragma unroll
     for (int r = 0; r < kClassifyItems; ++r) {
         const uint32_t g = base + (uint32_t)r * 256u + threadIdx.x;
-        cls[r] = -1;
-        loc[r] = 0;
+        if (g < n_groups) atomicAdd(&s_cnt[cost_bin(g, n_groups, gr.count[g], len[g])], 1u);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kBins; i += 256)
+        if (s_cnt[i]) atomicAdd(&hist[i], s_cnt[i]);
+}
+
+// One thread per class: bins to cursors (in place), part starts and the class size.
+__global__ void k_class_scan(uint32_t *cls, uint32_t stride)
+{
+    const uint32_t q = threadIdx.x;
+    if (q >= kForceClasses) return;
+    uint32_t *hist = cls + kClsBins + q * kXcds * kCostBuckets;
+    uint32_t *start = cls + kClsStarts + q * (kXcds + 1);
+    const uint32_t origin = kClsLists + q * stride;
+    uint32_t pos = origin;
+    for (int p = 0; p < kXcds; ++p) {
+        start[p] = pos;
+        for (int b = 0; b < kCostBuckets; ++b) {
+            const uint32_t c = hist[p * kCostBuckets + b];
+            hist[p * kCostBuckets + b] = pos;
+            pos += c;
+        }
+    }
+    start[kXcds] = pos;
+    cls[kClsCounts + q] = pos - origin;
+}
+
+__global__ __launch_bounds__(256) void k_class_scatter(GroupArrays gr, uint32_t n_groups,
+                                                       const uint32_t *__restrict__ len,
+                                                       uint32_t *cls)
+{
+    __shared__ uint32_t s_cnt[kBins];
+    for (int i = threadIdx.x; i < kBins; i += 256) s_cnt[i] = 0;
+    __syncthreads();
+    const uint32_t base = blockIdx.x * (256u * kClassifyItems);
+    uint32_t bin[kClassifyItems], loc[kClassifyItems];
+#pragma unroll
+    for (int r = 0; r < kClassifyItems; ++r) {
+        const uint32_t g = base + (uint32_t)r * 256u + threadIdx.x;
+        bin[r] = ~0u;
         if (g < n_groups) {
-            int J, K;
-            force_layout(gr.count[g], J, K);
-            cls[r] = K - 1;
-            loc[r] = atomicAdd(&s_cnt[K - 1], 1u);
+            bin[r] = cost_bin(g, n_groups, gr.count[g], len[g]);
+            loc[r] = atomicAdd(&s_cnt[bin[r]], 1u);
         }
     }
     __syncthreads();
-    if (threadIdx.x < kClasses && s_cnt[threadIdx.x])
-        s_base[threadIdx.x] = atomicAdd(&counts[threadIdx.x], s_cnt[threadIdx.x]);
+    // this block's run of each bin
+    for (int i = threadIdx.x; i < kBins; i += 256)
+        if (s_cnt[i]) s_cnt[i] = atomicAdd(&cls[kClsBins + i], s_cnt[i]);
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < kClassifyItems; ++r)
-        if (cls[r] >= 0)
-            lists[(uint32_t)cls[r] * stride + s_base[cls[r]] + loc[r]] =
-                base + (uint32_t)r * 256u + threadIdx.x;
+        if (bin[r] != ~0u) cls[s_cnt[bin[r]] + loc[r]] = base + (uint32_t)r * 256u + threadIdx.x;
 }
 
 // 1/sqrt(x) in FP64 for x > 0: the hardware estimate refined by two Newton steps
@@ -559,9 +601,11 @@ __global__ __launch_bounds__(64) void k_force_f64(
     const double half_side = 0.5 * ldexp(L, -(int)nd.level[gr.node[g]]);
     const bool pair_wrap = !(half_side + sqrt(fp.rc2) < 0.5 * L);
     const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+    uint32_t kept_total = 0;
     for (uint32_t ib = 0; ib < n_g; ib += 64) {
         const uint32_t i = ib + lane;
         const bool act = i < n_g;
+        kept_total = 0;
         double xi = 0.0, yi = 0.0, zi = 0.0;
         if (act) {
             const double4 r = ps[f + i];
@@ -595,6 +639,7 @@ __global__ __launch_bounds__(64) void k_force_f64(
             const uint64_t mi = __ballot(keep && inner), mn = __ballot(keep && !far && !inner),
                            mf = __ballot(keep && far);
             const int ni = __popcll(mi), nn = __popcll(mn), nf = __popcll(mf);
+            kept_total += (uint32_t)(ni + nn + nf);
             if (keep) {
                 if (far)
                     tile[kTileF64 - 1 - __popcll(mf & lt)] = v;
@@ -639,38 +684,45 @@ __global__ __launch_bounds__(64) void k_force_f64(
         }
         if (act) store3<OUT64>(ax, ay, az, pidx[f + i], ax_, ay_, az_);
     }
+    if (lane == 0) fp.kept[g] = kept_total;
 }
 
 } // namespace
 
-void launch_classify(GroupArrays gr, uint32_t n_groups, uint32_t *lists, uint32_t stride,
-                     uint32_t *counts, hipStream_t s)
+void launch_classify(GroupArrays gr, uint32_t n_groups, const uint32_t *len, uint32_t *cls,
+                     uint32_t stride, hipStream_t s)
 {
-    fill_u32(counts, kClasses, 0u, s);
+    fill_u32(cls, kClsLists, 0u, s);
     if (!n_groups) return;
     const unsigned b = (n_groups + 256u * kClassifyItems - 1) / (256u * kClassifyItems);
-    k_classify<<<b, 256, 0, s>>>(gr, n_groups, lists, stride, counts);
+    k_class_count<<<b, 256, 0, s>>>(gr, n_groups, len, cls + kClsBins);
+    k_class_scan<<<1, 64, 0, s>>>(cls, stride);
+    k_class_scatter<<<b, 256, 0, s>>>(gr, n_groups, len, cls);
 }
 
-void launch_force_f32(NodeArrays nd, GroupArrays gr, const uint32_t *lists, uint32_t stride,
-                      const uint32_t *class_counts, const uint64_t *off, const uint32_t *len,
-                      const uint32_t *entries, const double4 *ps, const uint32_t *pidx,
-                      ForceParams fp, void *ax, void *ay, void *az, int out_prec,
+void launch_force_f32(NodeArrays nd, GroupArrays gr, uint32_t *cls, const uint32_t *class_counts,
+                      const uint64_t *off, const uint32_t *len, const uint32_t *entries,
+                      const double4 *ps, const uint32_t *pidx, ForceParams fp, ForceTable ft,
+                      void *ax, void *ay, void *az, int out_prec, int n_cu,
                       const hipStream_t *streams, int n_streams)
 {
+    const size_t lds = ((size_t)ft.entries + (size_t)kForceWaves * kTileF32) * sizeof(float4);
     int next = 0;
 #define TPM_LAUNCH(KK)                                                                         \
     if (class_counts[KK - 1]) {                                                                \
-        const uint32_t *ids = lists + (size_t)(KK - 1) * stride;                               \
+        const uint32_t *starts = cls + kClsStarts + (KK - 1) * (kXcds + 1);                    \
+        uint32_t *queue = cls + kClsQueue + (KK - 1) * kXcds;                                  \
+        const uint32_t waves = class_counts[KK - 1];                                           \
+        const uint32_t cap = (uint32_t)n_cu * (uint32_t)force_waves_per_simd(KK);              \
+        const uint32_t want = (waves + kForceWaves - 1) / kForceWaves;                         \
+        const uint32_t blocks = want < cap ? want : cap;                                       \
         hipStream_t s = streams[next++ % n_streams];                                           \
         if (out_prec)                                                                          \
-            k_force_f32<KK, 1><<<class_counts[KK - 1], 64, 0, s>>>(                            \
-                nd, gr, ids, class_counts[KK - 1], off, len, entries, ps, pidx, fp, ax, \
-                ay, az);                                                                       \
+            k_force_f32<KK, 1><<<blocks, 64 * kForceWaves, lds, s>>>(                          \
+                nd, gr, cls, starts, queue, off, len, entries, ps, pidx, fp, ft, ax, ay, az);  \
         else                                                                                   \
-            k_force_f32<KK, 0><<<class_counts[KK - 1], 64, 0, s>>>(                            \
-                nd, gr, ids, class_counts[KK - 1], off, len, entries, ps, pidx, fp, ax, \
-                ay, az);                                                                       \
+            k_force_f32<KK, 0><<<blocks, 64 * kForceWaves, lds, s>>>(                          \
+                nd, gr, cls, starts, queue, off, len, entries, ps, pidx, fp, ft, ax, ay, az);  \
     }
     TPM_LAUNCH(8)
     TPM_LAUNCH(7)
@@ -683,16 +735,20 @@ void launch_force_f32(NodeArrays nd, GroupArrays gr, const uint32_t *lists, uint
 #undef TPM_LAUNCH
 }
 
+void launch_force_f32_prep(uint32_t *cls, hipStream_t s)
+{
+    fill_u32(cls + kClsQueue, kForceClasses * kXcds, 0u, s);
+}
+
 void launch_pairwise_f32(int64_t n_i, const double *xi, int64_t n_j, const double *xj,
-                         const double *mj, const double *xg, double eta, double eps,
+                         const double *mj, const double *xg, double eta, ForceTable ft,
                          double *out, hipStream_t s)
 {
     const double inv_eta = 1.0 / eta;
     const int64_t total = n_i * n_j;
     int64_t b = (total + 255) / 256;
     k_pairwise_f32<<<(unsigned)(b < 65536 ? (b > 0 ? b : 1) : 65536), 256, 0, s>>>(
-        n_i, xi, n_j, xj, mj, xg[0], xg[1], xg[2], inv_eta, (float)(eps * eps * inv_eta * inv_eta),
-        inv_eta * inv_eta, out);
+        n_i, xi, n_j, xj, mj, xg[0], xg[1], xg[2], inv_eta, ft, inv_eta * inv_eta, out);
 }
 
 void launch_kept_stats(GroupArrays gr, uint32_t n_groups, const uint32_t *kept,
@@ -716,6 +772,92 @@ void launch_force_f64(NodeArrays nd, GroupArrays gr, uint32_t n_groups, const ui
     else
         k_force_f64<0><<<n_groups, 64, 0, s>>>(nd, gr, n_groups, off, len, entries, ps, pidx, fp,
                                               ax, ay, az);
+}
+
+// ------------------------------------------------------------------ the pair-law table
+namespace {
+
+// H(s) = g(R) / ((s + e2)^(3/2) (4 - s)^5), R = sqrt(s) < 2, in double precision.  On eq. (2)'s
+// first branch g is evaluated in the form without cancellation the FP64 kernel uses; on the
+// second, g = (2 - R)^5 (7R^3 + 22R^2 + 10R + 4) / 140 and 4 - s = (2 - R)(2 + R), so the
+// fifth powers cancel exactly.
+double h_host(double s, double e2)
+{
+    const double R = std::sqrt(s), uncut = std::pow(s + e2, -1.5);
+    if (R < 1.0) {
+        const double R2 = R * R;
+        const double g =
+            1.0 + R2 * R * (-1.6 + R2 * (1.6 + R * (-0.5 + R * (-12.0 / 35.0 + 0.15 * R))));
+        return g * uncut / std::pow(4.0 - s, 5);
+    }
+    return (((7.0 * R + 22.0) * R + 10.0) * R + 4.0) / (140.0 * std::pow(2.0 + R, 5)) * uncut;
+}
+
+// Solves the 4 x 4 system M x = r (symmetric positive definite) by Gaussian elimination with
+// partial pivoting.
+void solve4(double M[4][4], double r[4], double x[4])
+{
+    for (int c = 0; c < 4; ++c) {
+        int piv = c;
+        for (int i = c + 1; i < 4; ++i)
+            if (std::fabs(M[i][c]) > std::fabs(M[piv][c])) piv = i;
+        for (int j = 0; j < 4; ++j) std::swap(M[c][j], M[piv][j]);
+        std::swap(r[c], r[piv]);
+        for (int i = c + 1; i < 4; ++i) {
+            const double f = M[i][c] / M[c][c];
+            for (int j = c; j < 4; ++j) M[i][j] -= f * M[c][j];
+            r[i] -= f * r[c];
+        }
+    }
+    for (int c = 3; c >= 0; --c) {
+        double v = r[c];
+        for (int j = c + 1; j < 4; ++j) v -= M[c][j] * x[j];
+        x[c] = v / M[c][c];
+    }
+}
+
+} // namespace
+
+bool build_force_table(double eps_over_eta, std::vector<float4> &coef, uint32_t &base, float &c)
+{
+    const double e2 = eps_over_eta * eps_over_eta;
+    if (!(e2 > 0.0) || !std::isfinite(e2)) return false;
+    // c: a power of two at most e2 / 64, so the pieces near s = 0 are narrow next to eps^2
+    const int kc = (int)std::floor(std::log2(e2)) - 6;
+    const int n_oct = 2 - kc; // u in [2^kc, 4)
+    const uint32_t pieces = (uint32_t)n_oct << kTabSegBits;
+    if (n_oct < 1 || pieces + 1 > kTabMaxEntries) return false;
+    const double cd = std::ldexp(1.0, kc);
+    c = (float)cd;
+    base = (uint32_t)(127 + kc) << kTabSegBits;
+    coef.assign(pieces + 1, make_float4(0.f, 0.f, 0.f, 0.f));
+    // Each piece: the cubic in t in [-1/2, 1/2) closest, in the relative least-squares sense
+    // at 16 Chebyshev nodes, to H(s) = G(s) / (4 - s)^5.  H is smooth and positive on
+    // [0, 4] (eq. 2's second branch is (2 - R)^5 times a polynomial, and (4 - s) =
+    // (2 - R)(2 + R)), so G = (4 - s)^5 H keeps its relative accuracy up to the cutoff.
+    constexpr int kNodes = 16;
+    const double pi = 3.14159265358979323846;
+    const double w_piece = 1.0 / (1 << kTabSegBits);
+    for (uint32_t k = 0; k < pieces; ++k) {
+        const int e = kc + (int)(k >> kTabSegBits);
+        const double lo = std::ldexp(1.0 + (double)(k & ((1u << kTabSegBits) - 1)) * w_piece, e);
+        const double w = std::ldexp(w_piece, e);
+        double M[4][4] = {}, r[4] = {}, x[4];
+        for (int i = 0; i < kNodes; ++i) {
+            const double t = 0.5 * std::cos(pi * (i + 0.5) / kNodes);
+            const double s = lo + (t + 0.5) * w - cd;
+            const double y = h_host(s, e2);
+            const double wt = 1.0 / (y * y);
+            const double v[4] = {1.0, t, t * t, t * t * t};
+            for (int a = 0; a < 4; ++a) {
+                r[a] += wt * v[a] * y;
+                for (int b = 0; b < 4; ++b) M[a][b] += wt * v[a] * v[b];
+            }
+        }
+        solve4(M, r, x);
+        coef[k] = make_float4((float)x[0], (float)x[1], (float)x[2], (float)x[3]);
+    }
+    return true;
 }
 
 } // namespace tpm

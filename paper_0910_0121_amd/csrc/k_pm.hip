@@ -14,10 +14,11 @@
 //    Green's function + z inverse in one kernel (a DIF forward leaves bit-reversed order, which
 //    is what the DIT inverse reads), y inverse, x inverse (writing the real potential);
 //  * mesh force: fourth-order central differences of the potential, one float4 per point;
-//  * interpolation: one thread per particle gathers the 27 points of its cloud (neighbouring
-//    threads hold neighbouring particles, so the gathers share cache lines) into a key-order
-//    stage; a second pass writes it in the caller's order through the inverse permutation,
-//    so no pass writes scattered words.
+//  * interpolation: one thread per particle (key order) gathers the 27 points of its cloud
+//    (neighbouring threads hold neighbouring particles, so the gathers share cache lines) and
+//    writes the 16-byte result to the particle's slot in the caller's order through the sort
+//    permutation (a scattered write); k_pm_split then writes the three output arrays
+//    contiguously.
 #include "common.hpp"
 
 namespace tpm {

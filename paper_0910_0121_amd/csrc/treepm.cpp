@@ -85,7 +85,11 @@ struct treepm_ctx {
     uint32_t mseq = 0;
     uint32_t walk_hint_groups = 0;
     uint64_t st[3] = {0, 0, 0};
-    Buf host_total; // unused placeholder for alignment of future pinned buffers
+    // FP32 pair-law table: device copy, and the eps / eta it was built for (0: none)
+    Buf tab;
+    double tab_key = 0.0;
+    ForceTable ftab{};
+    int n_cu = 256; // compute units of the device (persistent force grids)
     // particle mesh: fixed-point masses (later the potential), the complex work mesh, the
     // force mesh, the Green's table, twiddles, max mass
     Buf pm_mass, pm_grid, pm_f, pm_green, pm_tw, pm_mx;
@@ -202,6 +206,10 @@ int check_params(treepm_ctx *c, const treepm_params *p)
         return fail(c, TREEPM_ERR_ARG, "precision must be TREEPM_FP32 or TREEPM_FP64");
     if (p->precision == TREEPM_FP32 && !(p->eps > 0.0))
         return fail(c, TREEPM_ERR_ARG, "the FP32 kernel requires eps > 0");
+    if (p->precision == TREEPM_FP32 && !(p->eps >= std::ldexp(0.5 * p->r_cut, -12)))
+        return fail(c, TREEPM_ERR_ARG,
+                    "the FP32 kernel's pair-law table needs eps >= 2^-12 r_cut / 2; use "
+                    "TREEPM_FP64");
     return TREEPM_OK;
 }
 
@@ -602,16 +610,16 @@ int do_walk(treepm_ctx *c, hipStream_t s)
         }
     }
     if (!pooled && (rc = two_pass())) return rc;
-    if ((e = reserve(c->cls, (kForceClasses * ((size_t)G + 1) + kForceClasses) * 4)) !=
-        hipSuccess)
+    if ((e = reserve(c->cls, (kClsLists + kForceClasses * ((size_t)G + 1)) * 4)) != hipSuccess)
         return hip_fail(c, e, "group classes");
     uint32_t *cls = c->cls.as<uint32_t>();
     unsigned long long hs[4];
     unsigned hov = 0;
     for (;;) {
         launch_walk_stats(gr, G, len, gcells, ws, s);
-        launch_classify(gr, G, cls + kForceClasses, G + 1, cls, s);
-        if ((rc = fetch(c, s, {&hov, ovf, sizeof hov}, {c->class_counts, cls, sizeof c->class_counts},
+        launch_classify(gr, G, len, cls, G + 1, s);
+        if ((rc = fetch(c, s, {&hov, ovf, sizeof hov},
+                        {c->class_counts, cls + kClsCounts, sizeof c->class_counts},
                         {hs, ws, sizeof hs})))
             return rc;
         if (hov & 3u)
@@ -674,6 +682,10 @@ void retain_pool(int device)
     done[device] = true;
 }
 
+// The parameter checks of treepm_create, without a context or a device (used by the ensemble
+// server to validate a request before queueing it).
+int treepm_internal_check_params(const treepm_params *p) { return check_params(nullptr, p); }
+
 // Device bytes the context holds (used by the ensemble server's HBM accounting).
 size_t treepm_internal_ctx_bytes(const treepm_ctx *c)
 {
@@ -689,7 +701,8 @@ size_t treepm_internal_ctx_bytes(const treepm_ctx *c)
                         &c->g_xg[1], &c->g_xg[2], &c->g_lo[0], &c->g_lo[1], &c->g_lo[2],
                         &c->g_hi[0], &c->g_hi[1], &c->g_hi[2], &c->g_misc, &c->off, &c->glen, &c->wctr, &c->scan64,
                         &c->entries, &c->wstats, &c->overflow, &c->gcells, &c->cls,
-                        &c->kept, &c->kept_sum, &c->out[0], &c->out[1], &c->out[2], &c->bnd, &c->runs};
+                        &c->kept, &c->kept_sum, &c->out[0], &c->out[1], &c->out[2], &c->bnd, &c->runs,
+                        &c->tab};
     size_t t = 0;
     for (const Buf *b : all) t += b->bytes;
     return t;
@@ -715,6 +728,14 @@ TREEPM_API int treepm_create(const treepm_params *params, int device, treepm_ctx
         return TREEPM_ERR_DEVICE;
     }
     retain_pool(device);
+    {
+        int ncu = 0;
+        if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) ==
+                hipSuccess &&
+            ncu > 0)
+            c->n_cu = ncu;
+        (void)hipGetLastError();
+    }
     if (hipStreamCreateWithFlags(&c->own, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&c->freed, hipEventDisableTiming) != hipSuccess) {
         // no private stream: fall back to plain hipMalloc / hipFree
@@ -762,7 +783,7 @@ TREEPM_API int treepm_destroy(treepm_ctx *c)
                   &c->wstats, &c->overflow, &c->rec, &c->kept, &c->kept_sum, &c->gcells, &c->cls, &c->out[0],
                   &c->out[1], &c->out[2], &c->bnd, &c->runs, &c->pm_mass, &c->pm_grid,
                   &c->pm_f, &c->pm_green, &c->pm_tw, &c->pm_mx, &c->pm_stage,
-                  &c->n_q, &c->step_min};
+                  &c->n_q, &c->step_min, &c->tab};
     {
         CallScope scope(c, c->last);
         for (Buf *b : all) release(*b);
@@ -852,10 +873,36 @@ TREEPM_API int treepm_walk(treepm_ctx *c, void *hip_stream, treepm_stats *stats)
     return TREEPM_OK;
 }
 
+namespace {
+
+// The FP32 pair-law table of the context's eps / eta, built on the host and copied to the
+// device once per parameter set.
+int ensure_table(treepm_ctx *c, hipStream_t s)
+{
+    const double key = c->prm.eps / (0.5 * c->prm.r_cut);
+    if (c->tab.p && c->tab_key == key) return TREEPM_OK;
+    std::vector<float4> coef;
+    uint32_t base = 0;
+    float cc = 0.f;
+    if (!build_force_table(key, coef, base, cc))
+        return fail(c, TREEPM_ERR_ARG, "eps / eta = %g is outside the FP32 table's range", key);
+    hipError_t e = reserve(c->tab, coef.size() * sizeof(float4));
+    if (e != hipSuccess) return hip_fail(c, e, "pair-law table");
+    HIPCHK(c, hipMemcpyAsync(c->tab.p, coef.data(), coef.size() * sizeof(float4),
+                             hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipStreamSynchronize(s)); // coef is a host temporary
+    c->ftab = ForceTable{c->tab.as<float4>(), (uint32_t)coef.size(), base, cc};
+    c->tab_key = key;
+    return TREEPM_OK;
+}
+
+} // namespace
+
 TREEPM_API int treepm_force_short(treepm_ctx *c, void *ax, void *ay, void *az, int out_prec,
                                   int mem_kind, void *hip_stream)
 {
     if (!c) return TREEPM_ERR_ARG;
+    int rc;
     if (c->state < 2) return fail(c, TREEPM_ERR_STATE, "treepm_force_short needs a walk");
     c->err.clear();
     if (!ax || !ay || !az) return fail(c, TREEPM_ERR_ARG, "NULL output buffer");
@@ -900,8 +947,10 @@ TREEPM_API int treepm_force_short(treepm_ctx *c, void *ax, void *ay, void *az, i
     ForceParams fp{P.L, P.eps * P.eps, 1.0 / eta, eta, P.r_cut * P.r_cut,
                    c->kept.as<uint32_t>()};
     if (P.precision == TREEPM_FP32) {
+        if ((rc = ensure_table(c, s))) return rc;
         hipStream_t streams[1 + treepm_ctx::kSubStreams] = {s};
         int ns = 1;
+        launch_force_f32_prep(c->cls.as<uint32_t>(), s); // queues, before the fork
         if (c->fork) {
             HIPCHK(c, hipEventRecord(c->fork, s));
             for (int i = 0; i < treepm_ctx::kSubStreams; ++i) {
@@ -909,12 +958,10 @@ TREEPM_API int treepm_force_short(treepm_ctx *c, void *ax, void *ay, void *az, i
                 streams[ns++] = c->sub[i];
             }
         }
-        launch_force_f32(nd, gr, c->cls.as<uint32_t>() + kForceClasses, c->n_groups + 1,
-                         c->class_counts, c->off.as<uint64_t>(), c->glen.as<uint32_t>(),
-                         c->entries.as<uint32_t>(),
-                         c->psrc.as<double4>(), c->idx.as<uint32_t>(), fp, dst[0], dst[1],
-                         dst[2], out_prec, streams,
-                         ns);
+        launch_force_f32(nd, gr, c->cls.as<uint32_t>(), c->class_counts, c->off.as<uint64_t>(),
+                         c->glen.as<uint32_t>(), c->entries.as<uint32_t>(),
+                         c->psrc.as<double4>(), c->idx.as<uint32_t>(), fp, c->ftab, dst[0],
+                         dst[1], dst[2], out_prec, c->n_cu, streams, ns);
         if (c->fork)
             for (int i = 0; i < treepm_ctx::kSubStreams; ++i) {
                 HIPCHK(c, hipEventRecord(c->join[i], c->sub[i]));
@@ -932,8 +979,7 @@ TREEPM_API int treepm_force_short(treepm_ctx *c, void *ax, void *ay, void *az, i
                     P.precision == TREEPM_FP64, out_prec, s);
     HIPCHK(c, hipGetLastError());
     record(c, 5, s);
-    if (P.precision == TREEPM_FP32)
-        launch_kept_stats(gr, c->n_groups, c->kept.as<uint32_t>(),
+    launch_kept_stats(gr, c->n_groups, c->kept.as<uint32_t>(),
                           c->kept_sum.as<unsigned long long>(), s);
     c->last_force_prec = P.precision;
     c->ev_valid[2] = c->timing;
@@ -1110,13 +1156,11 @@ TREEPM_API int treepm_get_stats(treepm_ctx *c, treepm_stats *stats)
     HIPCHK(c, hipSetDevice(c->device));
     if (c->timing) HIPCHK(c, hipStreamSynchronize(c->last));
     fill_stats(c, stats);
-    if (c->state >= 2 && c->last_force_prec == TREEPM_FP32) {
+    if (c->state >= 2 && c->last_force_prec >= 0) {
         unsigned long long ev = 0;
         int rc = d2h(c, &ev, c->kept_sum.p, 1, c->last);
         if (rc) return rc;
         stats->evaluated = (int64_t)ev;
-    } else if (c->state >= 2 && c->last_force_prec == TREEPM_FP64) {
-        stats->evaluated = stats->interactions;
     }
     return TREEPM_OK;
 }
@@ -1314,18 +1358,26 @@ TREEPM_API int treepm_pairwise_f32(const treepm_params *params, int device, int6
     if (rc) return rc;
     if (n_i < 1 || n_j < 1 || n_i * n_j > (int64_t)1 << 28 || !xi || !xj || !mj || !xg || !out)
         return TREEPM_ERR_ARG;
+    std::vector<float4> coef;
+    uint32_t tbase = 0;
+    float tc = 0.f;
+    if (!build_force_table(params->eps / (0.5 * params->r_cut), coef, tbase, tc))
+        return TREEPM_ERR_ARG;
     if (hipSetDevice(device) != hipSuccess) return TREEPM_ERR_DEVICE;
-    size_t bi = (size_t)n_i * 3 * 8, bj = (size_t)n_j * 3 * 8, bm = (size_t)n_j * 8,
-           bo = (size_t)n_i * n_j * 3 * 8;
+    size_t bt = coef.size() * sizeof(float4), bi = (size_t)n_i * 3 * 8,
+           bj = (size_t)n_j * 3 * 8, bm = (size_t)n_j * 8, bo = (size_t)n_i * n_j * 3 * 8;
     char *d = nullptr;
-    if (hipMalloc(&d, bi + bj + bm + bo) != hipSuccess) return TREEPM_ERR_OOM;
-    double *dxi = (double *)d, *dxj = (double *)(d + bi), *dmj = (double *)(d + bi + bj),
-           *dout = (double *)(d + bi + bj + bm);
-    hipError_t e = hipMemcpy(dxi, xi, bi, hipMemcpyHostToDevice);
+    if (hipMalloc(&d, bt + bi + bj + bm + bo) != hipSuccess) return TREEPM_ERR_OOM;
+    float4 *dtab = (float4 *)d;
+    double *dxi = (double *)(d + bt), *dxj = (double *)(d + bt + bi),
+           *dmj = (double *)(d + bt + bi + bj), *dout = (double *)(d + bt + bi + bj + bm);
+    hipError_t e = hipMemcpy(dtab, coef.data(), bt, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(dxi, xi, bi, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(dxj, xj, bj, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(dmj, mj, bm, hipMemcpyHostToDevice);
     if (e == hipSuccess) {
-        launch_pairwise_f32(n_i, dxi, n_j, dxj, dmj, xg, 0.5 * params->r_cut, params->eps, dout,
+        const ForceTable ft{dtab, (uint32_t)coef.size(), tbase, tc};
+        launch_pairwise_f32(n_i, dxi, n_j, dxj, dmj, xg, 0.5 * params->r_cut, ft, dout,
                             nullptr);
         e = hipGetLastError();
     }
