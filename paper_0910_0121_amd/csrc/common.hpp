@@ -167,7 +167,7 @@ __device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t n)
 }
 
 struct ForceParams {
-    double L, eps2, inv_eta, eta, rc2;
+    double L, eps2, inv_eta, eta, rc2, rc;
     uint32_t *kept; // per group, list entries that survived the cutoff cull
 };
 

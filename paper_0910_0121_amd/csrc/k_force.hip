@@ -103,8 +103,10 @@ __device__ __forceinline__ void store3(void *ax, void *ay, void *az, uint32_t i,
 // two far below (eps/eta)^2, added inside the fused sum of squares) is cut into 32 pieces per
 // octave by its own bit pattern, so the piece index is the exponent and top five mantissa
 // bits of u and the position inside the piece is the remaining 18 mantissa bits, both exact.
-// u >= 4 (R >= 2) falls on a zero piece.  A pair costs 19 vector instructions and one LDS
-// read and needs no square root, reciprocal square root or branch.
+// The table holds H = G / (4 - s)^4 (the power of 4 - s takes most of eq. 2's fifth-order
+// zero at the cutoff, so the cubics keep G's relative accuracy there); u >= 4 (R >= 2) falls
+// on a zero piece.  A pair costs 22 vector instructions and one LDS read and needs no square
+// root, reciprocal square root or branch.
 //
 // One tile takes up to kTileF32 list entries.  Each lane examines kTileF32 / 64 of them and
 // drops those whose source is at least r_cut from the group's bounding box: every pair they
@@ -144,7 +146,18 @@ __device__ __forceinline__ void fetch_entries(const uint32_t *__restrict__ list,
     }
 }
 
-// Culls and packs one tile; returns the number of survivors (the same on every lane).
+// Culls and packs one tile; returns the number of survivors (the same on every lane).  WRAP
+// = false for a group whose bounding box, grown by r_cut, lies inside [0, L) on every axis:
+// then a source within r_cut of the box is its own nearest image, and a source whose nearest
+// image lies across the boundary is at least r_cut from the box without the wrap as with it,
+// so no coordinate needs wrapping.
+template <bool WRAP>
+__device__ __forceinline__ double wrapc(double v, double L)
+{
+    return WRAP ? wrapd(v, L) : v;
+}
+
+template <bool WRAP>
 __device__ __forceinline__ int load_tile_f32(float4 *tile, const uint32_t *ent, uint64_t jb,
                                              uint64_t Lg, int J, int lgJ, NodeArrays nd,
                                              const GroupFrame &F)
@@ -170,16 +183,16 @@ __device__ __forceinline__ int load_tile_f32(float4 *tile, const uint32_t *ent, 
         if (j < Lg) {
             const double4 src = srcs[r];
             const double sx = src.x, sy = src.y, sz = src.z, sm = src.w;
-            double w0 = fabs(wrapd(sx - F.cg0, F.L)) - F.hg0;
-            double w1 = fabs(wrapd(sy - F.cg1, F.L)) - F.hg1;
-            double w2 = fabs(wrapd(sz - F.cg2, F.L)) - F.hg2;
+            double w0 = fabs(wrapc<WRAP>(sx - F.cg0, F.L)) - F.hg0;
+            double w1 = fabs(wrapc<WRAP>(sy - F.cg1, F.L)) - F.hg1;
+            double w2 = fabs(wrapc<WRAP>(sz - F.cg2, F.L)) - F.hg2;
             w0 = w0 > 0.0 ? w0 : 0.0;
             w1 = w1 > 0.0 ? w1 : 0.0;
             w2 = w2 > 0.0 ? w2 : 0.0;
             keep = w0 * w0 + w1 * w1 + w2 * w2 < F.rc2;
-            v = make_float4((float)(wrapd(sx - F.xg0, F.L) * F.inv_eta),
-                            (float)(wrapd(sy - F.xg1, F.L) * F.inv_eta),
-                            (float)(wrapd(sz - F.xg2, F.L) * F.inv_eta), (float)sm);
+            v = make_float4((float)(wrapc<WRAP>(sx - F.xg0, F.L) * F.inv_eta),
+                            (float)(wrapc<WRAP>(sy - F.xg1, F.L) * F.inv_eta),
+                            (float)(wrapc<WRAP>(sz - F.xg2, F.L) * F.inv_eta), (float)sm);
         }
         const uint64_t mk = __ballot(keep);
         if (keep) {
@@ -220,29 +233,29 @@ __host__ __device__ __forceinline__ void force_layout(uint32_t n_g, int &J, int 
 }
 
 struct TabView {
-    const float4 *t; // the table in LDS
-    uint32_t base;   // bit pattern of c >> kTabShift
-    uint32_t last;   // base + index of the zero piece
+    const float4 *tb; // the table in LDS, offset so that tb[bits(u) >> kTabShift] is u's piece
+    uint32_t last;    // (bits of 4) >> kTabShift: the zero piece, taken by every u >= 4
     float c;
-    float c4;        // 4 + c
+    float c4;         // 4 + c
 };
 
 // One pair from the table: s = (x_j', m_j), lane particle (xi, yi, zi), all in units of eta.
+// 22 vector instructions.
 __device__ __forceinline__ void pair_f32(const float4 s, float xi, float yi, float zi,
                                          const TabView &T, float &tx, float &ty, float &tz)
 {
     const float dx = s.x - xi, dy = s.y - yi, dz = s.z - zi;
     const float u = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, T.c)));
     const uint32_t b = __float_as_uint(u);
-    const uint32_t k = min(b >> kTabShift, T.last) - T.base;
-    const float4 q = T.t[k];
-    // position inside the piece, in [-1/2, 1/2): the low mantissa bits as a float in [1, 2)
-    const float t = __uint_as_float(((b << kTabSegBits) & 0x007fffffu) | 0x3f800000u) - 1.5f;
-    const float H = fmaf(fmaf(fmaf(q.w, t, q.z), t, q.y), t, q.x);
-    // G = (4 - s)^5 H: the factor carries eq. (2)'s fifth-order zero at R = 2, so G keeps its
-    // relative accuracy up to the cutoff; 4 - s = (4 + c) - u is exact for u >= 2
+    const float4 q = T.tb[min(b >> kTabShift, T.last)];
+    // position inside the piece: the low mantissa bits as a float x in [1, 2)
+    const float x = __uint_as_float(((b << kTabSegBits) & 0x007fffffu) | 0x3f800000u);
+    const float H = fmaf(fmaf(fmaf(q.w, x, q.z), x, q.y), x, q.x);
+    // G = (4 - s)^4 H: the factor carries all but one order of eq. (2)'s fifth-order zero at
+    // R = 2, which the cubic takes as a simple zero, so G keeps its relative accuracy to
+    // within 0.01 eta of the cutoff; 4 - s = (4 + c) - u is exact for u >= 2
     const float w = T.c4 - u, w2 = w * w;
-    const float fm = s.w * (w2 * w2 * w) * H;
+    const float fm = s.w * ((w2 * w2) * H);
     tx = fmaf(fm, dx, tx);
     ty = fmaf(fm, dy, ty);
     tz = fmaf(fm, dz, tz);
@@ -279,7 +292,7 @@ __host__ __device__ constexpr bool force_prefetch(int K) { return K <= 4 || K ==
 // One group on one wave in the layout of force_layout (K i-particles per lane, J streams,
 // each stream taking every J-th surviving source); the J partial sums are added at the end
 // in stream order.  tile: this wave's kTileF32 LDS slots (also used for that reduction).
-template <int K, int OUT64>
+template <int K, int OUT64, bool WRAP>
 __device__ __forceinline__ void force_group_f32(float4 *tile, const TabView &T, NodeArrays nd,
                                                 uint32_t n_g, uint32_t f, const uint32_t *list,
                                                 uint64_t Lg, const double4 *__restrict__ ps,
@@ -315,7 +328,7 @@ __device__ __forceinline__ void force_group_f32(float4 *tile, const TabView &T, 
         if (force_prefetch(K) && Lg) fetch_entries(list, 0, Lg, ent);
         for (uint64_t jb = 0; jb < Lg; jb += kTileF32) {
             if (!force_prefetch(K)) fetch_entries(list, jb, Lg, ent);
-            const int nt = load_tile_f32(tile, ent, jb, Lg, J, lgJ, nd, F);
+            const int nt = load_tile_f32<WRAP>(tile, ent, jb, Lg, J, lgJ, nd, F);
             kept_total += (uint32_t)nt;
             wave_lds_sync();
             if (force_prefetch(K) && jb + kTileF32 < Lg)
@@ -387,7 +400,7 @@ __global__ __launch_bounds__(64 * kForceWaves, force_waves_per_simd(K)) void k_f
     extern __shared__ float4 smem[];
     for (uint32_t i = threadIdx.x; i < ft.entries; i += blockDim.x) smem[i] = ft.coef[i];
     __syncthreads();
-    const TabView T{smem, ft.base, ft.base + ft.entries - 1, ft.c, 4.0f + ft.c};
+    const TabView T{smem - ft.base, ft.base + ft.entries - 1, ft.c, 4.0f + ft.c};
     float4 *tile = smem + ft.entries + (threadIdx.x >> 6) * kTileF32;
     const uint32_t lane = __lane_id();
     GroupFrame F;
@@ -409,8 +422,18 @@ __global__ __launch_bounds__(64 * kForceWaves, force_waves_per_simd(K)) void k_f
             F.xg0 = gr.xgx[g]; F.xg1 = gr.xgy[g]; F.xg2 = gr.xgz[g];
             F.cg0 = gr.cgx[g]; F.cg1 = gr.cgy[g]; F.cg2 = gr.cgz[g];
             F.hg0 = gr.hgx[g]; F.hg1 = gr.hgy[g]; F.hg2 = gr.hgz[g];
-            force_group_f32<K, OUT64>(tile, T, nd, gr.count[g], gr.first[g], entries + off[g],
-                                      len[g], ps, pidx, F, scale, ax, ay, az, fp.kept + g);
+            const double rc = fp.rc * (1.0 + 0x1p-10); // clear of rounding at the boundary
+            const bool interior = gr.lox[g] - rc >= 0.0 && gr.hix[g] + rc < fp.L &&
+                                  gr.loy[g] - rc >= 0.0 && gr.hiy[g] + rc < fp.L &&
+                                  gr.loz[g] - rc >= 0.0 && gr.hiz[g] + rc < fp.L;
+            if (interior)
+                force_group_f32<K, OUT64, false>(tile, T, nd, gr.count[g], gr.first[g],
+                                                 entries + off[g], len[g], ps, pidx, F, scale,
+                                                 ax, ay, az, fp.kept + g);
+            else
+                force_group_f32<K, OUT64, true>(tile, T, nd, gr.count[g], gr.first[g],
+                                                entries + off[g], len[g], ps, pidx, F, scale,
+                                                ax, ay, az, fp.kept + g);
         }
     }
 }
@@ -441,7 +464,7 @@ __global__ __launch_bounds__(256) void k_pairwise_f32(int64_t n_i, const double 
                                                       ForceTable ft, double scale,
                                                       double *__restrict__ out)
 {
-    const TabView T{ft.coef, ft.base, ft.base + ft.entries - 1, ft.c, 4.0f + ft.c};
+    const TabView T{ft.coef - ft.base, ft.base + ft.entries - 1, ft.c, 4.0f + ft.c};
     const int64_t total = n_i * n_j;
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total;
          q += (int64_t)gridDim.x * blockDim.x) {
@@ -777,10 +800,10 @@ void launch_force_f64(NodeArrays nd, GroupArrays gr, uint32_t n_groups, const ui
 // ------------------------------------------------------------------ the pair-law table
 namespace {
 
-// H(s) = g(R) / ((s + e2)^(3/2) (4 - s)^5), R = sqrt(s) < 2, in double precision.  On eq. (2)'s
+// H(s) = g(R) / ((s + e2)^(3/2) (4 - s)^4), R = sqrt(s) < 2, in double precision.  On eq. (2)'s
 // first branch g is evaluated in the form without cancellation the FP64 kernel uses; on the
-// second, g = (2 - R)^5 (7R^3 + 22R^2 + 10R + 4) / 140 and 4 - s = (2 - R)(2 + R), so the
-// fifth powers cancel exactly.
+// second, g = (2 - R)^5 (7R^3 + 22R^2 + 10R + 4) / 140 and 4 - s = (2 - R)(2 + R), so four of
+// the five powers of (2 - R) cancel exactly.
 double h_host(double s, double e2)
 {
     const double R = std::sqrt(s), uncut = std::pow(s + e2, -1.5);
@@ -788,9 +811,10 @@ double h_host(double s, double e2)
         const double R2 = R * R;
         const double g =
             1.0 + R2 * R * (-1.6 + R2 * (1.6 + R * (-0.5 + R * (-12.0 / 35.0 + 0.15 * R))));
-        return g * uncut / std::pow(4.0 - s, 5);
+        return g * uncut / std::pow(4.0 - s, 4);
     }
-    return (((7.0 * R + 22.0) * R + 10.0) * R + 4.0) / (140.0 * std::pow(2.0 + R, 5)) * uncut;
+    return (2.0 - R) * (((7.0 * R + 22.0) * R + 10.0) * R + 4.0) /
+           (140.0 * std::pow(2.0 + R, 4)) * uncut;
 }
 
 // Solves the 4 x 4 system M x = r (symmetric positive definite) by Gaussian elimination with
@@ -831,10 +855,11 @@ bool build_force_table(double eps_over_eta, std::vector<float4> &coef, uint32_t 
     c = (float)cd;
     base = (uint32_t)(127 + kc) << kTabSegBits;
     coef.assign(pieces + 1, make_float4(0.f, 0.f, 0.f, 0.f));
-    // Each piece: the cubic in t in [-1/2, 1/2) closest, in the relative least-squares sense
-    // at 16 Chebyshev nodes, to H(s) = G(s) / (4 - s)^5.  H is smooth and positive on
-    // [0, 4] (eq. 2's second branch is (2 - R)^5 times a polynomial, and (4 - s) =
-    // (2 - R)(2 + R)), so G = (4 - s)^5 H keeps its relative accuracy up to the cutoff.
+    // Each piece: the cubic in x in [1, 2) (the position inside the piece, as the kernel forms
+    // it) closest, in the relative least-squares sense at 16 Chebyshev nodes, to
+    // H(s) = G(s) / (4 - s)^4.  H is smooth and positive below s = 4 (eq. 2's second branch
+    // is (2 - R)^5 times a polynomial, and 4 - s = (2 - R)(2 + R)), with a simple zero at
+    // s = 4.
     constexpr int kNodes = 16;
     const double pi = 3.14159265358979323846;
     const double w_piece = 1.0 / (1 << kTabSegBits);
@@ -844,11 +869,12 @@ bool build_force_table(double eps_over_eta, std::vector<float4> &coef, uint32_t 
         const double w = std::ldexp(w_piece, e);
         double M[4][4] = {}, r[4] = {}, x[4];
         for (int i = 0; i < kNodes; ++i) {
-            const double t = 0.5 * std::cos(pi * (i + 0.5) / kNodes);
+            const double t = 0.5 * std::cos(pi * (i + 0.5) / kNodes); // in (-1/2, 1/2)
             const double s = lo + (t + 0.5) * w - cd;
             const double y = h_host(s, e2);
             const double wt = 1.0 / (y * y);
-            const double v[4] = {1.0, t, t * t, t * t * t};
+            const double x = t + 1.5;
+            const double v[4] = {1.0, x, x * x, x * x * x};
             for (int a = 0; a < 4; ++a) {
                 r[a] += wt * v[a] * y;
                 for (int b = 0; b < 4; ++b) M[a][b] += wt * v[a] * v[b];

@@ -944,7 +944,7 @@ TREEPM_API int treepm_force_short(treepm_ctx *c, void *ax, void *ay, void *az, i
         if (e == hipSuccess) e = reserve(c->kept_sum, 64);
         if (e != hipSuccess) return hip_fail(c, e, "force statistics");
     }
-    ForceParams fp{P.L, P.eps * P.eps, 1.0 / eta, eta, P.r_cut * P.r_cut,
+    ForceParams fp{P.L, P.eps * P.eps, 1.0 / eta, eta, P.r_cut * P.r_cut, P.r_cut,
                    c->kept.as<uint32_t>()};
     if (P.precision == TREEPM_FP32) {
         if ((rc = ensure_table(c, s))) return rc;
