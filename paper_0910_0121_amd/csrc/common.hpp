@@ -171,22 +171,22 @@ struct ForceParams {
     uint32_t *kept; // per group, list entries that survived the cutoff cull
 };
 
-// The FP32 pair law G(s) = g(sqrt(s)) / (s + (eps/eta)^2)^(3/2) (s = r^2 in units of eta^2) as
-// cubic pieces in u = s + c: 2^kTabSegBits pieces per octave of u, located by the bit
-// pattern of u (index = (bits >> kTabShift) - base, position = the low kTabShift bits), from
-// u = c up to u = 4 (R = 2); the last entry is zero and takes every u >= 4.
+// The FP32 pair law G(s) = g(2 sqrt(s)) / (s + (eps/r_cut)^2)^(3/2) (s = r^2 in units of
+// r_cut^2) as cubic pieces in u = min(s + c, 1): 2^kTabSegBits pieces per octave of u,
+// located by the bit pattern of u (index = (bits >> kTabShift) - base, position = the low
+// kTabShift bits), from u = c up to u = 1 (R = 2); the last entry is zero and takes u = 1.
 constexpr int kTabSegBits = 5;
 constexpr int kTabShift = 23 - kTabSegBits;
-constexpr uint32_t kTabMaxEntries = 1025; // 32 octaves: eps / eta down to 2^-12
+constexpr uint32_t kTabMaxEntries = 1025; // 32 octaves: eps / r_cut down to 2^-13
 struct ForceTable {
     const float4 *coef; // entries x (c0, c1, c2, c3), device
     uint32_t entries;
     uint32_t base;      // (bit pattern of c) >> kTabShift
-    float c;            // a power of two at most (eps/eta)^2 / 64
+    float c;            // a power of two at most (eps/r_cut)^2 / 64
 };
-// Fills the table for eps / eta (host, FP64 fit, rounded to float); false if eps / eta is
+// Fills the table for eps / r_cut (host, FP64 fit, rounded to float); false if eps / r_cut is
 // not positive or too small for kTabMaxEntries entries.
-bool build_force_table(double eps_over_eta, std::vector<float4> &coef, uint32_t &base, float &c);
+bool build_force_table(double eps_over_rcut, std::vector<float4> &coef, uint32_t &base, float &c);
 
 constexpr int kForceClasses = 8; // FP32 force: one class per blocking factor K = 1..8
 // Layout of the class buffer (u32 words): the class sizes, per class the kXcds + 1 part

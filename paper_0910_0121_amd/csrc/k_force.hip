@@ -96,17 +96,18 @@ __device__ __forceinline__ void store3(void *ax, void *ay, void *az, uint32_t i,
     }
 }
 
-// FP32 path.  Lengths are in units of eta (the cutoff scale), and the pair law is
-//   a_i = (1/eta^2) sum_j m_j d'_ij G(|d'_ij|^2),   G(s) = g(sqrt(s)) / (s + (eps/eta)^2)^(3/2),
-// so the 1/eta^2 is applied once per particle.  G is read from a table of cubic pieces built
-// on the host for the box's eps/eta (build_force_table): the variable u = s + c (c a power of
-// two far below (eps/eta)^2, added inside the fused sum of squares) is cut into 32 pieces per
-// octave by its own bit pattern, so the piece index is the exponent and top five mantissa
-// bits of u and the position inside the piece is the remaining 18 mantissa bits, both exact.
-// The table holds H = G / (4 - s)^4 (the power of 4 - s takes most of eq. 2's fifth-order
-// zero at the cutoff, so the cubics keep G's relative accuracy there); u >= 4 (R >= 2) falls
-// on a zero piece.  A pair costs 22 vector instructions and one LDS read and needs no square
-// root, reciprocal square root or branch.
+// FP32 path.  Lengths are in units of r_cut = 2 eta, and the pair law is
+//   a_i = (1/r_cut^2) sum_j m_j d'_ij G(|d'_ij|^2),   G(s) = g(2 sqrt(s)) / (s + (eps/r_cut)^2)^(3/2),
+// so the 1/r_cut^2 is applied once per particle and the cutoff is at s = 1.  G is read from a
+// table of cubic pieces built on the host for the box's eps/r_cut (build_force_table): the
+// variable u = s + c (c a power of two far below (eps/r_cut)^2, added inside the fused sum
+// of squares, whose result is clamped to 1) is cut into 32 pieces per octave by its own bit
+// pattern, so the piece index is the exponent and top five mantissa bits of u and the
+// position inside the piece is the remaining 18 mantissa bits, both exact.  The table holds
+// H = G / (1 - s)^4 (the power of 1 - s takes most of eq. 2's fifth-order zero at the
+// cutoff, so the cubics keep G's relative accuracy there); u = 1 (every R >= 2, by the clamp)
+// falls on a zero piece.  A pair costs 21 vector instructions and one LDS read and needs no
+// square root, reciprocal square root or branch.
 //
 // One tile takes up to kTileF32 list entries.  Each lane examines kTileF32 / 64 of them and
 // drops those whose source is at least r_cut from the group's bounding box: every pair they
@@ -121,7 +122,7 @@ struct GroupFrame {
     double xg0, xg1, xg2;   // x_g, origin of the relative coordinates
     double cg0, cg1, cg2;   // bbox centre
     double hg0, hg1, hg2;   // bbox half size
-    double L, rc2, inv_eta;
+    double L, rc2, inv_len; // inv_len = 1 / r_cut, the FP32 path's length unit
 };
 
 // The LDS writes of this wave are complete before any of its lanes reads LDS again (the
@@ -190,9 +191,9 @@ __device__ __forceinline__ int load_tile_f32(float4 *tile, const uint32_t *ent, 
             w1 = w1 > 0.0 ? w1 : 0.0;
             w2 = w2 > 0.0 ? w2 : 0.0;
             keep = w0 * w0 + w1 * w1 + w2 * w2 < F.rc2;
-            v = make_float4((float)(wrapc<WRAP>(sx - F.xg0, F.L) * F.inv_eta),
-                            (float)(wrapc<WRAP>(sy - F.xg1, F.L) * F.inv_eta),
-                            (float)(wrapc<WRAP>(sz - F.xg2, F.L) * F.inv_eta), (float)sm);
+            v = make_float4((float)(wrapc<WRAP>(sx - F.xg0, F.L) * F.inv_len),
+                            (float)(wrapc<WRAP>(sy - F.xg1, F.L) * F.inv_len),
+                            (float)(wrapc<WRAP>(sz - F.xg2, F.L) * F.inv_len), (float)sm);
         }
         const uint64_t mk = __ballot(keep);
         if (keep) {
@@ -234,27 +235,31 @@ __host__ __device__ __forceinline__ void force_layout(uint32_t n_g, int &J, int 
 
 struct TabView {
     const float4 *tb; // the table in LDS, offset so that tb[bits(u) >> kTabShift] is u's piece
-    uint32_t last;    // (bits of 4) >> kTabShift: the zero piece, taken by every u >= 4
     float c;
-    float c4;         // 4 + c
+    float c1;         // 1 + c
 };
 
-// One pair from the table: s = (x_j', m_j), lane particle (xi, yi, zi), all in units of eta.
-// 22 vector instructions.
+// One pair from the table: s = (x_j', m_j), lane particle (xi, yi, zi), all in units of
+// r_cut.  21 vector instructions.
 __device__ __forceinline__ void pair_f32(const float4 s, float xi, float yi, float zi,
                                          const TabView &T, float &tx, float &ty, float &tz)
 {
     const float dx = s.x - xi, dy = s.y - yi, dz = s.z - zi;
-    const float u = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, T.c)));
+    // u = min(s + c, 1): the clamp is an output modifier of the last fma
+    const float u = __builtin_amdgcn_fmed3f(fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, T.c))), 0.0f,
+                                            1.0f);
     const uint32_t b = __float_as_uint(u);
-    const float4 q = T.tb[min(b >> kTabShift, T.last)];
+    // the piece index as a separate shift (an instruction the compiler does not merge with
+    // the address scaling, which then folds into one shift-and-add)
+    uint32_t k;
+    asm("v_lshrrev_b32 %0, 18, %1" : "=v"(k) : "v"(b));
+    static_assert(kTabShift == 18, "the shift above is kTabShift");
+    const float4 q = T.tb[k];
     // position inside the piece: the low mantissa bits as a float x in [1, 2)
     const float x = __uint_as_float(((b << kTabSegBits) & 0x007fffffu) | 0x3f800000u);
     const float H = fmaf(fmaf(fmaf(q.w, x, q.z), x, q.y), x, q.x);
-    // G = (4 - s)^4 H: the factor carries all but one order of eq. (2)'s fifth-order zero at
-    // R = 2, which the cubic takes as a simple zero, so G keeps its relative accuracy to
-    // within 0.01 eta of the cutoff; 4 - s = (4 + c) - u is exact for u >= 2
-    const float w = T.c4 - u, w2 = w * w;
+    // G = (1 - s)^4 H; 1 - s = (1 + c) - u is exact for u >= 1/2
+    const float w = T.c1 - u, w2 = w * w;
     const float fm = s.w * ((w2 * w2) * H);
     tx = fmaf(fm, dx, tx);
     ty = fmaf(fm, dy, ty);
@@ -318,9 +323,9 @@ __device__ __forceinline__ void force_group_f32(float4 *tile, const TabView &T, 
             xi[k] = yi[k] = zi[k] = 0.f;
             if (i < n_g) {
                 const double4 r = ps[f + i];
-                xi[k] = (float)((r.x - F.xg0) * F.inv_eta);
-                yi[k] = (float)((r.y - F.xg1) * F.inv_eta);
-                zi[k] = (float)((r.z - F.xg2) * F.inv_eta);
+                xi[k] = (float)((r.x - F.xg0) * F.inv_len);
+                yi[k] = (float)((r.y - F.xg1) * F.inv_len);
+                zi[k] = (float)((r.z - F.xg2) * F.inv_len);
             }
             hx[k] = hy[k] = hz[k] = lx[k] = ly[k] = lz[k] = 0.f;
         }
@@ -400,14 +405,14 @@ __global__ __launch_bounds__(64 * kForceWaves, force_waves_per_simd(K)) void k_f
     extern __shared__ float4 smem[];
     for (uint32_t i = threadIdx.x; i < ft.entries; i += blockDim.x) smem[i] = ft.coef[i];
     __syncthreads();
-    const TabView T{smem - ft.base, ft.base + ft.entries - 1, ft.c, 4.0f + ft.c};
+    const TabView T{smem - ft.base, ft.c, 1.0f + ft.c};
     float4 *tile = smem + ft.entries + (threadIdx.x >> 6) * kTileF32;
     const uint32_t lane = __lane_id();
     GroupFrame F;
     F.L = fp.L;
     F.rc2 = fp.rc2;
-    F.inv_eta = fp.inv_eta;
-    const double scale = fp.inv_eta * fp.inv_eta;
+    F.inv_len = 0.5 * fp.inv_eta; // 1 / r_cut
+    const double scale = F.inv_len * F.inv_len;
     const uint32_t xcd = blockIdx.x % kXcds;
     for (uint32_t p = 0; p < kXcds; ++p) {
         const uint32_t part = (xcd + p) % kXcds;
@@ -460,21 +465,21 @@ __global__ __launch_bounds__(256) void k_kept_stats(GroupArrays gr, uint32_t n_g
 __global__ __launch_bounds__(256) void k_pairwise_f32(int64_t n_i, const double *__restrict__ xi,
                                                       int64_t n_j, const double *__restrict__ xj,
                                                       const double *__restrict__ mj, double xg0,
-                                                      double xg1, double xg2, double inv_eta,
+                                                      double xg1, double xg2, double inv_len,
                                                       ForceTable ft, double scale,
                                                       double *__restrict__ out)
 {
-    const TabView T{ft.coef - ft.base, ft.base + ft.entries - 1, ft.c, 4.0f + ft.c};
+    const TabView T{ft.coef - ft.base, ft.c, 1.0f + ft.c};
     const int64_t total = n_i * n_j;
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total;
          q += (int64_t)gridDim.x * blockDim.x) {
         const int64_t i = q / n_j, j = q % n_j;
-        const float x = (float)((xi[3 * i + 0] - xg0) * inv_eta);
-        const float y = (float)((xi[3 * i + 1] - xg1) * inv_eta);
-        const float z = (float)((xi[3 * i + 2] - xg2) * inv_eta);
-        const float4 src = make_float4((float)((xj[3 * j + 0] - xg0) * inv_eta),
-                                       (float)((xj[3 * j + 1] - xg1) * inv_eta),
-                                       (float)((xj[3 * j + 2] - xg2) * inv_eta), (float)mj[j]);
+        const float x = (float)((xi[3 * i + 0] - xg0) * inv_len);
+        const float y = (float)((xi[3 * i + 1] - xg1) * inv_len);
+        const float z = (float)((xi[3 * i + 2] - xg2) * inv_len);
+        const float4 src = make_float4((float)((xj[3 * j + 0] - xg0) * inv_len),
+                                       (float)((xj[3 * j + 1] - xg1) * inv_len),
+                                       (float)((xj[3 * j + 2] - xg2) * inv_len), (float)mj[j]);
         float tx = 0.f, ty = 0.f, tz = 0.f;
         pair_f32(src, x, y, z, T, tx, ty, tz);
         out[3 * q + 0] = (double)tx * scale;
@@ -767,11 +772,11 @@ void launch_pairwise_f32(int64_t n_i, const double *xi, int64_t n_j, const doubl
                          const double *mj, const double *xg, double eta, ForceTable ft,
                          double *out, hipStream_t s)
 {
-    const double inv_eta = 1.0 / eta;
+    const double inv_len = 0.5 / eta; // 1 / r_cut
     const int64_t total = n_i * n_j;
     int64_t b = (total + 255) / 256;
     k_pairwise_f32<<<(unsigned)(b < 65536 ? (b > 0 ? b : 1) : 65536), 256, 0, s>>>(
-        n_i, xi, n_j, xj, mj, xg[0], xg[1], xg[2], inv_eta, ft, inv_eta * inv_eta, out);
+        n_i, xi, n_j, xj, mj, xg[0], xg[1], xg[2], inv_len, ft, inv_len * inv_len, out);
 }
 
 void launch_kept_stats(GroupArrays gr, uint32_t n_groups, const uint32_t *kept,
@@ -800,20 +805,20 @@ void launch_force_f64(NodeArrays nd, GroupArrays gr, uint32_t n_groups, const ui
 // ------------------------------------------------------------------ the pair-law table
 namespace {
 
-// H(s) = g(R) / ((s + e2)^(3/2) (4 - s)^4), R = sqrt(s) < 2, in double precision.  On eq. (2)'s
-// first branch g is evaluated in the form without cancellation the FP64 kernel uses; on the
-// second, g = (2 - R)^5 (7R^3 + 22R^2 + 10R + 4) / 140 and 4 - s = (2 - R)(2 + R), so four of
-// the five powers of (2 - R) cancel exactly.
+// H(s) = g(R) / ((s + e2)^(3/2) (1 - s)^4), R = 2 sqrt(s) < 2 (lengths in units of r_cut), in
+// double precision.  On eq. (2)'s first branch g is evaluated in the form without
+// cancellation the FP64 kernel uses; on the second, g = (2 - R)^5 (7R^3 + 22R^2 + 10R + 4) / 140
+// and 1 - s = (2 - R)(2 + R) / 4, so four of the five powers of (2 - R) cancel exactly.
 double h_host(double s, double e2)
 {
-    const double R = std::sqrt(s), uncut = std::pow(s + e2, -1.5);
+    const double R = 2.0 * std::sqrt(s), uncut = std::pow(s + e2, -1.5);
     if (R < 1.0) {
         const double R2 = R * R;
         const double g =
             1.0 + R2 * R * (-1.6 + R2 * (1.6 + R * (-0.5 + R * (-12.0 / 35.0 + 0.15 * R))));
-        return g * uncut / std::pow(4.0 - s, 4);
+        return g * uncut / std::pow(1.0 - s, 4);
     }
-    return (2.0 - R) * (((7.0 * R + 22.0) * R + 10.0) * R + 4.0) /
+    return 256.0 * (2.0 - R) * (((7.0 * R + 22.0) * R + 10.0) * R + 4.0) /
            (140.0 * std::pow(2.0 + R, 4)) * uncut;
 }
 
@@ -842,13 +847,13 @@ void solve4(double M[4][4], double r[4], double x[4])
 
 } // namespace
 
-bool build_force_table(double eps_over_eta, std::vector<float4> &coef, uint32_t &base, float &c)
+bool build_force_table(double eps_over_rcut, std::vector<float4> &coef, uint32_t &base, float &c)
 {
-    const double e2 = eps_over_eta * eps_over_eta;
+    const double e2 = eps_over_rcut * eps_over_rcut;
     if (!(e2 > 0.0) || !std::isfinite(e2)) return false;
     // c: a power of two at most e2 / 64, so the pieces near s = 0 are narrow next to eps^2
     const int kc = (int)std::floor(std::log2(e2)) - 6;
-    const int n_oct = 2 - kc; // u in [2^kc, 4)
+    const int n_oct = -kc; // u in [2^kc, 1)
     const uint32_t pieces = (uint32_t)n_oct << kTabSegBits;
     if (n_oct < 1 || pieces + 1 > kTabMaxEntries) return false;
     const double cd = std::ldexp(1.0, kc);
@@ -857,9 +862,9 @@ bool build_force_table(double eps_over_eta, std::vector<float4> &coef, uint32_t 
     coef.assign(pieces + 1, make_float4(0.f, 0.f, 0.f, 0.f));
     // Each piece: the cubic in x in [1, 2) (the position inside the piece, as the kernel forms
     // it) closest, in the relative least-squares sense at 16 Chebyshev nodes, to
-    // H(s) = G(s) / (4 - s)^4.  H is smooth and positive below s = 4 (eq. 2's second branch
-    // is (2 - R)^5 times a polynomial, and 4 - s = (2 - R)(2 + R)), with a simple zero at
-    // s = 4.
+    // H(s) = G(s) / (1 - s)^4.  H is smooth and positive below s = 1 (eq. 2's second branch
+    // is (2 - R)^5 times a polynomial, and 1 - s = (2 - R)(2 + R) / 4), with a simple zero at
+    // s = 1.
     constexpr int kNodes = 16;
     const double pi = 3.14159265358979323846;
     const double w_piece = 1.0 / (1 << kTabSegBits);

@@ -879,13 +879,13 @@ namespace {
 // device once per parameter set.
 int ensure_table(treepm_ctx *c, hipStream_t s)
 {
-    const double key = c->prm.eps / (0.5 * c->prm.r_cut);
+    const double key = c->prm.eps / c->prm.r_cut;
     if (c->tab.p && c->tab_key == key) return TREEPM_OK;
     std::vector<float4> coef;
     uint32_t base = 0;
     float cc = 0.f;
     if (!build_force_table(key, coef, base, cc))
-        return fail(c, TREEPM_ERR_ARG, "eps / eta = %g is outside the FP32 table's range", key);
+        return fail(c, TREEPM_ERR_ARG, "eps / r_cut = %g is outside the FP32 table's range", key);
     hipError_t e = reserve(c->tab, coef.size() * sizeof(float4));
     if (e != hipSuccess) return hip_fail(c, e, "pair-law table");
     HIPCHK(c, hipMemcpyAsync(c->tab.p, coef.data(), coef.size() * sizeof(float4),
@@ -1361,7 +1361,7 @@ TREEPM_API int treepm_pairwise_f32(const treepm_params *params, int device, int6
     std::vector<float4> coef;
     uint32_t tbase = 0;
     float tc = 0.f;
-    if (!build_force_table(params->eps / (0.5 * params->r_cut), coef, tbase, tc))
+    if (!build_force_table(params->eps / params->r_cut, coef, tbase, tc))
         return TREEPM_ERR_ARG;
     if (hipSetDevice(device) != hipSuccess) return TREEPM_ERR_DEVICE;
     size_t bt = coef.size() * sizeof(float4), bi = (size_t)n_i * 3 * 8,
