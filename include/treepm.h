@@ -199,6 +199,20 @@ int treepm_timestep(treepm_ctx *ctx, int64_t n, const double *vx, const double *
                     const double *vz, const void *ax, const void *ay, const void *az,
                     int acc_prec, double eps, double zeta, void *hip_stream, double *dt);
 
+/* treepm_timestep for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): same arguments, checks and
+ * result, but the reduction word lives in a static device array of the library (256 bytes
+ * per GPU, held until the process ends) instead of a buffer of the context, so the call
+ * makes no hipMalloc, hipFree or other allocating call.  n is limited to [1, 2^31) as for
+ * treepm_timestep (ERR_ARG beyond); the scratch does not grow with n.  Every call on one GPU
+ * shares the array and clears it itself (a fill kernel, not hipMemset); calls that overlap
+ * on one GPU race and must be serialised by the caller.  ERR_DEVICE if the array's device
+ * address cannot be obtained.  Synchronises with the stream's work. */
+int treepm_timestep_noalloc(treepm_ctx *ctx, int64_t n, const double *vx, const double *vy,
+                            const double *vz, const void *ax, const void *ay, const void *az,
+                            int acc_prec, double eps, double zeta, void *hip_stream,
+                            double *dt);
+
 /* One kick and drift, in place: v += a dt_kick, then x += v dt_drift, and each coordinate is
  * wrapped back into [0, L) by one box length (one that rounds to L is set to 0).  A leapfrog
  * starts with dt_kick = dt / 2.  Stream-ordered; does not synchronise. */

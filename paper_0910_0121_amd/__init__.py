@@ -35,6 +35,7 @@ from ._native import (  # noqa: F401
     treepm_force_long,
     treepm_kick_drift,
     treepm_timestep,
+    treepm_timestep_noalloc,
     treepm_force_short,
     treepm_get_stats,
     treepm_last_error,

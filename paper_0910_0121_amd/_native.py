@@ -65,6 +65,8 @@ _SIGS = {
     "treepm_eps_of_z": (C.c_double, [C.c_double, C.c_double, C.c_double]),
     "treepm_timestep": (_i, [_p, _i64, _p, _p, _p, _p, _p, _p, _i, C.c_double, C.c_double, _p,
                              C.POINTER(C.c_double)]),
+    "treepm_timestep_noalloc": (_i, [_p, _i64, _p, _p, _p, _p, _p, _p, _i, C.c_double,
+                                     C.c_double, _p, C.POINTER(C.c_double)]),
     "treepm_kick_drift": (_i, [_p, _i64, _p, _p, _p, _p, _p, _p, _p, _p, _p, _i, C.c_double,
                                C.c_double, _p]),
     "treepm_get_stats": (_i, [_p, C.POINTER(treepm_stats)]),
@@ -244,6 +246,17 @@ def treepm_timestep(ctx, vx, vy, vz, ax, ay, az, eps, zeta, stream=None) -> floa
     _check(lib().treepm_timestep(ctx, vx.shape[0], *ptr,
                                  TREEPM_FP64 if adt == "float64" else TREEPM_FP32, eps, zeta,
                                  _stream(stream, TREEPM_DEVICE), C.byref(dt)), ctx)
+    return dt.value
+
+
+def treepm_timestep_noalloc(ctx, vx, vy, vz, ax, ay, az, eps, zeta, stream=None) -> float:
+    """treepm_timestep without any device allocation (static scratch in the library)."""
+    adt = "float64" if str(ax.dtype) == "torch.float64" else "float32"
+    ptr = _dev_ptrs((vx, vy, vz, ax, ay, az), ("float64",) * 3 + (adt,) * 3)
+    dt = C.c_double()
+    _check(lib().treepm_timestep_noalloc(ctx, vx.shape[0], *ptr,
+                                         TREEPM_FP64 if adt == "float64" else TREEPM_FP32, eps,
+                                         zeta, _stream(stream, TREEPM_DEVICE), C.byref(dt)), ctx)
     return dt.value
 
 

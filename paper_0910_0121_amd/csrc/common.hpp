@@ -262,6 +262,11 @@ void launch_quad(NodeArrays nd, GroupArrays gr, uint32_t n_groups, const uint64_
 void launch_timestep(int64_t n, const double *vx, const double *vy, const double *vz,
                      const void *ax, const void *ay, const void *az, int acc_fp64, double eps,
                      unsigned long long *out, hipStream_t s);
+// Device scratch of the allocation-free time step (a static device array, 256 bytes): its
+// address on `device`, which must be the current device, looked up once per device.
+constexpr int kStepScratchWords = 32;
+constexpr int kMaxDevices = 64;
+hipError_t step_scratch(int device, unsigned long long **out);
 // v += a dt_kick, then x += v dt_drift wrapped into [0, L), in place.
 void launch_kick_drift(int64_t n, double *x, double *y, double *z, double *vx, double *vy,
                        double *vz, const void *ax, const void *ay, const void *az, int acc_fp64,

@@ -7,6 +7,15 @@
 //  * k_kick_drift: v += a dt_kick, then x += v dt_drift, wrapped back into [0, L).
 #include "common.hpp"
 
+#include <mutex>
+
+// Scratch of treepm_timestep_noalloc: the reduction word, in static device memory so that the
+// call allocates nothing.  Each GPU the library runs on holds its own copy until the process
+// ends; every call on one GPU shares it (calls that overlap on one GPU race).  Host code must
+// not pass this name to a kernel: it is a host-side stand-in, and the device address comes
+// from hipGetSymbolAddress (step_scratch below).
+static __device__ __align__(256) unsigned long long scratch[tpm::kStepScratchWords];
+
 namespace tpm {
 namespace {
 
@@ -88,6 +97,24 @@ void launch_timestep(int64_t n, const double *vx, const double *vy, const double
     else
         k_timestep<float><<<g, 256, 0, s>>>(n, vx, vy, vz, (const float *)ax,
                                             (const float *)ay, (const float *)az, eps, out);
+}
+
+hipError_t step_scratch(int device, unsigned long long **out)
+{
+    static std::mutex mu;
+    static unsigned long long *ptr[kMaxDevices] = {};
+    *out = nullptr;
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!ptr[device]) {
+        // the caller has made `device` current: this is that device's copy of the array
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        ptr[device] = static_cast<unsigned long long *>(p);
+    }
+    *out = ptr[device];
+    return hipSuccess;
 }
 
 void launch_kick_drift(int64_t n, double *x, double *y, double *z, double *vx, double *vy,

@@ -1085,13 +1085,13 @@ TREEPM_API double treepm_eps_of_z(double z, double eps_fin, double z_crit)
     return z >= z_crit ? (1.0 + z_crit) / (1.0 + z) * eps_fin : eps_fin;
 }
 
-TREEPM_API int treepm_timestep(treepm_ctx *c, int64_t n, const double *vx, const double *vy,
-                               const double *vz, const void *ax, const void *ay, const void *az,
-                               int acc_prec, double eps, double zeta, void *hip_stream,
-                               double *dt)
+namespace {
+
+// Argument checks shared by the two time-step entry points.
+int check_timestep(treepm_ctx *c, int64_t n, const double *vx, const double *vy,
+                   const double *vz, const void *ax, const void *ay, const void *az,
+                   int acc_prec, double eps, double zeta, double *dt)
 {
-    if (!c) return TREEPM_ERR_ARG;
-    c->err.clear();
     if (!dt) return fail(c, TREEPM_ERR_ARG, "dt is NULL");
     if (n < 1 || n > 0x7fffffffLL) return fail(c, TREEPM_ERR_ARG, "n must be in [1, 2^31)");
     if (!vx || !vy || !vz || !ax || !ay || !az) return fail(c, TREEPM_ERR_ARG, "NULL buffer");
@@ -1103,6 +1103,37 @@ TREEPM_API int treepm_timestep(treepm_ctx *c, int64_t n, const double *vx, const
     for (const void *p : {(const void *)vx, (const void *)vy, (const void *)vz, ax, ay, az})
         if (!device_array(p, c->device))
             return fail(c, TREEPM_ERR_ARG, "treepm_timestep takes device arrays");
+    return TREEPM_OK;
+}
+
+// The reduction into the device word `word`, then dt = zeta * min from its bit pattern.
+int run_timestep(treepm_ctx *c, int64_t n, const double *vx, const double *vy,
+                 const double *vz, const void *ax, const void *ay, const void *az,
+                 int acc_prec, double eps, double zeta, hipStream_t s, unsigned long long *word,
+                 double *dt)
+{
+    launch_timestep(n, vx, vy, vz, ax, ay, az, acc_prec == TREEPM_FP64, eps, word, s);
+    HIPCHK(c, hipGetLastError());
+    unsigned long long bits = 0;
+    int rc = fetch(c, s, {&bits, word, sizeof bits});
+    if (rc) return rc;
+    double m;
+    std::memcpy(&m, &bits, sizeof m);
+    *dt = zeta * m;
+    return TREEPM_OK;
+}
+
+} // namespace
+
+TREEPM_API int treepm_timestep(treepm_ctx *c, int64_t n, const double *vx, const double *vy,
+                               const double *vz, const void *ax, const void *ay, const void *az,
+                               int acc_prec, double eps, double zeta, void *hip_stream,
+                               double *dt)
+{
+    if (!c) return TREEPM_ERR_ARG;
+    c->err.clear();
+    int rc = check_timestep(c, n, vx, vy, vz, ax, ay, az, acc_prec, eps, zeta, dt);
+    if (rc) return rc;
     hipStream_t s = (hipStream_t)hip_stream;
     c->last = s;
     CallScope scope(c, s);
@@ -1110,16 +1141,28 @@ TREEPM_API int treepm_timestep(treepm_ctx *c, int64_t n, const double *vx, const
         hipError_t e = reserve(c->step_min, 8);
         if (e != hipSuccess) return hip_fail(c, e, "time step");
     }
-    launch_timestep(n, vx, vy, vz, ax, ay, az, acc_prec == TREEPM_FP64, eps,
-                    c->step_min.as<unsigned long long>(), s);
-    HIPCHK(c, hipGetLastError());
-    unsigned long long bits = 0;
-    int rc = d2h(c, &bits, c->step_min.p, 1, s);
+    return run_timestep(c, n, vx, vy, vz, ax, ay, az, acc_prec, eps, zeta, s,
+                        c->step_min.as<unsigned long long>(), dt);
+}
+
+TREEPM_API int treepm_timestep_noalloc(treepm_ctx *c, int64_t n, const double *vx,
+                                       const double *vy, const double *vz, const void *ax,
+                                       const void *ay, const void *az, int acc_prec, double eps,
+                                       double zeta, void *hip_stream, double *dt)
+{
+    if (!c) return TREEPM_ERR_ARG;
+    c->err.clear();
+    int rc = check_timestep(c, n, vx, vy, vz, ax, ay, az, acc_prec, eps, zeta, dt);
     if (rc) return rc;
-    double m;
-    std::memcpy(&m, &bits, sizeof m);
-    *dt = zeta * m;
-    return TREEPM_OK;
+    unsigned long long *word = nullptr;
+    {
+        const hipError_t e = step_scratch(c->device, &word);
+        if (e != hipSuccess) return hip_fail(c, e, "device scratch of the time step");
+    }
+    hipStream_t s = (hipStream_t)hip_stream;
+    c->last = s;
+    CallScope scope(c, s);
+    return run_timestep(c, n, vx, vy, vz, ax, ay, az, acc_prec, eps, zeta, s, word, dt);
 }
 
 TREEPM_API int treepm_kick_drift(treepm_ctx *c, int64_t n, double *x, double *y, double *z,
