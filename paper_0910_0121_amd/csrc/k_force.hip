@@ -489,13 +489,17 @@ __global__ __launch_bounds__(256) void k_pairwise_f32(int64_t n_i, const double 
 }
 
 // Classes and queues of the FP32 force.  Group g belongs to class q = K - 1 (K of its lane
-// layout), to XCD part p = floor(8 g / G) (contiguous key ranges) and to a cost bucket of
-// n_g L_g on a half-octave scale; the bins (q, p, bucket) are laid out with the costliest
-// bucket first, so each part of each class lists its groups longest first.  Three passes:
-// count the bins, scan them into cursors and part starts, scatter.  Blocks take
-// kClassifyItems * 256 consecutive groups and aggregate their bins in LDS first.
+// layout), to XCD part p = floor(8 g / G) (contiguous key ranges) and to a cost bucket: the
+// octave of n_g L_g for heavy groups (at least 2^kHeavyCost pairs, which take a wave a
+// large part of a millisecond), one bucket for all others.  The bins (q, p, bucket) are laid
+// out with the costliest bucket first, so each part of each class lists its heavy groups
+// longest first and then the rest in about key order (consecutive groups share sources
+// through the XCD's L2).  Three passes: count the bins, scan them into cursors and part
+// starts, scatter.  Blocks take kClassifyItems * 256 consecutive groups and aggregate their
+// bins in LDS first.
 constexpr int kClassifyItems = 8;
 constexpr int kCostBuckets = 64;
+constexpr uint32_t kHeavyCost = 17;
 constexpr int kBins = kForceClasses * kXcds * kCostBuckets;
 
 __device__ __forceinline__ uint32_t cost_bin(uint32_t g, uint32_t n_groups, uint32_t n_g,
@@ -506,9 +510,9 @@ __device__ __forceinline__ uint32_t cost_bin(uint32_t g, uint32_t n_groups, uint
     const uint32_t part = (uint32_t)(((uint64_t)g * kXcds) / n_groups);
     const uint64_t cost = (uint64_t)n_g * L_g;
     uint32_t b = 0;
-    if (cost > 1) {
+    if (cost >= (1ull << kHeavyCost)) {
         const uint32_t lg = 63u - (uint32_t)__clzll((long long)cost);
-        b = 2u * lg + (uint32_t)((cost >> (lg - 1)) & 1u);
+        b = lg - kHeavyCost + 1;
         b = b < kCostBuckets ? b : kCostBuckets - 1;
     }
     return ((uint32_t)(K - 1) * kXcds + part) * kCostBuckets + (kCostBuckets - 1 - b);
