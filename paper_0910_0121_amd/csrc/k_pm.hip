@@ -39,14 +39,16 @@ __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(
 // (no contraction into the add), so every kernel finds the same point for the same x.
 __device__ __forceinline__ int nearest(double x, double inv_h)
 {
-    return (int)floor(__dmul_rn(x, inv_h) + 0.5);
+#pragma clang fp contract(off)
+    return (int)floor(x * inv_h + 0.5);
 }
 
 // TSC cloud along one axis: the nearest mesh point (returned) and the weights of the points
 // before it, at it and after it.
 __device__ __forceinline__ int tsc(double x, double inv_h, double w[3])
 {
-    const double u = __dmul_rn(x, inv_h);
+#pragma clang fp contract(off)
+    const double u = x * inv_h;
     const double f = floor(u + 0.5);
     const double d = u - f;
     w[0] = 0.5 * (0.5 - d) * (0.5 - d);
