@@ -58,8 +58,8 @@ enum { TREEPM_OPEN_FIXED = 0, TREEPM_OPEN_DISTANCE = 1 }; /* opening criterion  
  *   mesh     PM mesh spacing L / N_PM, > 0.
  *   r_cut    cutoff radius, 0 < r_cut <= L/2, and r_cut = 3 mesh to relative 1e-12
  *            (2 eta = r_cut = 3 / N_PM).
- *   eps      Plummer softening, >= 0; the FP32 kernel requires eps >= 2^-12 r_cut / 2
- *            (its pair law is tabulated per box for eps / eta, eta = r_cut / 2).
+ *   eps      Plummer softening, >= 0; the FP32 kernel requires eps >= 2^-13 r_cut
+ *            (its pair law is tabulated per box for eps / r_cut).
  *   theta    opening angle, 0 <= theta <= 1.  A node of side l is used as one source when
  *            l < theta d, d = distance from its centre of mass to the group's bounding box
  *            (minimum image), and its cube does not touch that box.  Under
@@ -153,15 +153,26 @@ int treepm_build(treepm_ctx *ctx, int64_t n, const double *x, const double *y, c
 int treepm_walk(treepm_ctx *ctx, void *hip_stream, treepm_stats *stats);
 
 /* Short-range force on every particle from its group's list (eq. 1, 2), written in the
- * caller's original particle order.  TREEPM_FP32 boxes evaluate the pair law
- * G(s) = g_P3M(sqrt(s)) / (s + (eps/eta)^2)^(3/2), s = (r/eta)^2, from a table of cubic pieces
- * built on the host for the box (32 per octave of s + c, c a power of two below
- * (eps/eta)^2 / 64; least-squares fits within about 1.3e-7 of the uncut law), and the pair
- * arithmetic in FP32 on coordinates relative to the group's cube centre.  ax, ay, az: n values each of type out_prec
+ * caller's original particle order.  TREEPM_FP32 boxes work in lengths of r_cut, relative to
+ * the group's cube centre: with s = (r / r_cut)^2 the pair law
+ * G(s) = g_P3M(2 sqrt(s)) / (s + (eps/r_cut)^2)^(3/2) is G = (1 - s)^4 H(u), u = min(s + c, 1),
+ * c a power of two at most (eps/r_cut)^2 / 64, and H comes from a table of cubic pieces built
+ * on the host for the box (32 per octave of u, relative least-squares fits, zero at u = 1);
+ * the rest of the pair arithmetic is FP32.  ax, ay, az: n values each of type out_prec
  * (TREEPM_FP32 = float, TREEPM_FP64 = double) and kind mem_kind.  Requires a walk
- * (ERR_STATE). */
+ * (ERR_STATE).  Uses no memory beyond what the build and walk allocated (device outputs). */
 int treepm_force_short(treepm_ctx *ctx, void *ax, void *ay, void *az, int out_prec,
                        int mem_kind, void *hip_stream);
+
+/* The short-range kick fused with the force (Section 2.2 step 5: a particle's velocity is
+ * kicked with its short-range force as soon as that is computed, without storing it):
+ * v_i += dt a_i for every particle, a_i the acceleration treepm_force_short would give.
+ * vx, vy, vz: n doubles each, device arrays on the context's GPU in the caller's particle
+ * order (ERR_ARG for host memory); each product dt a_i and each sum is rounded on its own, so
+ * the result equals v + dt a with a from treepm_force_short(..., TREEPM_FP64, ...) bit for bit.
+ * Requires a walk (ERR_STATE); not for quadrupole boxes (ERR_ARG).  Stream-ordered. */
+int treepm_kick_short(treepm_ctx *ctx, double *vx, double *vy, double *vz, double dt,
+                      void *hip_stream);
 
 /* Long-range (particle-mesh) acceleration of every particle of the built box (Section 2.2
  * step 1; the long-range half of the split of Section 2.1), on the mesh N_PM = L / mesh,
@@ -259,8 +270,9 @@ int treepm_export_lists(treepm_ctx *ctx, int64_t group_cap, int64_t entry_cap, i
 /* The FP32 pair routine of treepm_force_short on explicit positions, pair by pair (the
  * pairwise-accuracy measurement of Section 3.1.1): out[(i n_j + j) 3 + a] is the
  * acceleration at xi[i] from a mass mj[j] at xj[j], computed exactly as the force kernel
- * does -- coordinates relative to xg and in units of eta = r_cut / 2, FP32 rsqrt, sqrt and
- * g -- but without periodic images and without the cull of sources beyond r_cut.
+ * does -- coordinates relative to xg and in units of r_cut, FP32 arithmetic and the box's
+ * table of the pair law -- but without periodic images and without the cull of sources
+ * beyond r_cut.
  * xi: 3 n_i doubles, xj: 3 n_j, mj: n_j, xg: 3, out: 3 n_i n_j (all host memory).
  * n_i n_j <= 2^28.  Uses params->r_cut and params->eps (validated as for treepm_create). */
 int treepm_pairwise_f32(const treepm_params *params, int device, int64_t n_i, const double *xi,

@@ -34,6 +34,7 @@ from ._native import (  # noqa: F401
     treepm_eps_of_z,
     treepm_force_long,
     treepm_kick_drift,
+    treepm_kick_short,
     treepm_timestep,
     treepm_timestep_noalloc,
     treepm_force_short,

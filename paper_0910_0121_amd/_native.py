@@ -67,6 +67,7 @@ _SIGS = {
                              C.POINTER(C.c_double)]),
     "treepm_timestep_noalloc": (_i, [_p, _i64, _p, _p, _p, _p, _p, _p, _i, C.c_double,
                                      C.c_double, _p, C.POINTER(C.c_double)]),
+    "treepm_kick_short": (_i, [_p, _p, _p, _p, C.c_double, _p]),
     "treepm_kick_drift": (_i, [_p, _i64, _p, _p, _p, _p, _p, _p, _p, _p, _p, _i, C.c_double,
                                C.c_double, _p]),
     "treepm_get_stats": (_i, [_p, C.POINTER(treepm_stats)]),
@@ -258,6 +259,12 @@ def treepm_timestep_noalloc(ctx, vx, vy, vz, ax, ay, az, eps, zeta, stream=None)
                                          TREEPM_FP64 if adt == "float64" else TREEPM_FP32, eps,
                                          zeta, _stream(stream, TREEPM_DEVICE), C.byref(dt)), ctx)
     return dt.value
+
+
+def treepm_kick_short(ctx, vx, vy, vz, dt, stream=None) -> None:
+    """In place on device float64 tensors: v += dt a_short (the kick fused with the force)."""
+    ptr = _dev_ptrs((vx, vy, vz), ("float64",) * 3)
+    _check(lib().treepm_kick_short(ctx, *ptr, dt, _stream(stream, TREEPM_DEVICE)), ctx)
 
 
 def treepm_kick_drift(ctx, x, y, z, vx, vy, vz, ax, ay, az, dt_kick, dt_drift,

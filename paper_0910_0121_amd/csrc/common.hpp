@@ -210,8 +210,14 @@ void launch_force_f32_prep(uint32_t *cls, hipStream_t s);
 void launch_force_f32(NodeArrays nd, GroupArrays gr, uint32_t *cls, const uint32_t *class_counts,
                       const uint64_t *off, const uint32_t *len, const uint32_t *entries,
                       const double4 *ps, const uint32_t *pidx, ForceParams fp, ForceTable ft,
-                      void *ax, void *ay, void *az, int out_prec, int n_cu,
-                      const hipStream_t *streams, int n_streams);
+                      void *rec, int rec64, int n_cu, const hipStream_t *streams,
+                      int n_streams);
+// rec of the force launchers: one record per particle in the caller's order (pidx), float4
+// (ax, ay, az, 0) or, with rec64, double4.  launch_force_out then writes them out: mode 0
+// float arrays, 1 double arrays (from float4 / double4 records), 2 kick (v += dt a into double
+// velocities, double4 records), walking the records in order.
+void launch_force_out(const void *rec, int mode, int64_t n, void *ax, void *ay, void *az,
+                      double dt, hipStream_t s);
 // FP32 pair routine on explicit positions, pair by pair (xg: host, 3 values).
 void launch_pairwise_f32(int64_t n_i, const double *xi, int64_t n_j, const double *xj,
                          const double *mj, const double *xg, double eta, ForceTable ft,
@@ -221,8 +227,7 @@ void launch_kept_stats(GroupArrays gr, uint32_t n_groups, const uint32_t *kept,
                        unsigned long long *out, hipStream_t s);
 void launch_force_f64(NodeArrays nd, GroupArrays gr, uint32_t n_groups, const uint64_t *off,
                       const uint32_t *len, const uint32_t *entries, const double4 *ps, const uint32_t *pidx,
-                      ForceParams fp, void *ax, void *ay, void *az, int out_prec,
-                      hipStream_t s);
+                      ForceParams fp, void *rec, int rec64, hipStream_t s);
 
 // Particle-mesh long-range force (k_pm.hip), mesh N^3 with N a power of two in [16, 1024].
 // Lines per FFT workgroup for mesh size N.
@@ -250,12 +255,12 @@ void launch_pm_split(const float4 *stage, int64_t n, void *ax, void *ay, void *a
 // xy, xz, yz about the centre of mass), filled level by level from the deepest.
 void launch_second_moments(NodeArrays nd, const double4 *ps, uint32_t lo, uint32_t hi,
                            double *Q, hipStream_t s);
-// Adds the cells' second-order terms to ax/ay/az (caller's order, float or double outputs),
-// computed in FP64 (fp64_math) or FP32.
+// Adds the cells' second-order terms to the force records (caller's order, float4 or, with
+// rec64, double4), computed in FP64 (fp64_math) or FP32.
 void launch_quad(NodeArrays nd, GroupArrays gr, uint32_t n_groups, const uint64_t *off,
                  const uint32_t *len, const uint32_t *entries, const double4 *ps,
-                 const uint32_t *pidx, const double *Q, ForceParams fp, void *ax, void *ay,
-                 void *az, int fp64_math, int out_prec, hipStream_t s);
+                 const uint32_t *pidx, const double *Q, ForceParams fp, void *rec,
+                 int fp64_math, int rec64, hipStream_t s);
 
 // Time stepping (k_step.hip).  Accelerations are float (acc_fp64 = 0) or double arrays.
 // out receives the bit pattern of min_i(sqrt(eps / |a_i|), eps / |v_i|) (+inf if none binds).

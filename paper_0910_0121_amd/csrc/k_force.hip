@@ -14,7 +14,9 @@
 // the rounding error of the subtraction scales with the group size, not the box.  The pair
 // law is read from a per-box table of cubic pieces (see the FP32 section).  The per-tile FP32
 // partial sums are folded into an FP32 (hi, lo) pair with TwoSum.  Persistent workgroups
-// take the groups from per-XCD queues, longest lists first.
+// take the groups from per-XCD queues, the heaviest groups first.  Each particle's result
+// leaves the kernels as one record in the caller's order, which a last pass splits into the
+// output arrays or applies as a kick.
 //
 // FP64 path: the same relative coordinates in FP64 (nearest image once per entry, or per pair
 // when the group's cube plus r_cut reaches half the box), (r^2 + eps^2)^(-1/2) and r^(-1)
@@ -81,19 +83,22 @@ __device__ __forceinline__ void two_sum_fold(float &hi, float &lo, float t)
     lo += err;
 }
 
-template <int OUT64>
-__device__ __forceinline__ void store3(void *ax, void *ay, void *az, uint32_t i, double vx,
-                                       double vy, double vz)
+// The force kernels leave one record per particle, in the caller's order: float4 (ax, ay, az,
+// 0) for float results, double4 for double results and for the kick.  The caller's order is
+// arbitrary, so each store lands in its own 32-byte HBM sector: one 16- or 32-byte record costs
+// one sector where three 4- or 8-byte component stores cost three.  k_force_out then walks the
+// records in order and splits them into the caller's three arrays (kOutF32, kOutF64) or adds dt
+// times them to double velocities (kOutKick: the kick of Section 2.2 step 5 taken with the
+// short-range force as soon as it is known), each product and sum rounded on its own.
+enum { kOutF32 = 0, kOutF64 = 1, kOutKick = 2 };
+
+template <int REC64>
+__device__ __forceinline__ void store_rec(void *rec, uint32_t i, double vx, double vy, double vz)
 {
-    if (OUT64) {
-        ((double *)ax)[i] = vx;
-        ((double *)ay)[i] = vy;
-        ((double *)az)[i] = vz;
-    } else {
-        ((float *)ax)[i] = (float)vx;
-        ((float *)ay)[i] = (float)vy;
-        ((float *)az)[i] = (float)vz;
-    }
+    if (REC64)
+        ((double4 *)rec)[i] = make_double4(vx, vy, vz, 0.0);
+    else
+        ((float4 *)rec)[i] = make_float4((float)vx, (float)vy, (float)vz, 0.0f);
 }
 
 // FP32 path.  Lengths are in units of r_cut = 2 eta, and the pair law is
@@ -297,13 +302,13 @@ __host__ __device__ constexpr bool force_prefetch(int K) { return K <= 4 || K ==
 // One group on one wave in the layout of force_layout (K i-particles per lane, J streams,
 // each stream taking every J-th surviving source); the J partial sums are added at the end
 // in stream order.  tile: this wave's kTileF32 LDS slots (also used for that reduction).
-template <int K, int OUT64, bool WRAP>
+template <int K, int REC64, bool WRAP>
 __device__ __forceinline__ void force_group_f32(float4 *tile, const TabView &T, NodeArrays nd,
                                                 uint32_t n_g, uint32_t f, const uint32_t *list,
                                                 uint64_t Lg, const double4 *__restrict__ ps,
                                                 const uint32_t *__restrict__ pidx,
-                                                const GroupFrame &F, double scale, void *ax,
-                                                void *ay, void *az, uint32_t *kept_out)
+                                                const GroupFrame &F, double scale, void *rec,
+                                                uint32_t *kept_out)
 {
     const int lane = __lane_id();
     int J, Kl;
@@ -377,7 +382,7 @@ __device__ __forceinline__ void force_group_f32(float4 *tile, const TabView &T, 
             }
             const uint32_t i = ib + slot + S * k;
             if (stream == 0 && i < n_g)
-                store3<OUT64>(ax, ay, az, pidx[f + i], vx * scale, vy * scale, vz * scale);
+                store_rec<REC64>(rec, pidx[f + i], vx * scale, vy * scale, vz * scale);
         }
     }
     *kept_out = kept_total; // the same value on every lane
@@ -394,13 +399,13 @@ constexpr int force_waves_per_simd(int K) { return K <= 5 ? 4 : K <= 7 ? 3 : 2; 
 // sorted by decreasing cost n_g L_g (the longest lists first, so the last groups to finish
 // are short).  A workgroup starts on the part of its own XCD (workgroups are dealt to the
 // XCDs round-robin by block index) and then takes from the others'.
-template <int K, int OUT64>
+template <int K, int REC64>
 __global__ __launch_bounds__(64 * kForceWaves, force_waves_per_simd(K)) void k_force_f32(
     NodeArrays nd, GroupArrays gr, const uint32_t *__restrict__ ids,
     const uint32_t *__restrict__ part_start, uint32_t *queue, const uint64_t *__restrict__ off,
     const uint32_t *__restrict__ len, const uint32_t *__restrict__ entries,
     const double4 *__restrict__ ps, const uint32_t *__restrict__ pidx, ForceParams fp,
-    ForceTable ft, void *ax, void *ay, void *az)
+    ForceTable ft, void *rec)
 {
     extern __shared__ float4 smem[];
     for (uint32_t i = threadIdx.x; i < ft.entries; i += blockDim.x) smem[i] = ft.coef[i];
@@ -432,13 +437,13 @@ __global__ __launch_bounds__(64 * kForceWaves, force_waves_per_simd(K)) void k_f
                                   gr.loy[g] - rc >= 0.0 && gr.hiy[g] + rc < fp.L &&
                                   gr.loz[g] - rc >= 0.0 && gr.hiz[g] + rc < fp.L;
             if (interior)
-                force_group_f32<K, OUT64, false>(tile, T, nd, gr.count[g], gr.first[g],
+                force_group_f32<K, REC64, false>(tile, T, nd, gr.count[g], gr.first[g],
                                                  entries + off[g], len[g], ps, pidx, F, scale,
-                                                 ax, ay, az, fp.kept + g);
+                                                 rec, fp.kept + g);
             else
-                force_group_f32<K, OUT64, true>(tile, T, nd, gr.count[g], gr.first[g],
+                force_group_f32<K, REC64, true>(tile, T, nd, gr.count[g], gr.first[g],
                                                 entries + off[g], len[g], ps, pidx, F, scale,
-                                                ax, ay, az, fp.kept + g);
+                                                rec, fp.kept + g);
         }
     }
 }
@@ -612,12 +617,12 @@ constexpr int kTileF64 = 64;
 
 enum F64Kind { kF64Near = 0, kF64Far = 1, kF64Inner = 2 };
 
-template <int OUT64>
+template <int REC64>
 __global__ __launch_bounds__(64) void k_force_f64(
     NodeArrays nd, GroupArrays gr, uint32_t n_groups, const uint64_t *__restrict__ off,
     const uint32_t *__restrict__ len, const uint32_t *__restrict__ entries,
-    const double4 *__restrict__ ps, const uint32_t *__restrict__ pidx, ForceParams fp, void *ax,
-    void *ay, void *az)
+    const double4 *__restrict__ ps, const uint32_t *__restrict__ pidx, ForceParams fp,
+    void *rec)
 {
     __shared__ double4 tile[kTileF64];
     const uint32_t g = xcd_block(blockIdx.x, gridDim.x);
@@ -714,9 +719,41 @@ __global__ __launch_bounds__(64) void k_force_f64(
 #undef TPM_F64_PAIRS
             __syncthreads();
         }
-        if (act) store3<OUT64>(ax, ay, az, pidx[f + i], ax_, ay_, az_);
+        if (act) store_rec<REC64>(rec, pidx[f + i], ax_, ay_, az_);
     }
     if (lane == 0) fp.kept[g] = kept_total;
+}
+
+// The records in the caller's order, split into three arrays or applied as a kick (modes as
+// for store_rec; records are float4 for kOutF32, double4 otherwise).
+template <int MODE>
+__global__ __launch_bounds__(256) void k_force_out(const void *__restrict__ rec, int64_t n,
+                                                   void *ax, void *ay, void *az, double dt)
+{
+    // the kick's product and sum are rounded separately: no fused multiply-add here (the
+    // rest of this file contracts)
+#pragma clang fp contract(off)
+    for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < n;
+         j += (int64_t)gridDim.x * 256) {
+        if (MODE == kOutF32) {
+            const float4 r = ((const float4 *)rec)[j];
+            ((float *)ax)[j] = r.x;
+            ((float *)ay)[j] = r.y;
+            ((float *)az)[j] = r.z;
+        } else {
+            const double4 r = ((const double4 *)rec)[j];
+            if (MODE == kOutF64) {
+                ((double *)ax)[j] = r.x;
+                ((double *)ay)[j] = r.y;
+                ((double *)az)[j] = r.z;
+            } else {
+                double *const vx = (double *)ax, *const vy = (double *)ay, *const vz = (double *)az;
+                vx[j] = vx[j] + dt * r.x;
+                vy[j] = vy[j] + dt * r.y;
+                vz[j] = vz[j] + dt * r.z;
+            }
+        }
+    }
 }
 
 } // namespace
@@ -735,8 +772,8 @@ void launch_classify(GroupArrays gr, uint32_t n_groups, const uint32_t *len, uin
 void launch_force_f32(NodeArrays nd, GroupArrays gr, uint32_t *cls, const uint32_t *class_counts,
                       const uint64_t *off, const uint32_t *len, const uint32_t *entries,
                       const double4 *ps, const uint32_t *pidx, ForceParams fp, ForceTable ft,
-                      void *ax, void *ay, void *az, int out_prec, int n_cu,
-                      const hipStream_t *streams, int n_streams)
+                      void *rec, int rec64, int n_cu, const hipStream_t *streams,
+                      int n_streams)
 {
     const size_t lds = ((size_t)ft.entries + (size_t)kForceWaves * kTileF32) * sizeof(float4);
     int next = 0;
@@ -749,12 +786,12 @@ void launch_force_f32(NodeArrays nd, GroupArrays gr, uint32_t *cls, const uint32
         const uint32_t want = (waves + kForceWaves - 1) / kForceWaves;                         \
         const uint32_t blocks = want < cap ? want : cap;                                       \
         hipStream_t s = streams[next++ % n_streams];                                           \
-        if (out_prec)                                                                          \
+        if (rec64)                                                                             \
             k_force_f32<KK, 1><<<blocks, 64 * kForceWaves, lds, s>>>(                          \
-                nd, gr, cls, starts, queue, off, len, entries, ps, pidx, fp, ft, ax, ay, az);  \
+                nd, gr, cls, starts, queue, off, len, entries, ps, pidx, fp, ft, rec);         \
         else                                                                                   \
             k_force_f32<KK, 0><<<blocks, 64 * kForceWaves, lds, s>>>(                          \
-                nd, gr, cls, starts, queue, off, len, entries, ps, pidx, fp, ft, ax, ay, az);  \
+                nd, gr, cls, starts, queue, off, len, entries, ps, pidx, fp, ft, rec);         \
     }
     TPM_LAUNCH(8)
     TPM_LAUNCH(7)
@@ -794,16 +831,29 @@ void launch_kept_stats(GroupArrays gr, uint32_t n_groups, const uint32_t *kept,
 
 void launch_force_f64(NodeArrays nd, GroupArrays gr, uint32_t n_groups, const uint64_t *off,
                       const uint32_t *len, const uint32_t *entries, const double4 *ps, const uint32_t *pidx,
-                      ForceParams fp, void *ax, void *ay, void *az, int out_prec,
-                      hipStream_t s)
+                      ForceParams fp, void *rec, int rec64, hipStream_t s)
 {
     if (!n_groups) return;
-    if (out_prec)
-        k_force_f64<1><<<n_groups, 64, 0, s>>>(nd, gr, n_groups, off, len, entries, ps, pidx, fp,
-                                              ax, ay, az);
+    if (rec64)
+        k_force_f64<1><<<n_groups, 64, 0, s>>>(nd, gr, n_groups, off, len, entries, ps, pidx,
+                                              fp, rec);
     else
-        k_force_f64<0><<<n_groups, 64, 0, s>>>(nd, gr, n_groups, off, len, entries, ps, pidx, fp,
-                                              ax, ay, az);
+        k_force_f64<0><<<n_groups, 64, 0, s>>>(nd, gr, n_groups, off, len, entries, ps, pidx,
+                                              fp, rec);
+}
+
+void launch_force_out(const void *rec, int mode, int64_t n, void *ax, void *ay, void *az,
+                      double dt, hipStream_t s)
+{
+    if (n <= 0) return;
+    const int64_t want = (n + 255) / 256;
+    const unsigned b = (unsigned)(want < 4096 ? want : 4096);
+    if (mode == kOutKick)
+        k_force_out<kOutKick><<<b, 256, 0, s>>>(rec, n, ax, ay, az, dt);
+    else if (mode == kOutF64)
+        k_force_out<kOutF64><<<b, 256, 0, s>>>(rec, n, ax, ay, az, dt);
+    else
+        k_force_out<kOutF32><<<b, 256, 0, s>>>(rec, n, ax, ay, az, dt);
 }
 
 // ------------------------------------------------------------------ the pair-law table

@@ -11,7 +11,7 @@
 //    particles, an internal node from its children by the parallel-axis theorem);
 //  * k_quad<T>: one wave per group; its list's cell entries that can reach the group (gap to
 //    the group's box < r_cut) are gathered into LDS 64 at a time, and the lanes add their
-//    terms to the group's particles' accelerations (small groups spread each particle's
+//    terms to the group's particles' acceleration records (small groups spread each particle's
 //    cells over several lanes), in T = float (relative to the group's cube centre, as the
 //    FP32 force kernel; hardware reciprocal square roots) or double.
 #include "common.hpp"
@@ -124,7 +124,7 @@ struct alignas(4 * sizeof(T)) QuadCell {
 // are added with lane shuffles at the end.
 constexpr int kQuadK = 4;
 
-template <typename T, int OUT64, int WRAP>
+template <typename T, int REC64, int WRAP>
 __global__ __launch_bounds__(64) void k_quad(NodeArrays nd, GroupArrays gr, uint32_t n_groups,
                                              const uint64_t *__restrict__ off,
                                              const uint32_t *__restrict__ len,
@@ -132,7 +132,7 @@ __global__ __launch_bounds__(64) void k_quad(NodeArrays nd, GroupArrays gr, uint
                                              const double4 *__restrict__ ps,
                                              const uint32_t *__restrict__ pidx,
                                              const double *__restrict__ Q, ForceParams fp,
-                                             void *ax, void *ay, void *az)
+                                             void *rec)
 {
     __shared__ QuadCell<T> tile[kQuadTile];
     const uint32_t g = xcd_block(blockIdx.x, gridDim.x);
@@ -275,14 +275,16 @@ __global__ __launch_bounds__(64) void k_quad(NodeArrays nd, GroupArrays gr, uint
             const uint32_t i = ib + slot + k * S;
             if (i < n_g && ph == 0) {
                 const uint32_t o = pidx[f + i];
-                if (OUT64) {
-                    ((double *)ax)[o] += double(ax_[k]);
-                    ((double *)ay)[o] += double(ay_[k]);
-                    ((double *)az)[o] += double(az_[k]);
+                if (REC64) {
+                    double4 *const r = (double4 *)rec + o;
+                    r->x += double(ax_[k]);
+                    r->y += double(ay_[k]);
+                    r->z += double(az_[k]);
                 } else {
-                    ((float *)ax)[o] += float(ax_[k]);
-                    ((float *)ay)[o] += float(ay_[k]);
-                    ((float *)az)[o] += float(az_[k]);
+                    float4 *const r = (float4 *)rec + o;
+                    r->x += float(ax_[k]);
+                    r->y += float(ay_[k]);
+                    r->z += float(az_[k]);
                 }
             }
         }
@@ -302,24 +304,24 @@ void launch_second_moments(NodeArrays nd, const double4 *ps, uint32_t lo, uint32
 
 void launch_quad(NodeArrays nd, GroupArrays gr, uint32_t n_groups, const uint64_t *off,
                  const uint32_t *len, const uint32_t *entries, const double4 *ps,
-                 const uint32_t *pidx, const double *Q, ForceParams fp, void *ax, void *ay,
-                 void *az, int fp64_math, int out_prec, hipStream_t s)
+                 const uint32_t *pidx, const double *Q, ForceParams fp, void *rec,
+                 int fp64_math, int rec64, hipStream_t s)
 {
     if (!n_groups) return;
     if (fp64_math) {
-        if (out_prec)
+        if (rec64)
             k_quad<double, 1, 1><<<n_groups, 64, 0, s>>>(nd, gr, n_groups, off, len, entries,
-                                                         ps, pidx, Q, fp, ax, ay, az);
+                                                         ps, pidx, Q, fp, rec);
         else
             k_quad<double, 0, 1><<<n_groups, 64, 0, s>>>(nd, gr, n_groups, off, len, entries,
-                                                         ps, pidx, Q, fp, ax, ay, az);
+                                                         ps, pidx, Q, fp, rec);
     } else {
-        if (out_prec)
+        if (rec64)
             k_quad<float, 1, 0><<<n_groups, 64, 0, s>>>(nd, gr, n_groups, off, len, entries,
-                                                        ps, pidx, Q, fp, ax, ay, az);
+                                                        ps, pidx, Q, fp, rec);
         else
             k_quad<float, 0, 0><<<n_groups, 64, 0, s>>>(nd, gr, n_groups, off, len, entries,
-                                                        ps, pidx, Q, fp, ax, ay, az);
+                                                        ps, pidx, Q, fp, rec);
     }
 }
 

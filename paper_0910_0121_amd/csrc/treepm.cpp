@@ -56,7 +56,9 @@ struct treepm_ctx {
     bool ev_valid[3] = {false, false, false};
     // particles and sort
     Buf in[4], key, key_alt, idx, idx_alt, hist, scan32, flags, levcnt, gstart, gflag;
-    Buf rec; // (x, y, z, m) records in input order, for the gather
+    // Per particle in input order, 32 bytes: the build's (x, y, z, m) records for the gather;
+    // after the build, the force's acceleration records (float4 or double4).
+    Buf rec;
     // nodes
     Buf n_code, n_first, n_count, n_cf, n_parent, n_nch, n_level, n_mass, n_com[3], n_cn[3];
     Buf n_walk; // packed per-node walk records
@@ -898,18 +900,16 @@ int ensure_table(treepm_ctx *c, hipStream_t s)
 
 } // namespace
 
-TREEPM_API int treepm_force_short(treepm_ctx *c, void *ax, void *ay, void *az, int out_prec,
-                                  int mem_kind, void *hip_stream)
+namespace {
+
+// The short-range force into ax, ay, az: out mode 0 / 1 stores float / double accelerations,
+// 2 (kick) adds kick_dt times them to double velocities.  Arguments checked by the caller.
+// The kernels leave one record per particle in c->rec (free once the build has gathered from
+// it), which a last pass writes out in the caller's order.
+int do_force_short(treepm_ctx *c, void *ax, void *ay, void *az, int out_prec, int mem_kind,
+                   void *hip_stream, double kick_dt)
 {
-    if (!c) return TREEPM_ERR_ARG;
     int rc;
-    if (c->state < 2) return fail(c, TREEPM_ERR_STATE, "treepm_force_short needs a walk");
-    c->err.clear();
-    if (!ax || !ay || !az) return fail(c, TREEPM_ERR_ARG, "NULL output buffer");
-    if (out_prec != TREEPM_FP32 && out_prec != TREEPM_FP64)
-        return fail(c, TREEPM_ERR_ARG, "out_prec must be TREEPM_FP32 or TREEPM_FP64");
-    if (mem_kind != TREEPM_HOST && mem_kind != TREEPM_DEVICE)
-        return fail(c, TREEPM_ERR_ARG, "mem_kind must be TREEPM_HOST or TREEPM_DEVICE");
     const treepm_params &P = c->prm;
     if (P.precision == TREEPM_FP32) {
         // Positions are taken relative to the group's cube centre with one image per list
@@ -926,7 +926,7 @@ TREEPM_API int treepm_force_short(treepm_ctx *c, void *ax, void *ay, void *az, i
     hipStream_t s = (hipStream_t)hip_stream;
     c->last = s;
     CallScope scope(c, s);
-    size_t esz = out_prec == TREEPM_FP64 ? 8 : 4;
+    size_t esz = out_prec == TREEPM_FP32 ? 4 : 8;
     void *dst[3] = {ax, ay, az};
     if (mem_kind == TREEPM_HOST) {
         for (int a = 0; a < 3; ++a) {
@@ -946,6 +946,8 @@ TREEPM_API int treepm_force_short(treepm_ctx *c, void *ax, void *ay, void *az, i
     }
     ForceParams fp{P.L, P.eps * P.eps, 1.0 / eta, eta, P.r_cut * P.r_cut, P.r_cut,
                    c->kept.as<uint32_t>()};
+    const int rec64 = out_prec != TREEPM_FP32;
+    void *rec = c->rec.p; // n x 32 bytes since the build
     if (P.precision == TREEPM_FP32) {
         if ((rc = ensure_table(c, s))) return rc;
         hipStream_t streams[1 + treepm_ctx::kSubStreams] = {s};
@@ -960,8 +962,8 @@ TREEPM_API int treepm_force_short(treepm_ctx *c, void *ax, void *ay, void *az, i
         }
         launch_force_f32(nd, gr, c->cls.as<uint32_t>(), c->class_counts, c->off.as<uint64_t>(),
                          c->glen.as<uint32_t>(), c->entries.as<uint32_t>(),
-                         c->psrc.as<double4>(), c->idx.as<uint32_t>(), fp, c->ftab, dst[0],
-                         dst[1], dst[2], out_prec, c->n_cu, streams, ns);
+                         c->psrc.as<double4>(), c->idx.as<uint32_t>(), fp, c->ftab, rec, rec64,
+                         c->n_cu, streams, ns);
         if (c->fork)
             for (int i = 0; i < treepm_ctx::kSubStreams; ++i) {
                 HIPCHK(c, hipEventRecord(c->join[i], c->sub[i]));
@@ -970,13 +972,12 @@ TREEPM_API int treepm_force_short(treepm_ctx *c, void *ax, void *ay, void *az, i
     } else
         launch_force_f64(nd, gr, c->n_groups, c->off.as<uint64_t>(), c->glen.as<uint32_t>(),
                          c->entries.as<uint32_t>(),
-                         c->psrc.as<double4>(), c->idx.as<uint32_t>(), fp, dst[0], dst[1],
-                         dst[2], out_prec, s);
+                         c->psrc.as<double4>(), c->idx.as<uint32_t>(), fp, rec, rec64, s);
     if (P.quadrupole)
         launch_quad(nd, gr, c->n_groups, c->off.as<uint64_t>(), c->glen.as<uint32_t>(),
                     c->entries.as<uint32_t>(), c->psrc.as<double4>(), c->idx.as<uint32_t>(),
-                    c->n_q.as<double>(), fp, dst[0], dst[1], dst[2],
-                    P.precision == TREEPM_FP64, out_prec, s);
+                    c->n_q.as<double>(), fp, rec, P.precision == TREEPM_FP64, rec64, s);
+    launch_force_out(rec, out_prec, (int64_t)c->n, dst[0], dst[1], dst[2], kick_dt, s);
     HIPCHK(c, hipGetLastError());
     record(c, 5, s);
     launch_kept_stats(gr, c->n_groups, c->kept.as<uint32_t>(),
@@ -991,6 +992,41 @@ TREEPM_API int treepm_force_short(treepm_ctx *c, void *ax, void *ay, void *az, i
         HIPCHK(c, hipStreamSynchronize(s));
     }
     return TREEPM_OK;
+}
+
+} // namespace
+
+TREEPM_API int treepm_force_short(treepm_ctx *c, void *ax, void *ay, void *az, int out_prec,
+                                  int mem_kind, void *hip_stream)
+{
+    if (!c) return TREEPM_ERR_ARG;
+    if (c->state < 2) return fail(c, TREEPM_ERR_STATE, "treepm_force_short needs a walk");
+    c->err.clear();
+    if (!ax || !ay || !az) return fail(c, TREEPM_ERR_ARG, "NULL output buffer");
+    if (out_prec != TREEPM_FP32 && out_prec != TREEPM_FP64)
+        return fail(c, TREEPM_ERR_ARG, "out_prec must be TREEPM_FP32 or TREEPM_FP64");
+    if (mem_kind != TREEPM_HOST && mem_kind != TREEPM_DEVICE)
+        return fail(c, TREEPM_ERR_ARG, "mem_kind must be TREEPM_HOST or TREEPM_DEVICE");
+    return do_force_short(c, ax, ay, az, out_prec, mem_kind, hip_stream, 0.0);
+}
+
+static bool device_array(const void *p, int device);
+
+TREEPM_API int treepm_kick_short(treepm_ctx *c, double *vx, double *vy, double *vz, double dt,
+                                 void *hip_stream)
+{
+    if (!c) return TREEPM_ERR_ARG;
+    if (c->state < 2) return fail(c, TREEPM_ERR_STATE, "treepm_kick_short needs a walk");
+    c->err.clear();
+    if (!vx || !vy || !vz) return fail(c, TREEPM_ERR_ARG, "NULL velocity array");
+    if (!std::isfinite(dt)) return fail(c, TREEPM_ERR_ARG, "dt must be finite");
+    if (c->prm.quadrupole)
+        return fail(c, TREEPM_ERR_ARG, "treepm_kick_short does not take quadrupole boxes");
+    HIPCHK(c, hipSetDevice(c->device));
+    for (const void *p : {(const void *)vx, (const void *)vy, (const void *)vz})
+        if (!device_array(p, c->device))
+            return fail(c, TREEPM_ERR_ARG, "treepm_kick_short takes device arrays");
+    return do_force_short(c, vx, vy, vz, 2, TREEPM_DEVICE, hip_stream, dt);
 }
 
 TREEPM_API int treepm_force_long(treepm_ctx *c, void *ax, void *ay, void *az, int out_prec,

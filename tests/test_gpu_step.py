@@ -148,3 +148,47 @@ def test_two_body_orbit_on_gpu(tp, orc):
     _say(f"  max |x_gpu - x_oracle| / r0 = {err / r0:.2e}")
     assert err <= 1e-6 * r0
     assert abs(np.linalg.norm(gx[1] - gx[0]) / r0 - 1.0) < 1e-2
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_kick_short_is_the_force_then_the_kick(tp, prec):
+    """treepm_kick_short (the kick fused with the short-range force, Section 2.2 step 5) leaves
+    v + dt a in the velocity arrays, bit for bit, with a the acceleration of
+    treepm_force_short on the same walk; quadrupole boxes and host arrays are refused."""
+    _say(f"kick_short {prec}")
+    n = 20000
+    x, y, z, m = boxgen.nfw_box(n, 50, 31)
+    r_cut = 0.06
+    precision = tp.TREEPM_FP32 if prec == "fp32" else tp.TREEPM_FP64
+    p = tp.make_params(1.0, r_cut / 3, r_cut, r_cut / 60, 0.5, 10, 64, precision)
+    ctx = tp.treepm_create(p, 0)
+    try:
+        dev = [torch.from_numpy(a).cuda() for a in (x, y, z, m)]
+        tp.treepm_build(ctx, *dev)
+        tp.treepm_walk(ctx)
+        acc = [torch.zeros(n, dtype=torch.float64, device="cuda") for _ in range(3)]
+        tp.treepm_force_short(ctx, *acc)
+        v0 = _rand(n, 7) - 0.5
+        vel = [torch.from_numpy(np.ascontiguousarray(v0[:, c])).cuda() for c in range(3)]
+        dt = 3.7e-3
+        tp.treepm_kick_short(ctx, *vel, dt)
+        torch.cuda.synchronize()
+        a = np.stack([t.cpu().numpy() for t in acc], axis=1)
+        got = np.stack([t.cpu().numpy() for t in vel], axis=1)
+        ref = v0 + dt * a
+        np.testing.assert_array_equal(got, ref)
+        assert np.abs(a).max() > 0
+        with pytest.raises(ValueError):
+            tp.treepm_kick_short(ctx, *[t.cpu() for t in vel], dt)
+    finally:
+        tp.treepm_destroy(ctx)
+    pq = tp.make_params(1.0, r_cut / 3, r_cut, r_cut / 60, 0.5, 10, 64, precision, quadrupole=1)
+    ctx = tp.treepm_create(pq, 0)
+    try:
+        tp.treepm_build(ctx, *dev)
+        tp.treepm_walk(ctx)
+        with pytest.raises(tp.TreePMError) as e:
+            tp.treepm_kick_short(ctx, *vel, dt)
+        assert e.value.code == -1
+    finally:
+        tp.treepm_destroy(ctx)
