@@ -2,7 +2,11 @@
 //
 // One 64-lane wavefront walks one group.  A stack of node indices lives in LDS; each step
 // pops up to 64 nodes (one per lane), tests them in parallel and uses wave prefix sums to
-// place the entries they emit and the children they push.  For each node, in FP64 and
+// place the entries they emit and the children they push.  A step pops only as many nodes as
+// leave kStackReserve slots free after their pushes (each pushes at most 8); when not even
+// one fits, it pops one node, which continues the walk depth first: from a node at level l
+// that needs at most 7 more slots per level below l, so the stack never outgrows kStackCap
+// (wide walks, such as theta = 0, slow down instead of failing).  For each node, in FP64 and
 // without FMA contraction (so the decisions equal a plain IEEE evaluation bit for bit):
 //
 //   prune  (beyond the cutoff from the group's box, cf. Section 2.2 step 3):
@@ -33,6 +37,7 @@ namespace tpm {
 namespace {
 
 constexpr int kStackCap = 1024;
+constexpr int kStackReserve = 7 * kMaxLevel; // a depth-first descent from the root's children
 constexpr uint32_t kWalkBatch = 4;
 
 // |wrap(v)| for |v| <= L (both points in [0, L)): min(|v|, L - |v|).  Bit for bit the
@@ -170,8 +175,8 @@ __device__ __forceinline__ uint64_t walk_group(const WalkNode *__restrict__ wn,
     int top = 1;
     __syncthreads();
     while (top > 0) {
-        // a popped node pushes at most 8 children: top - k + 8k <= kStackCap
-        int room = (kStackCap - top) / 7;
+        // a popped node pushes at most 8 children: top - k + 8k <= kStackCap - kStackReserve
+        int room = (kStackCap - kStackReserve - top) / 7;
         int k = top < 64 ? top : 64;
         if (room < 1) room = 1;
         if (k > room) k = room;
