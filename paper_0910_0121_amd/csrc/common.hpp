@@ -108,7 +108,25 @@ void launch_split(NodeArrays nd, const uint64_t *key, uint32_t lo, uint32_t hi, 
 // Emit children of nodes [lo, hi) at base + exclusive prefix in cnt, from the bounds in bnd.
 void launch_emit(NodeArrays nd, const uint32_t *bnd, uint32_t lo, uint32_t hi, int level,
                  uint32_t base, const uint32_t *cnt, double L, hipStream_t s);
-void launch_moments(NodeArrays nd, const double4 *ps, uint32_t lo, uint32_t hi, hipStream_t s);
+// derive = 1 for a tree from launch_tree_emit: nchild and internal counts are set here, the
+// children of the level's nodes being the nodes [child_first[lo], child_end).
+void launch_moments(NodeArrays nd, const double4 *ps, uint32_t lo, uint32_t hi, int derive,
+                    uint32_t child_end, hipStream_t s);
+// The octree straight from the sorted keys (n >= 1, n_leaf - 1 <= kTreeWin): the same nodes in
+// the same order as the level-by-level split.  launch_tree_levels writes per particle the
+// levels of the nodes that start there and its leaf's count (sl, n words), per block of tree_blocks(n) the counts
+// per level (blk, kMaxLevel + 1 rows of tree_blocks(n) words, left as exclusive prefixes) and
+// the nodes per level into tot (kMaxLevel + 1 words).  With off[] from tot, launch_tree_emit
+// writes every node but nchild and the internal counts (left to the moments with derive = 1).
+constexpr int kTreeWin = 256;
+struct TreeOffsets {
+    uint32_t off[kMaxLevel + 3]; // first node of each level; off[22] = off[23] = node count
+};
+uint32_t tree_blocks(int64_t n);
+void launch_tree_levels(const uint64_t *key, uint32_t n, int n_leaf, uint32_t *sl, uint32_t *blk,
+                        uint32_t *tot, hipStream_t s);
+void launch_tree_emit(NodeArrays nd, const uint64_t *key, const uint32_t *sl, const uint32_t *blk,
+                      const TreeOffsets &to, uint32_t n, double L, hipStream_t s);
 // com = S / M for every node, after all levels' moments; also fills the walk records.
 void launch_com_divide(NodeArrays nd, uint32_t n_nodes, WalkNode *wn, hipStream_t s);
 // Groups: mark in gstart[first] (n values, zeroed here) every maximal node with

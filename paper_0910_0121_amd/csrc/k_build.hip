@@ -473,13 +473,309 @@ __global__ __launch_bounds__(256) void k_emit(NodeArrays nd, const uint32_t *__r
     }
 }
 
+// ---------------------------------------------------------------- octree from the sorted keys
+// The tree of the level-by-level split, built in three passes without per-level searches.
+// With d_i the number of levels (leading key digits) particle i shares with particle i - 1,
+// particle i is the first particle of one cell at every level from s_i = d_i + 1 on (s_0 = 0:
+// the root).  A cell at level l >= 1 is a node iff its parent cell holds at least n_leaf
+// particles and l <= 21; counts only shrink down the tree, so the parent's ancestors are then
+// subdivided too.  The parent of particle i's level-l cell holds at least n_leaf particles iff
+// some n_leaf consecutive particles including i share l - 1 levels; so with m_a the levels
+// particles a and a + n_leaf - 1 share, lambda_i = max of m_a over the windows
+// a = i - n_leaf + 1 .. i, i's leaf is at level L_i = min(lambda_i + 1, 21) (L_i = 0 if the box
+// holds fewer than n_leaf particles), and the nodes that start at particle i are its cells at
+// levels s_i .. L_i.  Stored level by level and within a level by first particle (the order
+// the level-by-level split produces), node (l, i) has index off[l] + (level-l nodes that start
+// before i); its first child, if any, is node (l + 1, i); its parent is the last level-(l - 1)
+// node that starts at or before i.
+constexpr int kTreeThreads = 256;
+constexpr int kTreeItems = 16;
+constexpr int kTreeTile = kTreeThreads * kTreeItems;
+constexpr int kTreeLevels = kMaxLevel + 1;
+constexpr uint32_t kTreeLong = 0x3fffffu; // leaf count not found within the window
+
+// This wave's LDS writes are complete before any of its lanes reads LDS again.
+__device__ __forceinline__ void wave_sync_lds()
+{
+    __builtin_amdgcn_s_waitcnt(0xc07f); // lgkmcnt(0); vector memory counters untouched
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Levels two keys share: 21 if equal, else the number of equal leading 3-bit digits.
+__device__ __forceinline__ int shared_levels(uint64_t a, uint64_t b)
+{
+    const uint64_t x = a ^ b;
+    if (!x) return kMaxLevel;
+    const int h = 63 - (int)__clzll((long long)x);
+    return kMaxLevel - 1 - h / 3;
+}
+
+// Per particle i a packed word: s_i (bits 0-4; 22 if no node starts there), L_i (bits 5-9)
+// and, if a node starts at i, the particle count of its leaf (L_i, i) (bits 10-31; kTreeLong if
+// that leaf is a level-21 cell longer than the window, found later by a search).  Per block,
+// the number of nodes of each level that start in its tile: blk[l * nblk + b].  The block
+// keeps in LDS, as bytes, the levels shared by each window and the first level of a cell at
+// each particle, over [b0 - W, b0 + tile + W), W = n_leaf - 1: the window maxima need W
+// windows before the tile, and a leaf below level 21 holds fewer than n_leaf particles, so its
+// end lies within W particles after its first.
+__device__ __forceinline__ uint32_t tree_word(int s, int Lf, uint32_t cnt)
+{
+    return (uint32_t)s | ((uint32_t)Lf << 5) | (cnt << 10);
+}
+
+__global__ __launch_bounds__(kTreeThreads) void k_tree_levels(const uint64_t *__restrict__ key,
+                                                             uint32_t n, int n_leaf,
+                                                             uint32_t *__restrict__ sl,
+                                                             uint32_t *__restrict__ blk,
+                                                             uint32_t nblk)
+{
+    __shared__ uint8_t ms[kTreeTile + kTreeWin];
+    __shared__ uint8_t ss[kTreeTile + kTreeWin];
+    __shared__ uint32_t lc[kTreeLevels];
+    const uint32_t b = blockIdx.x;
+    const int W = n_leaf - 1;
+    const int64_t b0 = (int64_t)b * kTreeTile, k0 = b0 - W;
+    if (threadIdx.x < kTreeLevels) lc[threadIdx.x] = 0u;
+    // ms[t]: levels shared by the window a = k0 + t (its first and last particle), 0xff if
+    // there is no such window (a < 0 or a + W >= n); ss[t]: s of particle j = b0 + t, the
+    // first level of a cell starting there (0 for the first particle; 0xff past the end)
+    const int64_t last_a = (int64_t)n - n_leaf;
+    for (int t = threadIdx.x; t < kTreeTile + W; t += kTreeThreads) {
+        const int64_t a = k0 + t;
+        ms[t] = (a >= 0 && a <= last_a) ? (uint8_t)shared_levels(key[a], key[a + W])
+                                        : (uint8_t)0xff;
+        const int64_t j = b0 + t;
+        ss[t] = j >= (int64_t)n ? (uint8_t)0xff
+                : j == 0        ? (uint8_t)0
+                                : (uint8_t)(shared_levels(key[j - 1], key[j]) + 1);
+    }
+    __syncthreads();
+    // item q of thread x is particle b0 + q * kTreeThreads + x (neighbouring lanes read
+    // neighbouring LDS bytes); lm[q]: the levels s .. L of the nodes that start there
+    uint32_t lm[kTreeItems];
+#pragma unroll
+    for (int q = 0; q < kTreeItems; ++q) {
+        const int tt = q * kTreeThreads + (int)threadIdx.x; // particle b0 + tt
+        const int64_t i = b0 + tt;
+        lm[q] = 0u;
+        if (i >= (int64_t)n) continue;
+        const int t = tt + W; // position of window i in ms
+        const int s = ss[tt];
+        int lam = -1;
+        for (int a = t - W; a <= t; ++a) {
+            const int m = ms[a];
+            if (m != 0xff && m > lam) lam = m;
+        }
+        const int Lf = (int64_t)n < n_leaf ? 0 : min(lam + 1, kMaxLevel);
+        uint32_t cnt = 0;
+        if (s <= Lf) {
+            // the leaf (Lf, i) ends at the first j > i where a cell of level <= Lf starts
+            // (ss = 0xff past the last particle ends it too); below level 21 it holds at
+            // most W particles, so the end lies within W
+            cnt = kTreeLong;
+            for (int d = 1; d <= W; ++d) {
+                if (ss[tt + d] <= Lf || ss[tt + d] == 0xff) {
+                    cnt = (uint32_t)d;
+                    break;
+                }
+            }
+            lm[q] = (2u << Lf) - (1u << s);
+        }
+        sl[i] = tree_word(s <= Lf ? s : 22, Lf, cnt);
+    }
+    // nodes per level starting in this tile: one ballot per level and item, one LDS add per
+    // level and wave
+#pragma unroll
+    for (int l = 0; l < kTreeLevels; ++l) {
+        uint32_t c = 0;
+#pragma unroll
+        for (int q = 0; q < kTreeItems; ++q) c += (uint32_t)__popcll(__ballot((lm[q] >> l) & 1u));
+        if ((threadIdx.x & 63) == 0 && c) atomicAdd(&lc[l], c);
+    }
+    __syncthreads();
+    if (threadIdx.x < kTreeLevels) blk[(size_t)threadIdx.x * nblk + b] = lc[threadIdx.x];
+}
+
+// One block per level: exclusive prefix over the blocks' counts, in place; the level's total
+// into tot[l].
+__global__ __launch_bounds__(1024) void k_tree_scan(uint32_t *__restrict__ blk, uint32_t nblk,
+                                                    uint32_t *__restrict__ tot)
+{
+    __shared__ uint32_t part[1024];
+    uint32_t *row = blk + (size_t)blockIdx.x * nblk;
+    const uint32_t per = (nblk + 1023) / 1024;
+    const uint32_t lo = min(threadIdx.x * per, nblk), hi = min(lo + per, nblk);
+    uint32_t sum = 0;
+    for (uint32_t j = lo; j < hi; ++j) sum += row[j];
+    part[threadIdx.x] = sum;
+    __syncthreads();
+    for (int d = 1; d < 1024; d <<= 1) {
+        const uint32_t v = (int)threadIdx.x >= d ? part[threadIdx.x - d] : 0u;
+        __syncthreads();
+        part[threadIdx.x] += v;
+        __syncthreads();
+    }
+    uint32_t run = threadIdx.x ? part[threadIdx.x - 1] : 0u;
+    for (uint32_t j = lo; j < hi; ++j) {
+        const uint32_t v = row[j];
+        row[j] = run;
+        run += v;
+    }
+    if (threadIdx.x == 1023) tot[blockIdx.x] = part[1023];
+}
+
+// First particle after i outside the cell that holds i at the level of shift sh (p = key[i]
+// >> sh): a doubling search, then bisection.
+__device__ __forceinline__ uint32_t cell_end(const uint64_t *__restrict__ key, uint32_t n,
+                                             uint32_t i, int sh, uint64_t p)
+{
+    uint64_t lo = i, hi = n, step = 1;
+    for (;;) {
+        const uint64_t j = lo + step;
+        if (j >= n) break;
+        if ((key[j] >> sh) != p) {
+            hi = j;
+            break;
+        }
+        lo = j;
+        step <<= 1;
+    }
+    while (hi - lo > 1) { // key[lo] is in the cell, hi is not (or n)
+        const uint64_t mid = lo + ((hi - lo) >> 1);
+        if ((key[mid] >> sh) == p)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return (uint32_t)hi;
+}
+
+// Every node, at its index: code, first, level, parent, cube centre, child_first = the index
+// its first child has or would have (the moments pass derives nchild from it), and the count
+// of leaves (internal counts are summed by the moments pass).  Level by level, each wave lists
+// the particles of its tile part at which a node of that level starts (in particle order, so
+// in node order) and then writes 64 consecutive nodes at a time.  msk[l][t]: which of thread
+// t's 16 particles start a level-l node; cur[l][t]: the index of the first of them.
+__global__ __launch_bounds__(kTreeThreads) void k_tree_emit(NodeArrays nd,
+                                                           const uint64_t *__restrict__ key,
+                                                           const uint32_t *__restrict__ sl,
+                                                           const uint32_t *__restrict__ blk,
+                                                           uint32_t nblk, TreeOffsets to,
+                                                           uint32_t n, double L)
+{
+    __shared__ uint32_t cur[kTreeLevels][kTreeThreads];
+    __shared__ uint16_t msk[kTreeLevels][kTreeThreads];
+    __shared__ uint16_t lst[kTreeThreads / 64][64 * kTreeItems];
+    const uint32_t b = blockIdx.x, tid = threadIdx.x;
+    const int64_t b0 = (int64_t)b * kTreeTile;
+    const int64_t i0 = b0 + (int64_t)tid * kTreeItems;
+    uint32_t w[kTreeItems];
+#pragma unroll
+    for (int q = 0; q < kTreeItems; ++q) {
+        const int64_t i = i0 + q;
+        w[q] = i < (int64_t)n ? sl[i] : 22u; // s = 22: no node
+    }
+    for (int l = 0; l < kTreeLevels; ++l) {
+        uint32_t m = 0;
+#pragma unroll
+        for (int q = 0; q < kTreeItems; ++q) {
+            const int s = (int)(w[q] & 31u), Lf = (int)((w[q] >> 5) & 31u);
+            m |= (s <= l && l <= Lf) ? (1u << q) : 0u;
+        }
+        msk[l][tid] = (uint16_t)m;
+        cur[l][tid] = (uint32_t)__popc(m);
+    }
+    __syncthreads();
+    // each level's counts, exclusive prefix over the threads (wave v takes levels v, v + 4,
+    // ...; a lane holds four threads' counts), plus the level offset and the block's base
+    const int wave = tid >> 6, lane = tid & 63;
+    for (int l = wave; l < kTreeLevels; l += kTreeThreads / 64) {
+        const uint32_t x0 = cur[l][4 * lane], x1 = cur[l][4 * lane + 1],
+                       x2 = cur[l][4 * lane + 2], x3 = cur[l][4 * lane + 3];
+        const uint32_t s4 = x0 + x1 + x2 + x3;
+        uint32_t incl = s4;
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t y = (uint32_t)__shfl_up((int)incl, d, 64);
+            if (lane >= d) incl += y;
+        }
+        uint32_t ex = incl - s4 + blk[(size_t)l * nblk + b] + to.off[l];
+        cur[l][4 * lane] = ex;
+        ex += x0;
+        cur[l][4 * lane + 1] = ex;
+        ex += x1;
+        cur[l][4 * lane + 2] = ex;
+        ex += x2;
+        cur[l][4 * lane + 3] = ex;
+    }
+    __syncthreads();
+    uint16_t *my = lst[wave];
+    const uint32_t t0 = (uint32_t)wave * 64; // first thread of this wave
+    for (int l = 0; l < kTreeLevels; ++l) {
+        const uint32_t base = cur[l][t0];
+        const uint32_t total = cur[l][t0 + 63] + (uint32_t)__popc(msk[l][t0 + 63]) - base;
+        if (!total) continue; // the same on every lane
+        // list this lane's particles in node order
+        uint32_t m = msk[l][tid], pos = cur[l][tid] - base;
+        while (m) {
+            const int q = __ffs((int)m) - 1;
+            m &= m - 1u;
+            my[pos++] = (uint16_t)(tid * kTreeItems + q);
+        }
+        wave_sync_lds();
+        const int sh = 3 * (kMaxLevel - l);
+        for (uint32_t j = lane; j < total; j += 64) {
+            const uint32_t p = my[j];
+            const uint32_t t = p >> 4, q = p & 15u;
+            const uint32_t i = (uint32_t)b0 + p;
+            const uint32_t u = base + j;
+            const uint64_t k = key[i];
+            const uint64_t code = (k >> sh) | (1ull << (3 * l));
+            nd.code[u] = code;
+            nd.first[u] = i;
+            nd.level[u] = (uint8_t)l;
+            nd.nchild[u] = 0;
+            nd.parent[u] =
+                l ? cur[l - 1][t] + (uint32_t)__popc(msk[l - 1][t] & ((2u << q) - 1u)) - 1u : 0u;
+            nd.child_first[u] =
+                l < kMaxLevel ? cur[l + 1][t] + (uint32_t)__popc(msk[l + 1][t] & ((1u << q) - 1u))
+                              : to.off[kTreeLevels];
+            const uint32_t wi = sl[i];
+            uint32_t cnt = 0;
+            if ((int)((wi >> 5) & 31u) == l) {
+                cnt = wi >> 10;
+                if (cnt == kTreeLong) cnt = cell_end(key, n, i, sh, k >> sh) - i;
+            }
+            nd.count[u] = cnt;
+            double cc[3];
+            cube_centre(code, l, L, cc);
+            nd.cnx[u] = cc[0];
+            nd.cny[u] = cc[1];
+            nd.cnz[u] = cc[2];
+        }
+        wave_sync_lds(); // the list is read before the next level rewrites it
+    }
+}
+
+// Moments of the nodes [lo, hi) of one level, from their particles (leaves) or their children
+// in octant order.  DERIVE (a tree from k_tree_emit): a node's children are the next level's
+// nodes from its child_first up to the child_first of the next node of its level (child_end
+// after the level's last node), so nchild is set here, and an internal node's count is the sum
+// of its children's.
+template <int DERIVE>
 __global__ __launch_bounds__(256) void k_moments(NodeArrays nd, const double4 *__restrict__ ps,
-                                                 uint32_t lo, uint32_t hi)
+                                                 uint32_t lo, uint32_t hi, uint32_t child_end)
 {
     for (uint32_t u = lo + blockIdx.x * blockDim.x + threadIdx.x; u < hi;
          u += gridDim.x * blockDim.x) {
         double M = 0.0, Sx = 0.0, Sy = 0.0, Sz = 0.0;
-        uint32_t nch = nd.nchild[u];
+        uint32_t nch;
+        if (DERIVE) {
+            const uint32_t nx = u + 1 < hi ? nd.child_first[u + 1] : child_end;
+            nch = nx - nd.child_first[u];
+            nd.nchild[u] = (uint8_t)nch;
+        } else {
+            nch = nd.nchild[u];
+        }
         if (nch == 0) {
             uint32_t f = nd.first[u], e = f + nd.count[u];
             for (uint32_t k = f; k < e; ++k) {
@@ -491,12 +787,15 @@ __global__ __launch_bounds__(256) void k_moments(NodeArrays nd, const double4 *_
             }
         } else {
             uint32_t cf = nd.child_first[u];
+            uint32_t cnt = 0;
             for (uint32_t c = cf; c < cf + nch; ++c) {
                 M += nd.mass[c];
                 Sx += nd.comx[c];
                 Sy += nd.comy[c];
                 Sz += nd.comz[c];
+                if (DERIVE) cnt += nd.count[c];
             }
+            if (DERIVE) nd.count[u] = cnt;
         }
         nd.mass[u] = M;
         nd.comx[u] = Sx;
@@ -735,9 +1034,31 @@ void launch_emit(NodeArrays nd, const uint32_t *bnd, uint32_t lo, uint32_t hi, i
     k_emit<<<grid_for(hi - lo, 256), 256, 0, s>>>(nd, bnd, lo, hi, level, base, cnt, L);
 }
 
-void launch_moments(NodeArrays nd, const double4 *ps, uint32_t lo, uint32_t hi, hipStream_t s)
+void launch_moments(NodeArrays nd, const double4 *ps, uint32_t lo, uint32_t hi, int derive,
+                    uint32_t child_end, hipStream_t s)
 {
-    k_moments<<<grid_for(hi - lo, 256), 256, 0, s>>>(nd, ps, lo, hi);
+    if (hi <= lo) return;
+    if (derive)
+        k_moments<1><<<grid_for(hi - lo, 256), 256, 0, s>>>(nd, ps, lo, hi, child_end);
+    else
+        k_moments<0><<<grid_for(hi - lo, 256), 256, 0, s>>>(nd, ps, lo, hi, child_end);
+}
+
+uint32_t tree_blocks(int64_t n) { return (uint32_t)((n + kTreeTile - 1) / kTreeTile); }
+
+void launch_tree_levels(const uint64_t *key, uint32_t n, int n_leaf, uint32_t *sl, uint32_t *blk,
+                        uint32_t *tot, hipStream_t s)
+{
+    const uint32_t nblk = tree_blocks(n);
+    k_tree_levels<<<nblk, kTreeThreads, 0, s>>>(key, n, n_leaf, sl, blk, nblk);
+    k_tree_scan<<<kTreeLevels, 1024, 0, s>>>(blk, nblk, tot);
+}
+
+void launch_tree_emit(NodeArrays nd, const uint64_t *key, const uint32_t *sl, const uint32_t *blk,
+                      const TreeOffsets &to, uint32_t n, double L, hipStream_t s)
+{
+    const uint32_t nblk = tree_blocks(n);
+    k_tree_emit<<<nblk, kTreeThreads, 0, s>>>(nd, key, sl, blk, nblk, to, n, L);
 }
 
 void launch_com_divide(NodeArrays nd, uint32_t n_nodes, WalkNode *wn, hipStream_t s)

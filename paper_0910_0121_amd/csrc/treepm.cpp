@@ -62,6 +62,7 @@ struct treepm_ctx {
     // nodes
     Buf n_code, n_first, n_count, n_cf, n_parent, n_nch, n_level, n_mass, n_com[3], n_cn[3];
     Buf n_walk; // packed per-node walk records
+    Buf tree_sl, tree_blk; // flat octree build: per-particle levels, per-block level counts
     Buf n_src;  // per-node (com, mass) records
     Buf psrc;   // key-ordered particle (x, y, z, m) records
     size_t node_cap = 0;
@@ -464,42 +465,78 @@ int do_build(treepm_ctx *c, int64_t n, const double *x, const double *y, const d
     }
     launch_permute(n, c->idx.as<uint32_t>(), c->rec.as<double4>(), c->psrc.as<double4>(),
                    c->pm_mx.as<unsigned long long>(), s);
-    // octree, level by level
-    c->n_nodes = 0;
-    if ((rc = ensure_nodes(c, std::max<size_t>(1024, N / 2 + 64), s))) return rc;
-    NodeArrays nd = nodes_view(c);
-    launch_root(nd, (uint32_t)n, P.L, s);
-    c->n_nodes = 1;
-    c->lvl.assign({0u, 1u});
-    c->max_level = 0;
+    // octree: straight from the sorted keys, or level by level for n_leaf above the window
+    const double4 *ps = c->psrc.as<double4>();
     uint32_t *cnt = c->levcnt.as<uint32_t>();
     uint32_t *cnt_total = cnt + (N + 1);
     uint32_t *cnt_tmp = cnt_total + 16;
-    for (int l = 0; l <= kMaxLevel; ++l) {
-        uint32_t lo = c->lvl[l], hi = c->lvl[l + 1];
-        nd = nodes_view(c);
-        {
-            hipError_t e = reserve(c->bnd, (size_t)(hi - lo) * 7 * 4);
-            if (e != hipSuccess) return hip_fail(c, e, "octant bounds");
+    NodeArrays nd{};
+    if (n >= 1 && P.n_leaf - 1 <= kTreeWin) {
+        const uint32_t nblk = tree_blocks(n);
+        hipError_t e = reserve(c->tree_sl, (size_t)n * sizeof(uint32_t));
+        if (e == hipSuccess)
+            e = reserve(c->tree_blk, ((size_t)nblk * (kMaxLevel + 1) + 64) * sizeof(uint32_t));
+        if (e != hipSuccess) return hip_fail(c, e, "tree build buffers");
+        uint32_t *blk = c->tree_blk.as<uint32_t>();
+        uint32_t *tot = blk + (size_t)nblk * (kMaxLevel + 1);
+        launch_tree_levels(c->key.as<uint64_t>(), (uint32_t)n, P.n_leaf,
+                           c->tree_sl.as<uint32_t>(), blk, tot, s);
+        uint32_t per_level[kMaxLevel + 1] = {};
+        if ((rc = fetch(c, s, {per_level, tot, sizeof per_level}))) return rc;
+        TreeOffsets to{};
+        uint64_t acc = 0;
+        c->max_level = 0;
+        for (int l = 0; l <= kMaxLevel; ++l) {
+            to.off[l] = (uint32_t)acc;
+            acc += per_level[l];
+            if (per_level[l]) c->max_level = l;
+            if (acc > 0x7fffffffull)
+                return fail(c, TREEPM_ERR_OVERFLOW, "more than 2^31 tree nodes");
         }
-        launch_split(nd, c->key.as<uint64_t>(), lo, hi, l, P.n_leaf, cnt, c->bnd.as<uint32_t>(), s);
-        scan_u32(cnt, hi - lo, cnt_total, cnt_tmp, s);
-        uint32_t add = 0;
-        if ((rc = fetch(c, s, {&add, cnt_total, sizeof add}))) return rc;
-        c->max_level = l;
-        if (add == 0) break;
-        if ((uint64_t)hi + add > 0x7fffffffull)
-            return fail(c, TREEPM_ERR_OVERFLOW, "more than 2^31 tree nodes");
-        if ((rc = ensure_nodes(c, (size_t)hi + add, s))) return rc;
+        to.off[kMaxLevel + 1] = to.off[kMaxLevel + 2] = (uint32_t)acc;
+        c->n_nodes = 0; // nothing to keep if the arrays grow
+        if ((rc = ensure_nodes(c, (size_t)acc, s))) return rc;
+        c->n_nodes = (uint32_t)acc;
+        c->lvl.assign(to.off, to.off + c->max_level + 2);
         nd = nodes_view(c);
-        launch_emit(nd, c->bnd.as<uint32_t>(), lo, hi, l, hi, cnt, P.L, s);
-        c->lvl.push_back(hi + add);
-        c->n_nodes = hi + add;
+        launch_tree_emit(nd, c->key.as<uint64_t>(), c->tree_sl.as<uint32_t>(), blk, to,
+                         (uint32_t)n, P.L, s);
+        for (int l = c->max_level; l >= 0; --l)
+            launch_moments(nd, ps, to.off[l], to.off[l + 1], 1, to.off[l + 2], s);
+    } else {
+        c->n_nodes = 0;
+        if ((rc = ensure_nodes(c, std::max<size_t>(1024, N / 2 + 64), s))) return rc;
+        nd = nodes_view(c);
+        launch_root(nd, (uint32_t)n, P.L, s);
+        c->n_nodes = 1;
+        c->lvl.assign({0u, 1u});
+        c->max_level = 0;
+        for (int l = 0; l <= kMaxLevel; ++l) {
+            uint32_t lo = c->lvl[l], hi = c->lvl[l + 1];
+            nd = nodes_view(c);
+            {
+                hipError_t e = reserve(c->bnd, (size_t)(hi - lo) * 7 * 4);
+                if (e != hipSuccess) return hip_fail(c, e, "octant bounds");
+            }
+            launch_split(nd, c->key.as<uint64_t>(), lo, hi, l, P.n_leaf, cnt,
+                         c->bnd.as<uint32_t>(), s);
+            scan_u32(cnt, hi - lo, cnt_total, cnt_tmp, s);
+            uint32_t add = 0;
+            if ((rc = fetch(c, s, {&add, cnt_total, sizeof add}))) return rc;
+            c->max_level = l;
+            if (add == 0) break;
+            if ((uint64_t)hi + add > 0x7fffffffull)
+                return fail(c, TREEPM_ERR_OVERFLOW, "more than 2^31 tree nodes");
+            if ((rc = ensure_nodes(c, (size_t)hi + add, s))) return rc;
+            nd = nodes_view(c);
+            launch_emit(nd, c->bnd.as<uint32_t>(), lo, hi, l, hi, cnt, P.L, s);
+            c->lvl.push_back(hi + add);
+            c->n_nodes = hi + add;
+        }
+        nd = nodes_view(c);
+        for (int l = c->max_level; l >= 0; --l)
+            launch_moments(nd, ps, c->lvl[l], c->lvl[l + 1], 0, 0u, s);
     }
-    nd = nodes_view(c);
-    const double4 *ps = c->psrc.as<double4>();
-    for (int l = c->max_level; l >= 0; --l)
-        launch_moments(nd, ps, c->lvl[l], c->lvl[l + 1], s);
     {
         hipError_t e = reserve(c->n_walk, (size_t)c->n_nodes * sizeof(WalkNode));
         if (e == hipSuccess) e = reserve(c->n_src, (size_t)c->n_nodes * sizeof(double4));
@@ -697,7 +734,7 @@ size_t treepm_internal_ctx_bytes(const treepm_ctx *c)
                         &c->rec, &c->n_code, &c->n_first, &c->n_count, &c->n_cf, &c->n_parent,
                         &c->n_nch, &c->n_level, &c->n_mass, &c->n_com[0], &c->n_com[1],
                         &c->n_com[2], &c->n_cn[0], &c->n_cn[1], &c->n_cn[2], &c->n_walk,
-                        &c->n_src, &c->psrc,
+                        &c->n_src, &c->psrc, &c->tree_sl, &c->tree_blk,
                         &c->g_node, &c->g_first, &c->g_count, &c->g_cg[0], &c->g_cg[1],
                         &c->g_cg[2], &c->g_hg[0], &c->g_hg[1], &c->g_hg[2], &c->g_xg[0],
                         &c->g_xg[1], &c->g_xg[2], &c->g_lo[0], &c->g_lo[1], &c->g_lo[2],
@@ -778,7 +815,8 @@ TREEPM_API int treepm_destroy(treepm_ctx *c)
                   &c->scan32, &c->flags, &c->levcnt, &c->gstart, &c->gflag, &c->n_code,
                   &c->n_first, &c->n_count, &c->n_cf, &c->n_parent, &c->n_nch, &c->n_level,
                   &c->n_mass, &c->n_com[0], &c->n_com[1], &c->n_com[2], &c->n_cn[0],
-                  &c->n_cn[1], &c->n_cn[2], &c->n_walk, &c->n_src, &c->psrc, &c->g_node, &c->g_first, &c->g_count, &c->g_cg[0],
+                  &c->n_cn[1], &c->n_cn[2], &c->n_walk, &c->n_src, &c->psrc, &c->tree_sl,
+                  &c->tree_blk, &c->g_node, &c->g_first, &c->g_count, &c->g_cg[0],
                   &c->g_cg[1], &c->g_cg[2], &c->g_hg[0], &c->g_hg[1], &c->g_hg[2], &c->g_xg[0],
                   &c->g_xg[1], &c->g_xg[2], &c->g_lo[0], &c->g_lo[1], &c->g_lo[2], &c->g_hi[0],
                   &c->g_hi[1], &c->g_hi[2], &c->g_misc, &c->off, &c->glen, &c->wctr, &c->scan64, &c->entries,

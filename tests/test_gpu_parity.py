@@ -89,6 +89,7 @@ CASES = [
     ("nfw", 20011, 3, 0.08, 0.8, 4, 37),             # ragged N, deep chains, odd n_crit
     ("uniform", 777, 4, 0.25, 0.3, 2, 5),            # tiny, n_leaf 2
     ("nfw", 30000, 5, 0.05, 1.0, 10, 300),
+    ("nfw", 25000, 6, 0.06, 0.5, 300, 256),          # n_leaf above the flat build's window
 ]
 
 
@@ -432,6 +433,11 @@ def test_edge_cases(tp, orc):
     r = Run(tp, x, y, z, m, 1.0, 0.1, 0.002, 0.5, 10, 64, tp.TREEPM_FP64)
     T = orc.Tree(x, y, z, m, 1.0, 0.1, 0.002, 0.5, 10, 64)
     assert r.stats.max_level == 21
+    gn, on = tp.treepm_export_nodes(r.ctx), T.nodes()
+    go, oo = np.argsort(gn["code"]), np.argsort(on["code"])
+    for k in ("code", "first", "count", "nchild", "mass", "com"):
+        np.testing.assert_array_equal(gn[k][go], on[k][oo], err_msg=k)
+    assert on["count"].max() == n  # the root; the clump's level-21 leaf holds 500
     ref = np.stack(T.force())
     assert np.all(np.abs(r.acc - ref) <= 1e-13 * T.error_scale()[None, :] + 1e-300)
     r.close()
