@@ -32,7 +32,7 @@ struct NodeArrays {
     uint8_t *nchild;       // 0 for a leaf
     uint8_t *level;
     double *mass;          // FP64 moments
-    double *comx, *comy, *comz;
+    double *comx, *comy, *comz; // mass-weighted position sums (the centre of mass is in nsrc)
     double *cnx, *cny, *cnz; // cube centres ((i + 1/2) * L / 2^level)
     // Sources as 32-byte records, one cache-line sector per list entry:
     double4 *nsrc;        // per node: centre of mass and mass
@@ -108,10 +108,12 @@ void launch_split(NodeArrays nd, const uint64_t *key, uint32_t lo, uint32_t hi, 
 // Emit children of nodes [lo, hi) at base + exclusive prefix in cnt, from the bounds in bnd.
 void launch_emit(NodeArrays nd, const uint32_t *bnd, uint32_t lo, uint32_t hi, int level,
                  uint32_t base, const uint32_t *cnt, double L, hipStream_t s);
+// Moments of the nodes [lo, hi) of one level, deepest level first: mass, position sums S
+// (comx/comy/comz; the centre of mass S / M goes to nsrc and the walk records wn).
 // derive = 1 for a tree from launch_tree_emit: nchild and internal counts are set here, the
 // children of the level's nodes being the nodes [child_first[lo], child_end).
 void launch_moments(NodeArrays nd, const double4 *ps, uint32_t lo, uint32_t hi, int derive,
-                    uint32_t child_end, hipStream_t s);
+                    uint32_t child_end, WalkNode *wn, hipStream_t s);
 // The octree straight from the sorted keys (n >= 1, n_leaf - 1 <= kTreeWin): the same nodes in
 // the same order as the level-by-level split.  launch_tree_levels writes per particle the
 // levels of the nodes that start there and its leaf's count (sl, n words), per block of tree_blocks(n) the counts
@@ -127,8 +129,6 @@ void launch_tree_levels(const uint64_t *key, uint32_t n, int n_leaf, uint32_t *s
                         uint32_t *tot, hipStream_t s);
 void launch_tree_emit(NodeArrays nd, const uint64_t *key, const uint32_t *sl, const uint32_t *blk,
                       const TreeOffsets &to, uint32_t n, double L, hipStream_t s);
-// com = S / M for every node, after all levels' moments; also fills the walk records.
-void launch_com_divide(NodeArrays nd, uint32_t n_nodes, WalkNode *wn, hipStream_t s);
 // Groups: mark in gstart[first] (n values, zeroed here) every maximal node with
 // count <= n_crit or no children; then compact in key order.
 void launch_group_mark(NodeArrays nd, uint32_t n_nodes, int n_crit, uint32_t *gstart,

@@ -757,13 +757,15 @@ __global__ __launch_bounds__(kTreeThreads) void k_tree_emit(NodeArrays nd,
 }
 
 // Moments of the nodes [lo, hi) of one level, from their particles (leaves) or their children
-// in octant order.  DERIVE (a tree from k_tree_emit): a node's children are the next level's
-// nodes from its child_first up to the child_first of the next node of its level (child_end
-// after the level's last node), so nchild is set here, and an internal node's count is the sum
-// of its children's.
+// in octant order: mass and mass-weighted position sums S (kept for the parents), and the
+// node's final records, the source (S / M, M) and the walk record.  DERIVE (a tree from
+// k_tree_emit): a node's children are the next level's nodes from its child_first up to the
+// child_first of the next node of its level (child_end after the level's last node), so
+// nchild is set here, and an internal node's count is the sum of its children's.
 template <int DERIVE>
 __global__ __launch_bounds__(256) void k_moments(NodeArrays nd, const double4 *__restrict__ ps,
-                                                 uint32_t lo, uint32_t hi, uint32_t child_end)
+                                                 uint32_t lo, uint32_t hi, uint32_t child_end,
+                                                 WalkNode *__restrict__ wn)
 {
     for (uint32_t u = lo + blockIdx.x * blockDim.x + threadIdx.x; u < hi;
          u += gridDim.x * blockDim.x) {
@@ -776,9 +778,11 @@ __global__ __launch_bounds__(256) void k_moments(NodeArrays nd, const double4 *_
         } else {
             nch = nd.nchild[u];
         }
+        const uint32_t f = nd.first[u];
+        uint32_t cnt, cf = 0;
         if (nch == 0) {
-            uint32_t f = nd.first[u], e = f + nd.count[u];
-            for (uint32_t k = f; k < e; ++k) {
+            cnt = nd.count[u];
+            for (uint32_t k = f; k < f + cnt; ++k) {
                 const double4 r = ps[k];
                 M += r.w;
                 Sx += r.w * r.x;
@@ -786,14 +790,14 @@ __global__ __launch_bounds__(256) void k_moments(NodeArrays nd, const double4 *_
                 Sz += r.w * r.z;
             }
         } else {
-            uint32_t cf = nd.child_first[u];
-            uint32_t cnt = 0;
+            cf = nd.child_first[u];
+            cnt = 0;
             for (uint32_t c = cf; c < cf + nch; ++c) {
                 M += nd.mass[c];
                 Sx += nd.comx[c];
                 Sy += nd.comy[c];
                 Sz += nd.comz[c];
-                if (DERIVE) cnt += nd.count[c];
+                cnt += nd.count[c];
             }
             if (DERIVE) nd.count[u] = cnt;
         }
@@ -801,19 +805,7 @@ __global__ __launch_bounds__(256) void k_moments(NodeArrays nd, const double4 *_
         nd.comx[u] = Sx;
         nd.comy[u] = Sy;
         nd.comz[u] = Sz;
-    }
-}
-
-__global__ __launch_bounds__(256) void k_com_divide(NodeArrays nd, uint32_t n_nodes,
-                                                    WalkNode *__restrict__ wn)
-{
-    for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < n_nodes;
-         u += gridDim.x * blockDim.x) {
-        double M = nd.mass[u];
-        double c0 = nd.comx[u] / M, c1 = nd.comy[u] / M, c2 = nd.comz[u] / M;
-        nd.comx[u] = c0;
-        nd.comy[u] = c1;
-        nd.comz[u] = c2;
+        const double c0 = Sx / M, c1 = Sy / M, c2 = Sz / M;
         nd.nsrc[u] = make_double4(c0, c1, c2, M);
         WalkNode w;
         w.cn[0] = nd.cnx[u];
@@ -822,10 +814,10 @@ __global__ __launch_bounds__(256) void k_com_divide(NodeArrays nd, uint32_t n_no
         w.com[0] = c0;
         w.com[1] = c1;
         w.com[2] = c2;
-        w.first = nd.first[u];
-        w.count = nd.count[u];
-        w.nchild = nd.nchild[u];
-        w.child_first = w.nchild ? nd.child_first[u] : 0u;
+        w.first = f;
+        w.count = cnt;
+        w.nchild = (uint8_t)nch;
+        w.child_first = cf;
         w.level = nd.level[u];
         w.pad0 = w.pad1 = 0;
         wn[u] = w;
@@ -1035,13 +1027,13 @@ void launch_emit(NodeArrays nd, const uint32_t *bnd, uint32_t lo, uint32_t hi, i
 }
 
 void launch_moments(NodeArrays nd, const double4 *ps, uint32_t lo, uint32_t hi, int derive,
-                    uint32_t child_end, hipStream_t s)
+                    uint32_t child_end, WalkNode *wn, hipStream_t s)
 {
     if (hi <= lo) return;
     if (derive)
-        k_moments<1><<<grid_for(hi - lo, 256), 256, 0, s>>>(nd, ps, lo, hi, child_end);
+        k_moments<1><<<grid_for(hi - lo, 256), 256, 0, s>>>(nd, ps, lo, hi, child_end, wn);
     else
-        k_moments<0><<<grid_for(hi - lo, 256), 256, 0, s>>>(nd, ps, lo, hi, child_end);
+        k_moments<0><<<grid_for(hi - lo, 256), 256, 0, s>>>(nd, ps, lo, hi, child_end, wn);
 }
 
 uint32_t tree_blocks(int64_t n) { return (uint32_t)((n + kTreeTile - 1) / kTreeTile); }
@@ -1061,10 +1053,6 @@ void launch_tree_emit(NodeArrays nd, const uint64_t *key, const uint32_t *sl, co
     k_tree_emit<<<nblk, kTreeThreads, 0, s>>>(nd, key, sl, blk, nblk, to, n, L);
 }
 
-void launch_com_divide(NodeArrays nd, uint32_t n_nodes, WalkNode *wn, hipStream_t s)
-{
-    k_com_divide<<<grid_for(n_nodes, 256), 256, 0, s>>>(nd, n_nodes, wn);
-}
 
 void launch_group_mark(NodeArrays nd, uint32_t n_nodes, int n_crit, uint32_t *gstart,
                        uint32_t *gflag, int64_t n, hipStream_t s)

@@ -36,7 +36,8 @@ __global__ __launch_bounds__(256) void k_second_moments(NodeArrays nd,
 {
     for (uint32_t u = lo + blockIdx.x * blockDim.x + threadIdx.x; u < hi;
          u += gridDim.x * blockDim.x) {
-        const double X = nd.comx[u], Y = nd.comy[u], Z = nd.comz[u];
+        const double4 cu = nd.nsrc[u]; // centre of mass, mass
+        const double X = cu.x, Y = cu.y, Z = cu.z;
         double q[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         const uint32_t nch = nd.nchild[u];
         if (nch == 0) {
@@ -54,8 +55,9 @@ __global__ __launch_bounds__(256) void k_second_moments(NodeArrays nd,
         } else {
             const uint32_t cf = nd.child_first[u];
             for (uint32_t c = cf; c < cf + nch; ++c) {
-                const double m = nd.mass[c];
-                const double dx = nd.comx[c] - X, dy = nd.comy[c] - Y, dz = nd.comz[c] - Z;
+                const double4 cc = nd.nsrc[c];
+                const double m = cc.w;
+                const double dx = cc.x - X, dy = cc.y - Y, dz = cc.z - Z;
                 const double *qc = Q + 6 * (size_t)c;
                 q[0] += qc[0] + m * dx * dx;
                 q[1] += qc[1] + m * dy * dy;

@@ -280,6 +280,15 @@ int ensure_nodes(treepm_ctx *c, size_t need, hipStream_t s)
     return TREEPM_OK;
 }
 
+// The walk records and source records of c->n_nodes nodes (written by the moments pass).
+int reserve_node_records(treepm_ctx *c)
+{
+    hipError_t e = reserve(c->n_walk, (size_t)c->n_nodes * sizeof(WalkNode));
+    if (e == hipSuccess) e = reserve(c->n_src, (size_t)c->n_nodes * sizeof(double4));
+    if (e != hipSuccess) return hip_fail(c, e, "walk records");
+    return TREEPM_OK;
+}
+
 int ensure_groups(treepm_ctx *c, size_t need)
 {
     if (need <= c->group_cap && c->g_node.p) return TREEPM_OK;
@@ -498,11 +507,13 @@ int do_build(treepm_ctx *c, int64_t n, const double *x, const double *y, const d
         if ((rc = ensure_nodes(c, (size_t)acc, s))) return rc;
         c->n_nodes = (uint32_t)acc;
         c->lvl.assign(to.off, to.off + c->max_level + 2);
+        if ((rc = reserve_node_records(c))) return rc;
         nd = nodes_view(c);
         launch_tree_emit(nd, c->key.as<uint64_t>(), c->tree_sl.as<uint32_t>(), blk, to,
                          (uint32_t)n, P.L, s);
         for (int l = c->max_level; l >= 0; --l)
-            launch_moments(nd, ps, to.off[l], to.off[l + 1], 1, to.off[l + 2], s);
+            launch_moments(nd, ps, to.off[l], to.off[l + 1], 1, to.off[l + 2],
+                           c->n_walk.as<WalkNode>(), s);
     } else {
         c->n_nodes = 0;
         if ((rc = ensure_nodes(c, std::max<size_t>(1024, N / 2 + 64), s))) return rc;
@@ -533,17 +544,12 @@ int do_build(treepm_ctx *c, int64_t n, const double *x, const double *y, const d
             c->lvl.push_back(hi + add);
             c->n_nodes = hi + add;
         }
+        if ((rc = reserve_node_records(c))) return rc;
         nd = nodes_view(c);
         for (int l = c->max_level; l >= 0; --l)
-            launch_moments(nd, ps, c->lvl[l], c->lvl[l + 1], 0, 0u, s);
+            launch_moments(nd, ps, c->lvl[l], c->lvl[l + 1], 0, 0u, c->n_walk.as<WalkNode>(),
+                           s);
     }
-    {
-        hipError_t e = reserve(c->n_walk, (size_t)c->n_nodes * sizeof(WalkNode));
-        if (e == hipSuccess) e = reserve(c->n_src, (size_t)c->n_nodes * sizeof(double4));
-        if (e != hipSuccess) return hip_fail(c, e, "walk records");
-    }
-    nd = nodes_view(c);
-    launch_com_divide(nd, c->n_nodes, c->n_walk.as<WalkNode>(), s);
     if (P.quadrupole) {
         hipError_t e = reserve(c->n_q, (size_t)c->n_nodes * 6 * sizeof(double));
         if (e != hipSuccess) return hip_fail(c, e, "second moments");
@@ -1317,10 +1323,10 @@ TREEPM_API int treepm_export_nodes(treepm_ctx *c, int64_t cap, uint64_t *code, i
     if ((rc = d2h(c, b.data(), c->n_nch.p, nn, s))) return rc;
     for (size_t k = 0; k < nn; ++k) nchild[k] = b[k];
     if ((rc = d2h(c, mass, c->n_mass.p, nn, s))) return rc;
-    for (int a = 0; a < 3; ++a) {
-        if ((rc = d2h(c, d.data(), c->n_com[a].p, nn, s))) return rc;
-        for (size_t k = 0; k < nn; ++k) com[3 * k + a] = d[k];
-    }
+    std::vector<double> src(4 * nn); // (centre of mass, mass) per node
+    if ((rc = d2h(c, src.data(), c->n_src.p, 4 * nn, s))) return rc;
+    for (size_t k = 0; k < nn; ++k)
+        for (int a = 0; a < 3; ++a) com[3 * k + a] = src[4 * k + a];
     return TREEPM_OK;
 }
 
