@@ -186,7 +186,8 @@ def serving_bench(tp, n_boxes, per_box, inflight, budget_frac=0.25):
     """The ensemble serving workload: n_boxes independent clustered boxes with N log-uniform
     in [32^3, 256^3] (seed 999; box i uses seed 1000 + i and max(1, round(N/1e4)) halos),
     mesh = N^(1/3), r_cut = 3/mesh, eps = mesh/20, theta = 0.5, FP32.  First the closed-loop
-    capacity (2 * inflight requests kept outstanding); then n_boxes * per_box requests in
+    capacity (2 * inflight requests kept outstanding, the first 4 * n_boxes requests); then
+    n_boxes * per_box requests in
     seeded order arriving as a Poisson process at 0.8 x that capacity, then again at 0.5 x,
     with the HBM budget set to 25% of the ensemble's total resident footprint.  Reports p50/p99
     latency (completion minus submission) and aggregate particles/s for both rates."""
@@ -223,12 +224,13 @@ def serving_bench(tp, n_boxes, per_box, inflight, budget_frac=0.25):
         for t in list(pending):
             rc, st = tp.treepm_ensemble_poll(ens, t)
             if rc == tp.TREEPM_OK:
-                out_lat.append(st.latency_ms)
+                out_lat.append((st.latency_ms, st.queue_ms))
                 done.append(pending.pop(t))
 
     try:
-        # closed loop: keep 2 * inflight requests outstanding
-        n_closed = min(len(order), max(4 * inflight, n_boxes))
+        # closed loop: keep 2 * inflight requests outstanding, over 4 requests per box (the
+        # capacity of a short run depends on which box sizes it happens to draw)
+        n_closed = min(len(order), max(4 * inflight, 4 * n_boxes))
         pending, done, lat = {}, [], []
         t0 = time.perf_counter()
         k = 0
@@ -266,7 +268,7 @@ def serving_bench(tp, n_boxes, per_box, inflight, budget_frac=0.25):
                     drain(pending, done, lat)
                 time.sleep(0.0005)
             th.join()
-            return lam, np.array(lat), done, time.perf_counter() - t_start
+            return lam, np.array(lat).reshape(-1, 2), done, time.perf_counter() - t_start
 
         lam, lat, done, makespan = open_loop(0.8)
         info = tp.treepm_ens_info(ens)
@@ -285,16 +287,24 @@ def serving_bench(tp, n_boxes, per_box, inflight, budget_frac=0.25):
         "max_inflight": inflight,
         "closed_loop_requests_per_s": cap,
         "arrival_rate_per_s": lam,
-        "latency_ms_p50": float(np.percentile(lat, 50)),
-        "latency_ms_p99": float(np.percentile(lat, 99)),
-        "latency_ms_max": float(lat.max()),
+        "latency_ms_p50": float(np.percentile(lat[:, 0], 50)),
+        "latency_ms_p99": float(np.percentile(lat[:, 0], 99)),
+        "latency_ms_max": float(lat[:, 0].max()),
+        "queue_ms_p50": float(np.percentile(lat[:, 1], 50)),
+        "queue_ms_p99": float(np.percentile(lat[:, 1], 99)),
+        "service_ms_p50": float(np.percentile(lat[:, 0] - lat[:, 1], 50)),
+        "service_ms_p99": float(np.percentile(lat[:, 0] - lat[:, 1], 99)),
         "particles_per_s": parts / makespan,
         "resident_boxes_at_end": info["resident_boxes"],
         "at_half_capacity": {
             "arrival_rate_per_s": lam5,
             "requests": len(done5),
-            "latency_ms_p50": float(np.percentile(lat5, 50)),
-            "latency_ms_p99": float(np.percentile(lat5, 99)),
+            "latency_ms_p50": float(np.percentile(lat5[:, 0], 50)),
+            "latency_ms_p99": float(np.percentile(lat5[:, 0], 99)),
+            "queue_ms_p50": float(np.percentile(lat5[:, 1], 50)),
+            "queue_ms_p99": float(np.percentile(lat5[:, 1], 99)),
+            "service_ms_p50": float(np.percentile(lat5[:, 0] - lat5[:, 1], 50)),
+            "service_ms_p99": float(np.percentile(lat5[:, 0] - lat5[:, 1], 99)),
             "particles_per_s": parts5 / makespan5,
         },
     }

@@ -119,6 +119,8 @@ typedef struct {
                                the group's bounding box (every pair they form adds
                                exactly zero), so this is at most interactions            */
     double latency_ms;      /* ensemble results only: completion minus submission (ms)    */
+    double queue_ms;        /* ensemble results only: start of service minus submission,
+                               the part of latency_ms spent queued (ms)                  */
 } treepm_stats;
 
 /* Create a context for one box on HIP device `device`.  Validates *params (ERR_ARG).  The

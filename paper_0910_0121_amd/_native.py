@@ -39,7 +39,7 @@ class treepm_stats(C.Structure):
                 ("n_cell_entries", C.c_int64), ("n_part_entries", C.c_int64),
                 ("interactions", C.c_int64), ("max_level", C.c_int32),
                 ("max_group", C.c_int32), ("t_ms", C.c_double * 4), ("evaluated", C.c_int64),
-                ("latency_ms", C.c_double)]
+                ("latency_ms", C.c_double), ("queue_ms", C.c_double)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "t_ms"}

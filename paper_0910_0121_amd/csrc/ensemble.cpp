@@ -46,7 +46,10 @@ double now_s()
 size_t estimate_bytes(int64_t n) { return (size_t)n * 320 + ((size_t)64 << 20); }
 
 // Pinned host blocks, reused across requests (sizes rounded up to a power of two), so a
-// request neither page-faults fresh memory nor needs a second staging copy.
+// request neither page-faults fresh memory nor needs a second staging copy.  A request takes
+// the smallest free block that holds it and is at most four times its size: pinning fresh
+// memory is slow for a large block (hundreds of ms) and holds up other HIP calls meanwhile,
+// while a small one is cheap to pin and should not take a block a large request needs.
 class PinnedPool {
   public:
     ~PinnedPool()
@@ -59,8 +62,9 @@ class PinnedPool {
         while (c < bytes) c <<= 1;
         {
             std::lock_guard<std::mutex> lk(mu_);
-            auto it = free_.find(c);
-            if (it != free_.end()) {
+            auto it = free_.lower_bound(c);
+            if (it != free_.end() && it->first <= 4 * c) {
+                c = it->first;
                 void *p = it->second;
                 free_.erase(it);
                 *cap = c;
@@ -173,9 +177,10 @@ size_t box_need(const treepm_ens *e, const Request &r)
     return it->second.bytes >= est ? 0 : est - it->second.bytes;
 }
 
-// With e->mu held: evict idle boxes (least recently used first) until `need` more bytes fit.
-// Returns false if they cannot be made to fit now.
-bool make_room(treepm_ens *e, size_t need, uint64_t keep_box)
+// With e->mu held: evict idle boxes (least recently used first) until `need` more bytes fit;
+// their contexts go to `gone`, for the caller to destroy after releasing the lock (destroying
+// waits for the context's last work).  Returns false if they cannot be made to fit now.
+bool make_room(treepm_ens *e, size_t need, uint64_t keep_box, std::vector<treepm_ctx *> &gone)
 {
     while (e->resident + need > e->budget) {
         uint64_t victim = 0;
@@ -189,22 +194,23 @@ bool make_room(treepm_ens *e, size_t need, uint64_t keep_box)
             }
         if (!found) return false;
         Box &b = e->boxes[victim];
-        treepm_destroy(b.ctx);
+        if (b.ctx) gone.push_back(b.ctx);
         e->resident -= std::min(e->resident, b.bytes);
         e->boxes.erase(victim);
     }
     return true;
 }
 
-// With e->mu held: the first queued request that can start now, or nullptr.
-std::shared_ptr<Request> pick(treepm_ens *e)
+// With e->mu held: the first queued request that can start now, or nullptr; evicted contexts
+// are added to `gone`.
+std::shared_ptr<Request> pick(treepm_ens *e, std::vector<treepm_ctx *> &gone)
 {
     for (auto it = e->queue.begin(); it != e->queue.end(); ++it) {
         Request &r = **it;
         auto bi = e->boxes.find(r.box_id);
         if (bi != e->boxes.end() && bi->second.busy) continue;
         size_t need = box_need(e, r);
-        if (!make_room(e, need, r.box_id)) continue;
+        if (!make_room(e, need, r.box_id, gone)) continue;
         Box &b = e->boxes[r.box_id];
         b.busy = true;
         b.last_use = ++e->clock;
@@ -256,17 +262,28 @@ void worker_main(treepm_ens *e, int wi)
     hipStreamCreateWithFlags(&w.stream, hipStreamNonBlocking);
     for (;;) {
         std::shared_ptr<Request> r;
+        std::vector<treepm_ctx *> gone;
+        bool quit = false;
         {
             std::unique_lock<std::mutex> lk(e->mu);
+            // also wake for contexts evicted on the way, to destroy them promptly
             e->cv.wait(lk, [&] {
                 if (e->stop) return true;
-                r = pick(e);
-                return r != nullptr;
+                r = pick(e, gone);
+                return r != nullptr || !gone.empty();
             });
-            if (e->stop && !r) break;
-            r->state = 1;
-            r->t_start = now_s();
-            ++e->inflight;
+            if (r) {
+                r->state = 1;
+                r->t_start = now_s();
+                ++e->inflight;
+            } else {
+                quit = e->stop;
+            }
+        }
+        for (treepm_ctx *g : gone) treepm_destroy(g); // evicted: outside the lock
+        if (!r) {
+            if (quit) break;
+            continue;
         }
         Box local;
         {
@@ -433,6 +450,7 @@ TREEPM_API int treepm_ensemble_poll(treepm_ens *e, uint64_t ticket, float *ax, f
     if (stats) {
         *stats = r->stats;
         stats->latency_ms = (r->t_done - r->t_submit) * 1e3;
+        stats->queue_ms = (r->t_start - r->t_submit) * 1e3;
     }
     return TREEPM_OK;
 }

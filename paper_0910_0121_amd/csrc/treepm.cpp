@@ -42,6 +42,11 @@ struct treepm_ctx {
     // synchronises the device, so contexts on other streams are not stalled.
     hipStream_t own = nullptr;
     hipEvent_t freed = nullptr;
+    // Recorded on the call's stream as each API call returns: all of this context's work is
+    // before it, so destroying the context waits for it rather than for its last stream,
+    // which other work (another context's, in a serving worker) may share.
+    hipEvent_t idle = nullptr;
+    bool idle_set = false;
     hipStream_t cur = nullptr;
     // The FP32 force's size classes run concurrently on the call's stream and these.
     static constexpr int kSubStreams = 3;
@@ -174,13 +179,19 @@ hipError_t reserve(Buf &b, size_t bytes)
 
 // Enter an API call on context c with stream s: allocation bookkeeping follows s.
 struct CallScope {
-    treepm_ctx *prev;
-    CallScope(treepm_ctx *c, hipStream_t s) : prev(t_ctx)
+    treepm_ctx *prev, *ctx;
+    hipStream_t stream;
+    CallScope(treepm_ctx *c, hipStream_t s) : prev(t_ctx), ctx(c), stream(s)
     {
         t_ctx = c;
         if (c) c->cur = s;
     }
-    ~CallScope() { t_ctx = prev; }
+    ~CallScope()
+    {
+        if (ctx && ctx->idle && hipEventRecord(ctx->idle, stream) == hipSuccess)
+            ctx->idle_set = true;
+        t_ctx = prev;
+    }
 };
 
 int check_params(treepm_ctx *c, const treepm_params *p)
@@ -472,15 +483,37 @@ int do_build(treepm_ctx *c, int64_t n, const double *x, const double *y, const d
         hipError_t e = reserve(c->pm_mx, 8);
         if (e != hipSuccess) return hip_fail(c, e, "largest-mass word");
     }
+    // The gather into key order reads only the sort's indices, and the octree passes only the
+    // keys: the gather runs on a side stream beside them, and the moments wait for it.
+    // Every exit after the fork joins the side stream back into s (an error return too, so
+    // nothing is released while the gather may still read it).
+    struct SideJoin {
+        treepm_ctx *c;
+        hipStream_t s, sp;
+        ~SideJoin()
+        {
+            if (sp != s) {
+                (void)hipEventRecord(c->join[0], sp);
+                (void)hipStreamWaitEvent(s, c->join[0], 0);
+            }
+        }
+    } side{c, s, s};
+    if (c->fork) {
+        HIPCHK(c, hipEventRecord(c->fork, s));
+        HIPCHK(c, hipStreamWaitEvent(c->sub[0], c->fork, 0));
+        side.sp = c->sub[0];
+    }
+    const hipStream_t sp = side.sp;
     launch_permute(n, c->idx.as<uint32_t>(), c->rec.as<double4>(), c->psrc.as<double4>(),
-                   c->pm_mx.as<unsigned long long>(), s);
+                   c->pm_mx.as<unsigned long long>(), sp);
     // octree: straight from the sorted keys, or level by level for n_leaf above the window
     const double4 *ps = c->psrc.as<double4>();
     uint32_t *cnt = c->levcnt.as<uint32_t>();
     uint32_t *cnt_total = cnt + (N + 1);
     uint32_t *cnt_tmp = cnt_total + 16;
     NodeArrays nd{};
-    if (n >= 1 && P.n_leaf - 1 <= kTreeWin) {
+    const bool flat = n >= 1 && P.n_leaf - 1 <= kTreeWin;
+    if (flat) {
         const uint32_t nblk = tree_blocks(n);
         hipError_t e = reserve(c->tree_sl, (size_t)n * sizeof(uint32_t));
         if (e == hipSuccess)
@@ -511,9 +544,6 @@ int do_build(treepm_ctx *c, int64_t n, const double *x, const double *y, const d
         nd = nodes_view(c);
         launch_tree_emit(nd, c->key.as<uint64_t>(), c->tree_sl.as<uint32_t>(), blk, to,
                          (uint32_t)n, P.L, s);
-        for (int l = c->max_level; l >= 0; --l)
-            launch_moments(nd, ps, to.off[l], to.off[l + 1], 1, to.off[l + 2],
-                           c->n_walk.as<WalkNode>(), s);
     } else {
         c->n_nodes = 0;
         if ((rc = ensure_nodes(c, std::max<size_t>(1024, N / 2 + 64), s))) return rc;
@@ -545,10 +575,20 @@ int do_build(treepm_ctx *c, int64_t n, const double *x, const double *y, const d
             c->n_nodes = hi + add;
         }
         if ((rc = reserve_node_records(c))) return rc;
-        nd = nodes_view(c);
-        for (int l = c->max_level; l >= 0; --l)
-            launch_moments(nd, ps, c->lvl[l], c->lvl[l + 1], 0, 0u, c->n_walk.as<WalkNode>(),
-                           s);
+    }
+    if (sp != s) {
+        side.sp = s; // joined here
+        HIPCHK(c, hipEventRecord(c->join[0], sp));
+        HIPCHK(c, hipStreamWaitEvent(s, c->join[0], 0));
+    }
+    // moments from the deepest level up (a flat-built tree has its nchild and internal counts
+    // set here; the children of level l end where level l + 2 starts)
+    nd = nodes_view(c);
+    for (int l = c->max_level; l >= 0; --l) {
+        const uint32_t child_end =
+            (size_t)l + 2 < c->lvl.size() ? c->lvl[l + 2] : c->n_nodes;
+        launch_moments(nd, ps, c->lvl[l], c->lvl[l + 1], flat ? 1 : 0, child_end,
+                       c->n_walk.as<WalkNode>(), s);
     }
     if (P.quadrupole) {
         hipError_t e = reserve(c->n_q, (size_t)c->n_nodes * 6 * sizeof(double));
@@ -789,6 +829,10 @@ TREEPM_API int treepm_create(const treepm_params *params, int device, treepm_ctx
         c->freed = nullptr;
         (void)hipGetLastError();
     }
+    if (hipEventCreateWithFlags(&c->idle, hipEventDisableTiming) != hipSuccess) {
+        c->idle = nullptr; // destroy then waits for the last stream instead
+        (void)hipGetLastError();
+    }
     bool subs_ok = hipEventCreateWithFlags(&c->fork, hipEventDisableTiming) == hipSuccess;
     for (int i = 0; subs_ok && i < treepm_ctx::kSubStreams; ++i)
         subs_ok = hipStreamCreateWithFlags(&c->sub[i], hipStreamNonBlocking) == hipSuccess &&
@@ -814,8 +858,14 @@ TREEPM_API int treepm_destroy(treepm_ctx *c)
 {
     if (!c) return TREEPM_OK;
     hipSetDevice(c->device);
-    if (c->last) hipStreamSynchronize(c->last);
+    // this context's own work, not the rest of a stream it may share
+    if (c->idle && c->idle_set) hipEventSynchronize(c->idle);
+    else if (c->last) hipStreamSynchronize(c->last);
     else hipDeviceSynchronize();
+    if (c->idle) { // no more records: the scope below must not touch the event
+        (void)hipEventDestroy(c->idle);
+        c->idle = nullptr;
+    }
     Buf *all[] = {&c->in[0], &c->in[1], &c->in[2], &c->in[3], &c->key, &c->key_alt, &c->idx,
                   &c->idx_alt, &c->hist,
                   &c->scan32, &c->flags, &c->levcnt, &c->gstart, &c->gflag, &c->n_code,
@@ -831,7 +881,8 @@ TREEPM_API int treepm_destroy(treepm_ctx *c)
                   &c->pm_f, &c->pm_green, &c->pm_tw, &c->pm_mx, &c->pm_stage,
                   &c->n_q, &c->step_min, &c->tab};
     {
-        CallScope scope(c, c->last);
+        // the work is done: free on the private stream, not behind the last stream
+        CallScope scope(c, c->own ? c->own : c->last);
         for (Buf *b : all) release(*b);
     }
     if (c->own) {
