@@ -252,9 +252,17 @@ void launch_force_f64(NodeArrays nd, GroupArrays gr, uint32_t n_groups, const ui
 int pm_bundle_lines(int N);
 // Octant table of the Green's function ((N/2+1)^3 floats) and N/2 twiddles.
 void launch_pm_green(int N, double L, double eta, float *green, float2 *tw, hipStream_t s);
-// Clears and fills the fixed-point mass mesh (N^3 words); mx receives the largest mass.
-void launch_pm_assign(const double4 *ps, int64_t n, int N, double L, unsigned long long *mx,
-                      unsigned long long *mass, hipStream_t s);
+// Fills the fixed-point mass mesh (N^3 words, every word written) from the key-ordered records
+// and their sorted keys; mx holds the largest mass.  Scratch: cell_start (cells + 1 words),
+// item_start (cells + 1 words), scan_tmp (scan_tmp_elems(cells) words) and slots
+// (pm_assign_items_max x pm_assign_slot_words() words), cells = pm_assign_cells(N).
+size_t pm_assign_cells(int N);
+size_t pm_assign_items_max(int N, int64_t n);
+size_t pm_assign_slot_words();
+void launch_pm_assign(const double4 *ps, const uint64_t *key, int64_t n, int N, double L,
+                      const unsigned long long *mx, uint32_t *cell_start, uint32_t *item_start,
+                      uint32_t *scan_tmp, unsigned long long *slots, unsigned long long *mass,
+                      hipStream_t s);
 // Potential phi (N^3 floats) from the mass mesh, through the complex work mesh grid.
 void launch_pm_potential(const unsigned long long *mass, const unsigned long long *mx,
                          int64_t n, int N, float2 *grid, float *phi, const float *green,

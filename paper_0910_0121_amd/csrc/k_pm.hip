@@ -65,119 +65,115 @@ __device__ __forceinline__ double pm_scale(unsigned long long mmax_bits, int64_t
     return ldexp(1.0, 61 - ilogb(t));
 }
 
-// One wave takes kAssignChunk consecutive particles in key order, kAssignPer consecutive ones
-// per lane.  A lane sums the 27 contributions of a run of particles with the same nearest mesh
-// point in registers and adds them once.  The adds go to an LDS box of mesh points, which is
-// then added to the mesh with one global atomic per nonzero point.  The box is chosen per group
-// of lanes: the whole wave's particles if the mesh points their clouds touch fit kAssignTile
-// words; otherwise each half-wave's in a box of kAssignTile / 2 words, then each quarter's and
-// each eighth's, taking for every group the largest one that fits.  A group of 8 << l lanes
-// (level l) owns words [g, g + 1) * (kAssignTile / 8 << l) of the tile, g = lane / (8 << l),
-// so the boxes of one wave never overlap.  An eighth that still does not fit (particles
-// spread over a large region, or across the periodic seam) adds to the mesh directly.  Every
-// sum is a fixed sequence of integer adds, so the mesh is the same on every run.
-constexpr int kAssignThreads = 64;
-constexpr int kAssignPer = 4;
-constexpr int kAssignChunk = kAssignThreads * kAssignPer;
-constexpr int kAssignTile = 4096;
-constexpr int kAssignSlot = kAssignTile / 8;  // words owned by eight lanes
+// Mass assignment, owner by owner.  The mesh is cut into cells of kCellPts^3 points, which
+// are the tree cells of level l_c = log2(N / kCellPts): a particle's cell c (per axis) is its
+// key's prefix, and its nearest mesh point i0 = floor(x N / L + 1/2) lies in [8c, 8c + 8] (the
+// key's product x 2^21 / L and x N / L differ from the exact values by a relative 2^-52 at
+// most, far below the half point of margin; at x -> L the key is clamped and i0 = N, still in
+// range).  So the particles of a cell, contiguous in key order, touch only the kBox^3 points
+// [8c - 1, 8c + 9] of the cell's box.  One workgroup sums a chunk of a cell's particles into
+// its box in LDS and writes the box to the chunk's own slot with plain stores; then each mesh
+// point sums the slot words that cover it (one or two cells per axis, every chunk of each) and
+// writes its mesh word.  No global atomics, and every sum is a fixed set of integer adds, so
+// the mesh is the same on every run.  A thread sums the 27 contributions of a run of its
+// particles with the same nearest point in registers (fixed point, rounded once per run and
+// point).
+constexpr int kCellPts = 8;
+constexpr int kBox = kCellPts + 3;             // 11 points per axis
+constexpr int kBoxWords = kBox * kBox * kBox;  // 1331
+constexpr int kCellChunk = 4096;               // particles per workgroup at most
+constexpr int kAssignThreads = 256;
 
+__device__ __forceinline__ uint32_t spread3_10(uint32_t v) // 10 bits -> every third bit
+{
+    v &= 0x3ffu;
+    v = (v | (v << 16)) & 0x030000ffu;
+    v = (v | (v << 8)) & 0x0300f00fu;
+    v = (v | (v << 4)) & 0x030c30c3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
+}
+__device__ __forceinline__ uint32_t compact3_10(uint32_t v)
+{
+    v &= 0x09249249u;
+    v = (v | (v >> 2)) & 0x030c30c3u;
+    v = (v | (v >> 4)) & 0x0300f00fu;
+    v = (v | (v >> 8)) & 0x030000ffu;
+    v = (v | (v >> 16)) & 0x3ffu;
+    return v;
+}
+// The Morton index of cell (cx, cy, cz), in the keys' bit order (x above y above z).
+__device__ __forceinline__ uint32_t cell_index(uint32_t cx, uint32_t cy, uint32_t cz)
+{
+    return (spread3_10(cx) << 2) | (spread3_10(cy) << 1) | spread3_10(cz);
+}
+
+// cell_start[m] = the first particle (key order) of Morton cell m, m = 0 .. ncells; the
+// cell of a key is key >> sh.
+__global__ __launch_bounds__(256) void k_pm_cells(const uint64_t *__restrict__ key, int64_t n,
+                                                  int sh, uint32_t ncells,
+                                                  uint32_t *__restrict__ cell_start)
+{
+    const uint32_t m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m > ncells) return;
+    int64_t lo = 0, hi = n; // first i with key[i] >> sh >= m
+    while (lo < hi) {
+        const int64_t mid = lo + ((hi - lo) >> 1);
+        if ((key[mid] >> sh) < (uint64_t)m)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    cell_start[m] = (uint32_t)lo;
+}
+
+// items[m] = chunks of cell m (exclusive prefix taken afterwards).
+__global__ __launch_bounds__(256) void k_pm_cell_items(const uint32_t *__restrict__ cell_start,
+                                                       uint32_t ncells,
+                                                       uint32_t *__restrict__ items)
+{
+    const uint32_t m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= ncells) return;
+    const uint32_t c = cell_start[m + 1] - cell_start[m];
+    items[m] = (c + kCellChunk - 1) / kCellChunk;
+}
+
+// One workgroup per chunk (grid: an upper bound on the chunks; the rest leave).
 __global__ __launch_bounds__(kAssignThreads) void k_pm_assign(
     const double4 *__restrict__ ps, int64_t n, int N, double inv_h,
-    const unsigned long long *__restrict__ mx, unsigned long long *__restrict__ mass)
+    const unsigned long long *__restrict__ mx, const uint32_t *__restrict__ cell_start,
+    const uint32_t *__restrict__ item_start, uint32_t ncells,
+    unsigned long long *__restrict__ slots)
 {
-    __shared__ unsigned long long tile[kAssignTile];
-    const int lane = threadIdx.x;
-    // neighbouring chunks on one XCD, so their mesh points share its L2
-    const int64_t first = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kAssignChunk +
-                          (int64_t)lane * kAssignPer;
-    int lo[3] = {0x7fffffff, 0x7fffffff, 0x7fffffff}, hi[3] = {-0x7fffffff, -0x7fffffff, -0x7fffffff};
-#pragma unroll
-    for (int k = 0; k < kAssignPer; ++k) {
-        if (first + k < n) {
-            const double4 p = ps[first + k];
-            const int c[3] = {nearest(p.x, inv_h), nearest(p.y, inv_h), nearest(p.z, inv_h)};
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                lo[a] = min(lo[a], c[a]);
-                hi[a] = max(hi[a], c[a]);
-            }
-        }
+    __shared__ unsigned long long box[kBoxWords];
+    const uint32_t item = blockIdx.x;
+    if (item >= item_start[ncells]) return; // the same for the whole workgroup
+    // the cell whose chunks include this one: the last m with item_start[m] <= item
+    uint32_t lo = 0, hi = ncells;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (item_start[mid] <= item)
+            lo = mid;
+        else
+            hi = mid;
     }
-    // Bounding boxes of the lane's groups of 8, 16, 32 and 64 lanes (one butterfly), and the
-    // largest group whose box fits its share of the tile.  All lanes of a group see the same
-    // boxes for it and for every larger group, so they agree on the level.
-    int base = 0, ox = 0, oy = 0, oz = 0, ey = 1, ez = 1, cells = 0;
-    bool local = false;
-    {
-#pragma unroll
-        for (int d = 1; d < 8; d <<= 1)
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                lo[a] = min(lo[a], __shfl_xor(lo[a], d, 64));
-                hi[a] = max(hi[a], __shfl_xor(hi[a], d, 64));
-            }
-        int glo[4][3], ghi[4][3];
-#pragma unroll
-        for (int l = 0; l < 4; ++l) {
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                glo[l][a] = lo[a];
-                ghi[l][a] = hi[a];
-            }
-            if (l < 3) {
-                const int d = 8 << l;
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    lo[a] = min(lo[a], __shfl_xor(lo[a], d, 64));
-                    hi[a] = max(hi[a], __shfl_xor(hi[a], d, 64));
-                }
-            }
-        }
-#pragma unroll
-        for (int l = 3; l >= 0; --l) {
-            if (local) continue;
-            const int cap = kAssignSlot << l;
-            if (glo[l][0] > ghi[l][0]) {  // no particles in this group (ragged tail)
-                local = true;
-                base = (lane >> (3 + l)) * cap;
-                cells = 0;
-                continue;
-            }
-            const int ex = ghi[l][0] - glo[l][0] + 3, fy = ghi[l][1] - glo[l][1] + 3,
-                      fz = ghi[l][2] - glo[l][2] + 3;
-            if ((int64_t)ex * fy * fz <= cap) {
-                local = true;
-                base = (lane >> (3 + l)) * cap;
-                cells = ex * fy * fz;
-                ox = glo[l][0] - 1;
-                oy = glo[l][1] - 1;
-                oz = glo[l][2] - 1;
-                ey = fy;
-                ez = fz;
-            }
-        }
-    }
-    // Word t of slot q (words q * kAssignSlot ...) belongs to the box of lane 8 q's group: it is
-    // used iff t - base < cells there (base and cells of a direct group are 0).
-#pragma unroll 1
-    for (int q = 0; q < 8; ++q) {
-        const int qb = __shfl(base, 8 * q, 64), qc = __shfl(cells, 8 * q, 64);
-#pragma unroll
-        for (int j = 0; j < kAssignSlot / kAssignThreads; ++j) {
-            const int t = q * kAssignSlot + j * kAssignThreads + lane;
-            if (t - qb < qc) tile[t] = 0ull;
-        }
-    }
+    const uint32_t m = lo;
+    const uint32_t first = cell_start[m] + (item - item_start[m]) * (uint32_t)kCellChunk;
+    const uint32_t end = min(cell_start[m + 1], first + (uint32_t)kCellChunk);
+    const int ox = 8 * (int)compact3_10(m >> 2) - 1, oy = 8 * (int)compact3_10(m >> 1) - 1,
+              oz = 8 * (int)compact3_10(m) - 1;
+    for (int t = threadIdx.x; t < kBoxWords; t += kAssignThreads) box[t] = 0ull;
     __syncthreads();
     const double S = pm_scale(*mx, n);
-    const int mask = N - 1;
+    const uint32_t per = (end - first + kAssignThreads - 1) / kAssignThreads;
+    const uint32_t i0 = first + threadIdx.x * per, i1 = min(end, i0 + per);
     double acc[27];
 #pragma unroll
     for (int j = 0; j < 27; ++j) acc[j] = 0.0;
     int cx = 0, cy = 0, cz = 0;
     bool open = false;
     auto add_run = [&]() {
+        const int bx = cx - 1 - ox, by = cy - 1 - oy, bz = cz - 1 - oz; // in [0, 8]
 #pragma unroll
         for (int a = 0; a < 3; ++a)
 #pragma unroll
@@ -185,62 +181,78 @@ __global__ __launch_bounds__(kAssignThreads) void k_pm_assign(
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     const unsigned long long v = __double2ull_rn(acc[(a * 3 + b) * 3 + c]);
-                    if (local)
-                        atomicAdd(&tile[base + ((cx - 1 + a - ox) * ey + (cy - 1 + b - oy)) * ez +
-                                        (cz - 1 + c - oz)],
-                                  v);
-                    else
-                        atomicAdd(&mass[((size_t)((cx - 1 + a) & mask) * N +
-                                         ((cy - 1 + b) & mask)) * N + ((cz - 1 + c) & mask)],
-                                  v);
+                    if (v) atomicAdd(&box[((bx + a) * kBox + (by + b)) * kBox + (bz + c)], v);
                 }
     };
+    for (uint32_t i = i0; i < i1; ++i) {
+        const double4 p = ps[i];
+        double wx[3], wy[3], wz[3];
+        const int ix = tsc(p.x, inv_h, wx), iy = tsc(p.y, inv_h, wy), iz = tsc(p.z, inv_h, wz);
+        if (open && (ix != cx || iy != cy || iz != cz)) {
+            add_run();
 #pragma unroll
-    for (int k = 0; k < kAssignPer; ++k) {
-        if (first + k < n) {
-            const double4 p = ps[first + k];
-            double wx[3], wy[3], wz[3];
-            const int ix = tsc(p.x, inv_h, wx), iy = tsc(p.y, inv_h, wy), iz = tsc(p.z, inv_h, wz);
-            if (open && (ix != cx || iy != cy || iz != cz)) {
-                add_run();
-#pragma unroll
-                for (int j = 0; j < 27; ++j) acc[j] = 0.0;
-            }
-            cx = ix;
-            cy = iy;
-            cz = iz;
-            open = true;
-            const double ms = p.w * S;
-#pragma unroll
-            for (int a = 0; a < 3; ++a)
-#pragma unroll
-                for (int b = 0; b < 3; ++b) {
-                    const double wab = ms * wx[a] * wy[b];
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) acc[(a * 3 + b) * 3 + c] += wab * wz[c];
-                }
+            for (int j = 0; j < 27; ++j) acc[j] = 0.0;
         }
+        cx = ix;
+        cy = iy;
+        cz = iz;
+        open = true;
+        const double ms = p.w * S;
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                const double wab = ms * wx[a] * wy[b];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) acc[(a * 3 + b) * 3 + c] += wab * wz[c];
+            }
     }
     if (open) add_run();
     __syncthreads();
-#pragma unroll 1
-    for (int q = 0; q < 8; ++q) {
-        const int qb = __shfl(base, 8 * q, 64), qc = __shfl(cells, 8 * q, 64);
-        const int qx = __shfl(ox, 8 * q, 64), qy = __shfl(oy, 8 * q, 64),
-                  qz = __shfl(oz, 8 * q, 64), qey = __shfl(ey, 8 * q, 64),
-                  qez = __shfl(ez, 8 * q, 64);
-        for (int j = 0; j < kAssignSlot / kAssignThreads; ++j) {
-            const int t = q * kAssignSlot + j * kAssignThreads + lane;
-            const int u = t - qb;
-            if (u >= qc) continue;
-            const unsigned long long v = tile[t];
-            if (!v) continue;
-            const int lz = u % qez, ly = (u / qez) % qey, lx = u / (qez * qey);
-            atomicAdd(&mass[((size_t)((qx + lx) & mask) * N + ((qy + ly) & mask)) * N +
-                            ((qz + lz) & mask)],
-                      v);
+    unsigned long long *dst = slots + (size_t)item * kBoxWords;
+    for (int t = threadIdx.x; t < kBoxWords; t += kAssignThreads) dst[t] = box[t];
+}
+
+// One workgroup per cell, one thread per mesh point of the cell: the sum of the slot words of
+// every chunk of every cell whose box covers the point (its own cell, and the neighbour on
+// the low side for the cell's first two planes, on the high side for its last plane, per
+// axis).  The 27 neighbours' chunk ranges are read into LDS once.
+__global__ __launch_bounds__(kCellPts * kCellPts * kCellPts) void k_pm_gather(
+    int N, const uint32_t *__restrict__ item_start, const unsigned long long *__restrict__ slots,
+    unsigned long long *__restrict__ mass)
+{
+    __shared__ uint32_t rng[27][2];
+    const int ncell = N / kCellPts, cm = ncell - 1;
+    const int cx = (int)blockIdx.x / (ncell * ncell), cy = ((int)blockIdx.x / ncell) % ncell,
+              cz = (int)blockIdx.x % ncell;
+    const int t = threadIdx.x;
+    if (t < 27) {
+        const int dx = t / 9 - 1, dy = (t / 3) % 3 - 1, dz = t % 3 - 1;
+        const uint32_t m = cell_index((uint32_t)((cx + dx) & cm), (uint32_t)((cy + dy) & cm),
+                                      (uint32_t)((cz + dz) & cm));
+        rng[t][0] = item_start[m];
+        rng[t][1] = item_start[m + 1];
+    }
+    __syncthreads();
+    const int x0 = t >> 6, y0 = (t >> 3) & 7, z0 = t & 7; // point within the cell
+    unsigned long long sum = 0ull;
+    for (int dx = -1; dx <= 1; ++dx) {
+        const int lx = x0 - 8 * dx + 1; // the point in the box of neighbour dx
+        if (lx < 0 || lx >= kBox) continue;
+        for (int dy = -1; dy <= 1; ++dy) {
+            const int ly = y0 - 8 * dy + 1;
+            if (ly < 0 || ly >= kBox) continue;
+            for (int dz = -1; dz <= 1; ++dz) {
+                const int lz = z0 - 8 * dz + 1;
+                if (lz < 0 || lz >= kBox) continue;
+                const int k = ((dx + 1) * 3 + (dy + 1)) * 3 + (dz + 1);
+                const int w = (lx * kBox + ly) * kBox + lz;
+                for (uint32_t it = rng[k][0]; it < rng[k][1]; ++it)
+                    sum += slots[(size_t)it * kBoxWords + w];
+            }
         }
     }
+    mass[((size_t)(8 * cx + x0) * N + (size_t)(8 * cy + y0)) * N + (size_t)(8 * cz + z0)] = sum;
 }
 
 // ---------------------------------------------------------------- FFT on bundles of lines
@@ -584,13 +596,29 @@ void launch_pm_green(int N, double L, double eta, float *green, float2 *tw, hipS
     k_pm_green<<<(unsigned)((work + 255) / 256), 256, 0, s>>>(N, L, eta, green, tw);
 }
 
-void launch_pm_assign(const double4 *ps, int64_t n, int N, double L, unsigned long long *mx,
-                      unsigned long long *mass, hipStream_t s)
+size_t pm_assign_cells(int N) { const size_t c = (size_t)N / kCellPts; return c * c * c; }
+size_t pm_assign_items_max(int N, int64_t n)
 {
-    fill_u64((uint64_t *)mass, (size_t)N * N * N, 0ull, s);
-    if (!n) return;
-    k_pm_assign<<<(unsigned)((n + kAssignChunk - 1) / kAssignChunk), kAssignThreads, 0, s>>>(
-        ps, n, N, N / L, mx, mass);
+    return pm_assign_cells(N) + (size_t)((n + kCellChunk - 1) / kCellChunk);
+}
+size_t pm_assign_slot_words() { return kBoxWords; }
+
+void launch_pm_assign(const double4 *ps, const uint64_t *key, int64_t n, int N, double L,
+                      const unsigned long long *mx, uint32_t *cell_start, uint32_t *item_start,
+                      uint32_t *scan_tmp, unsigned long long *slots, unsigned long long *mass,
+                      hipStream_t s)
+{
+    const uint32_t ncells = (uint32_t)pm_assign_cells(N);
+    const int lc = __builtin_ctz((unsigned)(N / kCellPts)); // tree level of the cells
+    const int sh = 3 * (21 - lc);
+    k_pm_cells<<<(ncells + 1 + 255) / 256, 256, 0, s>>>(key, n, sh, ncells, cell_start);
+    k_pm_cell_items<<<(ncells + 255) / 256, 256, 0, s>>>(cell_start, ncells, item_start);
+    scan_u32(item_start, ncells, item_start + ncells, scan_tmp, s); // exclusive; the total last
+    const size_t items = pm_assign_items_max(N, n);
+    if (n)
+        k_pm_assign<<<(unsigned)items, kAssignThreads, 0, s>>>(ps, n, N, N / L, mx, cell_start,
+                                                               item_start, ncells, slots);
+    k_pm_gather<<<ncells, kCellPts * kCellPts * kCellPts, 0, s>>>(N, item_start, slots, mass);
 }
 
 void launch_pm_potential(const unsigned long long *mass, const unsigned long long *mx,

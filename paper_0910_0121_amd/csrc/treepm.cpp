@@ -101,6 +101,9 @@ struct treepm_ctx {
     // particle mesh: fixed-point masses (later the potential), the complex work mesh, the
     // force mesh, the Green's table, twiddles, max mass
     Buf pm_mass, pm_grid, pm_f, pm_green, pm_tw, pm_mx;
+    // mass assignment scratch: per mesh cell first particle and chunk offsets, the chunks'
+    // boxes of partial sums
+    Buf pm_cells, pm_slots;
     // per particle: the mesh force in the caller's order (x, y, z, 0)
     Buf pm_stage;
     Buf n_q; // per node second moment (6 doubles), quadrupole boxes only
@@ -878,7 +881,7 @@ TREEPM_API int treepm_destroy(treepm_ctx *c)
                   &c->g_hi[1], &c->g_hi[2], &c->g_misc, &c->off, &c->glen, &c->wctr, &c->scan64, &c->entries,
                   &c->wstats, &c->overflow, &c->rec, &c->kept, &c->kept_sum, &c->gcells, &c->cls, &c->out[0],
                   &c->out[1], &c->out[2], &c->bnd, &c->runs, &c->pm_mass, &c->pm_grid,
-                  &c->pm_f, &c->pm_green, &c->pm_tw, &c->pm_mx, &c->pm_stage,
+                  &c->pm_f, &c->pm_green, &c->pm_tw, &c->pm_mx, &c->pm_stage, &c->pm_cells, &c->pm_slots,
                   &c->n_q, &c->step_min, &c->tab};
     {
         // the work is done: free on the private stream, not behind the last stream
@@ -1155,6 +1158,12 @@ TREEPM_API int treepm_force_long(treepm_ctx *c, void *ax, void *ay, void *az, in
         if (e == hipSuccess) e = reserve(c->pm_green, H * H * H * 4);
         if (e == hipSuccess) e = reserve(c->pm_tw, (size_t)N / 2 * 8);
         if (e == hipSuccess) e = reserve(c->pm_stage, (size_t)c->n * 16);
+        const size_t cells = pm_assign_cells((int)N);
+        if (e == hipSuccess)
+            e = reserve(c->pm_cells, (2 * (cells + 1) + scan_tmp_elems(cells) + 64) * 4);
+        if (e == hipSuccess)
+            e = reserve(c->pm_slots, pm_assign_items_max((int)N, c->n) *
+                                         pm_assign_slot_words() * 8);
         if (e != hipSuccess) return hip_fail(c, e, "PM meshes");
     }
     const double eta = 0.5 * P.r_cut;
@@ -1181,7 +1190,15 @@ TREEPM_API int treepm_force_long(treepm_ctx *c, void *ax, void *ay, void *az, in
     unsigned long long *mass = c->pm_mass.as<unsigned long long>();
     float2 *grid = c->pm_grid.as<float2>();
     float *phi = c->pm_mass.as<float>(); // the masses are consumed by the first pass
-    launch_pm_assign(ps, c->n, (int)N, P.L, c->pm_mx.as<unsigned long long>(), mass, s);
+    {
+        const size_t cells = pm_assign_cells((int)N);
+        uint32_t *cell_start = c->pm_cells.as<uint32_t>();
+        uint32_t *item_start = cell_start + (cells + 1);
+        uint32_t *scan_tmp = item_start + (cells + 1);
+        launch_pm_assign(ps, c->key.as<uint64_t>(), c->n, (int)N, P.L,
+                         c->pm_mx.as<unsigned long long>(), cell_start, item_start, scan_tmp,
+                         c->pm_slots.as<unsigned long long>(), mass, s);
+    }
     launch_pm_potential(mass, c->pm_mx.as<unsigned long long>(), c->n, (int)N, grid, phi,
                         c->pm_green.as<float>(), c->pm_tw.as<float2>(), s);
     launch_pm_force(phi, (int)N, P.L, c->pm_f.as<float4>(), s);
