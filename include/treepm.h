@@ -121,6 +121,12 @@ typedef struct {
     double latency_ms;      /* ensemble results only: completion minus submission (ms)    */
     double queue_ms;        /* ensemble results only: start of service minus submission,
                                the part of latency_ms spent queued (ms)                  */
+    double stage_ms[3];     /* ensemble results only, the service time in three parts
+                               (ms): admission, input staging and build; walk and force;
+                               results copied back to the host                           */
+    int32_t batch_boxes;    /* ensemble results only: boxes whose walk and force shared
+                               launches with this request's (1 when it ran alone)        */
+    int32_t reserved_;
 } treepm_stats;
 
 /* Create a context for one box on HIP device `device`.  Validates *params (ERR_ARG).  The
@@ -165,6 +171,21 @@ int treepm_walk(treepm_ctx *ctx, void *hip_stream, treepm_stats *stats);
  * (ERR_STATE).  Uses no memory beyond what the build and walk allocated (device outputs). */
 int treepm_force_short(treepm_ctx *ctx, void *ax, void *ay, void *az, int out_prec,
                        int mem_kind, void *hip_stream);
+
+/* Walk (as treepm_walk) and FP32 short-range force (as treepm_force_short with float outputs)
+ * of n_boxes built boxes at once, with shared launches (Section 2.2 steps 5 and 6 for every
+ * box): one traversal launch over the (box, group) pairs of all boxes, and one persistent
+ * force launch per size class over all of them.  Each box keeps its own particles, tree,
+ * lists and pair-law table, and its results equal, bit for bit, those of treepm_walk followed
+ * by treepm_force_short on that box alone.  ctxs: n_boxes (1 .. 16) distinct contexts on one
+ * device, each built (ERR_STATE) with precision TREEPM_FP32 (ERR_ARG); ax[b], ay[b], az[b]:
+ * box b's n floats each, of kind mem_kind.  The first box's streams and scratch serve the
+ * launches.  Returns when host outputs are written (TREEPM_HOST) or the work is queued
+ * (TREEPM_DEVICE).  On an error every box is left built but not walked; the failing box's
+ * last_error names the cause and the others' say that another box failed. */
+int treepm_force_short_batch(treepm_ctx *const *ctxs, int n_boxes, float *const *ax,
+                             float *const *ay, float *const *az, int mem_kind,
+                             void *hip_stream);
 
 /* The short-range kick fused with the force (Section 2.2 step 5: a particle's velocity is
  * kicked with its short-range force as soon as that is computed, without storing it):

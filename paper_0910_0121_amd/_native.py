@@ -39,11 +39,14 @@ class treepm_stats(C.Structure):
                 ("n_cell_entries", C.c_int64), ("n_part_entries", C.c_int64),
                 ("interactions", C.c_int64), ("max_level", C.c_int32),
                 ("max_group", C.c_int32), ("t_ms", C.c_double * 4), ("evaluated", C.c_int64),
-                ("latency_ms", C.c_double), ("queue_ms", C.c_double)]
+                ("latency_ms", C.c_double), ("queue_ms", C.c_double),
+                ("stage_ms", C.c_double * 3), ("batch_boxes", C.c_int32), ("reserved_", C.c_int32)]
 
     def as_dict(self):
-        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "t_ms"}
+        d = {k: getattr(self, k) for k, _ in self._fields_
+             if k not in ("t_ms", "stage_ms", "reserved_")}
         d["t_ms"] = list(self.t_ms)
+        d["stage_ms"] = list(self.stage_ms)
         return d
 
 
@@ -61,6 +64,7 @@ _SIGS = {
     "treepm_build": (_i, [_p, _i64, _p, _p, _p, _p, _i, _p]),
     "treepm_walk": (_i, [_p, _p, C.POINTER(treepm_stats)]),
     "treepm_force_short": (_i, [_p, _p, _p, _p, _i, _i, _p]),
+    "treepm_force_short_batch": (_i, [_p, _i, _p, _p, _p, _i, _p]),
     "treepm_force_long": (_i, [_p, _p, _p, _p, _i, _i, _i, _p]),
     "treepm_eps_of_z": (C.c_double, [C.c_double, C.c_double, C.c_double]),
     "treepm_timestep": (_i, [_p, _i64, _p, _p, _p, _p, _p, _p, _i, C.c_double, C.c_double, _p,
@@ -211,6 +215,27 @@ def treepm_force_short(ctx, ax, ay, az, stream=None) -> None:
     prec = TREEPM_FP64 if dt == "float64" else TREEPM_FP32
     _check(lib().treepm_force_short(ctx, bufs[0][0], bufs[1][0], bufs[2][0], prec, kind,
                                     _stream(stream, kind)), ctx)
+
+
+def treepm_force_short_batch(ctxs, outs, stream=None) -> None:
+    """Walk and FP32 short-range force of several built boxes with shared launches.  outs[b]
+    is box b's (ax, ay, az), float32, all host or all device buffers."""
+    nb = len(ctxs)
+    if nb != len(outs):
+        raise ValueError("one (ax, ay, az) per box")
+    bufs = [[_buf(a, "float32") for a in o] for o in outs]
+    kinds = {b[1] for bb in bufs for b in bb}
+    if len(kinds) != 1:
+        raise ValueError("all outputs must be host or all device buffers")
+    kind = kinds.pop()
+    arr = C.c_void_p * max(nb, 1)
+    cs = arr(*ctxs)
+    ax, ay, az = (arr(*[bb[a][0] for bb in bufs]) for a in range(3))
+    rc = lib().treepm_force_short_batch(cs, nb, ax, ay, az, kind, _stream(stream, kind))
+    if rc < 0:
+        msgs = [treepm_last_error(c) for c in ctxs if c]
+        named = [m for m in msgs if m and m != "another box of the batch failed"]
+        raise TreePMError(rc, named[0] if named else (msgs[0] if msgs else ""))
 
 
 def treepm_force_long(ctx, ax, ay, az, accumulate=False, stream=None) -> None:

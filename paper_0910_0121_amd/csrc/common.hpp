@@ -173,6 +173,32 @@ void launch_walk_pool(const WalkNode *wn, GroupArrays gr, uint32_t n_groups, Wal
 void launch_walk_stats(GroupArrays gr, uint32_t n_groups, const uint32_t *len,
                        const uint32_t *gcells, unsigned long long *stats, hipStream_t s);
 
+// Shared launches over several boxes.  The groups of boxes 0 .. nb-1 are laid end to end as
+// one sequence of work items; box b holds items [g0, g0 + n_groups).  Each box keeps its own
+// tree, lists and flags, exactly as in a walk of that box alone.
+constexpr int kMaxBatch = 16;
+struct WalkBox {
+    const WalkNode *wn;
+    GroupArrays gr;
+    WalkParams wp;
+    uint64_t *off;                 // counts (count pass) or list offsets
+    uint32_t *len, *entries, *gcells;
+    unsigned long long *pool_next; // one-pass walk: the box's pool counter
+    uint64_t pool_cap, chunk, reserve;
+    unsigned *overflow;
+    uint32_t g0, n_groups;
+};
+// The two passes over all items of the boxes (one wave per item; descriptors in device
+// memory, total = sum of n_groups).
+void launch_walk_count_multi(const WalkBox *boxes, int nb, uint32_t total, hipStream_t s);
+void launch_walk_emit_multi(const WalkBox *boxes, int nb, uint32_t total, hipStream_t s);
+// One pass over all items: n_waves waves take items in batches from kXcds counters (zeroed
+// here; counters holds kXcds words) and write each box's lists into chunks of that box's
+// pool.  A box whose list or pool runs out of room gets bit 4 of its overflow flag; the other
+// boxes are not affected.
+void launch_walk_pool_multi(const WalkBox *boxes, int nb, uint32_t total, uint32_t n_waves,
+                            uint32_t *counters, hipStream_t s);
+
 // ------------------------------------------------------------------ launchers (k_force.hip)
 // Workgroups are dealt to the 8 XCDs (each with its own L2) round-robin by block index.
 // xcd_block renumbers block b of n so that each XCD takes a contiguous run: neighbouring
@@ -230,6 +256,27 @@ void launch_force_f32(NodeArrays nd, GroupArrays gr, uint32_t *cls, const uint32
                       const double4 *ps, const uint32_t *pidx, ForceParams fp, ForceTable ft,
                       void *rec, int rec64, int n_cu, const hipStream_t *streams,
                       int n_streams);
+// The FP32 force of several boxes in one persistent launch per class: box b's class buffer,
+// lists and records as launch_force_f32 takes them for that box alone (queues zeroed by
+// launch_force_f32_prep).  Boxes whose tables have equal tab_id share one LDS copy; a
+// workgroup reloads the table when the next box's differs.  class_totals[K - 1] is the sum
+// over boxes of class K's size, max_entries the largest table.  float4 records only.
+struct ForceBox {
+    NodeArrays nd;
+    GroupArrays gr;
+    uint32_t *cls;
+    const uint64_t *off;
+    const uint32_t *len, *entries;
+    const double4 *ps;
+    const uint32_t *pidx;
+    ForceParams fp;
+    ForceTable ft;
+    void *rec;
+    uint64_t tab_id;
+};
+void launch_force_f32_multi(const ForceBox *boxes, int nb, const uint32_t *class_totals,
+                            uint32_t max_entries, int n_cu, const hipStream_t *streams,
+                            int n_streams);
 // rec of the force launchers: one record per particle in the caller's order (pidx), float4
 // (ax, ay, az, 0) or, with rec64, double4.  launch_force_out then writes them out: mode 0
 // float arrays, 1 double arrays (from float4 / double4 records), 2 kick (v += dt a into double

@@ -448,6 +448,70 @@ __global__ __launch_bounds__(64 * kForceWaves, force_waves_per_simd(K)) void k_f
     }
 }
 
+// k_force_f32 over several boxes (float4 records): the workgroup takes the boxes in order
+// and, within each, the class's queues as above.  The tiles sit at the front of LDS and the
+// table after them; at a box whose table differs from the one loaded, the workgroup waits
+// for its waves to finish the previous box and copies the new table.  Every wave sees the
+// same boxes, class sizes and table ids, so all reach the same barriers.
+template <int K>
+__global__ __launch_bounds__(64 * kForceWaves, force_waves_per_simd(K)) void k_force_f32_multi(
+    const ForceBox *__restrict__ bx, int nb)
+{
+    extern __shared__ float4 smem[];
+    float4 *tile = smem + (threadIdx.x >> 6) * kTileF32;
+    float4 *tab = smem + kForceWaves * kTileF32;
+    const uint32_t lane = __lane_id();
+    const uint32_t xcd = blockIdx.x % kXcds;
+    uint64_t loaded = 0;
+    bool have = false;
+    for (int b = 0; b < nb; ++b) {
+        const ForceBox &B = bx[b];
+        uint32_t *cls = B.cls;
+        if (cls[kClsCounts + K - 1] == 0) continue;
+        if (!have || B.tab_id != loaded) {
+            __syncthreads(); // the previous table is no longer read
+            for (uint32_t i = threadIdx.x; i < B.ft.entries; i += blockDim.x) tab[i] = B.ft.coef[i];
+            __syncthreads();
+            loaded = B.tab_id;
+            have = true;
+        }
+        const TabView T{tab - B.ft.base, B.ft.c, 1.0f + B.ft.c};
+        GroupFrame F;
+        F.L = B.fp.L;
+        F.rc2 = B.fp.rc2;
+        F.inv_len = 0.5 * B.fp.inv_eta; // 1 / r_cut
+        const double scale = F.inv_len * F.inv_len;
+        const double rc = B.fp.rc * (1.0 + 0x1p-10);
+        const uint32_t *part_start = cls + kClsStarts + (K - 1) * (kXcds + 1);
+        uint32_t *queue = cls + kClsQueue + (K - 1) * kXcds;
+        const GroupArrays &gr = B.gr;
+        for (uint32_t p = 0; p < kXcds; ++p) {
+            const uint32_t part = (xcd + p) % kXcds;
+            const uint32_t lo = part_start[part], size = part_start[part + 1] - lo;
+            for (;;) {
+                const uint32_t q =
+                    __builtin_amdgcn_readfirstlane(atomicAdd(&queue[part], lane == 0 ? 1u : 0u));
+                if (q >= size) break;
+                const uint32_t g = cls[lo + q];
+                F.xg0 = gr.xgx[g]; F.xg1 = gr.xgy[g]; F.xg2 = gr.xgz[g];
+                F.cg0 = gr.cgx[g]; F.cg1 = gr.cgy[g]; F.cg2 = gr.cgz[g];
+                F.hg0 = gr.hgx[g]; F.hg1 = gr.hgy[g]; F.hg2 = gr.hgz[g];
+                const bool interior = gr.lox[g] - rc >= 0.0 && gr.hix[g] + rc < F.L &&
+                                      gr.loy[g] - rc >= 0.0 && gr.hiy[g] + rc < F.L &&
+                                      gr.loz[g] - rc >= 0.0 && gr.hiz[g] + rc < F.L;
+                if (interior)
+                    force_group_f32<K, 0, false>(tile, T, B.nd, gr.count[g], gr.first[g],
+                                                 B.entries + B.off[g], B.len[g], B.ps, B.pidx,
+                                                 F, scale, B.rec, B.fp.kept + g);
+                else
+                    force_group_f32<K, 0, true>(tile, T, B.nd, gr.count[g], gr.first[g],
+                                                B.entries + B.off[g], B.len[g], B.ps, B.pidx,
+                                                F, scale, B.rec, B.fp.kept + g);
+            }
+        }
+    }
+}
+
 __global__ __launch_bounds__(256) void k_kept_stats(GroupArrays gr, uint32_t n_groups,
                                                     const uint32_t *__restrict__ kept,
                                                     unsigned long long *out)
@@ -792,6 +856,32 @@ void launch_force_f32(NodeArrays nd, GroupArrays gr, uint32_t *cls, const uint32
         else                                                                                   \
             k_force_f32<KK, 0><<<blocks, 64 * kForceWaves, lds, s>>>(                          \
                 nd, gr, cls, starts, queue, off, len, entries, ps, pidx, fp, ft, rec);         \
+    }
+    TPM_LAUNCH(8)
+    TPM_LAUNCH(7)
+    TPM_LAUNCH(6)
+    TPM_LAUNCH(5)
+    TPM_LAUNCH(4)
+    TPM_LAUNCH(3)
+    TPM_LAUNCH(2)
+    TPM_LAUNCH(1)
+#undef TPM_LAUNCH
+}
+
+void launch_force_f32_multi(const ForceBox *boxes, int nb, const uint32_t *class_totals,
+                            uint32_t max_entries, int n_cu, const hipStream_t *streams,
+                            int n_streams)
+{
+    const size_t lds = ((size_t)max_entries + (size_t)kForceWaves * kTileF32) * sizeof(float4);
+    int next = 0;
+#define TPM_LAUNCH(KK)                                                                         \
+    if (class_totals[KK - 1]) {                                                                \
+        const uint32_t waves = class_totals[KK - 1];                                           \
+        const uint32_t cap = (uint32_t)n_cu * (uint32_t)force_waves_per_simd(KK);              \
+        const uint32_t want = (waves + kForceWaves - 1) / kForceWaves;                         \
+        const uint32_t blocks = want < cap ? want : cap;                                       \
+        k_force_f32_multi<KK><<<blocks, 64 * kForceWaves, lds,                                 \
+                                streams[next++ % n_streams]>>>(boxes, nb);                     \
     }
     TPM_LAUNCH(8)
     TPM_LAUNCH(7)

@@ -333,6 +333,120 @@ __global__ __launch_bounds__(64) void k_walk_pool(const WalkNode *__restrict__ w
     }
 }
 
+// ------------------------------------------------------------------ several boxes at once
+// The box of work item t: the last box whose first item is at most t (uniform reads).
+__device__ __forceinline__ int box_of(const WalkBox *__restrict__ bx, int nb, uint32_t t)
+{
+    int b = 0;
+    while (b + 1 < nb && bx[b + 1].g0 <= t) ++b;
+    return b;
+}
+
+// Group g of box B with that box's opening rule.
+template <int EMIT>
+__device__ __forceinline__ uint64_t walk_box_group(const WalkBox &B, uint32_t g, uint32_t *stk,
+                                                   uint32_t *s_mark, uint32_t *dst, uint64_t cap,
+                                                   uint64_t *ncell)
+{
+    if (B.wp.open)
+        return walk_group<EMIT, 1>(B.wn, B.gr, g, B.wp, stk, s_mark, dst, cap, B.overflow,
+                                   ncell);
+    return walk_group<EMIT, 0>(B.wn, B.gr, g, B.wp, stk, s_mark, dst, cap, B.overflow, ncell);
+}
+
+// The two passes of k_walk over the items of several boxes, one wave per item.
+template <int EMIT>
+__global__ __launch_bounds__(64) void k_walk_multi(const WalkBox *__restrict__ bx, int nb,
+                                                   uint32_t total)
+{
+    __shared__ uint32_t stk[kStackCap];
+    __shared__ uint32_t s_mark[64];
+    const uint32_t t = xcd_block(blockIdx.x, gridDim.x);
+    if (t >= total) return;
+    const WalkBox &B = bx[box_of(bx, nb, t)];
+    const uint32_t g = t - B.g0;
+    uint64_t ncell = 0;
+    const uint64_t w =
+        walk_box_group<EMIT>(B, g, stk, s_mark, EMIT ? B.entries + B.off[g] : nullptr, ~0ull,
+                             &ncell);
+    if (threadIdx.x == 0) {
+        if (!EMIT) {
+            B.off[g] = w;
+        } else {
+            B.len[g] = (uint32_t)w;
+            B.gcells[g] = (uint32_t)ncell;
+        }
+    }
+}
+
+// k_walk_pool over the items of several boxes.  A wave's chunk belongs to one box: at the
+// first item of another box it takes a fresh chunk from that box's pool.  A list that does
+// not fit a chunk, or an exhausted pool, flags its box (bit 4) and the wave goes on with the
+// next item, so the other boxes' lists are complete.
+__global__ __launch_bounds__(64) void k_walk_pool_multi(const WalkBox *__restrict__ bx, int nb,
+                                                        uint32_t total, uint32_t *counters)
+{
+    __shared__ uint32_t stk[kStackCap];
+    __shared__ uint32_t s_mark[64];
+    uint64_t cur = 0, end = 0; // the wave's current chunk [cur, end) of box cb
+    int cb = -1;
+    const uint32_t x0 = blockIdx.x % kXcds;
+    for (uint32_t r = 0; r < kXcds; ++r) {
+        const uint32_t x = (x0 + r) % kXcds;
+        const uint32_t lo = (uint32_t)((uint64_t)total * x / kXcds);
+        const uint32_t hi = (uint32_t)((uint64_t)total * (x + 1) / kXcds);
+        for (;;) {
+            uint32_t k = 0;
+            if (threadIdx.x == 0) k = atomicAdd(&counters[x], kWalkBatch);
+            k = (uint32_t)__builtin_amdgcn_readfirstlane((int)k);
+            if (k >= hi - lo) break;
+            const uint32_t t1 = lo + k + kWalkBatch < hi ? lo + k + kWalkBatch : hi;
+            for (uint32_t t = lo + k; t < t1; ++t) {
+                const int b = box_of(bx, nb, t);
+                const WalkBox &B = bx[b];
+                if (b != cb) {
+                    cb = b;
+                    cur = end = 0;
+                }
+                const uint32_t g = t - B.g0;
+                uint64_t ncell = 0, w = 0;
+                bool fits = false;
+                if (end - cur >= B.reserve) {
+                    w = walk_box_group<1>(B, g, stk, s_mark, B.entries + cur, end - cur, &ncell);
+                    fits = w <= end - cur;
+                }
+                if (!fits) {
+                    unsigned long long c0 = 0;
+                    if (threadIdx.x == 0) c0 = atomicAdd(B.pool_next, (unsigned long long)B.chunk);
+                    const uint32_t c_lo =
+                        (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)c0);
+                    const uint32_t c_hi =
+                        (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(c0 >> 32));
+                    cur = ((uint64_t)c_hi << 32) | c_lo;
+                    end = cur + B.chunk;
+                    if (end > B.pool_cap) {
+                        if (threadIdx.x == 0) atomicOr(B.overflow, 4u);
+                        cur = end = 0;
+                        continue;
+                    }
+                    w = walk_box_group<1>(B, g, stk, s_mark, B.entries + cur, B.chunk, &ncell);
+                    if (w > B.chunk) {
+                        if (threadIdx.x == 0) atomicOr(B.overflow, 4u);
+                        cur = end = 0;
+                        continue;
+                    }
+                }
+                if (threadIdx.x == 0) {
+                    B.off[g] = cur;
+                    B.len[g] = (uint32_t)w;
+                    B.gcells[g] = (uint32_t)ncell;
+                }
+                cur += w;
+            }
+        }
+    }
+}
+
 // (cell entries, particle entries, interactions = sum_g count_g * L_g): block reductions and
 // one atomic per block.
 __global__ __launch_bounds__(256) void k_walk_stats(GroupArrays gr, uint32_t n_groups,
@@ -420,6 +534,24 @@ void launch_walk_pool(const WalkNode *wn, GroupArrays gr, uint32_t n_groups, Wal
                                               (unsigned long long *)(counters + kXcds),
                                               pool_cap, chunk, reserve, off, len, entries,
                                               overflow, gcells);
+}
+
+void launch_walk_count_multi(const WalkBox *boxes, int nb, uint32_t total, hipStream_t s)
+{
+    if (total) k_walk_multi<0><<<total, 64, 0, s>>>(boxes, nb, total);
+}
+
+void launch_walk_emit_multi(const WalkBox *boxes, int nb, uint32_t total, hipStream_t s)
+{
+    if (total) k_walk_multi<1><<<total, 64, 0, s>>>(boxes, nb, total);
+}
+
+void launch_walk_pool_multi(const WalkBox *boxes, int nb, uint32_t total, uint32_t n_waves,
+                            uint32_t *counters, hipStream_t s)
+{
+    if (!total) return;
+    fill_u32(counters, kXcds, 0u, s);
+    k_walk_pool_multi<<<n_waves, 64, 0, s>>>(boxes, nb, total, counters);
 }
 
 void launch_walk_stats(GroupArrays gr, uint32_t n_groups, const uint32_t *len,

@@ -3,6 +3,7 @@
 #include "treepm.h"
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -107,6 +108,7 @@ struct treepm_ctx {
     // per particle: the mesh force in the caller's order (x, y, z, 0)
     Buf pm_stage;
     Buf n_q; // per node second moment (6 doubles), quadrupole boxes only
+    Buf bdesc; // shared launches led by this context: the boxes' descriptors and counters
     Buf step_min; // time-step reduction result
     int pm_n = 0; // mesh size, box and eta the table was built for
     double pm_L = 0.0, pm_eta = 0.0;
@@ -376,9 +378,13 @@ struct Run3 {
     size_t bytes;
 };
 
-int fetch(treepm_ctx *c, hipStream_t s, Run3 a, Run3 b = {nullptr, nullptr, 0},
-          Run3 d = {nullptr, nullptr, 0})
+// fetch in two halves, so that several contexts' results can be queued before the host
+// waits: fetch_post queues the publishing kernel (or, without a mailbox or for too many words,
+// copies at once) and returns the sequence number to wait for (0: already copied).
+int fetch_post(treepm_ctx *c, hipStream_t s, uint32_t *seq_out, Run3 a,
+               Run3 b = {nullptr, nullptr, 0}, Run3 d = {nullptr, nullptr, 0})
 {
+    *seq_out = 0;
     const size_t words = (a.bytes + b.bytes + d.bytes) / 4;
     if (!c->mbox_h || words >= kMailboxWords) {
         int rc;
@@ -392,6 +398,14 @@ int fetch(treepm_ctx *c, hipStream_t s, Run3 a, Run3 b = {nullptr, nullptr, 0},
                   (uint32_t)(b.bytes / 4), (const uint32_t *)d.src, (uint32_t)(d.bytes / 4),
                   c->mbox_d, seq, s);
     HIPCHK(c, hipGetLastError());
+    *seq_out = seq;
+    return TREEPM_OK;
+}
+
+int fetch_wait(treepm_ctx *c, hipStream_t s, uint32_t seq, Run3 a,
+               Run3 b = {nullptr, nullptr, 0}, Run3 d = {nullptr, nullptr, 0})
+{
+    if (!seq) return TREEPM_OK;
     for (uint32_t spin = 0;
          __atomic_load_n(&c->mbox_h[0], __ATOMIC_ACQUIRE) != seq; ++spin) {
         if (spin < 2048) {
@@ -412,6 +426,14 @@ int fetch(treepm_ctx *c, hipStream_t s, Run3 a, Run3 b = {nullptr, nullptr, 0},
         w += r.bytes / 4;
     }
     return TREEPM_OK;
+}
+
+int fetch(treepm_ctx *c, hipStream_t s, Run3 a, Run3 b = {nullptr, nullptr, 0},
+          Run3 d = {nullptr, nullptr, 0})
+{
+    uint32_t seq = 0;
+    const int rc = fetch_post(c, s, &seq, a, b, d);
+    return rc ? rc : fetch_wait(c, s, seq, a, b, d);
 }
 
 void record(treepm_ctx *c, int i, hipStream_t s)
@@ -625,10 +647,20 @@ int do_build(treepm_ctx *c, int64_t n, const double *x, const double *y, const d
 // Waves of the one-pass walk: enough to fill the chip, about 16 groups each at least.
 uint32_t pool_waves(uint32_t G) { return std::max(1u, std::min(8192u, (G + 15) / 16)); }
 
-int do_walk(treepm_ctx *c, hipStream_t s)
+// One box's walk in parts, shared by treepm_walk and the shared launches of several boxes.
+struct BoxWalk {
+    uint32_t G = 0;
+    WalkParams wp{};
+    bool pooled = false; // one pass into a pool sized from the box's last walk
+    uint64_t pool = 0, chunk = 0, reserve_len = 0;
+    uint32_t waves = 0;
+};
+
+// Buffers, cleared flags and statistics, the opening parameters, and the one-pass layout
+// when the last walk of this context sizes it (its pool is then reserved).
+int prepare_walk(treepm_ctx *c, hipStream_t s, BoxWalk &bw)
 {
-    int rc;
-    uint32_t G = c->n_groups;
+    const uint32_t G = c->n_groups;
     hipError_t e;
     if ((e = reserve(c->off, ((size_t)G + 1) * 8)) != hipSuccess) return hip_fail(c, e, "offsets");
     if ((e = reserve(c->glen, ((size_t)G + 1) * 4)) != hipSuccess) return hip_fail(c, e, "lengths");
@@ -639,92 +671,132 @@ int do_walk(treepm_ctx *c, hipStream_t s)
     if ((e = reserve(c->overflow, 64)) != hipSuccess) return hip_fail(c, e, "flags");
     if ((e = reserve(c->gcells, ((size_t)G + 1) * 4)) != hipSuccess)
         return hip_fail(c, e, "group stats");
-    uint64_t *off = c->off.as<uint64_t>();
-    uint32_t *len = c->glen.as<uint32_t>();
-    uint64_t *tot = c->scan64.as<uint64_t>();
-    unsigned *ovf = c->overflow.as<unsigned>();
-    unsigned long long *ws = c->wstats.as<unsigned long long>();
-    fill_u32(ovf, 1, 0u, s);
-    fill_u64((uint64_t *)ws, 4, 0ull, s);
+    if ((e = reserve(c->cls, (kClsLists + kForceClasses * ((size_t)G + 1)) * 4)) != hipSuccess)
+        return hip_fail(c, e, "group classes");
+    fill_u32(c->overflow.as<unsigned>(), 1, 0u, s);
+    fill_u64(c->wstats.as<uint64_t>(), 4, 0ull, s);
     const treepm_params &P = c->prm;
     const bool open = P.opening == TREEPM_OPEN_DISTANCE;
     const double th_lo = std::min(P.theta_max, P.theta / std::sqrt(0.46));
-    WalkParams wp{P.L,
-                  P.r_cut * P.r_cut,
-                  open ? P.theta_max * P.theta_max : P.theta * P.theta,
-                  open ? th_lo * th_lo : 0.0,
-                  0.5 * P.r_cut,
-                  P.theta,
-                  P.theta_max,
-                  (uint32_t)c->n_nodes,
-                  open ? 1u : 0u};
-    NodeArrays nd = nodes_view(c);
-    GroupArrays gr = groups_view(c);
-    uint32_t *gcells = c->gcells.as<uint32_t>();
-    const WalkNode *wn = c->n_walk.as<WalkNode>();
-    // The list layout (one pass into the pool, else two passes), then the statistics and
-    // the force classes; everything the host needs comes back in one read.
-    auto two_pass = [&]() -> int {
-        fill_u64(off, (size_t)G + 1, 0ull, s);
-        launch_walk_count(wn, gr, G, wp, off, ovf, s);
-        scan_u64(off, (size_t)G + 1, tot, tot + 1, s);
-        uint64_t total = 0;
-        unsigned ov = 0;
-        int r = fetch(c, s, {&total, tot, sizeof total}, {&ov, ovf, sizeof ov});
-        if (r) return r;
-        if (ov)
-            return fail(c, TREEPM_ERR_OVERFLOW, ov & 2u ? "walk read a bad node index"
-                                                        : "walk stack overflow");
-        hipError_t e2 = reserve(c->entries, std::max<size_t>(total, 1) * 4);
-        if (e2 != hipSuccess) return hip_fail(c, e2, "interaction lists");
-        launch_walk_emit(wn, gr, G, wp, off, len, c->entries.as<uint32_t>(), ovf, gcells, s);
-        return TREEPM_OK;
-    };
-    bool pooled = false;
+    bw.G = G;
+    bw.wp = WalkParams{P.L,
+                       P.r_cut * P.r_cut,
+                       open ? P.theta_max * P.theta_max : P.theta * P.theta,
+                       open ? th_lo * th_lo : 0.0,
+                       0.5 * P.r_cut,
+                       P.theta,
+                       P.theta_max,
+                       (uint32_t)c->n_nodes,
+                       open ? 1u : 0u};
+    bw.pooled = false;
     if (c->walk_hint && G) {
         // One pass, sized from the last walk: chunks of at least four of the longest list,
         // a group tried in the current chunk if twice the mean list length is left there,
         // and a pool of 25 % more entries than then plus one chunk per wave.
-        const uint32_t W = pool_waves(G);
-        const uint64_t chunk = std::max<uint64_t>(4 * c->walk_hint_max, 32768);
+        bw.waves = pool_waves(G);
+        bw.chunk = std::max<uint64_t>(4 * c->walk_hint_max, 32768);
         const uint64_t mean = c->walk_hint / std::max<uint32_t>(c->walk_hint_groups, 1);
-        const uint64_t reserve_len = std::min<uint64_t>(std::max<uint64_t>(2 * mean, 64),
-                                                        chunk / 4);
-        const uint64_t pool = c->walk_hint + c->walk_hint / 4 + (uint64_t)W * chunk;
-        if (reserve(c->entries, pool * 4) == hipSuccess) {
-            launch_walk_pool(wn, gr, G, wp, W, pool, chunk, reserve_len, c->wctr.as<uint32_t>(),
-                             off, len, c->entries.as<uint32_t>(), ovf, gcells, s);
-            pooled = true;
-        }
+        bw.reserve_len = std::min<uint64_t>(std::max<uint64_t>(2 * mean, 64), bw.chunk / 4);
+        bw.pool = c->walk_hint + c->walk_hint / 4 + (uint64_t)bw.waves * bw.chunk;
+        bw.pooled = reserve(c->entries, bw.pool * 4) == hipSuccess;
     }
-    if (!pooled && (rc = two_pass())) return rc;
-    if ((e = reserve(c->cls, (kClsLists + kForceClasses * ((size_t)G + 1)) * 4)) != hipSuccess)
-        return hip_fail(c, e, "group classes");
-    uint32_t *cls = c->cls.as<uint32_t>();
-    unsigned long long hs[4];
-    unsigned hov = 0;
-    for (;;) {
-        launch_walk_stats(gr, G, len, gcells, ws, s);
-        launch_classify(gr, G, len, cls, G + 1, s);
-        if ((rc = fetch(c, s, {&hov, ovf, sizeof hov},
-                        {c->class_counts, cls + kClsCounts, sizeof c->class_counts},
-                        {hs, ws, sizeof hs})))
-            return rc;
-        if (hov & 3u)
-            return fail(c, TREEPM_ERR_OVERFLOW, hov & 2u ? "walk read a bad node index"
-                                                         : "walk stack overflow");
-        if (!hov) break;
-        // the pool was too small for these lists: two passes, then the statistics again
-        fill_u32(ovf, 1, 0u, s);
-        fill_u64((uint64_t *)ws, 4, 0ull, s);
-        if ((rc = two_pass())) return rc;
-    }
-    c->n_entries = hs[0] + hs[1];
-    c->walk_hint = c->n_entries;
-    c->walk_hint_max = hs[3];
-    c->walk_hint_groups = G;
-    for (int i = 0; i < 3; ++i) c->st[i] = hs[i];
     return TREEPM_OK;
+}
+
+// The lists in two passes: counts, their prefix sum, the lists.
+int walk_two_pass(treepm_ctx *c, hipStream_t s, const BoxWalk &bw)
+{
+    const uint32_t G = bw.G;
+    uint64_t *off = c->off.as<uint64_t>(), *tot = c->scan64.as<uint64_t>();
+    unsigned *ovf = c->overflow.as<unsigned>();
+    const WalkNode *wn = c->n_walk.as<WalkNode>();
+    GroupArrays gr = groups_view(c);
+    fill_u64(off, (size_t)G + 1, 0ull, s);
+    launch_walk_count(wn, gr, G, bw.wp, off, ovf, s);
+    scan_u64(off, (size_t)G + 1, tot, tot + 1, s);
+    uint64_t total = 0;
+    unsigned ov = 0;
+    int r = fetch(c, s, {&total, tot, sizeof total}, {&ov, ovf, sizeof ov});
+    if (r) return r;
+    if (ov)
+        return fail(c, TREEPM_ERR_OVERFLOW, ov & 2u ? "walk read a bad node index"
+                                                    : "walk stack overflow");
+    hipError_t e = reserve(c->entries, std::max<size_t>(total, 1) * 4);
+    if (e != hipSuccess) return hip_fail(c, e, "interaction lists");
+    launch_walk_emit(wn, gr, G, bw.wp, off, c->glen.as<uint32_t>(), c->entries.as<uint32_t>(),
+                     ovf, c->gcells.as<uint32_t>(), s);
+    return TREEPM_OK;
+}
+
+// Statistics and force classes of the lists, queued with the flags for the host.
+struct WalkResults {
+    unsigned long long hs[4] = {};
+    unsigned hov = 0;
+    uint32_t seq = 0;
+};
+
+int post_walk_results(treepm_ctx *c, hipStream_t s, WalkResults &wr)
+{
+    const uint32_t G = c->n_groups;
+    GroupArrays gr = groups_view(c);
+    uint32_t *len = c->glen.as<uint32_t>(), *cls = c->cls.as<uint32_t>();
+    launch_walk_stats(gr, G, len, c->gcells.as<uint32_t>(), c->wstats.as<unsigned long long>(), s);
+    launch_classify(gr, G, len, cls, G + 1, s);
+    return fetch_post(c, s, &wr.seq, {&wr.hov, c->overflow.p, sizeof wr.hov},
+                      {c->class_counts, cls + kClsCounts, sizeof c->class_counts},
+                      {wr.hs, c->wstats.p, sizeof wr.hs});
+}
+
+int wait_walk_results(treepm_ctx *c, hipStream_t s, WalkResults &wr)
+{
+    int rc = fetch_wait(c, s, wr.seq, {&wr.hov, c->overflow.p, sizeof wr.hov},
+                        {c->class_counts, c->cls.as<uint32_t>() + kClsCounts,
+                         sizeof c->class_counts},
+                        {wr.hs, c->wstats.p, sizeof wr.hs});
+    if (rc) return rc;
+    if (wr.hov & 3u)
+        return fail(c, TREEPM_ERR_OVERFLOW, wr.hov & 2u ? "walk read a bad node index"
+                                                         : "walk stack overflow");
+    return TREEPM_OK;
+}
+
+// Until the results show complete lists: a pool that was too small (bit 4) means two
+// passes, then the statistics again.
+int settle_walk(treepm_ctx *c, hipStream_t s, const BoxWalk &bw, WalkResults &wr)
+{
+    int rc;
+    while (wr.hov) {
+        fill_u32(c->overflow.as<unsigned>(), 1, 0u, s);
+        fill_u64(c->wstats.as<uint64_t>(), 4, 0ull, s);
+        if ((rc = walk_two_pass(c, s, bw))) return rc;
+        wr = WalkResults{};
+        if ((rc = post_walk_results(c, s, wr))) return rc;
+        if ((rc = wait_walk_results(c, s, wr))) return rc;
+    }
+    c->n_entries = wr.hs[0] + wr.hs[1];
+    c->walk_hint = c->n_entries;
+    c->walk_hint_max = wr.hs[3];
+    c->walk_hint_groups = bw.G;
+    for (int i = 0; i < 3; ++i) c->st[i] = wr.hs[i];
+    return TREEPM_OK;
+}
+
+int do_walk(treepm_ctx *c, hipStream_t s)
+{
+    int rc;
+    BoxWalk bw;
+    if ((rc = prepare_walk(c, s, bw))) return rc;
+    if (bw.pooled)
+        launch_walk_pool(c->n_walk.as<WalkNode>(), groups_view(c), bw.G, bw.wp, bw.waves, bw.pool,
+                         bw.chunk, bw.reserve_len, c->wctr.as<uint32_t>(), c->off.as<uint64_t>(),
+                         c->glen.as<uint32_t>(), c->entries.as<uint32_t>(),
+                         c->overflow.as<unsigned>(), c->gcells.as<uint32_t>(), s);
+    else if ((rc = walk_two_pass(c, s, bw)))
+        return rc;
+    WalkResults wr;
+    if ((rc = post_walk_results(c, s, wr))) return rc;
+    if ((rc = wait_walk_results(c, s, wr))) return rc;
+    return settle_walk(c, s, bw, wr);
 }
 
 void fill_stats(treepm_ctx *c, treepm_stats *st)
@@ -882,7 +954,7 @@ TREEPM_API int treepm_destroy(treepm_ctx *c)
                   &c->wstats, &c->overflow, &c->rec, &c->kept, &c->kept_sum, &c->gcells, &c->cls, &c->out[0],
                   &c->out[1], &c->out[2], &c->bnd, &c->runs, &c->pm_mass, &c->pm_grid,
                   &c->pm_f, &c->pm_green, &c->pm_tw, &c->pm_mx, &c->pm_stage, &c->pm_cells, &c->pm_slots,
-                  &c->n_q, &c->step_min, &c->tab};
+                  &c->n_q, &c->step_min, &c->tab, &c->bdesc};
     {
         // the work is done: free on the private stream, not behind the last stream
         CallScope scope(c, c->own ? c->own : c->last);
@@ -1106,6 +1178,296 @@ TREEPM_API int treepm_force_short(treepm_ctx *c, void *ax, void *ay, void *az, i
     if (mem_kind != TREEPM_HOST && mem_kind != TREEPM_DEVICE)
         return fail(c, TREEPM_ERR_ARG, "mem_kind must be TREEPM_HOST or TREEPM_DEVICE");
     return do_force_short(c, ax, ay, az, out_prec, mem_kind, hip_stream, 0.0);
+}
+
+namespace {
+
+// Binds the buffer bookkeeping (reserve / release) to context c and stream s for a scope.
+struct Bind {
+    treepm_ctx *prev;
+    Bind(treepm_ctx *c, hipStream_t s) : prev(t_ctx)
+    {
+        t_ctx = c;
+        c->cur = s;
+    }
+    ~Bind() { t_ctx = prev; }
+};
+
+// On leaving a batch call every box marks the stream position after its work, as each
+// single-box call does (treepm_destroy waits for it).
+struct BatchScope {
+    treepm_ctx *const *cs;
+    int nb;
+    hipStream_t s;
+    ~BatchScope()
+    {
+        for (int b = 0; b < nb; ++b) {
+            cs[b]->last = s;
+            if (cs[b]->idle && hipEventRecord(cs[b]->idle, s) == hipSuccess)
+                cs[b]->idle_set = true;
+        }
+    }
+};
+
+// The box descriptors of one shared launch, copied to the leader's device buffer at `at`
+// (bytes); the host copy stays alive until the batch has synchronised.
+template <typename T>
+int upload(treepm_ctx *lead, hipStream_t s, const std::vector<T> &v, size_t at, T **dev)
+{
+    *dev = reinterpret_cast<T *>(static_cast<char *>(lead->bdesc.p) + at);
+    if (!v.empty())
+        HIPCHK(lead, hipMemcpyAsync(*dev, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    return TREEPM_OK;
+}
+
+WalkBox walk_box(treepm_ctx *c, const BoxWalk &bw, uint32_t g0)
+{
+    WalkBox w{};
+    w.wn = c->n_walk.as<WalkNode>();
+    w.gr = groups_view(c);
+    w.wp = bw.wp;
+    w.off = c->off.as<uint64_t>();
+    w.len = c->glen.as<uint32_t>();
+    w.entries = c->entries.as<uint32_t>();
+    w.gcells = c->gcells.as<uint32_t>();
+    w.pool_next = reinterpret_cast<unsigned long long *>(c->wctr.as<uint32_t>() + kXcds);
+    w.pool_cap = bw.pool;
+    w.chunk = bw.chunk;
+    w.reserve = bw.reserve_len;
+    w.overflow = c->overflow.as<unsigned>();
+    w.g0 = g0;
+    w.n_groups = bw.G;
+    return w;
+}
+
+// The walk of boxes cs[0 .. nb) with shared launches: the boxes whose last walk sizes a pool
+// in one pass together, the others in two passes together (one host wait for all their
+// list lengths); then every box's statistics and classes, and one wait for all of them.  A
+// box whose pool was too small is walked again alone.  Each box ends exactly as treepm_walk
+// would leave it.
+int batch_walk(treepm_ctx *const *cs, int nb, hipStream_t s)
+{
+    treepm_ctx *lead = cs[0];
+    int rc;
+    std::vector<BoxWalk> bw(nb);
+    for (int b = 0; b < nb; ++b) {
+        Bind bind(cs[b], s);
+        if ((rc = prepare_walk(cs[b], s, bw[b]))) return rc;
+    }
+    std::vector<WalkBox> two, pool;
+    std::vector<int> two_ix;
+    uint32_t two_total = 0, pool_total = 0, pool_waves_sum = 0;
+    for (int b = 0; b < nb; ++b) {
+        if (!bw[b].G) continue;
+        if (bw[b].pooled) {
+            pool.push_back(walk_box(cs[b], bw[b], pool_total));
+            pool_total += bw[b].G;
+            pool_waves_sum += bw[b].waves;
+        } else {
+            two.push_back(walk_box(cs[b], bw[b], two_total));
+            two_ix.push_back(b);
+            two_total += bw[b].G;
+        }
+    }
+    {
+        Bind bind(lead, s);
+        const size_t bytes = (2 * (size_t)kMaxBatch) * sizeof(WalkBox) +
+                             (size_t)kMaxBatch * sizeof(ForceBox) + 256;
+        hipError_t e = reserve(lead->bdesc, bytes);
+        if (e != hipSuccess) return hip_fail(lead, e, "batch descriptors");
+    }
+    const size_t at_two = 0, at_pool = (size_t)kMaxBatch * sizeof(WalkBox);
+    const size_t at_ctr = 2 * (size_t)kMaxBatch * sizeof(WalkBox) + (size_t)kMaxBatch * sizeof(ForceBox);
+    uint32_t *counters = reinterpret_cast<uint32_t *>(static_cast<char *>(lead->bdesc.p) + at_ctr);
+    WalkBox *dev = nullptr;
+    if (!two.empty()) {
+        for (const WalkBox &w : two) fill_u64(w.off, (size_t)w.n_groups + 1, 0ull, s);
+        if ((rc = upload(lead, s, two, at_two, &dev))) return rc;
+        launch_walk_count_multi(dev, (int)two.size(), two_total, s);
+        std::vector<uint64_t> total(two.size());
+        std::vector<unsigned> ov(two.size());
+        std::vector<uint32_t> seq(two.size());
+        for (size_t k = 0; k < two.size(); ++k) {
+            treepm_ctx *c = cs[two_ix[k]];
+            uint64_t *tot = c->scan64.as<uint64_t>();
+            scan_u64(two[k].off, (size_t)two[k].n_groups + 1, tot, tot + 1, s);
+            if ((rc = fetch_post(c, s, &seq[k], {&total[k], tot, sizeof total[k]},
+                                 {&ov[k], two[k].overflow, sizeof ov[k]})))
+                return rc;
+        }
+        for (size_t k = 0; k < two.size(); ++k) {
+            treepm_ctx *c = cs[two_ix[k]];
+            if ((rc = fetch_wait(c, s, seq[k], {&total[k], c->scan64.p, sizeof total[k]},
+                                 {&ov[k], two[k].overflow, sizeof ov[k]})))
+                return rc;
+            if (ov[k])
+                return fail(c, TREEPM_ERR_OVERFLOW, ov[k] & 2u ? "walk read a bad node index"
+                                                               : "walk stack overflow");
+            Bind bind(c, s);
+            hipError_t e = reserve(c->entries, std::max<size_t>(total[k], 1) * 4);
+            if (e != hipSuccess) return hip_fail(c, e, "interaction lists");
+            two[k].entries = c->entries.as<uint32_t>();
+        }
+        if ((rc = upload(lead, s, two, at_two, &dev))) return rc;
+        launch_walk_emit_multi(dev, (int)two.size(), two_total, s);
+    }
+    if (!pool.empty()) {
+        for (const WalkBox &w : pool) fill_u64(reinterpret_cast<uint64_t *>(w.pool_next), 1, 0ull, s);
+        if ((rc = upload(lead, s, pool, at_pool, &dev))) return rc;
+        launch_walk_pool_multi(dev, (int)pool.size(), pool_total,
+                               std::max(1u, std::min(8192u, pool_waves_sum)), counters, s);
+    }
+    std::vector<WalkResults> wr(nb);
+    for (int b = 0; b < nb; ++b)
+        if ((rc = post_walk_results(cs[b], s, wr[b]))) return rc;
+    for (int b = 0; b < nb; ++b)
+        if ((rc = wait_walk_results(cs[b], s, wr[b]))) return rc;
+    for (int b = 0; b < nb; ++b) {
+        Bind bind(cs[b], s);
+        if ((rc = settle_walk(cs[b], s, bw[b], wr[b]))) return rc;
+    }
+    return TREEPM_OK;
+}
+
+// The FP32 short-range force of walked boxes with one persistent launch per size class over
+// all of them (forked over the leader's sub-streams), then per box the quadrupole terms, the
+// float outputs and the statistics; host outputs are copied back and waited for.
+int batch_force(treepm_ctx *const *cs, int nb, float *const *ax, float *const *ay,
+                float *const *az, int mem_kind, hipStream_t s)
+{
+    treepm_ctx *lead = cs[0];
+    int rc;
+    std::vector<ForceBox> fb(nb);
+    uint32_t totals[kForceClasses] = {};
+    uint32_t max_entries = 0;
+    std::vector<std::array<float *, 3>> dst(nb);
+    for (int b = 0; b < nb; ++b) {
+        treepm_ctx *c = cs[b];
+        Bind bind(c, s);
+        const treepm_params &P = c->prm;
+        if ((rc = ensure_table(c, s))) return rc;
+        hipError_t e = reserve(c->kept, ((size_t)c->n_groups + 1) * 4);
+        if (e == hipSuccess) e = reserve(c->kept_sum, 64);
+        if (e != hipSuccess) return hip_fail(c, e, "force statistics");
+        dst[b] = {ax[b], ay[b], az[b]};
+        if (mem_kind == TREEPM_HOST)
+            for (int a = 0; a < 3; ++a) {
+                e = reserve(c->out[a], (size_t)c->n * 4);
+                if (e != hipSuccess) return hip_fail(c, e, "output staging");
+                dst[b][a] = c->out[a].as<float>();
+            }
+        const double eta = 0.5 * P.r_cut;
+        ForceBox &F = fb[b];
+        F.nd = nodes_view(c);
+        F.gr = groups_view(c);
+        F.cls = c->cls.as<uint32_t>();
+        F.off = c->off.as<uint64_t>();
+        F.len = c->glen.as<uint32_t>();
+        F.entries = c->entries.as<uint32_t>();
+        F.ps = c->psrc.as<double4>();
+        F.pidx = c->idx.as<uint32_t>();
+        F.fp = ForceParams{P.L, P.eps * P.eps, 1.0 / eta, eta, P.r_cut * P.r_cut, P.r_cut,
+                           c->kept.as<uint32_t>()};
+        F.ft = c->ftab;
+        F.rec = c->rec.p;
+        uint64_t id;
+        std::memcpy(&id, &c->tab_key, sizeof id);
+        F.tab_id = id;
+        max_entries = std::max(max_entries, c->ftab.entries);
+        for (int k = 0; k < kForceClasses; ++k) totals[k] += c->class_counts[k];
+        launch_force_f32_prep(F.cls, s);
+    }
+    ForceBox *dev = nullptr;
+    const size_t at_force = 2 * (size_t)kMaxBatch * sizeof(WalkBox);
+    if ((rc = upload(lead, s, fb, at_force, &dev))) return rc;
+    hipStream_t streams[1 + treepm_ctx::kSubStreams] = {s};
+    int ns = 1;
+    if (lead->fork) {
+        HIPCHK(lead, hipEventRecord(lead->fork, s));
+        for (int i = 0; i < treepm_ctx::kSubStreams; ++i) {
+            HIPCHK(lead, hipStreamWaitEvent(lead->sub[i], lead->fork, 0));
+            streams[ns++] = lead->sub[i];
+        }
+    }
+    launch_force_f32_multi(dev, nb, totals, max_entries, lead->n_cu, streams, ns);
+    if (lead->fork)
+        for (int i = 0; i < treepm_ctx::kSubStreams; ++i) {
+            HIPCHK(lead, hipEventRecord(lead->join[i], lead->sub[i]));
+            HIPCHK(lead, hipStreamWaitEvent(s, lead->join[i], 0));
+        }
+    for (int b = 0; b < nb; ++b) {
+        treepm_ctx *c = cs[b];
+        const ForceBox &F = fb[b];
+        if (c->prm.quadrupole)
+            launch_quad(F.nd, F.gr, c->n_groups, F.off, F.len, F.entries, F.ps, F.pidx,
+                        c->n_q.as<double>(), F.fp, F.rec, 0, 0, s);
+        launch_force_out(F.rec, TREEPM_FP32, (int64_t)c->n, dst[b][0], dst[b][1], dst[b][2],
+                         0.0, s);
+        launch_kept_stats(F.gr, c->n_groups, c->kept.as<uint32_t>(),
+                          c->kept_sum.as<unsigned long long>(), s);
+        c->last_force_prec = TREEPM_FP32;
+        c->ev_valid[1] = c->ev_valid[2] = false;
+    }
+    HIPCHK(lead, hipGetLastError());
+    if (mem_kind == TREEPM_HOST)
+        for (int b = 0; b < nb; ++b) {
+            float *hdst[3] = {ax[b], ay[b], az[b]};
+            for (int a = 0; a < 3; ++a)
+                HIPCHK(cs[b], hipMemcpyAsync(hdst[a], dst[b][a], (size_t)cs[b]->n * 4,
+                                             hipMemcpyDeviceToHost, s));
+        }
+    HIPCHK(lead, hipStreamSynchronize(s)); // the descriptors' host copies may go now
+    return TREEPM_OK;
+}
+
+} // namespace
+
+TREEPM_API int treepm_force_short_batch(treepm_ctx *const *ctxs, int n_boxes, float *const *ax,
+                                        float *const *ay, float *const *az, int mem_kind,
+                                        void *hip_stream)
+{
+    if (!ctxs || n_boxes < 1 || n_boxes > kMaxBatch || !ax || !ay || !az)
+        return TREEPM_ERR_ARG;
+    for (int b = 0; b < n_boxes; ++b)
+        if (!ctxs[b]) return TREEPM_ERR_ARG;
+    treepm_ctx *lead = ctxs[0];
+    for (int b = 0; b < n_boxes; ++b) {
+        treepm_ctx *c = ctxs[b];
+        c->err.clear();
+        for (int q = 0; q < b; ++q)
+            if (ctxs[q] == c) return fail(c, TREEPM_ERR_ARG, "a box appears twice in the batch");
+        if (c->device != lead->device)
+            return fail(c, TREEPM_ERR_ARG, "the boxes of a batch share one device");
+        if (c->state < 1) return fail(c, TREEPM_ERR_STATE, "treepm_force_short_batch needs a build");
+        if (c->prm.precision != TREEPM_FP32)
+            return fail(c, TREEPM_ERR_ARG, "shared launches run the FP32 path only");
+        if (!ax[b] || !ay[b] || !az[b]) return fail(c, TREEPM_ERR_ARG, "NULL output buffer");
+        if (mem_kind != TREEPM_HOST && mem_kind != TREEPM_DEVICE)
+            return fail(c, TREEPM_ERR_ARG, "mem_kind must be TREEPM_HOST or TREEPM_DEVICE");
+        const double half_side = 0.5 * std::ldexp(c->prm.L, -(int)c->min_group_level);
+        if (half_side + c->prm.r_cut > 0.5 * c->prm.L)
+            return fail(c, TREEPM_ERR_ARG,
+                        "FP32 path needs group cube half-side + r_cut <= L/2 (a group at "
+                        "level %u is too large for r_cut); use TREEPM_FP64",
+                        c->min_group_level);
+    }
+    HIPCHK(lead, hipSetDevice(lead->device));
+    hipStream_t s = (hipStream_t)hip_stream;
+    BatchScope scope{ctxs, n_boxes, s};
+    int rc = batch_walk(ctxs, n_boxes, s);
+    if (!rc) {
+        for (int b = 0; b < n_boxes; ++b) ctxs[b]->state = 2;
+        rc = batch_force(ctxs, n_boxes, ax, ay, az, mem_kind, s);
+    }
+    if (rc) {
+        // the failing box named the error; the others are left built, to be walked again
+        for (int b = 0; b < n_boxes; ++b) {
+            ctxs[b]->state = std::min(ctxs[b]->state, 1);
+            if (ctxs[b]->err.empty()) ctxs[b]->err = "another box of the batch failed";
+        }
+        (void)hipStreamSynchronize(s);
+    }
+    return rc;
 }
 
 static bool device_array(const void *p, int device);
