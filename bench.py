@@ -79,6 +79,8 @@ def parse():
     ap.add_argument("--serving-boxes", type=int, default=64)
     ap.add_argument("--serving-requests-per-box", type=int, default=10)
     ap.add_argument("--serving-inflight", type=int, default=4)
+    ap.add_argument("--serving-batching", action="store_true",
+                    help="serve with shared walk and force launches across boxes")
     ap.add_argument("--serving-budget-frac", type=float, default=0.25)
     ap.add_argument("--serving-only", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -182,15 +184,17 @@ def cpu_baseline(spec, arrays, n_crit, stride_arg):
     }
 
 
-def serving_bench(tp, n_boxes, per_box, inflight, budget_frac=0.25):
+def serving_bench(tp, n_boxes, per_box, inflight, budget_frac=0.25, batching=False):
     """The ensemble serving workload: n_boxes independent clustered boxes with N log-uniform
     in [32^3, 256^3] (seed 999; box i uses seed 1000 + i and max(1, round(N/1e4)) halos),
     mesh = N^(1/3), r_cut = 3/mesh, eps = mesh/20, theta = 0.5, FP32.  First the closed-loop
-    capacity (2 * inflight requests kept outstanding, the first 4 * n_boxes requests); then
-    n_boxes * per_box requests in
+    capacity (2 * inflight requests kept outstanding, over the whole request sequence); then
+    the same n_boxes * per_box requests in
     seeded order arriving as a Poisson process at 0.8 x that capacity, then again at 0.5 x,
     with the HBM budget set to 25% of the ensemble's total resident footprint.  Reports p50/p99
-    latency (completion minus submission) and aggregate particles/s for both rates."""
+    latency (completion minus submission), its queued and service parts, the median service
+    stages, the mean number of boxes per shared launch and aggregate particles/s for both
+    rates."""
     import concurrent.futures as cf
     import threading
 
@@ -217,6 +221,7 @@ def serving_bench(tp, n_boxes, per_box, inflight, budget_frac=0.25):
     footprint = int(sum(int(n) * 320 + (64 << 20) for n in ns))
     budget = max(int(footprint * budget_frac), int(ns.max()) * 320 + (64 << 20))
     ens = tp.treepm_ens_create(0, budget, inflight)
+    tp.treepm_ens_set_batching(ens, batching)
     rng = boxgen.SplitMix64(998)
     order = np.argsort(rng.next_u64(n_boxes * per_box), kind="stable") % n_boxes
 
@@ -224,13 +229,14 @@ def serving_bench(tp, n_boxes, per_box, inflight, budget_frac=0.25):
         for t in list(pending):
             rc, st = tp.treepm_ensemble_poll(ens, t)
             if rc == tp.TREEPM_OK:
-                out_lat.append((st.latency_ms, st.queue_ms))
+                out_lat.append((st.latency_ms, st.queue_ms, st.stage_ms[0], st.stage_ms[1],
+                                st.stage_ms[2], st.batch_boxes))
                 done.append(pending.pop(t))
 
     try:
-        # closed loop: keep 2 * inflight requests outstanding, over 4 requests per box (the
-        # capacity of a short run depends on which box sizes it happens to draw)
-        n_closed = min(len(order), max(4 * inflight, 4 * n_boxes))
+        # closed loop: keep 2 * inflight requests outstanding, over the whole request sequence
+        # (a prefix can draw an easier mix of box sizes and evictions than the open loops get)
+        n_closed = len(order)
         pending, done, lat = {}, [], []
         t0 = time.perf_counter()
         k = 0
@@ -242,6 +248,7 @@ def serving_bench(tp, n_boxes, per_box, inflight, budget_frac=0.25):
             time.sleep(0.0005)
         t_closed = time.perf_counter() - t0
         cap = n_closed / t_closed
+        log(f"[serving] closed loop: {n_closed} requests in {t_closed:.1f} s ({cap:.1f} req/s)")
         def open_loop(frac):
             """Poisson arrivals at frac x capacity: (latencies, requests done, makespan)."""
             lam = frac * cap
@@ -268,13 +275,21 @@ def serving_bench(tp, n_boxes, per_box, inflight, budget_frac=0.25):
                     drain(pending, done, lat)
                 time.sleep(0.0005)
             th.join()
-            return lam, np.array(lat).reshape(-1, 2), done, time.perf_counter() - t_start
+            return lam, np.array(lat).reshape(-1, 6), done, time.perf_counter() - t_start
 
         lam, lat, done, makespan = open_loop(0.8)
+        log(f"[serving] open loop at 0.8 x capacity: {len(done)} requests in {makespan:.1f} s")
         info = tp.treepm_ens_info(ens)
         lam5, lat5, done5, makespan5 = open_loop(0.5)
+        log(f"[serving] open loop at 0.5 x capacity: {len(done5)} requests in {makespan5:.1f} s")
     finally:
         tp.treepm_ens_destroy(ens)
+    def stages(l):
+        # median of each part of the service time: context, input copy and build; wait for a
+        # batch; the batch's walk, force and result copy
+        return {k: float(np.percentile(l[:, 2 + j], 50))
+                for j, k in enumerate(("build", "wait_for_batch", "batch"))}
+
     parts = float(sum(int(ns[i]) for i in done))
     parts5 = float(sum(int(ns[i]) for i in done5))
     return {
@@ -285,6 +300,7 @@ def serving_bench(tp, n_boxes, per_box, inflight, budget_frac=0.25):
         "hbm_budget_gib": budget / 2 ** 30,
         "footprint_gib": footprint / 2 ** 30,
         "max_inflight": inflight,
+        "shared_launches": bool(batching),
         "closed_loop_requests_per_s": cap,
         "arrival_rate_per_s": lam,
         "latency_ms_p50": float(np.percentile(lat[:, 0], 50)),
@@ -295,6 +311,8 @@ def serving_bench(tp, n_boxes, per_box, inflight, budget_frac=0.25):
         "service_ms_p50": float(np.percentile(lat[:, 0] - lat[:, 1], 50)),
         "service_ms_p99": float(np.percentile(lat[:, 0] - lat[:, 1], 99)),
         "particles_per_s": parts / makespan,
+        "stage_ms_p50": stages(lat),
+        "batch_boxes_mean": float(lat[:, 5].mean()),
         "resident_boxes_at_end": info["resident_boxes"],
         "at_half_capacity": {
             "arrival_rate_per_s": lam5,
@@ -306,6 +324,8 @@ def serving_bench(tp, n_boxes, per_box, inflight, budget_frac=0.25):
             "service_ms_p50": float(np.percentile(lat5[:, 0] - lat5[:, 1], 50)),
             "service_ms_p99": float(np.percentile(lat5[:, 0] - lat5[:, 1], 99)),
             "particles_per_s": parts5 / makespan5,
+            "stage_ms_p50": stages(lat5),
+            "batch_boxes_mean": float(lat5[:, 5].mean()),
         },
     }
 
@@ -437,7 +457,8 @@ def main():
         return
     if args.serving_only:
         print(json.dumps(serving_bench(tp, args.serving_boxes, args.serving_requests_per_box,
-                                       args.serving_inflight, args.serving_budget_frac)),
+                                       args.serving_inflight, args.serving_budget_frac,
+                                       args.serving_batching)),
               flush=True)
         return
     spec = boxgen.CONFIGS[args.workload]
@@ -694,7 +715,8 @@ def main():
     if not args.no_serving:
         log("[bench] ensemble serving")
         result["ensemble"] = serving_bench(tp, args.serving_boxes, args.serving_requests_per_box,
-                                           args.serving_inflight, args.serving_budget_frac)
+                                           args.serving_inflight, args.serving_budget_frac,
+                                           args.serving_batching)
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline (bounded sample)")
         result["cpu_baseline"] = cpu_baseline(spec, arrays, n_crit, args.cpu_stride)

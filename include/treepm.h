@@ -122,8 +122,8 @@ typedef struct {
     double queue_ms;        /* ensemble results only: start of service minus submission,
                                the part of latency_ms spent queued (ms)                  */
     double stage_ms[3];     /* ensemble results only, the service time in three parts
-                               (ms): admission, input staging and build; walk and force;
-                               results copied back to the host                           */
+                               (ms): context, input copy and build; wait for a batch;
+                               the batch's walk, force and copy of the results to host  */
     int32_t batch_boxes;    /* ensemble results only: boxes whose walk and force shared
                                launches with this request's (1 when it ran alone)        */
     int32_t reserved_;
@@ -310,6 +310,15 @@ int treepm_pairwise_f32(const treepm_params *params, int device, int64_t n_i, co
  * thread and HIP stream.  A box (identified by the caller's box_id) keeps its device state
  * between requests until it is evicted, least recently used first, to admit another box. */
 int treepm_ens_create(int device, size_t hbm_budget, int max_inflight, treepm_ens **out);
+
+/* Shared launches in the server (enable = 1; 0, the default, switches them off).  When on, a
+ * worker that has built a box hands it to a ready list instead of walking it, and whenever no
+ * batch is running the next free worker takes every ready box (up to 16) and runs their walks
+ * and forces with treepm_force_short_batch (Section 2.2 steps 5 and 6 for all of them in one
+ * traversal launch and one force launch per size class) while the other workers build the
+ * next boxes.  Results are those of the boxes alone, bit for bit.  Takes effect for boxes
+ * built after the call.  ERR_ARG for a NULL server or another value of enable. */
+int treepm_ens_set_batching(treepm_ens *ens, int enable);
 
 /* Stop the server: queued requests are dropped, running ones finish, all device memory is
  * released.  NULL is accepted. */

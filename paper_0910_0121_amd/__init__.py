@@ -39,6 +39,7 @@ from ._native import (  # noqa: F401
     treepm_timestep_noalloc,
     treepm_force_short,
     treepm_force_short_batch,
+    treepm_ens_set_batching,
     treepm_get_stats,
     treepm_last_error,
     treepm_pairwise_f32,

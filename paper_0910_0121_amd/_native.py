@@ -84,6 +84,7 @@ _SIGS = {
     "treepm_autotune": (_i, [_p, _i64, _p, _p, _p, _p, _i, _p, _p, C.c_int32, _p, _p]),
     "treepm_ens_create": (_i, [_i, C.c_size_t, _i, C.POINTER(_p)]),
     "treepm_ens_destroy": (_i, [_p]),
+    "treepm_ens_set_batching": (_i, [_p, _i]),
     "treepm_ensemble_submit": (_i, [_p, C.c_uint64, C.POINTER(treepm_params), _i64, _p, _p, _p,
                                     _p, C.POINTER(C.c_uint64)]),
     "treepm_ensemble_poll": (_i, [_p, C.c_uint64, _p, _p, _p, C.POINTER(treepm_stats)]),
@@ -415,6 +416,10 @@ def treepm_ensemble_poll(ens, ticket: int, ax=None, ay=None, az=None):
         return rc, None
     _check(rc)
     return rc, st
+
+
+def treepm_ens_set_batching(ens, enable: bool) -> None:
+    _check(lib().treepm_ens_set_batching(ens, 1 if enable else 0))
 
 
 def treepm_ens_info(ens):

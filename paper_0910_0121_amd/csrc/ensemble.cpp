@@ -1,13 +1,17 @@
 // Ensemble server: force evaluations for many independent periodic boxes, admitted by an
-// HBM budget, run concurrently on one GPU.
+// HBM budget, run concurrently on one GPU with shared launches.
 //
 // submit() copies a request's inputs and queues it.  max_inflight worker threads each own a
-// HIP stream and pinned staging buffers; a worker takes the first queued request that can
-// run now -- its box is not busy with another request, and the box is already resident or
-// its estimated footprint fits in the budget after evicting idle boxes, least recently used
-// first -- and runs build, walk and FP32 force for it on its stream.  A box's context (its
-// device buffers: particles, tree, lists) stays resident between requests until evicted.
-// Requests from different workers overlap on the device.  poll() is non-blocking.
+// HIP stream.  A worker takes the first queued request that can run now -- its box is not
+// busy with another request, and the box is already resident or its estimated footprint
+// fits in the budget after evicting idle boxes, least recently used first -- and builds the
+// box's tree on its stream, then runs its walk and FP32 force there.  With shared launches
+// switched on (treepm_ens_set_batching) a built box instead waits in a ready list, and
+// whenever no batch is running the next free worker takes every ready box (up to kMaxBatch)
+// and runs their walks and forces together (treepm_force_short_batch: one traversal launch
+// and one launch per size class for all of them) while the other workers build the next
+// boxes.  A box's context (its device buffers: particles, tree, lists) stays resident between
+// requests until evicted.  poll() is non-blocking.
 #include <algorithm>
 #include <atomic>
 #include <chrono>
@@ -72,7 +76,10 @@ class PinnedPool {
             }
         }
         void *p = nullptr;
-        if (hipHostMalloc(&p, c) != hipSuccess) return nullptr;
+        if (hipHostMalloc(&p, c) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
         *cap = c;
         return p;
     }
@@ -88,18 +95,37 @@ class PinnedPool {
     std::multimap<size_t, void *> free_;
 };
 
+// A pinned host block from the pool (p is null if pinning failed).
+struct HostBlock {
+    void *p = nullptr;
+    size_t cap = 0;
+};
+
+HostBlock take_block(PinnedPool &pool, size_t bytes)
+{
+    HostBlock b;
+    b.p = pool.get(bytes, &b.cap);
+    return b;
+}
+
+void give_block(PinnedPool &pool, HostBlock &b)
+{
+    if (b.p) pool.put(b.p, b.cap);
+    b = HostBlock{};
+}
+
 struct Request {
     uint64_t ticket = 0, box_id = 0;
     treepm_params prm{};
     int64_t n = 0;
-    double *in = nullptr; // pinned: x, y, z, m blocks
-    size_t in_cap = 0;
-    float *out = nullptr; // pinned: ax, ay, az blocks
-    size_t out_cap = 0;
+    HostBlock in;  // x, y, z, m blocks of n doubles
+    HostBlock out; // ax, ay, az blocks of n floats
     int state = 0; // 0 queued, 1 running, 2 done
     int rc = 0;
+    int batch = 1; // boxes that shared the walk and force launches
+    treepm_ctx *ctx = nullptr; // the box's context while the request runs
     treepm_stats stats{};
-    double t_submit = 0, t_start = 0, t_done = 0;
+    double t_submit = 0, t_start = 0, t_built = 0, t_batch = 0, t_done = 0;
 };
 
 // Copy k arrays of n doubles/floats.  Large requests are cut into pieces of at least 4 MiB
@@ -158,6 +184,10 @@ struct treepm_ens {
     std::deque<std::shared_ptr<Request>> queue;
     std::unordered_map<uint64_t, std::shared_ptr<Request>> tickets;
     std::unordered_map<uint64_t, Box> boxes;
+    // built boxes waiting for their walk and force, and whether a batch is running
+    std::vector<std::shared_ptr<Request>> ready;
+    bool leading = false;
+    bool batching = false; // shared launches (treepm_ens_set_batching)
     size_t resident = 0;
     uint64_t clock = 0, next_ticket = 1;
     int inflight = 0;
@@ -223,7 +253,9 @@ std::shared_ptr<Request> pick(treepm_ens *e, std::vector<treepm_ctx *> &gone)
     return nullptr;
 }
 
-int run_request(treepm_ens *e, Worker &w, Request &r, Box &b)
+// The box's context (created, or given the request's parameters) and its tree, built from
+// the request's inputs on the worker's stream.
+int build_request(treepm_ens *e, Worker &w, Request &r, Box &b)
 {
     int rc;
     if (!b.ctx) {
@@ -235,24 +267,99 @@ int run_request(treepm_ens *e, Worker &w, Request &r, Box &b)
         if (rc) return rc;
         b.prm = r.prm;
     }
-    const double *x = r.in, *y = x + r.n, *z = y + r.n, *m = z + r.n;
+    const double *x = static_cast<const double *>(r.in.p), *y = x + r.n, *z = y + r.n,
+                 *m = z + r.n;
+    // returns once the inputs have been copied and the tree is built
     rc = treepm_build(b.ctx, r.n, x, y, z, m, TREEPM_HOST, w.stream);
-    // no copy from the pinned inputs may still be in flight when the block is reused
-    hipError_t se = hipStreamSynchronize(w.stream);
-    if (!rc && se != hipSuccess) rc = TREEPM_ERR_DEVICE;
-    e->pool.put(r.in, r.in_cap);
-    r.in = nullptr;
-    if (rc) return rc;
-    rc = treepm_walk(b.ctx, w.stream, nullptr);
-    if (rc) return rc;
-    r.out = (float *)e->pool.get((size_t)r.n * 3 * sizeof(float), &r.out_cap);
-    if (!r.out) return TREEPM_ERR_OOM;
-    float *ax = r.out, *ay = ax + r.n, *az = ay + r.n;
-    rc = treepm_force_short(b.ctx, ax, ay, az, TREEPM_FP32, TREEPM_HOST, w.stream);
-    if (rc) return rc;
-    rc = treepm_get_stats(b.ctx, &r.stats);
-    if (rc) return rc;
-    return TREEPM_OK;
+    give_block(e->pool, r.in);
+    return rc;
+}
+
+// Walk and force of the ready boxes `batch` with shared launches; if the batch call fails,
+// each box runs alone so that the failure stays with the box that caused it.
+void run_batch(treepm_ens *e, Worker &w, std::vector<std::shared_ptr<Request>> &batch)
+{
+    const int nb = (int)batch.size();
+    std::vector<treepm_ctx *> ctxs;
+    std::vector<float *> ax, ay, az;
+    std::vector<std::shared_ptr<Request>> run;
+    for (auto &r : batch) {
+        r->t_batch = now_s();
+        r->out = take_block(e->pool, (size_t)r->n * 3 * sizeof(float));
+        if (!r->out.p) {
+            r->rc = TREEPM_ERR_OOM;
+            continue;
+        }
+        float *o = static_cast<float *>(r->out.p);
+        ctxs.push_back(r->ctx);
+        ax.push_back(o);
+        ay.push_back(o + r->n);
+        az.push_back(o + 2 * r->n);
+        run.push_back(r);
+    }
+    if (run.empty()) return;
+    int rc = treepm_force_short_batch(ctxs.data(), (int)run.size(), ax.data(), ay.data(),
+                                      az.data(), TREEPM_HOST, w.stream);
+    for (size_t k = 0; k < run.size(); ++k) {
+        Request &r = *run[k];
+        int rk = rc;
+        r.batch = rc ? 1 : (int)run.size();
+        if (rc) {
+            rk = treepm_walk(r.ctx, w.stream, nullptr);
+            if (!rk)
+                rk = treepm_force_short(r.ctx, ax[k], ay[k], az[k], TREEPM_FP32, TREEPM_HOST,
+                                        w.stream);
+        }
+        if (!rk) rk = treepm_get_stats(r.ctx, &r.stats);
+        r.rc = rk;
+    }
+    (void)nb;
+}
+
+// Walk and force of one built box alone, on the worker's stream.
+void run_alone(treepm_ens *e, Worker &w, Request &r)
+{
+    r.t_batch = now_s();
+    r.batch = 1;
+    r.out = take_block(e->pool, (size_t)r.n * 3 * sizeof(float));
+    if (!r.out.p) {
+        r.rc = TREEPM_ERR_OOM;
+        return;
+    }
+    float *o = static_cast<float *>(r.out.p);
+    int rc = treepm_walk(r.ctx, w.stream, nullptr);
+    if (!rc) rc = treepm_force_short(r.ctx, o, o + r.n, o + 2 * r.n, TREEPM_FP32, TREEPM_HOST,
+                                     w.stream);
+    if (!rc) rc = treepm_get_stats(r.ctx, &r.stats);
+    r.rc = rc;
+}
+
+// With e->mu held: request r is over (rc set); its box becomes idle, or is dropped (its
+// context to `gone`) if the request failed, so that it cannot poison later requests.
+void finish(treepm_ens *e, Request &r, std::vector<treepm_ctx *> &gone)
+{
+    Box &b = e->boxes[r.box_id];
+    if (b.ctx) {
+        size_t actual = treepm_internal_ctx_bytes(b.ctx);
+        if (actual > b.bytes) {
+            e->resident += actual - b.bytes;
+            b.bytes = actual;
+        }
+    }
+    if (r.rc) {
+        if (b.ctx) gone.push_back(b.ctx);
+        e->resident -= std::min(e->resident, b.bytes);
+        e->boxes.erase(r.box_id);
+        give_block(e->pool, r.out);
+    } else {
+        b.busy = false;
+        b.last_use = ++e->clock;
+    }
+    give_block(e->pool, r.in);
+    r.ctx = nullptr;
+    r.t_done = now_s();
+    r.state = 2;
+    --e->inflight;
 }
 
 void worker_main(treepm_ens *e, int wi)
@@ -262,13 +369,22 @@ void worker_main(treepm_ens *e, int wi)
     hipStreamCreateWithFlags(&w.stream, hipStreamNonBlocking);
     for (;;) {
         std::shared_ptr<Request> r;
+        std::vector<std::shared_ptr<Request>> batch;
         std::vector<treepm_ctx *> gone;
         bool quit = false;
         {
             std::unique_lock<std::mutex> lk(e->mu);
+            // lead a batch when built boxes wait and none runs; else build the next request;
             // also wake for contexts evicted on the way, to destroy them promptly
             e->cv.wait(lk, [&] {
                 if (e->stop) return true;
+                if (!e->leading && !e->ready.empty()) {
+                    const size_t k = std::min<size_t>(e->ready.size(), tpm::kMaxBatch);
+                    batch.assign(e->ready.begin(), e->ready.begin() + k);
+                    e->ready.erase(e->ready.begin(), e->ready.begin() + k);
+                    e->leading = true;
+                    return true;
+                }
                 r = pick(e, gone);
                 return r != nullptr || !gone.empty();
             });
@@ -276,11 +392,23 @@ void worker_main(treepm_ens *e, int wi)
                 r->state = 1;
                 r->t_start = now_s();
                 ++e->inflight;
-            } else {
+            } else if (batch.empty()) {
                 quit = e->stop;
             }
         }
         for (treepm_ctx *g : gone) treepm_destroy(g); // evicted: outside the lock
+        gone.clear();
+        if (!batch.empty()) {
+            run_batch(e, w, batch);
+            {
+                std::lock_guard<std::mutex> lk(e->mu);
+                for (auto &q : batch) finish(e, *q, gone);
+                e->leading = false;
+            }
+            for (treepm_ctx *g : gone) treepm_destroy(g);
+            e->cv.notify_all();
+            continue;
+        }
         if (!r) {
             if (quit) break;
             continue;
@@ -291,38 +419,31 @@ void worker_main(treepm_ens *e, int wi)
             std::lock_guard<std::mutex> lk(e->mu);
             local = e->boxes[r->box_id];
         }
-        int rc = run_request(e, w, *r, local);
+        int rc = build_request(e, w, *r, local);
+        bool alone = false;
         {
             std::lock_guard<std::mutex> lk(e->mu);
             Box &b = e->boxes[r->box_id];
             b.ctx = local.ctx;
             b.prm = local.prm;
-            if (b.ctx) {
-                size_t actual = treepm_internal_ctx_bytes(b.ctx);
-                if (actual > b.bytes) {
-                    e->resident += actual - b.bytes;
-                    b.bytes = actual;
-                }
-            }
-            if (rc) { // a failed box is dropped so it cannot poison later requests
-                if (b.ctx) treepm_destroy(b.ctx);
-                e->resident -= std::min(e->resident, b.bytes);
-                e->boxes.erase(r->box_id);
-            } else {
-                b.busy = false;
-                b.last_use = ++e->clock;
-            }
+            r->t_built = now_s();
             r->rc = rc;
-            r->t_done = now_s();
-            r->state = 2;
-            if (r->in) e->pool.put(r->in, r->in_cap);
-            r->in = nullptr;
-            if (rc && r->out) {
-                e->pool.put(r->out, r->out_cap);
-                r->out = nullptr;
+            r->ctx = b.ctx;
+            if (rc) {
+                r->t_batch = r->t_built;
+                finish(e, *r, gone);
+            } else if (e->batching) {
+                e->ready.push_back(r);
+            } else {
+                alone = true;
             }
-            --e->inflight;
         }
+        if (alone) {
+            run_alone(e, w, *r);
+            std::lock_guard<std::mutex> lk(e->mu);
+            finish(e, *r, gone);
+        }
+        for (treepm_ctx *g : gone) treepm_destroy(g);
         e->cv.notify_all();
     }
     // the stream outlives the thread: resident boxes still name it as their last stream
@@ -350,6 +471,17 @@ TREEPM_API int treepm_ens_create(int device, size_t hbm_budget, int max_inflight
     return TREEPM_OK;
 }
 
+TREEPM_API int treepm_ens_set_batching(treepm_ens *e, int enable)
+{
+    if (!e || (enable != 0 && enable != 1)) return TREEPM_ERR_ARG;
+    {
+        std::lock_guard<std::mutex> lk(e->mu);
+        e->batching = enable != 0;
+    }
+    e->cv.notify_all();
+    return TREEPM_OK;
+}
+
 TREEPM_API int treepm_ens_destroy(treepm_ens *e)
 {
     if (!e) return TREEPM_OK;
@@ -365,8 +497,8 @@ TREEPM_API int treepm_ens_destroy(treepm_ens *e)
     for (auto &w : e->workers)
         if (w.stream) (void)hipStreamDestroy(w.stream);
     for (auto &kv : e->tickets) {
-        if (kv.second->in) e->pool.put(kv.second->in, kv.second->in_cap);
-        if (kv.second->out) e->pool.put(kv.second->out, kv.second->out_cap);
+        give_block(e->pool, kv.second->in);
+        give_block(e->pool, kv.second->out);
     }
     e->tickets.clear();
     delete e;
@@ -391,9 +523,10 @@ TREEPM_API int treepm_ensemble_submit(treepm_ens *e, uint64_t box_id, const tree
     r->box_id = box_id;
     r->prm = *p;
     r->n = n;
-    r->in = (double *)e->pool.get((size_t)n * 4 * sizeof(double), &r->in_cap);
-    if (!r->in) return TREEPM_ERR_OOM;
-    double *dst[4] = {r->in, r->in + n, r->in + 2 * n, r->in + 3 * n};
+    r->in = take_block(e->pool, (size_t)n * 4 * sizeof(double));
+    if (!r->in.p) return TREEPM_ERR_OOM;
+    double *in = static_cast<double *>(r->in.p);
+    double *dst[4] = {in, in + n, in + 2 * n, in + 3 * n};
     const double *src[4] = {x, y, z, m};
     copy_parallel(dst, src, 4, n);
     {
@@ -403,9 +536,8 @@ TREEPM_API int treepm_ensemble_submit(treepm_ens *e, uint64_t box_id, const tree
             rc = TREEPM_ERR_STATE;
         else if (e->queue.size() >= e->queue_cap)
             rc = TREEPM_ERR_QUEUE_FULL;
-        if (rc) { // the pinned block goes back to the pool
-            e->pool.put(r->in, r->in_cap);
-            r->in = nullptr;
+        if (rc) {
+            give_block(e->pool, r->in);
             return rc;
         }
         r->ticket = e->next_ticket++;
@@ -433,7 +565,8 @@ TREEPM_API int treepm_ensemble_poll(treepm_ens *e, uint64_t ticket, float *ax, f
     if (r->rc) return r->rc;
     {
         float *dst[3] = {ax, ay, az};
-        const float *src[3] = {r->out, r->out + r->n, r->out + 2 * r->n};
+        const float *o = static_cast<const float *>(r->out.p);
+        const float *src[3] = {o, o + r->n, o + 2 * r->n};
         int k = 0;
         float *d2[3];
         const float *s2[3];
@@ -445,12 +578,15 @@ TREEPM_API int treepm_ensemble_poll(treepm_ens *e, uint64_t ticket, float *ax, f
             }
         if (k) copy_parallel(d2, s2, k, r->n);
     }
-    e->pool.put(r->out, r->out_cap);
-    r->out = nullptr;
+    give_block(e->pool, r->out);
     if (stats) {
         *stats = r->stats;
         stats->latency_ms = (r->t_done - r->t_submit) * 1e3;
         stats->queue_ms = (r->t_start - r->t_submit) * 1e3;
+        stats->stage_ms[0] = (r->t_built - r->t_start) * 1e3;
+        stats->stage_ms[1] = (r->t_batch - r->t_built) * 1e3;
+        stats->stage_ms[2] = (r->t_done - r->t_batch) * 1e3;
+        stats->batch_boxes = r->batch;
     }
     return TREEPM_OK;
 }

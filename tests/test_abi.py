@@ -102,6 +102,7 @@ def test_ensemble_argument_checks_without_gpu(native):
     assert lib.treepm_ens_create(0, 1 << 30, 0, C.byref(h)) == -1      # max_inflight 0
     assert lib.treepm_ens_create(0, 0, 2, C.byref(h)) == -1            # no budget
     assert lib.treepm_ens_destroy(None) == 0
+    assert lib.treepm_ens_set_batching(None, 1) == -1
     assert lib.treepm_ensemble_poll(None, 1, None, None, None, None) == -1
     t = C.c_uint64()
     assert lib.treepm_ensemble_submit(None, 0, None, 1, None, None, None, None, C.byref(t)) == -1

@@ -1,7 +1,8 @@
 """Ensemble serving on the GPU: several boxes submitted together give, for every request,
 exactly the accelerations the same box gives alone through the single-box calls (same
-kernels, same inputs, per-box state); a tight HBM budget forces queueing and eviction
-without changing results; errors are reported per request."""
+kernels, same inputs, per-box state), each request run alone or with shared launches; a
+tight HBM budget forces queueing and eviction without changing results; errors are reported
+per request."""
 import time
 
 import numpy as np
@@ -66,14 +67,18 @@ def _drain(tp, ens, tickets, sizes, timeout=120.0):
     return res
 
 
-@pytest.mark.parametrize("budget_boxes,inflight", [(100, 4), (1.2, 2)])
-def test_mix_equals_alone(tp, budget_boxes, inflight):
-    print(f"[gpu-case] ensemble budget={budget_boxes} boxes inflight={inflight}", flush=True)
+@pytest.mark.parametrize("budget_boxes,inflight,batching",
+                         [(100, 4, False), (1.2, 2, False), (100, 4, True), (1.2, 2, True)])
+def test_mix_equals_alone(tp, budget_boxes, inflight, batching):
+    print(f"[gpu-case] ensemble budget={budget_boxes} boxes inflight={inflight} "
+          f"batching={batching}", flush=True)
     boxes = _boxes()
     ref = {i: _alone(tp, arr, mesh) for i, arr, mesh in boxes}
     biggest = max(len(arr[0]) for _, arr, _ in boxes)
     budget = int(budget_boxes * (biggest * 320 + (64 << 20)))
     ens = tp.treepm_ens_create(0, budget, inflight)
+    if batching:
+        tp.treepm_ens_set_batching(ens, True)
     try:
         tickets, sizes, which = [], {}, {}
         for rep in range(3):
@@ -88,6 +93,8 @@ def test_mix_equals_alone(tp, budget_boxes, inflight):
             np.testing.assert_array_equal(a, ref[which[t]][0])
             assert st.interactions == ref[which[t]][1]
             assert st.latency_ms > 0
+            assert 1 <= st.batch_boxes <= (16 if batching else 1)
+            assert min(st.stage_ms) >= 0 and sum(st.stage_ms) <= st.latency_ms - st.queue_ms + 1e-6
         info = tp.treepm_ens_info(ens)
         assert info["queued"] == 0 and info["inflight"] == 0
         if budget_boxes < 2:
@@ -96,10 +103,12 @@ def test_mix_equals_alone(tp, budget_boxes, inflight):
         tp.treepm_ens_destroy(ens)
 
 
-def test_modes_mix_equals_alone(tp):
+@pytest.mark.parametrize("batching", [False, True])
+def test_modes_mix_equals_alone(tp, batching):
     """Boxes with the distance-dependent opening angle and with quadrupole cells, served in one
     mix, give exactly what each gives alone with the same parameters."""
-    print("[gpu-case] ensemble with opening and quadrupole modes", flush=True)
+    print(f"[gpu-case] ensemble with opening and quadrupole modes, batching={batching}",
+          flush=True)
     boxes = _boxes()
 
     def params(i, mesh):
@@ -121,6 +130,7 @@ def test_modes_mix_equals_alone(tp):
             tp.treepm_destroy(ctx)
     biggest = max(len(arr[0]) for _, arr, _ in boxes)
     ens = tp.treepm_ens_create(0, int(100 * (biggest * 320 + (64 << 20))), 4)
+    tp.treepm_ens_set_batching(ens, batching)
     try:
         tickets, sizes, which = [], {}, {}
         for rep in range(2):
