@@ -317,9 +317,11 @@ void launch_pm_potential(const unsigned long long *mass, const unsigned long lon
 // Mesh force (N^3 float4: Fx, Fy, Fz, 0) from phi.
 void launch_pm_force(const float *phi, int N, double L, float4 *f, hipStream_t s);
 // Interpolated force of key-ordered particle k (ps[k]) into stage[idx[k]] = (ax, ay, az, 0),
-// i.e. in the caller's order (idx is the sort permutation).
+// i.e. in the caller's order (idx is the sort permutation).  cell_start and item_start as
+// launch_pm_assign left them for the same particles.
 void launch_pm_interp(const double4 *ps, int64_t n, int N, double L, const float4 *f,
-                      const uint32_t *idx, float4 *stage, hipStream_t s);
+                      const uint32_t *idx, float4 *stage, const uint32_t *cell_start,
+                      const uint32_t *item_start, hipStream_t s);
 // ax[o] = stage[o].x etc. (float or double; accumulate adds).
 void launch_pm_split(const float4 *stage, int64_t n, void *ax, void *ay, void *az,
                      int out_fp64, int accumulate, hipStream_t s);

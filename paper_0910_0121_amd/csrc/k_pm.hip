@@ -138,6 +138,21 @@ __global__ __launch_bounds__(256) void k_pm_cell_items(const uint32_t *__restric
     items[m] = (c + kCellChunk - 1) / kCellChunk;
 }
 
+// The cell whose chunks include chunk `item`: the last m with item_start[m] <= item.
+__device__ __forceinline__ uint32_t item_cell(const uint32_t *__restrict__ item_start,
+                                              uint32_t ncells, uint32_t item)
+{
+    uint32_t lo = 0, hi = ncells;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (item_start[mid] <= item)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
 // One workgroup per chunk (grid: an upper bound on the chunks; the rest leave).
 __global__ __launch_bounds__(kAssignThreads) void k_pm_assign(
     const double4 *__restrict__ ps, int64_t n, int N, double inv_h,
@@ -148,16 +163,7 @@ __global__ __launch_bounds__(kAssignThreads) void k_pm_assign(
     __shared__ unsigned long long box[kBoxWords];
     const uint32_t item = blockIdx.x;
     if (item >= item_start[ncells]) return; // the same for the whole workgroup
-    // the cell whose chunks include this one: the last m with item_start[m] <= item
-    uint32_t lo = 0, hi = ncells;
-    while (hi - lo > 1) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (item_start[mid] <= item)
-            lo = mid;
-        else
-            hi = mid;
-    }
-    const uint32_t m = lo;
+    const uint32_t m = item_cell(item_start, ncells, item);
     const uint32_t first = cell_start[m] + (item - item_start[m]) * (uint32_t)kCellChunk;
     const uint32_t end = min(cell_start[m + 1], first + (uint32_t)kCellChunk);
     const int ox = 8 * (int)compact3_10(m >> 2) - 1, oy = 8 * (int)compact3_10(m >> 1) - 1,
@@ -223,8 +229,9 @@ __global__ __launch_bounds__(kCellPts * kCellPts * kCellPts) void k_pm_gather(
 {
     __shared__ uint32_t rng[27][2];
     const int ncell = N / kCellPts, cm = ncell - 1;
-    const int cx = (int)blockIdx.x / (ncell * ncell), cy = ((int)blockIdx.x / ncell) % ncell,
-              cz = (int)blockIdx.x % ncell;
+    // each XCD takes a contiguous slab of cells, whose neighbours' slots its L2 then shares
+    const int cell = (int)xcd_block(blockIdx.x, gridDim.x);
+    const int cx = cell / (ncell * ncell), cy = (cell / ncell) % ncell, cz = cell % ncell;
     const int t = threadIdx.x;
     if (t < 27) {
         const int dx = t / 9 - 1, dy = (t / 3) % 3 - 1, dz = t % 3 - 1;
@@ -527,42 +534,58 @@ __global__ __launch_bounds__(256) void k_pm_fd(const float *__restrict__ phi, in
         0.0f);
 }
 
-// TSC interpolation of the mesh force to each particle, taken in key order, written to
-// stage[idx[i]] = (ax, ay, az, 0), i.e. already in the caller's order.  Neighbouring threads
-// hold neighbouring particles, so the 27-point gathers mostly hit the same cache lines; each
-// thread writes one whole 16-byte record (k_pm_split then writes the three arrays
-// contiguously).
-__global__ __launch_bounds__(256) void k_pm_interp(const double4 *__restrict__ ps, int64_t n,
-                                                   int N, double inv_h,
-                                                   const float4 *__restrict__ f,
-                                                   const uint32_t *__restrict__ idx,
-                                                   float4 *__restrict__ stage)
+// TSC interpolation of the mesh force to each particle, written to stage[idx[i]] =
+// (ax, ay, az, 0), i.e. already in the caller's order (k_pm_split then writes the three arrays
+// contiguously).  One workgroup per chunk of a cell's particles (the chunks of the
+// assignment): the kBox^3 force words around the cell, [8c - 1, 8c + 9] per axis, are read
+// into LDS once, and each particle's 27 words come from there.  The weights and the order of
+// the sums are those of a plain per-particle gather.
+__global__ __launch_bounds__(kAssignThreads) void k_pm_interp(
+    const double4 *__restrict__ ps, int N, double inv_h, const float4 *__restrict__ f,
+    const uint32_t *__restrict__ idx, float4 *__restrict__ stage,
+    const uint32_t *__restrict__ cell_start, const uint32_t *__restrict__ item_start,
+    uint32_t ncells)
 {
-    const int64_t i = xcd_block(blockIdx.x, gridDim.x) * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const double4 p = ps[i];
-    double wx[3], wy[3], wz[3];
-    const int ix = tsc(p.x, inv_h, wx), iy = tsc(p.y, inv_h, wy), iz = tsc(p.z, inv_h, wz);
+    __shared__ float4 box[kBoxWords];
+    // each XCD takes a contiguous run of chunks (cells in Morton order): the chunks of one
+    // cell and its neighbours then read their boxes through one L2
+    const uint32_t item = xcd_block(blockIdx.x, gridDim.x);
+    if (item >= item_start[ncells]) return; // the same for the whole workgroup
+    const uint32_t m = item_cell(item_start, ncells, item);
+    const uint32_t first = cell_start[m] + (item - item_start[m]) * (uint32_t)kCellChunk;
+    const uint32_t end = min(cell_start[m + 1], first + (uint32_t)kCellChunk);
+    const int ox = 8 * (int)compact3_10(m >> 2) - 1, oy = 8 * (int)compact3_10(m >> 1) - 1,
+              oz = 8 * (int)compact3_10(m) - 1;
     const int mask = N - 1;
-    float sx = 0.0f, sy = 0.0f, sz = 0.0f;
+    for (int t = threadIdx.x; t < kBoxWords; t += kAssignThreads) {
+        const int bx = t / (kBox * kBox), by = (t / kBox) % kBox, bz = t % kBox;
+        box[t] = f[((size_t)((ox + bx) & mask) * N + ((oy + by) & mask)) * N + ((oz + bz) & mask)];
+    }
+    __syncthreads();
+    for (uint32_t i = first + threadIdx.x; i < end; i += kAssignThreads) {
+        const double4 p = ps[i];
+        double wx[3], wy[3], wz[3];
+        const int ix = tsc(p.x, inv_h, wx), iy = tsc(p.y, inv_h, wy), iz = tsc(p.z, inv_h, wz);
+        const int bx = ix - 1 - ox, by = iy - 1 - oy, bz = iz - 1 - oz; // in [0, 8]
+        float sx = 0.0f, sy = 0.0f, sz = 0.0f;
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        const size_t xa = (size_t)((ix - 1 + a) & mask) * N;
+        for (int a = 0; a < 3; ++a) {
 #pragma unroll
-        for (int b = 0; b < 3; ++b) {
-            const size_t yb = (xa + ((iy - 1 + b) & mask)) * N;
-            const double wab = wx[a] * wy[b];
+            for (int b = 0; b < 3; ++b) {
+                const float4 *row = box + ((bx + a) * kBox + (by + b)) * kBox + bz;
+                const double wab = wx[a] * wy[b];
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                const float w = (float)(wab * wz[c]);
-                const float4 v = f[yb + ((iz - 1 + c) & mask)];
-                sx += w * v.x;
-                sy += w * v.y;
-                sz += w * v.z;
+                for (int c = 0; c < 3; ++c) {
+                    const float w = (float)(wab * wz[c]);
+                    const float4 v = row[c];
+                    sx += w * v.x;
+                    sy += w * v.y;
+                    sz += w * v.z;
+                }
             }
         }
+        stage[idx[i]] = make_float4(sx, sy, sz, 0.0f);
     }
-    stage[idx[i]] = make_float4(sx, sy, sz, 0.0f);
 }
 
 // The caller's order o: ax[o], ay[o], az[o] = stage[o] (written, or added to with ACC).
@@ -646,10 +669,13 @@ void launch_pm_force(const float *phi, int N, double L, float4 *f, hipStream_t s
 }
 
 void launch_pm_interp(const double4 *ps, int64_t n, int N, double L, const float4 *f,
-                      const uint32_t *idx, float4 *stage, hipStream_t s)
+                      const uint32_t *idx, float4 *stage, const uint32_t *cell_start,
+                      const uint32_t *item_start, hipStream_t s)
 {
     if (!n) return;
-    k_pm_interp<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(ps, n, N, N / L, f, idx, stage);
+    const uint32_t ncells = (uint32_t)pm_assign_cells(N);
+    k_pm_interp<<<(unsigned)pm_assign_items_max(N, n), kAssignThreads, 0, s>>>(
+        ps, N, N / L, f, idx, stage, cell_start, item_start, ncells);
 }
 
 void launch_pm_split(const float4 *stage, int64_t n, void *ax, void *ay, void *az,

@@ -1552,20 +1552,18 @@ TREEPM_API int treepm_force_long(treepm_ctx *c, void *ax, void *ay, void *az, in
     unsigned long long *mass = c->pm_mass.as<unsigned long long>();
     float2 *grid = c->pm_grid.as<float2>();
     float *phi = c->pm_mass.as<float>(); // the masses are consumed by the first pass
-    {
-        const size_t cells = pm_assign_cells((int)N);
-        uint32_t *cell_start = c->pm_cells.as<uint32_t>();
-        uint32_t *item_start = cell_start + (cells + 1);
-        uint32_t *scan_tmp = item_start + (cells + 1);
-        launch_pm_assign(ps, c->key.as<uint64_t>(), c->n, (int)N, P.L,
-                         c->pm_mx.as<unsigned long long>(), cell_start, item_start, scan_tmp,
-                         c->pm_slots.as<unsigned long long>(), mass, s);
-    }
+    const size_t cells = pm_assign_cells((int)N);
+    uint32_t *cell_start = c->pm_cells.as<uint32_t>();
+    uint32_t *item_start = cell_start + (cells + 1);
+    uint32_t *scan_tmp = item_start + (cells + 1);
+    launch_pm_assign(ps, c->key.as<uint64_t>(), c->n, (int)N, P.L,
+                     c->pm_mx.as<unsigned long long>(), cell_start, item_start, scan_tmp,
+                     c->pm_slots.as<unsigned long long>(), mass, s);
     launch_pm_potential(mass, c->pm_mx.as<unsigned long long>(), c->n, (int)N, grid, phi,
                         c->pm_green.as<float>(), c->pm_tw.as<float2>(), s);
     launch_pm_force(phi, (int)N, P.L, c->pm_f.as<float4>(), s);
     launch_pm_interp(ps, c->n, (int)N, P.L, c->pm_f.as<float4>(), c->idx.as<uint32_t>(),
-                     c->pm_stage.as<float4>(), s);
+                     c->pm_stage.as<float4>(), cell_start, item_start, s);
     launch_pm_split(c->pm_stage.as<float4>(), c->n, dst[0], dst[1], dst[2],
                     out_prec == TREEPM_FP64, accumulate, s);
     HIPCHK(c, hipGetLastError());
