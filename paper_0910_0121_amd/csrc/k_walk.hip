@@ -155,9 +155,34 @@ __device__ __forceinline__ Visit visit(const WalkNode &w, const WalkParams &wp, 
     return r;
 }
 
+// How many nodes a step pops from a stack holding `top`: at most 64, and only as many as leave
+// kStackReserve slots free after their pushes (each pushes at most 8), but at least one.
+__device__ __forceinline__ int pop_count(int top)
+{
+    int room = (kStackCap - kStackReserve - top) / 7;
+    int k = top < 64 ? top : 64;
+    if (room < 1) room = 1;
+    return k > room ? room : k;
+}
+
+// The node a lane pops (lanes at or past k read the root, node 0, and ignore it).
+__device__ __forceinline__ uint32_t pop_node(const uint32_t *stk, int top, int k, int lane,
+                                             const WalkParams &wp, unsigned *overflow)
+{
+    uint32_t u = lane < k ? stk[top - k + lane] : 0u;
+    if (u >= wp.n_nodes) { // cannot happen for a well-formed tree: report, never read
+        atomicOr(overflow, 2u);
+        u = 0u;
+    }
+    return u;
+}
+
 // Walks group g with the calling wave.  EMIT: writes the list to dst[0 .. cap) (entries past
 // cap are counted but not stored).  Returns the list length; *ncell gets the cell entries.
-// stk (kStackCap) and s_mark (64) are the wave's LDS scratch.
+// stk (kStackCap) and s_mark (64) are the wave's LDS scratch.  Each step visits the popped
+// nodes, pushes the children of the opened ones, pops the next step's nodes and starts
+// reading their records, and only then writes this step's list entries, so the writes
+// overlap the reads.
 template <int EMIT, int OPEN>
 __device__ __forceinline__ uint64_t walk_group(const WalkNode *__restrict__ wn,
                                                const GroupArrays &gr, uint32_t g,
@@ -170,30 +195,29 @@ __device__ __forceinline__ uint64_t walk_group(const WalkNode *__restrict__ wn,
     const double cg0 = gr.cgx[g], cg1 = gr.cgy[g], cg2 = gr.cgz[g];
     const double hg0 = gr.hgx[g], hg1 = gr.hgy[g], hg2 = gr.hgz[g];
     uint64_t written = 0, ncell = 0;
-    __syncthreads(); // the previous group's last stack reads are done
-    if (lane == 0) stk[0] = 0;
-    int top = 1;
-    __syncthreads();
-    while (top > 0) {
-        // a popped node pushes at most 8 children: top - k + 8k <= kStackCap - kStackReserve
-        int room = (kStackCap - kStackReserve - top) / 7;
-        int k = top < 64 ? top : 64;
-        if (room < 1) room = 1;
-        if (k > room) k = room;
+    // the first step pops the root alone
+    int k = 1, top = 0;
+    uint32_t u = 0u;
+    WalkNode rec = wn[0];
+    while (k > 0) {
         Visit a{0, 0u, 0u, 0u, 0u};
-        const bool has = lane < k;
-        uint32_t u = has ? stk[top - k + lane] : 0u;
-        if (u >= wp.n_nodes) { // cannot happen for a well-formed tree: report, never read
-            atomicOr(overflow, 2u);
-            u = 0u;
-        }
-        const WalkNode rec = wn[u]; // an idle lane reads the root's record (node 0)
-        if (has) a = visit<OPEN>(rec, wp, cg0, cg1, cg2, hg0, hg1, hg2);
-        __syncthreads(); // every lane has read its stack slot before the stack is rewritten
-        top -= k;
+        if (lane < k) a = visit<OPEN>(rec, wp, cg0, cg1, cg2, hg0, hg1, hg2);
         uint32_t ne_tot, np_tot;
         const uint32_t ne_ex = wave_excl_scan(a.ne, &ne_tot);
         const uint32_t np_ex = wave_excl_scan(a.np, &np_tot);
+        if (top + (int)np_tot > kStackCap) {
+            if (lane == 0) atomicOr(overflow, 1u);
+            break;
+        }
+        __syncthreads(); // the last step's stack reads are done before these pushes
+        if (a.kind == 3)
+            for (uint32_t c = 0; c < a.np; ++c) stk[top + np_ex + c] = a.cf + c;
+        top += (int)np_tot;
+        __syncthreads(); // pushes visible before the pops
+        const int k2 = top > 0 ? pop_count(top) : 0;
+        const uint32_t u2 = pop_node(stk, top, k2, lane, wp, overflow);
+        const WalkNode rec2 = wn[u2];
+        top -= k2;
         if (EMIT && ne_tot) {
             // Expand this step's entries cooperatively so the global writes are contiguous,
             // 64 slots at a time.  Each lane whose run starts inside the chunk marks its
@@ -219,15 +243,11 @@ __device__ __forceinline__ uint64_t walk_group(const WalkNode *__restrict__ wn,
         }
         written += ne_tot;
         ncell += (uint64_t)__popcll(__ballot(a.kind == 1));
-        if (top + (int)np_tot > kStackCap) {
-            if (lane == 0) atomicOr(overflow, 1u);
-            break;
-        }
-        if (a.kind == 3)
-            for (uint32_t c = 0; c < a.np; ++c) stk[top + np_ex + c] = a.cf + c;
-        top += (int)np_tot;
-        __syncthreads(); // pushes visible before the next pops
+        k = k2;
+        u = u2;
+        rec = rec2;
     }
+    __syncthreads(); // the stack and marks are free for the next group
     *ncell_out = ncell;
     return written;
 }
