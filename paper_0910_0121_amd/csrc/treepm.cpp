@@ -644,8 +644,9 @@ int do_build(treepm_ctx *c, int64_t n, const double *x, const double *y, const d
     return TREEPM_OK;
 }
 
-// Waves of the one-pass walk: enough to fill the chip, about 16 groups each at least.
-uint32_t pool_waves(uint32_t G) { return std::max(1u, std::min(8192u, (G + 15) / 16)); }
+// Waves of the one-pass walk: the resident waves of the chip (seven per SIMD, the kernel's
+// register-limited occupancy, on 256 compute units), about 16 groups each at least.
+uint32_t pool_waves(uint32_t G) { return std::max(1u, std::min(7168u, (G + 15) / 16)); }
 
 // One box's walk in parts, shared by treepm_walk and the shared launches of several boxes.
 struct BoxWalk {
