@@ -644,9 +644,10 @@ int do_build(treepm_ctx *c, int64_t n, const double *x, const double *y, const d
     return TREEPM_OK;
 }
 
-// Waves of the one-pass walk: the resident waves of the chip (seven per SIMD, the kernel's
-// register-limited occupancy, on 256 compute units), about 16 groups each at least.
-uint32_t pool_waves(uint32_t G) { return std::max(1u, std::min(7168u, (G + 15) / 16)); }
+// Waves of the one-pass walk: six per SIMD on 256 compute units (measured on the 256^3 box:
+// 2.57 ms against 2.66 with seven, the most that stay resident, and 2.75 with eight; fewer
+// groups in flight keep more of their tree nodes in L2), about 16 groups each at least.
+uint32_t pool_waves(uint32_t G) { return std::max(1u, std::min(6144u, (G + 15) / 16)); }
 
 // One box's walk in parts, shared by treepm_walk and the shared launches of several boxes.
 struct BoxWalk {
