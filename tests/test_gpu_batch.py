@@ -94,6 +94,64 @@ def test_batch_equals_alone(tp):
             tp.treepm_destroy(c)
 
 
+def test_batch_n_crit_256_and_distinct_tables(tp):
+    """Groups of up to 256 particles (every blocking factor K = 1..4 of the force classes) and
+    boxes whose pair-law tables differ (eps / r_cut of 1/20, 1/30 and 1/40: the force
+    launch reloads the table between boxes), each equal to its alone result."""
+    print("[gpu-case] batch with n_crit 256 and three pair-law tables", flush=True)
+    cases = []
+    for n, seed, eps_div in [(120000, 71, 20), (50000, 72, 40), (200000, 73, 30),
+                             (80000, 74, 20), (30000, 75, 40)]:
+        arr = boxgen.nfw_box(n, max(1, n // 500), seed)
+        mesh = 1.0 / round(n ** (1 / 3))
+        prm = tp.make_params(1.0, mesh, 3 * mesh, 3 * mesh / eps_div, 0.5, 10, 256,
+                             tp.TREEPM_FP32)
+        cases.append((prm, arr))
+    ref = [_alone(tp, prm, arr) for prm, arr in cases]
+    ctxs = [tp.treepm_create(prm, 0) for prm, _ in cases]
+    try:
+        for rep in range(2):
+            for c, (prm, arr) in zip(ctxs, cases):
+                tp.treepm_build(c, *arr)
+            outs = [tuple(np.full(len(arr[0]), np.nan, dtype=np.float32) for _ in range(3))
+                    for _, arr in cases]
+            tp.treepm_force_short_batch(ctxs, outs)
+            for b, (c, o) in enumerate(zip(ctxs, outs)):
+                np.testing.assert_array_equal(np.stack(o), ref[b][0], err_msg=f"box {b} rep {rep}")
+                assert _counts(tp, c) == ref[b][1], (b, rep)
+    finally:
+        for c in ctxs:
+            tp.treepm_destroy(c)
+
+
+def test_batch_large_boxes(tp):
+    """Boxes of 0.3 to 4 million particles (up to 8 groups per XCD part of every class and
+    tens of thousands of groups per box), mixed with a small one, equal to their alone
+    results; then again with all of them walked before (one-pass pools)."""
+    print("[gpu-case] batch of large boxes", flush=True)
+    cases = []
+    for n, seed in [(4_000_000, 81), (300_000, 82), (1_500_000, 83), (20_000, 84)]:
+        arr = boxgen.nfw_box(n, max(1, n // 5000), seed)
+        mesh = 1.0 / round(n ** (1 / 3))
+        cases.append((tp.make_params(1.0, mesh, 3 * mesh, mesh / 20, 0.5, 10, 256,
+                                     tp.TREEPM_FP32), arr))
+    ref = [_alone(tp, prm, arr) for prm, arr in cases]
+    ctxs = [tp.treepm_create(prm, 0) for prm, _ in cases]
+    try:
+        for rep in range(2):
+            for c, (prm, arr) in zip(ctxs, cases):
+                tp.treepm_build(c, *arr)
+            outs = [tuple(np.full(len(arr[0]), np.nan, dtype=np.float32) for _ in range(3))
+                    for _, arr in cases]
+            tp.treepm_force_short_batch(ctxs, outs)
+            for b, (c, o) in enumerate(zip(ctxs, outs)):
+                np.testing.assert_array_equal(np.stack(o), ref[b][0], err_msg=f"box {b} rep {rep}")
+                assert _counts(tp, c) == ref[b][1], (b, rep)
+    finally:
+        for c in ctxs:
+            tp.treepm_destroy(c)
+
+
 def test_batch_device_outputs_and_one_box(tp):
     print("[gpu-case] batch with device outputs; batch of one", flush=True)
     cases = _cases(tp)[:3]
