@@ -4,9 +4,12 @@
 // interpolation back to the particles.
 //
 // Mesh layout: point (x, y, z) at (x N + y) N + z, z contiguous; N a power of two.
-//  * assignment: a wave sums 256 consecutive particles (key order, so they are close
-//    together) into an LDS box of mesh points and adds the box to the mesh; masses are summed
-//    as 64-bit fixed point, so the mesh does not depend on the order of the atomics;
+//  * assignment by owner cells: the mesh is cut into cells of 8^3 points (tree cells, so a
+//    cell's particles are contiguous in key order); a workgroup sums a chunk of one cell's
+//    particles into the cell's 11^3 box in LDS and stores the box to its own slot, then one
+//    workgroup per cell adds, for each of its points, the slot words that cover it.  Masses
+//    are 64-bit fixed point and every sum is a fixed set of integer adds, so the mesh is the
+//    same on every run; there are no global atomics;
 //  * FFT: complex, radix 2, one workgroup per bundle of B lines of one axis held in LDS
 //    (B N = 4096 values, B <= 16).  Bundles along x and y are B neighbouring lines in z, so a
 //    load of one element row is B contiguous values; bundles along z are B contiguous rows.
@@ -14,11 +17,10 @@
 //    Green's function + z inverse in one kernel (a DIF forward leaves bit-reversed order, which
 //    is what the DIT inverse reads), y inverse, x inverse (writing the real potential);
 //  * mesh force: fourth-order central differences of the potential, one float4 per point;
-//  * interpolation: one thread per particle (key order) gathers the 27 points of its cloud
-//    (neighbouring threads hold neighbouring particles, so the gathers share cache lines) and
-//    writes the 16-byte result to the particle's slot in the caller's order through the sort
-//    permutation (a scattered write); k_pm_split then writes the three output arrays
-//    contiguously.
+//  * interpolation: over the assignment's chunks, the cell's 11^3 box of force words read
+//    into LDS once, each particle's 27 words from there; the 16-byte result goes to the
+//    particle's slot in the caller's order through the sort permutation (a scattered write);
+//    k_pm_split then writes the three output arrays contiguously.
 #include "common.hpp"
 
 namespace tpm {
