@@ -31,6 +31,8 @@
 //     a fresh one).  Pool and chunk sizes come from the caller (from an earlier walk); if a
 //     list or the pool runs out of room, the pass reports it and the caller falls back to
 //     two passes, so the result never depends on those sizes.
+// Both layouts also run over the groups of several boxes in one launch (k_walk_multi,
+// k_walk_pool_multi: per-box descriptors in device memory, each box's own lists and flags).
 #include "common.hpp"
 
 namespace tpm {
