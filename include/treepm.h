@@ -133,8 +133,18 @@ typedef struct {
  * context allocates device memory lazily and keeps it for later calls. */
 int treepm_create(const treepm_params *params, int device, treepm_ctx **out);
 
-/* Release every resource of the context.  NULL is accepted. */
+/* Release every resource of the context, after waiting for its queued work.  NULL is
+ * accepted.  Its device buffers, streams and events are kept by the library (per device,
+ * process-wide) for later contexts rather than handed back to the driver: a server that
+ * evicts and creates boxes continuously then neither frees nor maps device memory while
+ * other boxes run.  At most a quarter of the device's memory is kept that way (the rest is
+ * freed); treepm_release_cached gives it back. */
 int treepm_destroy(treepm_ctx *ctx);
+
+/* Give the device memory that destroyed contexts left for reuse on `device` back to the
+ * driver, waiting for any queued work that may still use it.  Contexts alive on the device
+ * keep their own buffers.  Returns TREEPM_ERR_DEVICE for a device that does not exist. */
+int treepm_release_cached(int device);
 
 /* Replace the parameters of an existing context (same validation as create).  The next
  * call must be treepm_build. */

@@ -27,6 +27,7 @@ from ._native import (  # noqa: F401
     treepm_ensemble_submit,
     treepm_create,
     treepm_destroy,
+    treepm_release_cached,
     treepm_export_groups,
     treepm_export_lists,
     treepm_export_nodes,

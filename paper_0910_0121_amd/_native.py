@@ -59,6 +59,7 @@ _SIGS = {
     "treepm_version": (C.c_char_p, []),
     "treepm_create": (_i, [C.POINTER(treepm_params), _i, C.POINTER(_p)]),
     "treepm_destroy": (_i, [_p]),
+    "treepm_release_cached": (_i, [_i]),
     "treepm_set_params": (_i, [_p, C.POINTER(treepm_params)]),
     "treepm_set_timing": (_i, [_p, _i]),
     "treepm_build": (_i, [_p, _i64, _p, _p, _p, _p, _i, _p]),
@@ -179,6 +180,10 @@ def treepm_create(params: treepm_params, device: int = 0):
 
 def treepm_destroy(ctx) -> None:
     _check(lib().treepm_destroy(ctx))
+
+
+def treepm_release_cached(device: int = 0) -> None:
+    _check(lib().treepm_release_cached(device))
 
 
 def treepm_set_params(ctx, params: treepm_params) -> None:

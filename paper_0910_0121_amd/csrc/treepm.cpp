@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
 #include <thread>
@@ -38,11 +39,9 @@ constexpr int kDefaultNCrit = 128;
 struct treepm_ctx {
     treepm_params prm{};
     int device = 0;
-    // Device memory comes from the stream-ordered allocator on a private stream: freeing a
-    // buffer waits (through `freed`) for the work of the current call's stream and never
-    // synchronises the device, so contexts on other streams are not stalled.
+    // A private stream: destroying the context releases its buffers in a call scope on it,
+    // after the context's own work has finished.
     hipStream_t own = nullptr;
-    hipEvent_t freed = nullptr;
     // Recorded on the call's stream as each API call returns: all of this context's work is
     // before it, so destroying the context waits for it rather than for its last stream,
     // which other work (another context's, in a serving worker) may share.
@@ -143,15 +142,161 @@ int hip_fail(treepm_ctx *c, hipError_t e, const char *what)
 // The context whose buffers reserve()/release() manage on this thread (set by each call).
 thread_local treepm_ctx *t_ctx = nullptr;
 
+// ------------------------------------------------------------------ device memory
+// Released device buffers are kept, per device, for the next buffers of any context instead
+// of going back to the driver: a server that evicts and creates boxes all the time would
+// otherwise hand gigabytes a second back and forth, and freeing and mapping device memory
+// holds up the other streams' HIP calls meanwhile.  A block released while work on a stream
+// may still use it carries an event recorded on that stream and is taken again only once the
+// event has completed.  What is kept is bounded (a quarter of the device's memory): past
+// that, completed blocks go back to the driver, largest first; an allocation that fails gives
+// back everything kept on the device and tries once more.  treepm_release_cached empties it.
+struct Block {
+    void *p = nullptr;
+    size_t bytes = 0;
+    hipEvent_t done = nullptr; // recorded where the last work that may use it was queued
+};
+
+struct DevCache {
+    std::mutex mu;
+    std::multimap<size_t, Block> blocks; // by size
+    std::vector<hipEvent_t> spare;       // events of blocks taken again
+    size_t kept = 0, cap = 0;
+};
+
+DevCache g_dev[kMaxDevices];
+
+// Sizes of fresh blocks: powers of two up to 1 MiB, then multiples of 2 MiB, so that a block
+// serves later requests of nearby sizes.
+size_t block_size(size_t bytes)
+{
+    if (bytes <= ((size_t)1 << 20)) {
+        size_t b = 4096;
+        while (b < bytes) b <<= 1;
+        return b;
+    }
+    const size_t g = (size_t)2 << 20;
+    return (bytes + g - 1) / g * g;
+}
+
+// With d.mu held: has the block's last use completed?  Queried only while this thread holds
+// no unread HIP error, which the query's not-ready status would otherwise replace.
+bool block_ready(DevCache &d, Block &b, bool may_query)
+{
+    if (!b.done) return true;
+    if (!may_query) return false;
+    const hipError_t e = hipEventQuery(b.done);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    d.spare.push_back(b.done);
+    b.done = nullptr;
+    return true;
+}
+
+// With d.mu held: give completed blocks back to the driver, largest first, until at most
+// `keep` bytes are kept (with wait, blocks still in use are waited for and given back too).
+void trim_blocks(DevCache &d, size_t keep, bool wait)
+{
+    const bool may_query = hipPeekAtLastError() == hipSuccess;
+    for (auto it = d.blocks.end(); it != d.blocks.begin() && d.kept > keep;) {
+        --it;
+        Block &b = it->second;
+        if (wait && b.done) {
+            (void)hipEventSynchronize(b.done);
+            d.spare.push_back(b.done);
+            b.done = nullptr;
+        }
+        if (!block_ready(d, b, may_query)) continue;
+        (void)hipFree(b.p);
+        d.kept -= b.bytes;
+        it = d.blocks.erase(it);
+    }
+}
+
+// A block of at least `bytes` on the current device (*got: its size), or an error.
+hipError_t take_block(int device, size_t bytes, void **p, size_t *got)
+{
+    DevCache &d = g_dev[device];
+    {
+        std::lock_guard<std::mutex> lk(d.mu);
+        const bool may_query = hipPeekAtLastError() == hipSuccess;
+        // the smallest completed block that holds the request
+        // (at most half again its size)
+        const size_t hi = bytes <= ((size_t)1 << 20) ? ((size_t)1 << 20) : bytes + bytes / 2;
+        for (auto it = d.blocks.lower_bound(bytes); it != d.blocks.end() && it->first <= hi;
+             ++it)
+            if (block_ready(d, it->second, may_query)) {
+                *p = it->second.p;
+                *got = it->second.bytes;
+                d.kept -= it->second.bytes;
+                d.blocks.erase(it);
+                return hipSuccess;
+            }
+    }
+    const size_t want = block_size(bytes);
+    hipError_t e = hipMalloc(p, want);
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) {
+        (void)hipGetLastError();
+        {
+            std::lock_guard<std::mutex> lk(d.mu);
+            trim_blocks(d, 0, true);
+        }
+        e = hipMalloc(p, want);
+    }
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        return e;
+    }
+    *got = want;
+    return hipSuccess;
+}
+
+// Keep a block for reuse; `in_use` (may be null) is a stream whose queued work may still use
+// it.
+void give_block(int device, void *p, size_t bytes, hipStream_t in_use, bool pending)
+{
+    DevCache &d = g_dev[device];
+    std::lock_guard<std::mutex> lk(d.mu);
+    if (!d.cap) {
+        size_t fr = 0, tot = 0;
+        d.cap = hipMemGetInfo(&fr, &tot) == hipSuccess ? tot / 4 : ((size_t)16 << 30);
+        (void)hipGetLastError();
+    }
+    Block b;
+    b.p = p;
+    b.bytes = bytes;
+    if (pending) {
+        hipEvent_t ev = nullptr;
+        if (!d.spare.empty()) {
+            ev = d.spare.back();
+            d.spare.pop_back();
+        } else if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+            ev = nullptr;
+        }
+        if (!ev || hipEventRecord(ev, in_use) != hipSuccess) {
+            // no event: wait here for the stream instead
+            if (ev) d.spare.push_back(ev);
+            ev = nullptr;
+            (void)hipStreamSynchronize(in_use);
+        }
+        b.done = ev;
+    }
+    d.blocks.emplace(bytes, b);
+    d.kept += bytes;
+    if (d.kept > d.cap) trim_blocks(d, d.cap, false);
+}
+
 void release(Buf &b)
 {
     if (!b.p) return;
     treepm_ctx *c = t_ctx;
-    if (c && c->own) {
-        // free once the current call's stream has finished with the buffer
-        (void)hipEventRecord(c->freed, c->cur);
-        (void)hipStreamWaitEvent(c->own, c->freed, 0);
-        (void)hipFreeAsync(b.p, c->own);
+    if (c && c->device < kMaxDevices) {
+        // work queued on the current call's stream may still use the buffer; in the private
+        // stream's scope (destroy) the context's work has finished
+        give_block(c->device, b.p, b.bytes, c->cur, c->cur != c->own || !c->own);
     } else {
         (void)hipFree(b.p);
     }
@@ -166,11 +311,12 @@ hipError_t reserve(Buf &b, size_t bytes)
     size_t want = bytes + bytes / 8 + 256;
     treepm_ctx *c = t_ctx;
     hipError_t e;
-    if (c && c->own) {
-        e = hipMallocAsync(&b.p, want, c->own);
-        if (e == hipSuccess) e = hipStreamSynchronize(c->own); // ready for any stream
+    size_t got = 0;
+    if (c && c->device < kMaxDevices) {
+        e = take_block(c->device, want, &b.p, &got);
     } else {
         e = hipMalloc(&b.p, want);
+        got = want;
     }
     if (e != hipSuccess) {
         b.p = nullptr;
@@ -178,7 +324,7 @@ hipError_t reserve(Buf &b, size_t bytes)
         (void)hipGetLastError();
         return e;
     }
-    b.bytes = want;
+    b.bytes = got;
     return hipSuccess;
 }
 
@@ -827,23 +973,6 @@ void fill_stats(treepm_ctx *c, treepm_stats *st)
 
 } // namespace
 
-// The device's default memory pool keeps freed blocks for reuse instead of returning them to
-// the driver at each synchronisation.
-void retain_pool(int device)
-{
-    static std::mutex mu;
-    static bool done[64] = {};
-    std::lock_guard<std::mutex> lk(mu);
-    if (device < 0 || device >= 64 || done[device]) return;
-    hipMemPool_t pool;
-    if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess) {
-        uint64_t thr = UINT64_MAX;
-        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
-    }
-    (void)hipGetLastError();
-    done[device] = true;
-}
-
 // The parameter checks of treepm_create, without a context or a device (used by the ensemble
 // server to validate a request before queueing it).
 int treepm_internal_check_params(const treepm_params *p) { return check_params(nullptr, p); }
@@ -872,6 +1001,45 @@ size_t treepm_internal_ctx_bytes(const treepm_ctx *c)
 
 TREEPM_API const char *treepm_version(void) { return "treepm-mi355x 0.1"; }
 
+namespace {
+
+// The streams and events of destroyed contexts, kept for the next contexts on the same device:
+// creating and destroying them takes milliseconds, and an ensemble evicts and creates boxes
+// all the time.  Only complete sets whose streams are idle are kept, at most kMaxShells.
+struct Shell {
+    int device = 0;
+    hipStream_t own = nullptr, sub[treepm_ctx::kSubStreams] = {};
+    hipEvent_t idle = nullptr, fork = nullptr, join[treepm_ctx::kSubStreams] = {};
+};
+constexpr size_t kMaxShells = 64;
+std::mutex g_shell_mu;
+std::vector<Shell> g_shells;
+
+bool take_shell(int device, Shell *out)
+{
+    std::lock_guard<std::mutex> lk(g_shell_mu);
+    for (size_t i = g_shells.size(); i-- > 0;)
+        if (g_shells[i].device == device) {
+            *out = g_shells[i];
+            g_shells.erase(g_shells.begin() + (std::ptrdiff_t)i);
+            return true;
+        }
+    return false;
+}
+
+bool keep_shell(const Shell &sh)
+{
+    if (!sh.own || !sh.idle || !sh.fork) return false;
+    for (int i = 0; i < treepm_ctx::kSubStreams; ++i)
+        if (!sh.sub[i] || !sh.join[i]) return false;
+    std::lock_guard<std::mutex> lk(g_shell_mu);
+    if (g_shells.size() >= kMaxShells) return false;
+    g_shells.push_back(sh);
+    return true;
+}
+
+} // namespace
+
 TREEPM_API int treepm_create(const treepm_params *params, int device, treepm_ctx **out)
 {
     if (!out) return TREEPM_ERR_ARG;
@@ -889,7 +1057,6 @@ TREEPM_API int treepm_create(const treepm_params *params, int device, treepm_ctx
         delete c;
         return TREEPM_ERR_DEVICE;
     }
-    retain_pool(device);
     {
         int ncu = 0;
         if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) ==
@@ -898,12 +1065,21 @@ TREEPM_API int treepm_create(const treepm_params *params, int device, treepm_ctx
             c->n_cu = ncu;
         (void)hipGetLastError();
     }
-    if (hipStreamCreateWithFlags(&c->own, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&c->freed, hipEventDisableTiming) != hipSuccess) {
-        // no private stream: fall back to plain hipMalloc / hipFree
-        if (c->own) (void)hipStreamDestroy(c->own);
-        c->own = nullptr;
-        c->freed = nullptr;
+    Shell sh;
+    if (take_shell(device, &sh)) {
+        c->own = sh.own;
+        c->idle = sh.idle;
+        c->fork = sh.fork;
+        for (int i = 0; i < treepm_ctx::kSubStreams; ++i) {
+            c->sub[i] = sh.sub[i];
+            c->join[i] = sh.join[i];
+        }
+        take_mailbox(&c->mbox_h, &c->mbox_d);
+        *out = c;
+        return TREEPM_OK;
+    }
+    if (hipStreamCreateWithFlags(&c->own, hipStreamNonBlocking) != hipSuccess) {
+        c->own = nullptr; // destroy then releases in the last stream's scope
         (void)hipGetLastError();
     }
     if (hipEventCreateWithFlags(&c->idle, hipEventDisableTiming) != hipSuccess) {
@@ -936,13 +1112,11 @@ TREEPM_API int treepm_destroy(treepm_ctx *c)
     if (!c) return TREEPM_OK;
     hipSetDevice(c->device);
     // this context's own work, not the rest of a stream it may share
-    if (c->idle && c->idle_set) hipEventSynchronize(c->idle);
-    else if (c->last) hipStreamSynchronize(c->last);
-    else hipDeviceSynchronize();
-    if (c->idle) { // no more records: the scope below must not touch the event
-        (void)hipEventDestroy(c->idle);
-        c->idle = nullptr;
-    }
+    if (c->idle && c->idle_set) (void)hipEventSynchronize(c->idle);
+    else if (c->last) (void)hipStreamSynchronize(c->last);
+    else (void)hipDeviceSynchronize();
+    hipEvent_t idle = c->idle;
+    c->idle = nullptr; // no more records: the scope below must not touch the event
     Buf *all[] = {&c->in[0], &c->in[1], &c->in[2], &c->in[3], &c->key, &c->key_alt, &c->idx,
                   &c->idx_alt, &c->hist,
                   &c->scan32, &c->flags, &c->levcnt, &c->gstart, &c->gflag, &c->n_code,
@@ -958,24 +1132,47 @@ TREEPM_API int treepm_destroy(treepm_ctx *c)
                   &c->pm_f, &c->pm_green, &c->pm_tw, &c->pm_mx, &c->pm_stage, &c->pm_cells, &c->pm_slots,
                   &c->n_q, &c->step_min, &c->tab, &c->bdesc};
     {
-        // the work is done: free on the private stream, not behind the last stream
+        // the work is done: the buffers are kept for reuse at once, not behind a stream
         CallScope scope(c, c->own ? c->own : c->last);
         for (Buf *b : all) release(*b);
     }
-    if (c->own) {
-        (void)hipStreamSynchronize(c->own);
-        (void)hipStreamDestroy(c->own);
-    }
-    if (c->freed) (void)hipEventDestroy(c->freed);
+    if (c->own) (void)hipStreamSynchronize(c->own);
     if (c->mbox_h) give_mailbox(c->mbox_h, c->mbox_d); // the stream is idle: nothing writes it
+    Shell sh;
+    sh.device = c->device;
+    sh.own = c->own;
+    sh.idle = idle;
+    sh.fork = c->fork;
     for (int i = 0; i < treepm_ctx::kSubStreams; ++i) {
-        if (c->sub[i]) (void)hipStreamDestroy(c->sub[i]);
-        if (c->join[i]) (void)hipEventDestroy(c->join[i]);
+        sh.sub[i] = c->sub[i];
+        sh.join[i] = c->join[i];
+        if (c->sub[i]) (void)hipStreamSynchronize(c->sub[i]);
     }
-    if (c->fork) (void)hipEventDestroy(c->fork);
+    if (!keep_shell(sh)) {
+        if (c->own) (void)hipStreamDestroy(c->own);
+        if (idle) (void)hipEventDestroy(idle);
+        for (int i = 0; i < treepm_ctx::kSubStreams; ++i) {
+            if (c->sub[i]) (void)hipStreamDestroy(c->sub[i]);
+            if (c->join[i]) (void)hipEventDestroy(c->join[i]);
+        }
+        if (c->fork) (void)hipEventDestroy(c->fork);
+    }
     if (c->ev[0])
         for (hipEvent_t &e : c->ev) (void)hipEventDestroy(e);
     delete c;
+    return TREEPM_OK;
+}
+
+TREEPM_API int treepm_release_cached(int device)
+{
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev ||
+        device >= kMaxDevices)
+        return TREEPM_ERR_DEVICE;
+    if (hipSetDevice(device) != hipSuccess) return TREEPM_ERR_DEVICE;
+    DevCache &d = g_dev[device];
+    std::lock_guard<std::mutex> lk(d.mu);
+    trim_blocks(d, 0, true);
     return TREEPM_OK;
 }
 
@@ -1935,7 +2132,7 @@ TREEPM_API int treepm_pairwise_f32(const treepm_params *params, int device, int6
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipMemcpy(out, dout, bo, hipMemcpyDeviceToHost);
-    hipFree(d);
+    (void)hipFree(d);
     return e == hipSuccess ? TREEPM_OK : TREEPM_ERR_DEVICE;
 }
 
