@@ -318,7 +318,9 @@ int treepm_pairwise_f32(const treepm_params *params, int device, int64_t n_i, co
  * hbm_budget: device bytes the server may keep allocated for resident boxes (particles,
  * tree, lists; > 0).  max_inflight: requests run at once (1..16), each on its own worker
  * thread and HIP stream.  A box (identified by the caller's box_id) keeps its device state
- * between requests until it is evicted, least recently used first, to admit another box. */
+ * between requests until it is evicted, least recently used first, to admit another box.
+ * An evicted box's device memory stays with the library for the next boxes (treepm_destroy),
+ * so the process can hold up to a quarter of the device's memory beyond the budget. */
 int treepm_ens_create(int device, size_t hbm_budget, int max_inflight, treepm_ens **out);
 
 /* Shared launches in the server (enable = 1; 0, the default, switches them off).  When on, a
