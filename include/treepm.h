@@ -153,6 +153,16 @@ int treepm_set_params(treepm_ctx *ctx, const treepm_params *params);
 /* Record per-phase device times into treepm_stats.t_ms (adds event records to the stream). */
 int treepm_set_timing(treepm_ctx *ctx, int enable);
 
+/* How treepm_walk (and treepm_force_short_batch) write a context's lists.  TREEPM_WALK_AUTO
+ * (the default): in one pass once an earlier walk has sized the device memory, if the box has
+ * at least 98,304 groups (16 per wave of the one-pass launch: below that the launch cannot
+ * fill the device and the two passes, a wave per group each, are faster); in two passes
+ * otherwise.  TREEPM_WALK_ONE_PASS: in one pass whenever an earlier walk sized it.
+ * TREEPM_WALK_TWO_PASS: always in two passes.  The lists are the same in every mode.
+ * ERR_ARG for another mode. */
+enum { TREEPM_WALK_AUTO = 0, TREEPM_WALK_ONE_PASS = 1, TREEPM_WALK_TWO_PASS = 2 };
+int treepm_set_walk_passes(treepm_ctx *ctx, int mode);
+
 /* Build the tree of n particles (Section 2.2 step 2): validate, compute 63-bit Morton keys,
  * stable radix sort, gather positions and masses into key order, build the octree with the
  * N_leaf rule, FP64 node masses and centres of mass, and the N_crit groups.
@@ -164,10 +174,11 @@ int treepm_build(treepm_ctx *ctx, int64_t n, const double *x, const double *y, c
 
 /* Barnes' group walk (Section 2.2 step 5): one interaction list per group.  Requires a
  * build (ERR_STATE).  Fills *stats if non-NULL.  The first walk on a context counts the lists
- * and then writes them (two passes); later walks write them in one pass into device memory
- * sized from the previous walk (about 1.25x its lists plus a chunk per wave) and fall back to
- * two passes if that is too small, so the lists never depend on the estimate.  ERR_OVERFLOW
- * if a group's traversal stack would exceed its capacity (see last_error). */
+ * and then writes them (two passes); later walks of boxes with at least 98,304 groups (see
+ * treepm_set_walk_passes) write them in one pass into device memory sized from the previous
+ * walk (about 1.25x its lists plus a chunk per wave) and fall back to two passes if that is
+ * too small, so the lists never depend on the estimate.  ERR_OVERFLOW if a group's traversal
+ * stack would exceed its capacity (see last_error). */
 int treepm_walk(treepm_ctx *ctx, void *hip_stream, treepm_stats *stats);
 
 /* Short-range force on every particle from its group's list (eq. 1, 2), written in the

@@ -13,6 +13,7 @@ TREEPM_OK, TREEPM_PENDING = 0, 1
 TREEPM_FP32, TREEPM_FP64 = 0, 1
 TREEPM_HOST, TREEPM_DEVICE = 0, 1
 TREEPM_OPEN_FIXED, TREEPM_OPEN_DISTANCE = 0, 1
+TREEPM_WALK_AUTO, TREEPM_WALK_ONE_PASS, TREEPM_WALK_TWO_PASS = 0, 1, 2
 
 ERROR_NAMES = {
     -1: "TREEPM_ERR_ARG", -2: "TREEPM_ERR_RANGE", -3: "TREEPM_ERR_OOM",
@@ -62,6 +63,7 @@ _SIGS = {
     "treepm_release_cached": (_i, [_i]),
     "treepm_set_params": (_i, [_p, C.POINTER(treepm_params)]),
     "treepm_set_timing": (_i, [_p, _i]),
+    "treepm_set_walk_passes": (_i, [_p, _i]),
     "treepm_build": (_i, [_p, _i64, _p, _p, _p, _p, _i, _p]),
     "treepm_walk": (_i, [_p, _p, C.POINTER(treepm_stats)]),
     "treepm_force_short": (_i, [_p, _p, _p, _p, _i, _i, _p]),
@@ -192,6 +194,10 @@ def treepm_set_params(ctx, params: treepm_params) -> None:
 
 def treepm_set_timing(ctx, enable: bool) -> None:
     _check(lib().treepm_set_timing(ctx, int(bool(enable))), ctx)
+
+
+def treepm_set_walk_passes(ctx, mode: int) -> None:
+    _check(lib().treepm_set_walk_passes(ctx, int(mode)), ctx)
 
 
 def treepm_build(ctx, x, y, z, m, stream=None) -> None:

@@ -94,6 +94,7 @@ def test_null_handles_are_rejected(native):
     assert lib.treepm_build(None, 1, None, None, None, None, 0, None) == -1
     assert lib.treepm_last_error(None) == b"NULL context"
     assert lib.treepm_release_cached(-1) == -4
+    assert lib.treepm_set_walk_passes(None, 0) == -1
 
 
 def test_ensemble_argument_checks_without_gpu(native):

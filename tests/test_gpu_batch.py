@@ -26,6 +26,14 @@ def tp():
     return t
 
 
+def _create(tp, prm):
+    """A context whose later walks use the one-pass pool whatever the box size (these boxes
+    are below the size where the automatic choice takes it)."""
+    ctx = tp.treepm_create(prm, 0)
+    tp.treepm_set_walk_passes(ctx, tp.TREEPM_WALK_ONE_PASS)
+    return ctx
+
+
 def _params(tp, mesh, theta=0.5, opening=0, theta_max=0.0, quad=0, n_crit=128, L=1.0):
     return tp.make_params(L, mesh, 3 * mesh, mesh / 20, theta, 10, n_crit, tp.TREEPM_FP32,
                           opening=opening, theta_max=theta_max, quadrupole=quad)
@@ -70,7 +78,7 @@ def test_batch_equals_alone(tp):
     print("[gpu-case] batch of 7 boxes vs each alone, fresh then walked", flush=True)
     cases = _cases(tp)
     ref = [_alone(tp, prm, arr) for prm, arr in cases]
-    ctxs = [tp.treepm_create(prm, 0) for prm, _ in cases]
+    ctxs = [_create(tp, prm) for prm, _ in cases]
     try:
         # boxes 1 and 3 walked before: their lists go into pools sized from that walk
         for k in (1, 3):
@@ -108,7 +116,7 @@ def test_batch_n_crit_256_and_distinct_tables(tp):
                              tp.TREEPM_FP32)
         cases.append((prm, arr))
     ref = [_alone(tp, prm, arr) for prm, arr in cases]
-    ctxs = [tp.treepm_create(prm, 0) for prm, _ in cases]
+    ctxs = [_create(tp, prm) for prm, _ in cases]
     try:
         for rep in range(2):
             for c, (prm, arr) in zip(ctxs, cases):
@@ -136,7 +144,7 @@ def test_batch_large_boxes(tp):
         cases.append((tp.make_params(1.0, mesh, 3 * mesh, mesh / 20, 0.5, 10, 256,
                                      tp.TREEPM_FP32), arr))
     ref = [_alone(tp, prm, arr) for prm, arr in cases]
-    ctxs = [tp.treepm_create(prm, 0) for prm, _ in cases]
+    ctxs = [_create(tp, prm) for prm, _ in cases]
     try:
         for rep in range(2):
             for c, (prm, arr) in zip(ctxs, cases):
@@ -156,7 +164,7 @@ def test_batch_device_outputs_and_one_box(tp):
     print("[gpu-case] batch with device outputs; batch of one", flush=True)
     cases = _cases(tp)[:3]
     ref = [_alone(tp, prm, arr) for prm, arr in cases]
-    ctxs = [tp.treepm_create(prm, 0) for prm, _ in cases]
+    ctxs = [_create(tp, prm) for prm, _ in cases]
     try:
         for c, (prm, arr) in zip(ctxs, cases):
             tp.treepm_build(c, *arr)
@@ -185,7 +193,7 @@ def test_batch_pool_too_small_walks_again(tp):
     big = boxgen.uniform_box(150000, 52)
     other_prm, other = _params(tp, 1.0 / 40), boxgen.nfw_box(64000, 128, 53)
     ref_big, ref_other = _alone(tp, prm, big), _alone(tp, other_prm, other)
-    c_big, c_other = tp.treepm_create(prm, 0), tp.treepm_create(other_prm, 0)
+    c_big, c_other = _create(tp, prm), _create(tp, other_prm)
     try:
         tp.treepm_build(c_big, *small)
         tp.treepm_walk(c_big)

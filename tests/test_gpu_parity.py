@@ -283,6 +283,7 @@ def test_one_pass_walk_on_a_reused_context(tp, orc):
     trees = {k: orc.Tree(*b, 1.0, r_cut, eps, theta, n_leaf, n_crit) for k, b in boxes.items()}
     p = tp.treepm_params(1.0, r_cut / 3.0, r_cut, eps, theta, n_leaf, n_crit, tp.TREEPM_FP64)
     ctx = tp.treepm_create(p, 0)
+    tp.treepm_set_walk_passes(ctx, tp.TREEPM_WALK_ONE_PASS)  # at any box size
     try:
         for name in ("small", "small", "big", "big"):
             _say(f"reused context: {name} box")
@@ -306,6 +307,41 @@ def test_one_pass_walk_on_a_reused_context(tp, orc):
             assert np.all(np.abs(got - ref) <= 1e-13 * T.error_scale()[None, :] + 1e-300)
     finally:
         tp.treepm_destroy(ctx)
+
+
+def test_walk_modes_give_the_same_lists(tp, orc):
+    """Every walk mode (automatic: two passes for a box this small; one pass into the pool;
+    always two passes) gives the oracle's lists and the same FP32 forces bit for bit, on the
+    first and on later walks of a context; other modes are rejected."""
+    x, y, z, m = boxgen.nfw_box(30000, 60, 41)
+    r_cut, eps = 0.07, 0.07 / 60
+    T = orc.Tree(x, y, z, m, 1.0, r_cut, eps, 0.5, 10, 64)
+    dev = [torch.from_numpy(a).cuda() for a in (x, y, z, m)]
+    p = tp.treepm_params(1.0, r_cut / 3.0, r_cut, eps, 0.5, 10, 64, tp.TREEPM_FP32)
+    ref = None
+    for mode in (tp.TREEPM_WALK_AUTO, tp.TREEPM_WALK_ONE_PASS, tp.TREEPM_WALK_TWO_PASS):
+        ctx = tp.treepm_create(p, 0)
+        try:
+            tp.treepm_set_walk_passes(ctx, mode)
+            for rep in range(3):
+                _say(f"walk mode {mode} walk {rep}")
+                tp.treepm_build(ctx, *dev)
+                st = tp.treepm_walk(ctx)
+                assert st.interactions == T.interactions()
+                _assert_lists_equal(tp, ctx, T, f"mode {mode} walk {rep}")
+                acc = [torch.zeros(30000, dtype=torch.float32, device="cuda") for _ in range(3)]
+                tp.treepm_force_short(ctx, *acc)
+                torch.cuda.synchronize()
+                got = np.stack([t.cpu().numpy() for t in acc])
+                if ref is None:
+                    ref = got
+                np.testing.assert_array_equal(got, ref)
+            for bad in (-1, 3):
+                with pytest.raises(tp.TreePMError) as e:
+                    tp.treepm_set_walk_passes(ctx, bad)
+                assert e.value.code == -1
+        finally:
+            tp.treepm_destroy(ctx)
 
 
 def _assert_lists_equal(tp, ctx, T, what):
@@ -343,6 +379,7 @@ def test_distance_opening_parity(tp, orc, case):
         p = tp.make_params(1.0, r_cut / 3.0, r_cut, eps, th0, n_leaf, n_crit, prec,
                            opening=tp.TREEPM_OPEN_DISTANCE, theta_max=tmax)
         ctx = tp.treepm_create(p, 0)
+        tp.treepm_set_walk_passes(ctx, tp.TREEPM_WALK_ONE_PASS)  # the second walk: one pass
         try:
             for walk in ("two-pass", "one-pass"):
                 _say(f"theta(r) {kind} n={n} th0={th0} max={tmax} prec={prec} {walk}")
