@@ -78,7 +78,7 @@ def parse():
     ap.add_argument("--scale-n-crit", type=int, default=192)
     ap.add_argument("--serving-boxes", type=int, default=64)
     ap.add_argument("--serving-requests-per-box", type=int, default=10)
-    ap.add_argument("--serving-inflight", type=int, default=4)
+    ap.add_argument("--serving-inflight", type=int, default=8)
     ap.add_argument("--serving-batching", action="store_true",
                     help="serve with shared walk and force launches across boxes")
     ap.add_argument("--serving-budget-frac", type=float, default=0.25)
