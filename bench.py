@@ -240,11 +240,15 @@ def serving_bench(tp, n_boxes, per_box, inflight, budget_frac=0.25, batching=Fal
         pending, done, lat = {}, [], []
         t0 = time.perf_counter()
         k = 0
+        shown = 0
         while len(done) < n_closed:
             while k < n_closed and len(pending) < 2 * inflight:
                 i = int(order[k]); k += 1
                 pending[tp.treepm_ensemble_submit(ens, i, params[i], *boxes[i])] = i
             drain(pending, done, lat)
+            if len(done) >= shown + 160:
+                shown = len(done) // 160 * 160
+                log(f"[serving] closed loop: {len(done)} of {n_closed} done")
             time.sleep(0.0005)
         t_closed = time.perf_counter() - t0
         cap = n_closed / t_closed
@@ -270,9 +274,13 @@ def serving_bench(tp, n_boxes, per_box, inflight, budget_frac=0.25, batching=Fal
 
             th = threading.Thread(target=submitter)
             th.start()
+            shown = 0
             while th.is_alive() or pending:
                 with lock:
                     drain(pending, done, lat)
+                if len(done) >= shown + 160:
+                    shown = len(done) // 160 * 160
+                    log(f"[serving] open loop at {frac} x: {len(done)} of {len(order)} done")
                 time.sleep(0.0005)
             th.join()
             return lam, np.array(lat).reshape(-1, 6), done, time.perf_counter() - t_start
